@@ -1,0 +1,386 @@
+/*
+ * dlj_ref.c -- plain FP64 CPU reference of the double-layer Jacobi method for
+ * finite-difference PDE-constrained NMPC (Deng & Ohtsuka, arXiv 2004.02484).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the oracle: it is compiled and called
+ * by the tests, by the smoke check and by the benchmark's CPU-baseline leg, and
+ * by nothing else. It shares no code with the HIP library.
+ *
+ * Everything is written as plain loops over explicit matrix rows so that it can
+ * be checked against the paper by eye:
+ *   - problem:   N-stage backward-Euler NMPC (Sec. 3, eq. nlp), stage cost
+ *                l = 0.5 q |x - xref|^2 + 0.5 r |u|^2, no inequality constraints
+ *                (barrier term and fraction-to-boundary rule inactive: alpha = 1);
+ *   - dynamics:  f(u, x) = k(x) .* (L x) + B u, k(w) = k0 (1 + k1 w), L the
+ *                central-difference Laplacian with zero Dirichlet values
+ *                (class of eq. pde, discretization of Sec. 2.1);
+ *   - KKT:       K_i(x_{i-1}, s_i, lambda_{i+1}) of Sec. 3.2 (eq. KKT);
+ *   - upper:     S^{k+1} = S^k - (D^k)^{-1} K^k, stage blocks independent
+ *                (eq. 1st_jacobi, Sec. 4.2);
+ *   - lower:     reordered stage system (eq. sublinsys_cpx / sublinsys_simple),
+ *                Schur elimination onto v3 (eq. step12) solved by the fixed-count
+ *                iteration with diagonal A_uu of Sec. 5.2, each saddle solve by
+ *                F_x v5 = b4 then F_x^T v4 = b5 - A_xx v5 (eq. coff), and every
+ *                F_x / F_x^T solve by point Jacobi from a zero initial guess
+ *                (Lemma lemma_jaco, Sec. 4.3).
+ *
+ * Layout: node p = iy * nsx + ix; X, LAM are [N][n], U is [N][m]; B is dense
+ * [n][m] row-major (the caller builds it).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int dim, nsx, nsy, N, m;
+    const double *B;                 /* [n][m] */
+    double h, k0, k1, q, r, gamma;
+} ref_problem;
+
+static int ref_n(const ref_problem *P) { return P->nsx * P->nsy; }
+
+/* Conductivity k(w) = k0 (1 + k1 w) and its derivative k' = k0 k1. */
+static double cond(const ref_problem *P, double w) { return P->k0 * (1.0 + P->k1 * w); }
+static double dcond(const ref_problem *P) { return P->k0 * P->k1; }
+
+/* Row p of the Laplacian L: off-diagonal neighbours (index, weight) and the
+ * diagonal weight. Off-grid neighbours carry the value 0 (Dirichlet). */
+static int lap_row(const ref_problem *P, int p, int *qi, double *qw, double *diag)
+{
+    int ix = p % P->nsx, iy = p / P->nsx, c = 0;
+    double ax = (double)(P->nsx + 1) * (double)(P->nsx + 1);   /* 1/dx^2 */
+    double ay = (double)(P->nsy + 1) * (double)(P->nsy + 1);   /* 1/dy^2 */
+    *diag = -2.0 * ax;
+    if (ix > 0)           { qi[c] = p - 1; qw[c++] = ax; }
+    if (ix < P->nsx - 1)  { qi[c] = p + 1; qw[c++] = ax; }
+    if (P->dim == 2) {
+        *diag += -2.0 * ay;
+        if (iy > 0)          { qi[c] = p - P->nsx; qw[c++] = ay; }
+        if (iy < P->nsy - 1) { qi[c] = p + P->nsx; qw[c++] = ay; }
+    }
+    return c;
+}
+
+static void lap_apply(const ref_problem *P, const double *v, double *out)
+{
+    int n = ref_n(P);
+    for (int p = 0; p < n; ++p) {
+        int qi[4]; double qw[4], d;
+        int c = lap_row(P, p, qi, qw, &d);
+        double s = d * v[p];
+        for (int j = 0; j < c; ++j) s += qw[j] * v[qi[j]];
+        out[p] = s;
+    }
+}
+
+/* f(u, x) = k(x) .* (L x) + B u  (dynamics of the discretized PDE). */
+static void dyn_f(const ref_problem *P, const double *x, const double *u, double *f)
+{
+    int n = ref_n(P), m = P->m;
+    double *Lx = (double *)malloc(sizeof(double) * n);
+    lap_apply(P, x, Lx);
+    for (int p = 0; p < n; ++p) {
+        double bu = 0.0;
+        for (int j = 0; j < m; ++j) bu += P->B[(size_t)p * m + j] * u[j];
+        f[p] = cond(P, x[p]) * Lx[p] + bu;
+    }
+    free(Lx);
+}
+
+/* (grad_x f)^T lam: scatter of the rows of grad_x f, whose entries are
+ * (grad_x f)_{pq} = k(x_p) L_{pq} + [p == q] k' (L x)_p. */
+static void dfx_T_apply(const ref_problem *P, const double *x, const double *lam, double *out)
+{
+    int n = ref_n(P);
+    double *Lx = (double *)malloc(sizeof(double) * n);
+    lap_apply(P, x, Lx);
+    for (int q = 0; q < n; ++q) out[q] = 0.0;
+    for (int p = 0; p < n; ++p) {
+        int qi[4]; double qw[4], d;
+        int c = lap_row(P, p, qi, qw, &d);
+        double kp = cond(P, x[p]);
+        out[p] += (kp * d + dcond(P) * Lx[p]) * lam[p];
+        for (int j = 0; j < c; ++j) out[qi[j]] += kp * qw[j] * lam[p];
+    }
+    free(Lx);
+}
+
+/*
+ * KKT function K_i of Sec. 3.2 for all stages, with x_0 = x0 and
+ * lambda_{N+1} = 0:
+ *   KX_i = x_{i-1} - x_i + h f(u_i, x_i)
+ *   KU_i = h (r u_i + B^T lam_i) + gamma (u_i - ut_i)
+ *   KL_i = lam_{i+1} - lam_i + h (q (x_i - xref_i) + (grad_x f_i)^T lam_i)
+ * xref has xref_stride = 0 (one reference for all stages) or n (per stage).
+ * ut (the regularization reference) may be NULL, meaning ut = u.
+ */
+void ref_kkt(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
+             const double *X, const double *U, const double *LAM, const double *UT,
+             double *KX, double *KU, double *KL)
+{
+    int n = ref_n(P), m = P->m, N = P->N;
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < N; ++i) {
+        const double *xprev = (i == 0) ? x0 : X + (size_t)(i - 1) * n;
+        const double *x = X + (size_t)i * n, *u = U + (size_t)i * m, *lam = LAM + (size_t)i * n;
+        const double *xr = xref + (size_t)i * xref_stride;
+        double *f = (double *)malloc(sizeof(double) * n);
+        double *g = (double *)malloc(sizeof(double) * n);
+        dyn_f(P, x, u, f);
+        for (int p = 0; p < n; ++p) KX[(size_t)i * n + p] = xprev[p] - x[p] + P->h * f[p];
+        for (int j = 0; j < m; ++j) {
+            double btl = 0.0;
+            for (int p = 0; p < n; ++p) btl += P->B[(size_t)p * m + j] * lam[p];
+            double reg = UT ? P->gamma * (u[j] - UT[(size_t)i * m + j]) : 0.0;
+            KU[(size_t)i * m + j] = P->h * (P->r * u[j] + btl) + reg;
+        }
+        dfx_T_apply(P, x, lam, g);
+        for (int p = 0; p < n; ++p) {
+            double lnext = (i == N - 1) ? 0.0 : LAM[(size_t)(i + 1) * n + p];
+            KL[(size_t)i * n + p] = lnext - lam[p] + P->h * (P->q * (x[p] - xr[p]) + g[p]);
+        }
+        free(f); free(g);
+    }
+}
+
+/* Residual norms: r_paper = |K|_inf; r_scaled divides the input rows by h r
+ * and the costate rows by h (units of u and of q (x - xref)). */
+void ref_norms(const ref_problem *P, const double *KX, const double *KU, const double *KL,
+               double *r_scaled, double *r_paper)
+{
+    size_t nN = (size_t)ref_n(P) * P->N, mN = (size_t)P->m * P->N;
+    double ax = 0.0, au = 0.0, al = 0.0;
+    int bad = 0;
+    for (size_t t = 0; t < nN; ++t) {
+        if (!isfinite(KX[t]) || !isfinite(KL[t])) bad = 1;
+        if (fabs(KX[t]) > ax) ax = fabs(KX[t]);
+        if (fabs(KL[t]) > al) al = fabs(KL[t]);
+    }
+    for (size_t t = 0; t < mN; ++t) {
+        if (!isfinite(KU[t])) bad = 1;
+        if (fabs(KU[t]) > au) au = fabs(KU[t]);
+    }
+    double rp = ax > au ? ax : au; rp = rp > al ? rp : al;
+    double rs = ax, su = au / (P->h * P->r), sl = al / P->h;
+    rs = rs > su ? rs : su; rs = rs > sl ? rs : sl;
+    if (bad) { rp = NAN; rs = NAN; }
+    if (r_paper) *r_paper = rp;
+    if (r_scaled) *r_scaled = rs;
+}
+
+/* ---------------------------------------------------------------- lower layer */
+
+typedef struct {
+    const ref_problem *P;
+    const double *x, *lam;   /* stage iterate */
+    double *kx, *Lx, *Fd;    /* k(x), L x, diagonal of F_x */
+} stage_ctx;
+
+/* F_x = h grad_x f - I: diagonal h (k(x_p) L_pp + k' (Lx)_p) - 1,
+ * off-diagonal (p, q) = h k(x_p) L_pq. */
+static void stage_setup(stage_ctx *S)
+{
+    const ref_problem *P = S->P;
+    int n = ref_n(P);
+    lap_apply(P, S->x, S->Lx);
+    for (int p = 0; p < n; ++p) {
+        int qi[4]; double qw[4], d;
+        lap_row(P, p, qi, qw, &d);
+        S->kx[p] = cond(P, S->x[p]);
+        S->Fd[p] = P->h * (S->kx[p] * d + dcond(P) * S->Lx[p]) - 1.0;
+    }
+}
+
+/* n_sw point-Jacobi sweeps for F_x y = c from y = 0. */
+static void jacobi_F(const stage_ctx *S, int n_sw, const double *c, double *y, double *tmp)
+{
+    const ref_problem *P = S->P;
+    int n = ref_n(P);
+    for (int p = 0; p < n; ++p) y[p] = 0.0;
+    for (int it = 0; it < n_sw; ++it) {
+        for (int p = 0; p < n; ++p) {
+            int qi[4]; double qw[4], d;
+            int cnt = lap_row(P, p, qi, qw, &d);
+            double off = 0.0;
+            for (int j = 0; j < cnt; ++j) off += P->h * S->kx[p] * qw[j] * y[qi[j]];
+            tmp[p] = (c[p] - off) / S->Fd[p];
+        }
+        memcpy(y, tmp, sizeof(double) * n);
+    }
+}
+
+/* n_sw point-Jacobi sweeps for F_x^T y = c from y = 0; (F_x^T)_{pq} = (F_x)_{qp}. */
+static void jacobi_FT(const stage_ctx *S, int n_sw, const double *c, double *y, double *tmp)
+{
+    const ref_problem *P = S->P;
+    int n = ref_n(P);
+    for (int p = 0; p < n; ++p) y[p] = 0.0;
+    for (int it = 0; it < n_sw; ++it) {
+        for (int p = 0; p < n; ++p) {
+            int qi[4]; double qw[4], d;
+            int cnt = lap_row(P, p, qi, qw, &d);
+            double off = 0.0;
+            /* L is symmetric, so L_qp = L_pq = qw[j]. */
+            for (int j = 0; j < cnt; ++j) off += P->h * S->kx[qi[j]] * qw[j] * y[qi[j]];
+            tmp[p] = (c[p] - off) / S->Fd[p];
+        }
+        memcpy(y, tmp, sizeof(double) * n);
+    }
+}
+
+/* A_xx y = h grad_xx^2 H y with (grad_xx^2 H)_{ps} = q [p == s] + k' L_ps (lam_p + lam_s),
+ * the second derivative of q/2 |x - xref|^2 + lam^T f in x (k'' = 0). */
+static void axx_apply(const stage_ctx *S, const double *y, double *out)
+{
+    const ref_problem *P = S->P;
+    int n = ref_n(P);
+    double kp = dcond(P);
+    for (int p = 0; p < n; ++p) {
+        int qi[4]; double qw[4], d;
+        int cnt = lap_row(P, p, qi, qw, &d);
+        double s = P->q * y[p] + kp * d * (2.0 * S->lam[p]) * y[p];
+        for (int j = 0; j < cnt; ++j) s += kp * qw[j] * (S->lam[p] + S->lam[qi[j]]) * y[qi[j]];
+        out[p] = P->h * s;
+    }
+}
+
+static void B_apply(const ref_problem *P, const double *v, double *out)
+{
+    int n = ref_n(P), m = P->m;
+    for (int p = 0; p < n; ++p) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += P->B[(size_t)p * m + j] * v[j];
+        out[p] = s;
+    }
+}
+
+static void BT_apply(const ref_problem *P, const double *y, double *out)
+{
+    int n = ref_n(P), m = P->m;
+    for (int j = 0; j < m; ++j) {
+        double s = 0.0;
+        for (int p = 0; p < n; ++p) s += P->B[(size_t)p * m + j] * y[p];
+        out[j] = s;
+    }
+}
+
+/*
+ * Lower layer for one stage: approximately solve D_i ds = K_i.
+ * Reordered unknowns v1 = d lambda, v2 = d x, v3 = d u and right-hand sides
+ * b1 = KX_i, b2 = KL_i, b3 = KU_i. Blocks: F_x = h grad_x f - I, F_u = h B,
+ * A_xx = h grad_xx^2 H, A_xu = A_ux = 0 (f is affine in u, l separable),
+ * A_uu = (h r + gamma) I.
+ *  Schur iteration (n_schur times from v3 = 0):
+ *     v5 = F_x^{-1} (F_u v3 - b1)
+ *     v4 = F_x^{-T} (-b2 - A_xx v5)
+ *     v3 = (b3 + F_u^T v4) / A_uu
+ *  then eq. step2:  v2 = F_x^{-1} (b1 - F_u v3),  v1 = F_x^{-T} (b2 - A_xx v2),
+ *  with every F_x^{-1} / F_x^{-T} replaced by n_sw point-Jacobi sweeps.
+ */
+void ref_stage_solve(const ref_problem *P, const double *x, const double *lam,
+                     const double *b1, const double *b2, const double *b3,
+                     int n_sw, int n_schur, double *dx, double *du, double *dlam)
+{
+    int n = ref_n(P), m = P->m;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(9 * n + 2 * m));
+    stage_ctx S = {P, x, lam, w, w + n, w + 2 * n};
+    double *c = w + 3 * n, *v5 = w + 4 * n, *v4 = w + 5 * n, *tmp = w + 6 * n;
+    double *Bv = w + 7 * n, *Ay = w + 8 * n;
+    double *v3 = w + 9 * n, *btv = w + 9 * n + m;
+    double Auu = P->h * P->r + P->gamma;
+    stage_setup(&S);
+
+    for (int j = 0; j < m; ++j) v3[j] = 0.0;
+    for (int it = 0; it < n_schur; ++it) {
+        B_apply(P, v3, Bv);
+        for (int p = 0; p < n; ++p) c[p] = P->h * Bv[p] - b1[p];
+        jacobi_F(&S, n_sw, c, v5, tmp);
+        axx_apply(&S, v5, Ay);
+        for (int p = 0; p < n; ++p) c[p] = -b2[p] - Ay[p];
+        jacobi_FT(&S, n_sw, c, v4, tmp);
+        BT_apply(P, v4, btv);
+        for (int j = 0; j < m; ++j) v3[j] = (b3[j] + P->h * btv[j]) / Auu;
+    }
+    B_apply(P, v3, Bv);
+    for (int p = 0; p < n; ++p) c[p] = b1[p] - P->h * Bv[p];
+    jacobi_F(&S, n_sw, c, v5, tmp);              /* v2 */
+    axx_apply(&S, v5, Ay);
+    for (int p = 0; p < n; ++p) c[p] = b2[p] - Ay[p];
+    jacobi_FT(&S, n_sw, c, v4, tmp);             /* v1 */
+    for (int p = 0; p < n; ++p) { dx[p] = v5[p]; dlam[p] = v4[p]; }
+    for (int j = 0; j < m; ++j) du[j] = v3[j];
+    free(w);
+}
+
+/* ---------------------------------------------------------------- upper layer */
+
+/*
+ * One upper-layer Jacobi iteration (eq. 1st_jacobi with alpha = 1 and the
+ * regularization reference ut = u^k): evaluates K^k, its norms, and writes
+ * S^{k+1} = S^k - (D^k)^{-1} K^k into (Xn, Un, LAMn). All stage blocks are
+ * solved independently from S^k.
+ */
+void ref_iterate(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
+                 const double *X, const double *U, const double *LAM,
+                 double *Xn, double *Un, double *LAMn, int n_sw, int n_schur,
+                 double *r_scaled, double *r_paper)
+{
+    int n = ref_n(P), m = P->m, N = P->N;
+    double *KX = (double *)malloc(sizeof(double) * (size_t)N * n);
+    double *KL = (double *)malloc(sizeof(double) * (size_t)N * n);
+    double *KU = (double *)malloc(sizeof(double) * (size_t)N * m);
+    ref_kkt(P, x0, xref, xref_stride, X, U, LAM, U, KX, KU, KL);
+    ref_norms(P, KX, KU, KL, r_scaled, r_paper);
+    if (Xn) {
+        #pragma omp parallel for schedule(static)
+        for (int i = 0; i < N; ++i) {
+            double *dx = (double *)malloc(sizeof(double) * (size_t)(2 * n + m));
+            double *dl = dx + n, *du = dx + 2 * n;
+            ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n,
+                            KX + (size_t)i * n, KL + (size_t)i * n, KU + (size_t)i * m,
+                            n_sw, n_schur, dx, du, dl);
+            for (int p = 0; p < n; ++p) {
+                Xn[(size_t)i * n + p] = X[(size_t)i * n + p] - dx[p];
+                LAMn[(size_t)i * n + p] = LAM[(size_t)i * n + p] - dl[p];
+            }
+            for (int j = 0; j < m; ++j) Un[(size_t)i * m + j] = U[(size_t)i * m + j] - du[j];
+            free(dx);
+        }
+    }
+    free(KX); free(KL); free(KU);
+}
+
+/*
+ * Iterate from the start held in (X, U, LAM) until r_scaled(S^k) <= tol or
+ * k == max_iter. On return (X, U, LAM) hold the last evaluated iterate S^k,
+ * *iters = k and the residuals of S^k. rhist (may be NULL) receives r_scaled
+ * of S^0..S^k. Returns 0 converged, 1 not converged, 2 non-finite residual.
+ */
+int ref_solve(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
+              double *X, double *U, double *LAM, double tol, int max_iter,
+              int n_sw, int n_schur, int *iters, double *r_scaled, double *r_paper,
+              double *rhist)
+{
+    int n = ref_n(P), m = P->m, N = P->N, k = 0, status = 1;
+    size_t sz = (size_t)N * (2 * n + m);
+    double *buf = (double *)malloc(sizeof(double) * sz);
+    double *Xn = buf, *LAMn = buf + (size_t)N * n, *Un = buf + (size_t)2 * N * n;
+    double rs = 0.0, rp = 0.0;
+    for (;;) {
+        int last = (k >= max_iter);
+        ref_iterate(P, x0, xref, xref_stride, X, U, LAM, Xn, Un, LAMn, n_sw, n_schur, &rs, &rp);
+        if (rhist) rhist[k] = rs;
+        if (!isfinite(rs)) { status = 2; break; }
+        if (rs <= tol) { status = 0; break; }
+        if (last) { status = 1; break; }
+        memcpy(X, Xn, sizeof(double) * (size_t)N * n);
+        memcpy(LAM, LAMn, sizeof(double) * (size_t)N * n);
+        memcpy(U, Un, sizeof(double) * (size_t)N * m);
+        ++k;
+    }
+    free(buf);
+    if (iters) *iters = k;
+    if (r_scaled) *r_scaled = rs;
+    if (r_paper) *r_paper = rp;
+    return status;
+}

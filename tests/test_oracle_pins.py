@@ -1,0 +1,367 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test ties the oracle to something other than itself: closed-form
+eigenpairs, finite differences of the Lagrangian, Newton's method with dense
+LU, the exact optimum of the NLP (direct minimization, or the condensed QP in
+the linear case), the nilpotency of Lemma lemma_rho0, and dense solves of the
+stage blocks.
+"""
+import numpy as np
+import pytest
+
+from nmpc_inputs import gaussian_factors, make_instance, make_problem
+
+import oracle
+from oracle import dense
+
+
+def tiny2d(nsx=4, nsy=3, N=3, gamma_rel=1.0, k1=0.5, lattice=2, sigma=0.25):
+    P = make_problem("grid", ns=nsx, N=N, gamma_rel=gamma_rel, lattice=lattice)
+    P = P.with_(nsy=nsy, gx=gaussian_factors(nsx, lattice, sigma),
+                gy=gaussian_factors(nsy, lattice, sigma), k1=k1)
+    P.gamma = gamma_rel * P.h * P.r
+    return P
+
+
+def tiny_data(P, seed=0, scale_lam=0.01):
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(0.0, 0.2, P.n)
+    xref = rng.uniform(-0.3, 0.3, P.n)
+    X = rng.normal(size=(P.N, P.n)) * 0.1
+    U = rng.normal(size=(P.N, P.m))
+    LAM = rng.normal(size=(P.N, P.n)) * scale_lam
+    UT = rng.normal(size=(P.N, P.m))
+    return x0, xref, X, U, LAM, UT
+
+
+def fd_grad(fun, S, eps=1e-6):
+    g = np.zeros_like(S)
+    for t in range(S.size):
+        Sp = S.copy(); Sp[t] += eps
+        Sm = S.copy(); Sm[t] -= eps
+        g[t] = (fun(Sp) - fun(Sm)) / (2 * eps)
+    return g
+
+
+# ---------------------------------------------------------------- P7: stencil
+
+@pytest.mark.parametrize("a,b", [(1, 1), (2, 3), (4, 1)])
+def test_stencil_eigenpairs(a, b):
+    """L sin(pi a x) sin(pi b y) = mu (same), mu = -(4/dx^2) sin^2(pi a dx/2) - (4/dy^2) sin^2(pi b dy/2)."""
+    P = tiny2d(nsx=6, nsy=5, N=1, k1=0.0).with_(k0=1.0)
+    xs = (np.arange(P.nsx) + 1) * P.dx
+    ys = (np.arange(P.nsy) + 1) * P.dy
+    v = (np.sin(np.pi * b * ys)[:, None] * np.sin(np.pi * a * xs)[None, :]).reshape(-1)
+    mu = -(4 / P.dx ** 2) * np.sin(np.pi * a * P.dx / 2) ** 2 - (4 / P.dy ** 2) * np.sin(np.pi * b * P.dy / 2) ** 2
+    # state row with x0 = 0, u = 0, k = 1: KX_1 = -x_1 + h L x_1
+    KX, _, _ = oracle.kkt(P, np.zeros(P.n), np.zeros(P.n), v[None, :], np.zeros((1, P.m)),
+                          np.zeros((1, P.n)))
+    Lv = (KX[0] + v) / P.h
+    np.testing.assert_allclose(Lv, mu * v, atol=1e-9 * abs(mu))
+    np.testing.assert_allclose(dense.lap_matrix(P) @ v, mu * v, atol=1e-9 * abs(mu))
+
+
+def test_stencil_eigenpairs_1d():
+    P = make_problem("c0").with_(N=1, k1=0.0, k0=1.0)
+    j = np.arange(1, P.nsx + 1)
+    for a in (1, 5, 16):
+        v = np.sin(np.pi * a * j * P.dx)
+        mu = -(4 / P.dx ** 2) * np.sin(np.pi * a * P.dx / 2) ** 2
+        KX, _, _ = oracle.kkt(P, np.zeros(P.n), np.zeros(P.n), v[None], np.zeros((1, P.m)),
+                              np.zeros((1, P.n)))
+        np.testing.assert_allclose((KX[0] + v) / P.h, mu * v, atol=1e-9 * abs(mu))
+
+
+# ------------------------------------------------- P3: K = grad of Lagrangian
+
+@pytest.mark.parametrize("which", ["2d", "1d"])
+def test_kkt_is_lagrangian_gradient(which):
+    """K_i = (d/dlam_i, d/du_i, d/dx_i) of the Lagrangian of the relaxed problem."""
+    if which == "2d":
+        P = tiny2d()
+    else:
+        P = make_problem("c0", N=3)
+    x0, xref, X, U, LAM, UT = tiny_data(P)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM, UT)
+    S = dense.pack(X, U, LAM)
+    g = fd_grad(lambda s: dense.lagrangian(P, x0, xref, *dense.unpack(P, s), UT), S)
+    gX, gU, gL = dense.unpack(P, g)
+    scale = max(np.abs(KX).max(), np.abs(KU).max(), np.abs(KL).max())
+    assert np.abs(gL - KX).max() <= 1e-8 * scale
+    assert np.abs(gU - KU).max() <= 1e-8 * scale
+    assert np.abs(gX - KL).max() <= 1e-8 * scale
+
+
+def test_time_varying_reference():
+    """A per-stage reference enters stage i's costate row only."""
+    P = tiny2d()
+    x0, xref, X, U, LAM, _ = tiny_data(P)
+    xr2 = np.stack([xref * (1 + 0.1 * i) for i in range(P.N)])
+    a = oracle.kkt(P, x0, xr2, X, U, LAM)
+    b = dense.kkt(P, x0, xr2, X, U, LAM)
+    for p, q in zip(a, b):
+        np.testing.assert_allclose(p, q, rtol=0, atol=1e-15)
+    c = oracle.kkt(P, x0, xref, X, U, LAM)
+    np.testing.assert_allclose(a[2][0], c[2][0], atol=1e-15)
+    assert np.abs(a[2][1] - c[2][1]).max() > 1e-6
+
+
+# ------------------------------------------- Newton matrix = Jacobian of K
+
+def test_newton_matrix_is_kkt_jacobian():
+    """eq. KKT_sys: diagonal blocks D_i = grad_{s_i} K_i, couplings M_L, M_U."""
+    P = tiny2d()
+    x0, xref, X, U, LAM, _ = tiny_data(P)
+    J = dense.jacobian(P, X, U, LAM)
+    S = dense.pack(X, U, LAM)
+    UT = U.copy()  # regularization reference frozen at the linearization point
+
+    def Kvec(s):
+        return dense.pack(*oracle.kkt(P, x0, xref, *dense.unpack(P, s), UT))
+
+    Jfd = np.zeros_like(J)
+    eps = 1e-6
+    for t in range(S.size):
+        Sp = S.copy(); Sp[t] += eps
+        Sm = S.copy(); Sm[t] -= eps
+        Jfd[:, t] = (Kvec(Sp) - Kvec(Sm)) / (2 * eps)
+    assert np.abs(Jfd - J).max() <= 1e-7 * np.abs(J).max()
+
+
+# -------------------------------------------------------- P1: Newton + LU
+
+@pytest.mark.parametrize("which", ["2d", "c0"])
+def test_newton_quadratic_and_jacobi_fixed_point(which):
+    P = tiny2d(N=4) if which == "2d" else make_problem("c0")
+    if which == "2d":
+        x0, xref = tiny_data(P)[:2]
+    else:
+        x0, xref = make_instance(P, 3)
+    (Xn, Un, Ln), hist = dense.newton(P, x0, xref, *oracle.cold_start(P, x0))
+    assert hist[-1] <= 1e-13
+    # quadratic convergence: e_{k+1} <= C e_k^2 once in the basin
+    ratios = [hist[k + 1] / hist[k] ** 2 for k in range(1, len(hist) - 1) if hist[k] > 1e-12]
+    assert len(hist) <= 8 and max(ratios) < 1e4
+    o = oracle.solve(P, x0, xref, tol=1e-13, max_iter=20000)
+    assert o["status"] == "converged"
+    np.testing.assert_allclose(o["U"], Un, atol=1e-9 * np.abs(Un).max())
+    np.testing.assert_allclose(o["X"], Xn, atol=1e-11)
+    np.testing.assert_allclose(o["LAM"], Ln, atol=1e-9 * np.abs(Ln).max())
+
+
+# --------------------------------------------------- NLP optimum (eq. nlp)
+
+def test_fixed_point_is_nlp_optimum():
+    """The KKT point equals the minimizer of the cost over u, states simulated
+    by backward Euler (no optimality formula involved)."""
+    P = tiny2d(N=3)
+    P.h = 0.02
+    P.gamma = P.h * P.r
+    x0, xref = tiny_data(P, seed=4)[:2]
+    o = oracle.solve(P, x0, xref, tol=1e-13, max_iter=20000)
+    assert o["status"] == "converged"
+    Xm, Um, res = dense.nlp_reduced(P, x0, xref)
+    assert np.abs(o["U"] - Um).max() <= 2e-5 * np.abs(Um).max()
+    assert np.abs(o["X"] - Xm).max() <= 1e-7
+
+
+# ----------------------------------------------- P2: linear-quadratic case
+
+@pytest.mark.parametrize("which", ["2d", "c0"])
+def test_lq_case_matches_condensed_qp(which):
+    P = (tiny2d(N=5) if which == "2d" else make_problem("c0", N=6)).with_(k1=0.0)
+    x0, xref = tiny_data(P, seed=2)[:2]
+    Xq, Uq = dense.lq_condensed(P, x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-13, max_iter=20000)
+    assert o["status"] == "converged"
+    np.testing.assert_allclose(o["U"], Uq, atol=1e-9 * np.abs(Uq).max())
+    np.testing.assert_allclose(o["X"], Xq, atol=1e-12)
+    # KKT is affine: one Newton step from any start is exact
+    (_, Un, _), hist = dense.newton(P, x0, xref, *oracle.cold_start(P, x0), max_it=2)
+    assert hist[1] <= 1e-12 * max(hist[0], 1.0)
+
+
+# ------------------------------------------------------- P4: nilpotency
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_dbar_coupling_is_nilpotent(N):
+    """Lemma lemma_rho0: rho(Dbar^{-1}(L+U)) = 0. Exact form: the
+    (2N-1)-th power vanishes (x errors move forward, lambda errors backward
+    one stage per iteration, and the only x->lambda turn is inside a stage)."""
+    P = tiny2d(N=N)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=5)
+    _, LU, Dbar = dense.split_DLU(P, X, U, LAM)
+    G = np.linalg.solve(Dbar, LU)
+    nG = np.linalg.norm(G, 2)
+    Gk = np.linalg.matrix_power(G, 2 * N - 1)
+    assert np.linalg.norm(Gk, 2) <= 1e-10 * nG ** (2 * N - 1)
+    Gk1 = np.linalg.matrix_power(G, 2 * N - 2)
+    assert np.linalg.norm(Gk1, 2) > 1e-6 * nG ** (2 * N - 2)
+    assert np.max(np.abs(np.linalg.eigvals(G))) < 1e-3
+
+
+# ----------------------------------------------- P5: lower layer exactness
+
+@pytest.mark.parametrize("which", ["2d", "c0"])
+def test_lower_layer_many_sweeps_is_dense_block_solve(which):
+    """Schur elimination + point Jacobi (eq. step12, coff) reproduce D_i^{-1} K_i
+    when the sweep counts grow; D_i is taken by finite differences of K_i."""
+    P = tiny2d() if which == "2d" else make_problem("c0", N=2)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=6)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM)
+    i = 1
+    dx, du, dl = oracle.stage_solve(P, X[i], LAM[i], KX[i], KL[i], KU[i], n_sw=400, n_schur=60)
+    UT = U.copy()
+
+    def Ki(si):
+        X2, U2, L2 = X.copy(), U.copy(), LAM.copy()
+        X2[i], U2[i], L2[i] = si[:P.n], si[P.n:P.n + P.m], si[P.n + P.m:]
+        a, b, c = oracle.kkt(P, x0, xref, X2, U2, L2, UT)
+        return np.concatenate([a[i], b[i], c[i]])
+
+    s = np.concatenate([X[i], U[i], LAM[i]])
+    D = np.zeros((s.size, s.size))
+    for t in range(s.size):
+        sp = s.copy(); sp[t] += 1e-6
+        sm = s.copy(); sm[t] -= 1e-6
+        D[:, t] = (Ki(sp) - Ki(sm)) / 2e-6
+    ref = np.linalg.solve(D, np.concatenate([KX[i], KU[i], KL[i]]))
+    got = np.concatenate([dx, du, dl])
+    assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max()
+    # and the analytic block agrees with the finite-difference one
+    Dan = dense.stage_block(P, dense.lap_matrix(P), P.dense_B(), X[i], LAM[i], P.gamma)
+    assert np.abs(Dan - D).max() <= 1e-7 * np.abs(D).max()
+
+
+def test_two_sweeps_are_the_stated_schedule():
+    """With n_sw = 1 the F_x solve is y = c / diag(F_x); with zero Schur passes v3 = 0."""
+    P = tiny2d()
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=7)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM)
+    i = 0
+    dx, du, dl = oracle.stage_solve(P, X[i], LAM[i], KX[i], KL[i], KU[i], n_sw=1, n_schur=0)
+    assert np.all(du == 0)
+    Fx = P.h * dense.fx_mat(P, dense.lap_matrix(P), X[i]) - np.eye(P.n)
+    np.testing.assert_allclose(dx, KX[i] / np.diag(Fx), rtol=1e-13)
+    Axx = P.h * dense.hxx_mat(P, dense.lap_matrix(P), LAM[i])
+    np.testing.assert_allclose(dl, (KL[i] - Axx @ dx) / np.diag(Fx), rtol=1e-12, atol=1e-18)
+
+
+# ---------------------------------------- upper layer = block Jacobi (eq. 1st_jacobi)
+
+def test_upper_iteration_is_block_jacobi_step():
+    P = tiny2d(N=4)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=8)
+    Xn, Un, Ln, rs, rp = oracle.iterate(P, x0, xref, X, U, LAM, n_sw=400, n_schur=60)
+    D, LU, _ = dense.split_DLU(P, X, U, LAM)
+    K = dense.pack(*dense.kkt(P, x0, xref, X, U, LAM))
+    Sn = dense.pack(X, U, LAM) - np.linalg.solve(D, K)
+    got = dense.pack(Xn, Un, Ln)
+    assert np.abs(got - Sn).max() <= 1e-9 * np.abs(Sn).max()
+    rs2, rp2 = dense.norms(P, *dense.kkt(P, x0, xref, X, U, LAM))
+    assert abs(rs - rs2) <= 1e-12 * rs2 and abs(rp - rp2) <= 1e-12 * rp2
+
+
+def test_single_stage_is_newton_step():
+    """P10: N = 1 has L = U = 0, so one iteration with an exact lower layer and
+    gamma = 0 is one Newton step."""
+    P = tiny2d(N=1, gamma_rel=0.0)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=9)
+    Xn, Un, Ln, _, _ = oracle.iterate(P, x0, xref, X, U, LAM, n_sw=400, n_schur=60)
+    J = dense.jacobian(P, X, U, LAM, gamma=0.0)
+    K = dense.pack(*dense.kkt(P, x0, xref, X, U, LAM))
+    Sn = dense.pack(X, U, LAM) - np.linalg.solve(J, K)
+    assert np.abs(dense.pack(Xn, Un, Ln) - Sn).max() <= 1e-9 * np.abs(Sn).max()
+
+
+def test_fixed_point_independent_of_schedule():
+    """gamma (with ut = u^k), n_sw and n_schur change the rate, not the solution."""
+    P0 = make_problem("c0")
+    x0, xref = make_instance(P0, 1)
+    sols = []
+    for g, nsw, nsc in [(1.0, 2, 2), (0.1, 1, 1), (0.0, 4, 3), (3.0, 2, 1)]:
+        P = make_problem("c0", gamma_rel=g)
+        o = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000, n_sw=nsw, n_schur=nsc)
+        assert o["status"] == "converged"
+        sols.append(o["U"])
+    for s in sols[1:]:
+        np.testing.assert_allclose(s, sols[0], atol=1e-9 * np.abs(sols[0]).max())
+
+
+# ---------------------------------------------- P6: diagonal dominance
+
+@pytest.mark.parametrize("name", ["c0", "g16"])
+def test_point_jacobi_contracts(name):
+    """Lemma lemma_jaco (element-wise): F_x is strictly diagonally dominant at
+    the step sizes used, with the contraction bound 2d h k/dx^2 / (1 + 2d h k/dx^2)."""
+    P = make_problem("c0") if name == "c0" else make_problem("grid", ns=16, N=4)
+    x0, xref = make_instance(P, 0)
+    o = oracle.solve(P, x0, xref, tol=1e-8, max_iter=20000)
+    L = dense.lap_matrix(P)
+    worst = 0.0
+    for i in range(P.N):
+        F = P.h * dense.fx_mat(P, L, o["X"][i]) - np.eye(P.n)
+        d = np.abs(np.diag(F))
+        off = np.abs(F).sum(1) - d
+        offT = np.abs(F).sum(0) - d
+        worst = max(worst, (off / d).max(), (offT / d).max())
+    kmax = P.k0 * (1 + P.k1 * np.abs(o["X"]).max())
+    c = (2 * P.dim) * P.h * kmax / P.dx ** 2
+    assert worst < 1.0
+    assert worst <= c / (1 + c) * 1.05
+
+
+# ---------------------------------------------------------- P8: rho < 1
+
+def test_rho_below_one_and_observed_rate():
+    """Theorem theorem_cvg: rho(D*^{-1}(L+U)) < 1 for gamma > 0 and short T.
+
+    With the regularization reference updated every iteration (ut = u^k, as in
+    the paper's experiment) the gamma term of K vanishes identically, so the
+    derivative of the iteration map at S* is D*^{-1}(gamma E_u - (L+U)), E_u
+    the projector on the input rows; the residual of the exact-lower-layer
+    iteration decays at that matrix's spectral radius (Lemma lemma_rate)."""
+    P = tiny2d(nsx=5, nsy=5, N=4, lattice=2, sigma=0.2)
+    x0, xref = tiny_data(P, seed=11)[:2]
+    o = oracle.solve(P, x0, xref, tol=1e-14, max_iter=20000)
+    D, LU, _ = dense.split_DLU(P, o["X"], o["U"], o["LAM"])
+    rho = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D, LU))))
+    assert 0.0 < rho < 1.0
+    w = 2 * P.n + P.m
+    E = np.zeros_like(D)
+    for i in range(P.N):
+        for j in range(P.m):
+            E[i * w + P.n + j, i * w + P.n + j] = 1.0
+    rho_k = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D, P.gamma * E - LU))))
+    assert 0.0 < rho_k < 1.0
+    t = oracle.solve(P, x0, xref, tol=1e-300, max_iter=200, n_sw=300, n_schur=40, trace=True)
+    r = t["rhist"]
+    k0 = int(np.argmax(r < 1e-3 * r[0]))
+    span = 20
+    assert k0 > 0 and r[k0 + span] > 1e-12 * r[0]
+    rate = (r[k0 + span] / r[k0]) ** (1.0 / span)
+    assert abs(rate - rho_k) <= 0.05 * rho_k
+
+
+# ------------------------------------------------------ status handling
+
+def test_nonfinite_and_noconv_status():
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 0)
+    X, U, L = oracle.cold_start(P, x0)
+    U[3, 1] = np.nan
+    o = oracle.solve(P, x0, xref, start=(X, U, L), tol=1e-6, max_iter=50)
+    assert o["status"] == "nonfinite"
+    o = oracle.solve(P, x0, xref, tol=1e-6, max_iter=3)
+    assert o["status"] == "max_iter" and o["iters"] == 3
+
+
+def test_c0_solution_satisfies_kkt():
+    """P9: the returned iterate satisfies the KKT conditions to the tolerance,
+    re-checked with the dense evaluation."""
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 0)
+    o = oracle.solve(P, x0, xref, tol=1e-6)
+    assert o["status"] == "converged"
+    rs, rp = dense.norms(P, *dense.kkt(P, x0, xref, o["X"], o["U"], o["LAM"]))
+    assert rs <= 1e-6 and abs(rs - o["r_scaled"]) <= 1e-12
