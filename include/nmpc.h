@@ -1,0 +1,166 @@
+/*
+ * nmpc.h -- C ABI of the MI355X double-layer Jacobi NMPC solver.
+ *
+ * Method: Deng & Ohtsuka, "A Double-Layer Jacobi Method for PDE-Constrained
+ * Nonlinear Model Predictive Control" (arXiv 2004.02484).
+ *
+ * Problem (Sec. 3, eq. nlp, without inequality constraints): minimize
+ *   sum_{i=1..N} h ( q/2 |x_i - xref_i|^2 + r/2 |u_i|^2 )
+ * subject to x_0 = x0 and the backward-Euler model
+ *   x_i = x_{i-1} + h f(u_i, x_i),   f(u, x) = k(x) .* (L x) + B u,
+ * where x is the PDE state on the nsy x nsx interior nodes of the unit
+ * interval/square (node p = iy*nsx + ix, zero Dirichlet values outside),
+ * L the central-difference Laplacian (Sec. 2.1), k(w) = k0 (1 + k1 w) the
+ * conductivity, and B the input operator
+ *   B[iy*nsx + ix][b*lx + a] = gy[b][iy] * gx[a][ix]        (m = lx*ly inputs).
+ *
+ * Solution: the KKT point K_i(x_{i-1}, s_i, lambda_{i+1}) = 0, i = 1..N
+ * (Sec. 3.2, eq. KKT), computed by the double-layer Jacobi method:
+ *   upper layer  S^{k+1} = S^k - (D^k)^{-1} K^k, every stage block solved
+ *                independently from S^k (Sec. 4.2, eq. 1st_jacobi; alpha = 1);
+ *   lower layer  Schur elimination onto the inputs with A_uu = (h r + gamma) I
+ *                iterated n_schur times, F_x / F_x^T solves by n_sweep
+ *                point-Jacobi sweeps from zero (Sec. 4.3, eqs. step12, coff;
+ *                Sec. 5.2 for the Schur iteration);
+ *   regularization reference u~ = u^k (Sec. 5.2 parameter table), so the
+ *                gamma term changes the rate, not the solution.
+ * Stopping rule: r_scaled(S^k) <= tol, where
+ *   r_scaled = max_i max(|K^x_i|_inf, |K^u_i|_inf / (h r), |K^lambda_i|_inf / h)
+ * (the paper's |K|_inf, Sec. 5.2, with the input and costate rows brought to
+ * the units of u and of q (x - xref)); r_paper = |K|_inf is also reported.
+ *
+ * Trajectory layout (row-major, caller-owned): x [N][n], u [N][m],
+ * lambda [N][n]; batched calls prepend the instance index: [count][N][n] ...
+ * The returned trajectory is the last evaluated iterate S^k, whose residuals
+ * are reported; lambda follows the paper's sign (lambda_i = lambda_{i+1} +
+ * h grad_x H_i^T at the solution).
+ *
+ * Errors: every int-returning call returns NMPC_OK (0) or an NMPC_E_* code;
+ * nothing is thrown across the ABI. nmpc_last_error() gives a message for the
+ * calling thread. Handles are not thread-safe: use one per host thread.
+ */
+#ifndef NMPC_H
+#define NMPC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    NMPC_OK = 0,
+    NMPC_E_ARG = 1,          /* invalid argument or shape */
+    NMPC_E_NOCONV = 2,       /* max_iter reached; outputs hold S^max_iter */
+    NMPC_E_NONFINITE = 3,    /* residual became NaN/Inf; outputs hold that iterate */
+    NMPC_E_DEVICE = 4,       /* HIP runtime error */
+    NMPC_E_OOM = 5,          /* device allocation failed */
+    NMPC_E_UNSUPPORTED = 6   /* valid problem but no kernel for this shape */
+};
+
+enum { NMPC_FP64 = 0, NMPC_FP32_SWEEP = 1 };
+
+enum { NMPC_START_COLD = 0, NMPC_START_WARM = 1 };
+
+/* Problem data (Sec. 3 notation). gx/gy are host arrays, copied at create. */
+typedef struct nmpc_problem {
+    int32_t dim;          /* 1 or 2 */
+    int32_t nsx, nsy;     /* interior nodes per axis; nsy = 1 when dim == 1 */
+    int32_t horizon;      /* N >= 1 */
+    int32_t lx, ly;       /* input lattice; m = lx * ly; ly = 1 when dim == 1 */
+    const double *gx;     /* [lx][nsx] */
+    const double *gy;     /* [ly][nsy] */
+    double h;             /* stage length T/N > 0 */
+    double k0, k1;        /* conductivity k(w) = k0 (1 + k1 w) */
+    double q, r;          /* cost weights Q = q I, R = r I; r > 0 */
+    double gamma;         /* regularization weight >= 0 */
+} nmpc_problem;
+
+/* Solver options. */
+typedef struct nmpc_options {
+    double tol;           /* stop when r_scaled <= tol */
+    int32_t max_iter;     /* upper iterations (>= 0) */
+    int32_t n_sweep;      /* point-Jacobi sweeps per F_x / F_x^T solve, 1..16 */
+    int32_t n_schur;      /* Schur input iterations, 0..16 */
+    int32_t precision;    /* NMPC_FP64, or NMPC_FP32_SWEEP: lower layer in FP32,
+                             S, K, the norms and the test in FP64, and once the
+                             test passes, FP64 iterations continue until an FP64
+                             step's result passes it (final FP64 correction) */
+    int32_t check_every;  /* iterations between host convergence polls (>= 1) */
+    int32_t xref_per_stage; /* 0: xref is [n] per instance; 1: [N][n] */
+} nmpc_options;
+
+/* Per-instance result information. */
+typedef struct nmpc_info {
+    double r_scaled;      /* scaled residual of the returned iterate */
+    double r_paper;       /* |K|_inf of the returned iterate */
+    int32_t iters;        /* k of the returned iterate S^k */
+    int32_t status;       /* NMPC_OK, NMPC_E_NOCONV or NMPC_E_NONFINITE */
+    int32_t fp32_iters;   /* iterations run with FP32 sweeps */
+    int32_t reserved;
+} nmpc_info;
+
+typedef struct nmpc_handle nmpc_handle;
+
+/* Fill options with the paper's lower-layer settings (2 sweeps, 2 Schur
+ * iterations), tol 1e-6, max_iter 2000, FP64, check_every 16. */
+void nmpc_default_options(nmpc_options *opt);
+
+/* Create a solver for one problem shape and up to max_batch instances on the
+ * current HIP device. Allocates all device workspace (two trajectory buffers
+ * per instance). Returns NMPC_E_ARG for invalid data, NMPC_E_UNSUPPORTED if
+ * no kernel covers the shape, NMPC_E_OOM/NMPC_E_DEVICE on device failure. */
+int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
+                nmpc_handle **out);
+
+/* Replace the options of an existing handle (same validation as create). */
+int nmpc_set_options(nmpc_handle *hd, const nmpc_options *opt);
+
+/* Solve one instance, host buffers. x0, xref: [n] (xref [N][n] with
+ * xref_per_stage). warm_x/warm_u/warm_lam: a start S^0 ([N][n], [N][m],
+ * [N][n]); all three NULL selects the cold start x_i = x0, u_i = 0,
+ * lambda_i = 0; any other mix is NMPC_E_ARG. out_* receive the returned
+ * iterate; info may be NULL. Returns the instance status (NMPC_OK,
+ * NMPC_E_NOCONV, NMPC_E_NONFINITE) or an error code. Blocks until done. */
+int nmpc_solve(nmpc_handle *hd, const double *x0, const double *xref,
+               const double *warm_x, const double *warm_u, const double *warm_lam,
+               double *out_x, double *out_u, double *out_lam, nmpc_info *info);
+
+/* Solve count <= max_batch instances, DEVICE buffers with a leading instance
+ * index (x0 [count][n], xref [count][n] or [count][N][n], warm_* and out_*
+ * [count][N][...]; warm pointers all NULL = cold). Work is ordered after
+ * everything already queued on `stream` (a hipStream_t, NULL = null stream)
+ * and the call returns when the results are written. info: HOST array
+ * [count] (may be NULL). Returns NMPC_OK if every instance converged,
+ * otherwise the first failing instance's status, or an error code. */
+int nmpc_solve_batch(nmpc_handle *hd, int32_t count, const double *x0, const double *xref,
+                     const double *warm_x, const double *warm_u, const double *warm_lam,
+                     double *out_x, double *out_u, double *out_lam, nmpc_info *info,
+                     void *stream);
+
+/* KKT residual norms of given trajectories (DEVICE buffers as in
+ * nmpc_solve_batch, ut = u). r_scaled/r_paper: HOST arrays [count]. */
+int nmpc_residual_batch(nmpc_handle *hd, int32_t count, const double *x0, const double *xref,
+                        const double *x, const double *u, const double *lam,
+                        double *r_scaled, double *r_paper, void *stream);
+
+/* Release the handle and its device memory. NULL is ignored. */
+void nmpc_destroy(nmpc_handle *hd);
+
+/* Static description of an error code. */
+const char *nmpc_strerror(int code);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char *nmpc_last_error(void);
+
+/* Kernel configuration chosen for the handle: rows per lane, waves per
+ * workgroup, workgroups per upper iteration at max_batch. Any pointer may be
+ * NULL. */
+int nmpc_kernel_config(const nmpc_handle *hd, int32_t *rows_per_lane, int32_t *waves,
+                       int32_t *workgroups);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NMPC_H */

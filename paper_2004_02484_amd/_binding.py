@@ -1,0 +1,289 @@
+"""ctypes binding of libnmpc.so: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libnmpc.so")
+
+NMPC_OK = 0
+NMPC_E_ARG = 1
+NMPC_E_NOCONV = 2
+NMPC_E_NONFINITE = 3
+NMPC_E_DEVICE = 4
+NMPC_E_OOM = 5
+NMPC_E_UNSUPPORTED = 6
+NMPC_FP64 = 0
+NMPC_FP32_SWEEP = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class nmpc_problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nsx", ctypes.c_int32), ("nsy", ctypes.c_int32),
+                ("horizon", ctypes.c_int32), ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
+                ("gx", _dp), ("gy", _dp),
+                ("h", ctypes.c_double), ("k0", ctypes.c_double), ("k1", ctypes.c_double),
+                ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class nmpc_options(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("n_sweep", ctypes.c_int32), ("n_schur", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("xref_per_stage", ctypes.c_int32)]
+
+
+class nmpc_info(ctypes.Structure):
+    _fields_ = [("r_scaled", ctypes.c_double), ("r_paper", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("fp32_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"r_scaled": self.r_scaled, "r_paper": self.r_paper, "iters": self.iters,
+                "status": self.status, "fp32_iters": self.fp32_iters}
+
+
+class NmpcError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {nmpc_strerror(code)} ({code}) {nmpc_last_error()}")
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_2004_02484_amd.build` (hipcc, gfx950)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp = ctypes.c_void_p
+    lib.nmpc_default_options.argtypes = [ctypes.POINTER(nmpc_options)]
+    lib.nmpc_default_options.restype = None
+    lib.nmpc_create.argtypes = [ctypes.POINTER(nmpc_problem), ctypes.POINTER(nmpc_options),
+                                ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.nmpc_create.restype = ctypes.c_int
+    lib.nmpc_set_options.argtypes = [vp, ctypes.POINTER(nmpc_options)]
+    lib.nmpc_set_options.restype = ctypes.c_int
+    lib.nmpc_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(nmpc_info)]
+    lib.nmpc_solve.restype = ctypes.c_int
+    lib.nmpc_solve_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                     ctypes.POINTER(nmpc_info), vp]
+    lib.nmpc_solve_batch.restype = ctypes.c_int
+    lib.nmpc_residual_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.nmpc_residual_batch.restype = ctypes.c_int
+    lib.nmpc_destroy.argtypes = [vp]
+    lib.nmpc_destroy.restype = None
+    lib.nmpc_strerror.argtypes = [ctypes.c_int]
+    lib.nmpc_strerror.restype = ctypes.c_char_p
+    lib.nmpc_last_error.argtypes = []
+    lib.nmpc_last_error.restype = ctypes.c_char_p
+    lib.nmpc_kernel_config.argtypes = [vp, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+    lib.nmpc_kernel_config.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ------------------------------------------------------------- C-named calls
+
+def nmpc_strerror(code: int) -> str:
+    return _load().nmpc_strerror(int(code)).decode()
+
+
+def nmpc_last_error() -> str:
+    return _load().nmpc_last_error().decode()
+
+
+def nmpc_default_options(**overrides) -> nmpc_options:
+    o = nmpc_options()
+    _load().nmpc_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+class _Problem:
+    """nmpc_problem plus the host arrays it points at (kept alive here)."""
+
+    def __init__(self, p):
+        self.gx = np.ascontiguousarray(p.gx, dtype=np.float64)
+        self.gy = np.ascontiguousarray(p.gy, dtype=np.float64)
+        self.s = nmpc_problem(int(p.dim), int(p.nsx), int(p.nsy), int(p.N), int(p.lx), int(p.ly),
+                              self.gx.ctypes.data_as(_dp), self.gy.ctypes.data_as(_dp),
+                              float(p.h), float(p.k0), float(p.k1), float(p.q), float(p.r),
+                              float(p.gamma))
+
+
+def nmpc_create(problem, options: nmpc_options, max_batch: int = 1) -> ctypes.c_void_p:
+    """problem: any object with dim, nsx, nsy, N, lx, ly, gx, gy, h, k0, k1, q, r, gamma."""
+    pr = _Problem(problem)
+    hd = ctypes.c_void_p()
+    rc = _load().nmpc_create(ctypes.byref(pr.s), ctypes.byref(options), int(max_batch),
+                             ctypes.byref(hd))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_create")
+    return hd
+
+
+def nmpc_set_options(hd, options: nmpc_options) -> None:
+    rc = _load().nmpc_set_options(hd, ctypes.byref(options))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_set_options")
+
+
+def nmpc_destroy(hd) -> None:
+    if hd:
+        _load().nmpc_destroy(hd)
+
+
+def _host(a, size, name):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != size:
+        raise ValueError(f"{name}: expected {size} values, got {a.size}")
+    return a
+
+
+def nmpc_solve(hd, x0, xref, warm=None, *, n: int, m: int, N: int, xref_stages: bool = False):
+    """Host-buffer solve. Returns (status, X [N,n], U [N,m], LAM [N,n], info dict)."""
+    x0 = _host(x0, n, "x0")
+    xref = _host(xref, n * (N if xref_stages else 1), "xref")
+    X = np.empty((N, n)); U = np.empty((N, m)); L = np.empty((N, n))
+    ws = [None, None, None]
+    if warm is not None:
+        ws = [_host(warm[0], N * n, "warm x"), _host(warm[1], N * m, "warm u"),
+              _host(warm[2], N * n, "warm lam")]
+    info = nmpc_info()
+    ptr = lambda a: None if a is None else a.ctypes.data
+    rc = _load().nmpc_solve(hd, x0.ctypes.data, xref.ctypes.data, ptr(ws[0]), ptr(ws[1]),
+                            ptr(ws[2]), X.ctypes.data, U.ctypes.data, L.ctypes.data,
+                            ctypes.byref(info))
+    if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
+        raise NmpcError(rc, "nmpc_solve")
+    return rc, X, U, L, info.as_dict()
+
+
+def _dev(t, shape, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise ValueError(f"{name}: need a contiguous float64 device tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def nmpc_solve_batch(hd, x0, xref, warm=None, out=None, *, n: int, m: int, N: int,
+                     xref_stages: bool = False):
+    """Device-tensor solve of count = x0.shape[0] instances on torch's current
+    stream. Returns (status, X, U, LAM, [info dicts])."""
+    import torch
+    B = x0.shape[0]
+    xs = (B, N, n) if xref_stages else (B, n)
+    px0 = _dev(x0, (B, n), "x0")
+    pxr = _dev(xref, xs, "xref")
+    if out is None:
+        out = (torch.empty((B, N, n), dtype=torch.float64, device=x0.device),
+               torch.empty((B, N, m), dtype=torch.float64, device=x0.device),
+               torch.empty((B, N, n), dtype=torch.float64, device=x0.device))
+    po = [_dev(out[0], (B, N, n), "out x"), _dev(out[1], (B, N, m), "out u"),
+          _dev(out[2], (B, N, n), "out lam")]
+    pw = [None, None, None]
+    if warm is not None:
+        pw = [_dev(warm[0], (B, N, n), "warm x"), _dev(warm[1], (B, N, m), "warm u"),
+              _dev(warm[2], (B, N, n), "warm lam")]
+    infos = (nmpc_info * B)()
+    rc = _load().nmpc_solve_batch(hd, B, px0, pxr, pw[0], pw[1], pw[2], po[0], po[1], po[2],
+                                  infos, _stream())
+    if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
+        raise NmpcError(rc, "nmpc_solve_batch")
+    return rc, out[0], out[1], out[2], [i.as_dict() for i in infos]
+
+
+def nmpc_residual_batch(hd, x0, xref, X, U, LAM, *, n: int, m: int, N: int,
+                        xref_stages: bool = False):
+    """(r_scaled [B], r_paper [B]) numpy arrays for device trajectories."""
+    B = x0.shape[0]
+    xs = (B, N, n) if xref_stages else (B, n)
+    rs = np.zeros(B); rp = np.zeros(B)
+    rc = _load().nmpc_residual_batch(hd, B, _dev(x0, (B, n), "x0"), _dev(xref, xs, "xref"),
+                                     _dev(X, (B, N, n), "x"), _dev(U, (B, N, m), "u"),
+                                     _dev(LAM, (B, N, n), "lam"), rs.ctypes.data,
+                                     rp.ctypes.data, _stream())
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_residual_batch")
+    return rs, rp
+
+
+def nmpc_kernel_config(hd):
+    r = ctypes.c_int32(); w = ctypes.c_int32(); g = ctypes.c_int32()
+    rc = _load().nmpc_kernel_config(hd, ctypes.byref(r), ctypes.byref(w), ctypes.byref(g))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_kernel_config")
+    return {"rows_per_lane": r.value, "waves": w.value, "workgroups": g.value}
+
+
+# ------------------------------------------------------------- convenience
+
+class Solver:
+    """Owns one handle; methods forward to the C-named calls above."""
+
+    def __init__(self, problem, *, max_batch: int = 1, **options):
+        _load()
+        self.problem = problem
+        self.n = int(problem.nsx) * int(problem.nsy)
+        self.m = int(problem.lx) * int(problem.ly)
+        self.N = int(problem.N)
+        self.options = nmpc_default_options(**options)
+        self.max_batch = max_batch
+        self.hd = nmpc_create(problem, self.options, max_batch)
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.options, k, v)
+        nmpc_set_options(self.hd, self.options)
+
+    @property
+    def _dims(self):
+        return dict(n=self.n, m=self.m, N=self.N, xref_stages=bool(self.options.xref_per_stage))
+
+    def solve(self, x0, xref, warm: Optional[Sequence] = None):
+        return nmpc_solve(self.hd, x0, xref, warm, **self._dims)
+
+    def solve_batch(self, x0, xref, warm=None, out=None):
+        return nmpc_solve_batch(self.hd, x0, xref, warm, out, **self._dims)
+
+    def residual_batch(self, x0, xref, X, U, LAM):
+        return nmpc_residual_batch(self.hd, x0, xref, X, U, LAM, **self._dims)
+
+    def kernel_config(self):
+        return nmpc_kernel_config(self.hd)
+
+    def close(self):
+        if getattr(self, "hd", None):
+            nmpc_destroy(self.hd)
+            self.hd = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

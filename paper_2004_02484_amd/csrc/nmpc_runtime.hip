@@ -1,0 +1,495 @@
+// nmpc_runtime.hip -- host runtime and C ABI of the double-layer Jacobi NMPC
+// library: validation, device workspace, the upper-iteration launch loop
+// (replayed as a captured hipGraph of check_every launches), convergence
+// polling and result copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nmpc.h"
+#include "nmpc_device.h"
+
+using nmpc::InitArgs;
+using nmpc::InstState;
+using nmpc::IterArgs;
+using nmpc::OutArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? NMPC_E_OOM : NMPC_E_DEVICE,       \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+struct nmpc_handle {
+    nmpc_problem prob{};
+    nmpc_options opt{};
+    int max_batch = 0;
+    int n = 0, m = 0, N = 0;
+    int rows = 1, waves = 1;
+    std::vector<double> gx, gy;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    double *d_gx = nullptr, *d_gy = nullptr;
+    double *d_S[2] = {nullptr, nullptr};
+    double *d_x0 = nullptr, *d_xref = nullptr, *d_out = nullptr;
+    unsigned long long *d_acc = nullptr;   // racc [3][B] then pacc [3][B]
+    InstState *d_st = nullptr;             // [2][B]
+    int *d_iters = nullptr;                // [B]
+    double *d_rfin = nullptr;              // [B][2]
+    int *d_ctr = nullptr;                  // [4]
+    unsigned *d_wgdone = nullptr;
+    int *h_poll = nullptr;                 // pinned
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_count = -1, graph_len = 0, graph_prec = -1;
+    size_t xref_len = 0;                   // elements of xref per instance
+
+    double *X(int b) const { return d_S[b]; }
+    double *L(int b) const { return d_S[b] + (size_t)max_batch * N * n; }
+    double *U(int b) const { return d_S[b] + (size_t)2 * max_batch * N * n; }
+};
+
+namespace {
+
+int choose_rows(int nsy)
+{
+    for (int r : {1, 2, 4})
+        if ((nsy + r - 1) / r <= nmpc::kMaxWaves) return r;
+    return -1;
+}
+
+int check_problem(const nmpc_problem *p)
+{
+    if (!p) return fail(NMPC_E_ARG, "problem is NULL");
+    if (p->dim != 1 && p->dim != 2) return fail(NMPC_E_ARG, "dim must be 1 or 2");
+    if (p->nsx < 1 || p->nsy < 1 || p->horizon < 1 || p->lx < 1 || p->ly < 1)
+        return fail(NMPC_E_ARG, "sizes must be positive");
+    if (p->dim == 1 && (p->nsy != 1 || p->ly != 1))
+        return fail(NMPC_E_ARG, "1D problems need nsy == 1 and ly == 1");
+    if (!p->gx || !p->gy) return fail(NMPC_E_ARG, "gx/gy are NULL");
+    if (!finite_pos(p->h) || !finite_pos(p->r) || !std::isfinite(p->k0) ||
+        !std::isfinite(p->k1) || !std::isfinite(p->q) || p->q < 0.0 ||
+        !std::isfinite(p->gamma) || p->gamma < 0.0)
+        return fail(NMPC_E_ARG, "need h > 0, r > 0, q >= 0, gamma >= 0, finite k0, k1");
+    for (long long t = 0; t < (long long)p->lx * p->nsx; ++t)
+        if (!std::isfinite(p->gx[t])) return fail(NMPC_E_ARG, "gx not finite");
+    for (long long t = 0; t < (long long)p->ly * p->nsy; ++t)
+        if (!std::isfinite(p->gy[t])) return fail(NMPC_E_ARG, "gy not finite");
+    if (p->nsx > nmpc::kWave || p->nsy > nmpc::kMaxRows || p->ly > nmpc::kMaxLy ||
+        p->lx * p->ly > nmpc::kMaxM)
+        return fail(NMPC_E_UNSUPPORTED, "fused stage kernel needs nsx <= 64, nsy <= 64, m <= 64");
+    const int rows = choose_rows(p->nsy);
+    if (rows < 0 || !nmpc::iterate_kernel(0, rows, p->lx, p->ly) ||
+        !nmpc::iterate_kernel(1, rows, p->lx, p->ly))
+        return fail(NMPC_E_UNSUPPORTED, "no kernel instance for this input lattice");
+    return NMPC_OK;
+}
+
+int check_options(const nmpc_options *o)
+{
+    if (!o) return fail(NMPC_E_ARG, "options are NULL");
+    if (!(o->tol >= 0.0) || std::isnan(o->tol)) return fail(NMPC_E_ARG, "tol must be >= 0");
+    if (o->max_iter < 0 || o->max_iter > 100000000) return fail(NMPC_E_ARG, "bad max_iter");
+    if (o->n_sweep < 1 || o->n_sweep > 16) return fail(NMPC_E_ARG, "n_sweep must be 1..16");
+    if (o->n_schur < 0 || o->n_schur > 16) return fail(NMPC_E_ARG, "n_schur must be 0..16");
+    if (o->precision != NMPC_FP64 && o->precision != NMPC_FP32_SWEEP)
+        return fail(NMPC_E_ARG, "unknown precision");
+    if (o->check_every < 1 || o->check_every > 4096) return fail(NMPC_E_ARG, "bad check_every");
+    if (o->xref_per_stage != 0 && o->xref_per_stage != 1)
+        return fail(NMPC_E_ARG, "xref_per_stage must be 0 or 1");
+    return NMPC_OK;
+}
+
+void release(nmpc_handle *h)
+{
+    if (!h) return;
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (void *p : {(void *)h->d_gx, (void *)h->d_gy, (void *)h->d_S[0], (void *)h->d_S[1],
+                    (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_acc,
+                    (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
+                    (void *)h->d_wgdone})
+        if (p) (void)hipFree(p);
+    if (h->h_poll) (void)hipHostFree(h->h_poll);
+    if (h->ev) (void)hipEventDestroy(h->ev);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+IterArgs iter_args(const nmpc_handle *h, int count)
+{
+    IterArgs a{};
+    const nmpc_problem &p = h->prob;
+    a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->n; a.P.N = h->N; a.P.m = h->m;
+    a.P.lx = p.lx; a.P.ly = p.ly;
+    a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
+    const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
+    a.P.idx2 = 1.0 / (dx * dx);
+    a.P.idy2 = p.dim == 2 ? 1.0 / (dy * dy) : 0.0;
+    a.P.c0 = 2.0 * a.P.idx2 + 2.0 * a.P.idy2;
+    a.gx = h->d_gx; a.gy = h->d_gy;
+    a.x0 = h->d_x0; a.xref = h->d_xref;
+    a.xref_inst_stride = (long long)h->xref_len;
+    a.xref_stage_stride = h->opt.xref_per_stage ? h->n : 0;
+    for (int b = 0; b < 2; ++b) { a.X[b] = h->X(b); a.U[b] = h->U(b); a.LAM[b] = h->L(b); }
+    a.racc = h->d_acc;
+    a.pacc = h->d_acc + 3 * (size_t)h->max_batch;
+    a.st = h->d_st; a.iters = h->d_iters; a.rfin = h->d_rfin;
+    a.ctr = h->d_ctr; a.wgdone = h->d_wgdone;
+    a.B = h->max_batch;
+    a.units = count * h->N;
+    a.per_xcd = (a.units + 7) / 8;
+    a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
+    a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
+    a.residual_only = 0;
+    return a;
+}
+
+int launch_iterate(nmpc_handle *h, const IterArgs &a, hipStream_t s)
+{
+    const void *fn = nmpc::iterate_kernel(h->opt.precision, h->rows, h->prob.lx, h->prob.ly);
+    if (!fn) return fail(NMPC_E_UNSUPPORTED, "no kernel instance");
+    void *args[] = {(void *)&a};
+    HIP_TRY(hipLaunchKernel(fn, dim3(8 * a.per_xcd), dim3(nmpc::kWave * h->waves), args, 0, s));
+    return NMPC_OK;
+}
+
+int ensure_graph(nmpc_handle *h, int count)
+{
+    const int len = h->opt.check_every;
+    if (h->gexec && h->graph_count == count && h->graph_len == len &&
+        h->graph_prec == h->opt.precision)
+        return NMPC_OK;
+    if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+    if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+    IterArgs a = iter_args(h, count);
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = NMPC_OK;
+    for (int t = 0; t < len && rc == NMPC_OK; ++t) rc = launch_iterate(h, a, h->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != NMPC_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(NMPC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    h->graph = g;
+    HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+    h->graph_count = count; h->graph_len = len; h->graph_prec = h->opt.precision;
+    return NMPC_OK;
+}
+
+// Run the upper iteration for `count` instances whose x0/xref already sit in
+// the handle's buffers; S^0 from the warm pointers (device) or cold.
+int run(nmpc_handle *h, int count, const double *wx, const double *wu, const double *wl,
+        double *ox, double *ou, double *ol)
+{
+    InitArgs ia{};
+    ia.count = count; ia.B = h->max_batch; ia.N = h->N; ia.n = h->n; ia.m = h->m;
+    ia.mode = h->opt.precision == NMPC_FP32_SWEEP ? 1 : 0;
+    ia.x0 = h->d_x0; ia.wx = wx; ia.wu = wu; ia.wl = wl;
+    ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
+    ia.st = h->d_st; ia.racc = h->d_acc; ia.pacc = h->d_acc + 3 * (size_t)h->max_batch;
+    ia.iters = h->d_iters; ia.ctr = h->d_ctr; ia.wgdone = h->d_wgdone;
+    {
+        void *args[] = {(void *)&ia};
+        const size_t tot = (size_t)count * h->N * h->n;
+        const unsigned grid = (unsigned)std::min<size_t>((tot + 255) / 256 + 1, 8192);
+        HIP_TRY(hipLaunchKernel(nmpc::init_kernel(), dim3(grid), dim3(256), args, 0, h->stream));
+    }
+    int rc = ensure_graph(h, count);
+    if (rc != NMPC_OK) return rc;
+    // Every instance finishes by kernel max_iter + 1 (+3 for the FP32 -> FP64
+    // switch and the correction step); later launches are no-ops.
+    const long long cap = (long long)h->opt.max_iter + 8 + h->graph_len;
+    long long launched = 0;
+    for (;;) {
+        HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+        launched += h->graph_len;
+        HIP_TRY(hipMemcpyAsync(h->h_poll, h->d_ctr + 2, sizeof(int), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (*h->h_poll >= count) break;
+        if (launched > cap)
+            return fail(NMPC_E_DEVICE, "instances did not finish within max_iter launches");
+    }
+    OutArgs oa{};
+    oa.count = count; oa.N = h->N; oa.n = h->n; oa.m = h->m; oa.iters = h->d_iters;
+    for (int b = 0; b < 2; ++b) { oa.X[b] = h->X(b); oa.U[b] = h->U(b); oa.LAM[b] = h->L(b); }
+    oa.ox = ox; oa.ou = ou; oa.ol = ol;
+    {
+        void *args[] = {(void *)&oa};
+        const size_t tot = (size_t)count * h->N * h->n;
+        const unsigned grid = (unsigned)std::min<size_t>((tot + 255) / 256 + 1, 8192);
+        HIP_TRY(hipLaunchKernel(nmpc::output_kernel(), dim3(grid), dim3(256), args, 0, h->stream));
+    }
+    return NMPC_OK;
+}
+
+int collect_info(nmpc_handle *h, int count, nmpc_info *info)
+{
+    std::vector<int> iters(count);
+    std::vector<double> rf(2 * (size_t)count);
+    std::vector<InstState> st(count);
+    // the final state lives in the parity slot of the last kernel + 1; the
+    // status is sticky once set, so read both slots and take the final one.
+    std::vector<InstState> st2(count);
+    HIP_TRY(hipMemcpyAsync(iters.data(), h->d_iters, sizeof(int) * count, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(rf.data(), h->d_rfin, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(st.data(), h->d_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(st2.data(), h->d_st + h->max_batch, sizeof(InstState) * count,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int worst = NMPC_OK;
+    for (int b = 0; b < count; ++b) {
+        const InstState &s = st[b].status != nmpc::kActive ? st[b] : st2[b];
+        const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
+        if (info) {
+            info[b].r_scaled = rf[2 * b];
+            info[b].r_paper = rf[2 * b + 1];
+            info[b].iters = iters[b];
+            info[b].status = status;
+            info[b].fp32_iters = s.f32;
+            info[b].reserved = 0;
+        }
+        if (status != NMPC_OK && worst == NMPC_OK) worst = status;
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+void nmpc_default_options(nmpc_options *opt)
+{
+    if (!opt) return;
+    opt->tol = 1e-6;
+    opt->max_iter = 2000;
+    opt->n_sweep = 2;
+    opt->n_schur = 2;
+    opt->precision = NMPC_FP64;
+    opt->check_every = 16;
+    opt->xref_per_stage = 0;
+}
+
+int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
+                nmpc_handle **out)
+{
+    g_err.clear();
+    if (!out) return fail(NMPC_E_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_problem(prob);
+    if (rc) return rc;
+    rc = check_options(opt);
+    if (rc) return rc;
+    if (max_batch < 1) return fail(NMPC_E_ARG, "max_batch must be >= 1");
+    nmpc_handle *h = new (std::nothrow) nmpc_handle();
+    if (!h) return fail(NMPC_E_OOM, "host allocation failed");
+    h->prob = *prob;
+    h->opt = *opt;
+    h->max_batch = max_batch;
+    h->n = prob->nsx * prob->nsy;
+    h->m = prob->lx * prob->ly;
+    h->N = prob->horizon;
+    h->rows = choose_rows(prob->nsy);
+    h->waves = (prob->nsy + h->rows - 1) / h->rows;
+    h->gx.assign(prob->gx, prob->gx + (size_t)prob->lx * prob->nsx);
+    h->gy.assign(prob->gy, prob->gy + (size_t)prob->ly * prob->nsy);
+    h->prob.gx = h->gx.data();
+    h->prob.gy = h->gy.data();
+    h->xref_len = (size_t)h->n * (opt->xref_per_stage ? h->N : 1);
+    const size_t B = max_batch, S = B * h->N * (2 * (size_t)h->n + h->m);
+#define ALLOC(ptr, bytes)                                                          \
+    do {                                                                           \
+        hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                       \
+        if (e_ != hipSuccess) {                                                    \
+            release(h);                                                            \
+            return fail(e_ == hipErrorOutOfMemory ? NMPC_E_OOM : NMPC_E_DEVICE,    \
+                        std::string("hipMalloc: ") + hipGetErrorString(e_));       \
+        }                                                                          \
+    } while (0)
+    ALLOC(h->d_gx, sizeof(double) * h->gx.size());
+    ALLOC(h->d_gy, sizeof(double) * h->gy.size());
+    ALLOC(h->d_S[0], sizeof(double) * S);
+    ALLOC(h->d_S[1], sizeof(double) * S);
+    ALLOC(h->d_x0, sizeof(double) * B * h->n);
+    ALLOC(h->d_xref, sizeof(double) * B * (size_t)h->n * h->N);   // room for per-stage xref
+    ALLOC(h->d_out, sizeof(double) * (size_t)h->N * (2 * (size_t)h->n + h->m));
+    ALLOC(h->d_acc, sizeof(unsigned long long) * 6 * B);
+    ALLOC(h->d_st, sizeof(InstState) * 2 * B);
+    ALLOC(h->d_iters, sizeof(int) * B);
+    ALLOC(h->d_rfin, sizeof(double) * 2 * B);
+    ALLOC(h->d_ctr, sizeof(int) * 4);
+    ALLOC(h->d_wgdone, sizeof(unsigned));
+#undef ALLOC
+    hipError_t e = hipHostMalloc((void **)&h->h_poll, sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->d_gx, h->gx.data(), sizeof(double) * h->gx.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(h->d_gy, h->gy.data(), sizeof(double) * h->gy.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(h->d_ctr, 0, sizeof(int) * 4);
+    if (e == hipSuccess) e = hipMemset(h->d_wgdone, 0, sizeof(unsigned));
+    if (e != hipSuccess) {
+        release(h);
+        return fail(NMPC_E_DEVICE, std::string("create: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return NMPC_OK;
+}
+
+int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
+{
+    g_err.clear();
+    if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    int rc = check_options(opt);
+    if (rc) return rc;
+    if (opt->xref_per_stage != h->opt.xref_per_stage)
+        h->xref_len = (size_t)h->n * (opt->xref_per_stage ? h->N : 1);
+    h->opt = *opt;
+    h->graph_count = -1;   // recapture: tolerances and counts are kernel arguments
+    return NMPC_OK;
+}
+
+int nmpc_solve(nmpc_handle *h, const double *x0, const double *xref, const double *warm_x,
+               const double *warm_u, const double *warm_lam, double *out_x, double *out_u,
+               double *out_lam, nmpc_info *info)
+{
+    g_err.clear();
+    if (!h || !x0 || !xref || !out_x || !out_u || !out_lam)
+        return fail(NMPC_E_ARG, "NULL argument");
+    const int nw = (warm_x != nullptr) + (warm_u != nullptr) + (warm_lam != nullptr);
+    if (nw != 0 && nw != 3) return fail(NMPC_E_ARG, "warm start needs x, u and lambda");
+    const size_t n = h->n, m = h->m, N = h->N;
+    HIP_TRY(hipMemcpyAsync(h->d_x0, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_xref, xref, sizeof(double) * h->xref_len, hipMemcpyHostToDevice,
+                           h->stream));
+    const double *wx = nullptr, *wu = nullptr, *wl = nullptr;
+    if (nw == 3) {   // stage the start in buffer 1 (overwritten by the first update)
+        HIP_TRY(hipMemcpyAsync(h->X(1), warm_x, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->L(1), warm_lam, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(h->U(1), warm_u, sizeof(double) * N * m, hipMemcpyHostToDevice, h->stream));
+        wx = h->X(1); wu = h->U(1); wl = h->L(1);
+    }
+    double *ox = h->d_out, *ol = h->d_out + N * n, *ou = h->d_out + 2 * N * n;
+    int rc = run(h, 1, wx, wu, wl, ox, ou, ol);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(out_x, ox, sizeof(double) * N * n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(out_lam, ol, sizeof(double) * N * n, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(out_u, ou, sizeof(double) * N * m, hipMemcpyDeviceToHost, h->stream));
+    nmpc_info tmp;
+    return collect_info(h, 1, info ? info : &tmp);
+}
+
+int nmpc_solve_batch(nmpc_handle *h, int32_t count, const double *x0, const double *xref,
+                     const double *warm_x, const double *warm_u, const double *warm_lam,
+                     double *out_x, double *out_u, double *out_lam, nmpc_info *info,
+                     void *stream)
+{
+    g_err.clear();
+    if (!h || !x0 || !xref || !out_x || !out_u || !out_lam)
+        return fail(NMPC_E_ARG, "NULL argument");
+    if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    const int nw = (warm_x != nullptr) + (warm_u != nullptr) + (warm_lam != nullptr);
+    if (nw != 0 && nw != 3) return fail(NMPC_E_ARG, "warm start needs x, u and lambda");
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(h->ev, us));
+    HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
+    HIP_TRY(hipMemcpyAsync(h->d_x0, x0, sizeof(double) * count * (size_t)h->n,
+                           hipMemcpyDeviceToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_xref, xref, sizeof(double) * count * h->xref_len,
+                           hipMemcpyDeviceToDevice, h->stream));
+    int rc = run(h, count, warm_x, warm_u, warm_lam, out_x, out_u, out_lam);
+    if (rc) return rc;
+    std::vector<nmpc_info> tmp;
+    if (!info) { tmp.resize(count); info = tmp.data(); }
+    return collect_info(h, count, info);
+}
+
+int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const double *xref,
+                        const double *x, const double *u, const double *lam, double *r_scaled,
+                        double *r_paper, void *stream)
+{
+    g_err.clear();
+    if (!h || !x0 || !xref || !x || !u || !lam || !r_scaled || !r_paper)
+        return fail(NMPC_E_ARG, "NULL argument");
+    if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(h->ev, us));
+    HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
+    IterArgs a = iter_args(h, count);
+    a.x0 = x0; a.xref = xref;
+    a.X[0] = const_cast<double *>(x);
+    a.U[0] = const_cast<double *>(u);
+    a.LAM[0] = const_cast<double *>(lam);
+    a.residual_only = 1;
+    HIP_TRY(hipMemsetAsync(h->d_acc, 0, sizeof(unsigned long long) * 6 * h->max_batch, h->stream));
+    int rc = launch_iterate(h, a, h->stream);
+    if (rc) return rc;
+    std::vector<unsigned long long> bits(2 * (size_t)count);
+    HIP_TRY(hipMemcpyAsync(bits.data(), a.racc, sizeof(unsigned long long) * count,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(bits.data() + count, a.pacc, sizeof(unsigned long long) * count,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int b = 0; b < count; ++b) {
+        std::memcpy(&r_scaled[b], &bits[b], sizeof(double));
+        std::memcpy(&r_paper[b], &bits[count + b], sizeof(double));
+    }
+    return NMPC_OK;
+}
+
+void nmpc_destroy(nmpc_handle *h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+}
+
+const char *nmpc_strerror(int code)
+{
+    switch (code) {
+    case NMPC_OK: return "ok";
+    case NMPC_E_ARG: return "invalid argument";
+    case NMPC_E_NOCONV: return "not converged within max_iter";
+    case NMPC_E_NONFINITE: return "residual became non-finite";
+    case NMPC_E_DEVICE: return "HIP device error";
+    case NMPC_E_OOM: return "out of device memory";
+    case NMPC_E_UNSUPPORTED: return "unsupported problem shape";
+    default: return "unknown error";
+    }
+}
+
+const char *nmpc_last_error(void) { return g_err.c_str(); }
+
+int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *waves,
+                       int32_t *workgroups)
+{
+    if (!h) return NMPC_E_ARG;
+    if (rows_per_lane) *rows_per_lane = h->rows;
+    if (waves) *waves = h->waves;
+    if (workgroups) *workgroups = 8 * ((h->max_batch * h->N + 7) / 8);
+    return NMPC_OK;
+}
+
+}  // extern "C"

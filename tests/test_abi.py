@@ -1,0 +1,80 @@
+"""C-ABI library checks that need no GPU: exported symbols and argument
+validation (both happen before any device call)."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+from nmpc_inputs import make_problem
+
+import paper_2004_02484_amd as nm
+from paper_2004_02484_amd import _binding
+
+
+def declared_functions():
+    src = open(_binding.library_path().replace("paper_2004_02484_amd/libnmpc.so",
+                                               "include/nmpc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nmpc_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_binding.library_path())
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_default_options_are_the_papers_lower_layer():
+    o = nm.nmpc_default_options()
+    assert (o.n_sweep, o.n_schur, o.precision) == (2, 2, nm.NMPC_FP64)
+    assert o.tol == 1e-6 and o.check_every >= 1
+
+
+@pytest.mark.parametrize("field,value", [("dim", 3), ("nsx", 0), ("N", 0), ("h", 0.0),
+                                         ("r", 0.0), ("gamma", -1.0), ("q", -1.0),
+                                         ("h", float("nan"))])
+def test_invalid_problem_rejected(field, value):
+    p = make_problem("c0")
+    setattr(p, field, value)
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, nm.nmpc_default_options(), 1)
+    assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_1d_needs_single_row():
+    p = make_problem("c0").with_(nsy=2, gy=np.ones((1, 2)))
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, nm.nmpc_default_options(), 1)
+    assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_unsupported_shapes_reported():
+    p = make_problem("grid", ns=96, N=4)   # wider than one wavefront of columns
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, nm.nmpc_default_options(), 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+    p = make_problem("grid", ns=16, N=4, lattice=3)   # no kernel for a 3x3 lattice
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, nm.nmpc_default_options(), 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value", [("n_sweep", 0), ("n_sweep", 17), ("n_schur", -1),
+                                         ("precision", 7), ("check_every", 0),
+                                         ("max_iter", -1), ("tol", -1.0)])
+def test_invalid_options_rejected(field, value):
+    o = nm.nmpc_default_options(**{field: value})
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(make_problem("c0"), o, 1)
+    assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_null_handle_calls():
+    lib = ctypes.CDLL(_binding.library_path())
+    lib.nmpc_destroy(None)
+    assert lib.nmpc_kernel_config(None, None, None, None) == nm.NMPC_E_ARG
+    lib.nmpc_strerror.restype = ctypes.c_char_p
+    assert b"argument" in lib.nmpc_strerror(1)

@@ -1,0 +1,197 @@
+"""GPU parity: the HIP path against the CPU oracle, through the C ABI.
+
+Same start and schedule: iterate S^k must agree element by element (the only
+differences are FP64 rounding order, e.g. in the B^T sums), so the bar is a
+relative 1e-10 on every trajectory. Converged results are also compared with
+the oracle run to r_scaled <= 1e-12 ("exact"), and the measured control error
+is asserted against the FP64 (1e-6) and FP32-sweep (1e-4) bars.
+"""
+import numpy as np
+import pytest
+
+from nmpc_inputs import gaussian_factors, make_batch, make_instance, make_problem
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def nm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_02484_amd as nm
+    return nm
+
+
+def ragged2d(nsx, nsy, N, lattice=2, sigma=0.2, gamma_rel=1.0):
+    P = make_problem("grid", ns=nsx, N=N, lattice=lattice, gamma_rel=gamma_rel)
+    P = P.with_(nsy=nsy, gx=gaussian_factors(nsx, lattice, sigma),
+                gy=gaussian_factors(nsy, lattice, sigma))
+    P.h = 0.2 / (0.75 * max(nsx + 1, nsy + 1) ** 2)
+    P.gamma = gamma_rel * P.h * P.r
+    return P
+
+
+def check_same_iterate(P, x0, xref, k, nm, **opts):
+    s = nm.Solver(P, tol=0.0, max_iter=k, **opts)
+    rc, X, U, L, info = s.solve(x0, xref)
+    s.close()
+    o = oracle.solve(P, x0, xref, tol=0.0, max_iter=k,
+                     n_sw=opts.get("n_sweep", 2), n_schur=opts.get("n_schur", 2))
+    assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+    assert rel(X, o["X"]) <= REL
+    assert rel(L, o["LAM"]) <= REL if np.abs(o["LAM"]).max() > 0 else np.all(L == 0)
+    assert rel(U, o["U"]) <= REL if np.abs(o["U"]).max() > 0 else np.all(U == 0)
+    # the input rows h (r u + B^T lam) cancel; their B^T sums run in another
+    # order on the GPU, so the norms carry a few ulps of the summands
+    assert abs(info["r_scaled"] - o["r_scaled"]) <= 1e-9 * o["r_scaled"]
+    assert abs(info["r_paper"] - o["r_paper"]) <= 1e-9 * o["r_paper"]
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 7, 40])
+def test_c0_iterates_match_oracle(nm, k):
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 0)
+    check_same_iterate(P, x0, xref, k, nm)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_c1_iterates_match_oracle(nm, k):
+    P = make_problem("c1")
+    x0, xref = make_instance(P, 1)
+    check_same_iterate(P, x0, xref, k, nm)
+
+
+@pytest.mark.parametrize("shape", [(13, 37, 6), (64, 5, 3), (7, 16, 4), (40, 64, 2)])
+def test_ragged_shapes_match_oracle(nm, shape):
+    """Grids that leave lanes, rows and waves partly empty (ragged tails)."""
+    nsx, nsy, N = shape
+    P = ragged2d(nsx, nsy, N)
+    x0, xref = make_instance(P, 5)
+    check_same_iterate(P, x0, xref, 5, nm)
+
+
+@pytest.mark.parametrize("nsw,nsc", [(1, 0), (3, 1), (4, 3)])
+def test_schedule_variants_match_oracle(nm, nsw, nsc):
+    P = make_problem("grid", ns=24, N=5)
+    x0, xref = make_instance(P, 2)
+    check_same_iterate(P, x0, xref, 4, nm, n_sweep=nsw, n_schur=nsc)
+
+
+def test_degenerate_single_node_single_stage(nm):
+    P = make_problem("c0").with_(nsx=1, N=1, lx=1, gx=np.ones((1, 1)))
+    x0 = np.array([0.1]); xref = np.array([0.3])
+    check_same_iterate(P, x0, xref, 3, nm)
+    s = nm.Solver(P)
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-6)
+    assert rc == nm.NMPC_OK and info["iters"] == o["iters"]
+    assert rel(U, o["U"]) <= REL
+
+
+@pytest.mark.parametrize("name,seed", [("c0", 3), ("c1", 4)])
+def test_converged_solution_matches_oracle(nm, name, seed):
+    P = make_problem(name)
+    x0, xref = make_instance(P, seed)
+    s = nm.Solver(P)
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-6)
+    assert rc == nm.NMPC_OK and o["status"] == "converged"
+    assert abs(info["iters"] - o["iters"]) <= 1
+    if info["iters"] == o["iters"]:
+        assert rel(U, o["U"]) <= 1e-9 and rel(L, o["LAM"]) <= 1e-9
+    assert info["r_scaled"] <= 1e-6
+    # the returned trajectory satisfies the KKT conditions (oracle re-check)
+    rs, _ = oracle.residual(P, x0, xref, X, U, L)
+    assert rs <= 1e-6 and abs(rs - info["r_scaled"]) <= 1e-9 * rs
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    err = rel(U, ex["U"])
+    print(f"{name}: iters {info['iters']}, control rel. error vs exact {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_batch_matches_single_solves(nm):
+    import torch
+    P = make_problem("c1")
+    seeds = [10, 11, 12]
+    x0, xref = make_batch(P, seeds)
+    s = nm.Solver(P, max_batch=4)
+    rc, X, U, L, infos = s.solve_batch(torch.tensor(x0, device="cuda"),
+                                       torch.tensor(xref, device="cuda"))
+    assert rc == nm.NMPC_OK
+    for b, sd in enumerate(seeds):
+        o = oracle.solve(P, x0[b], xref[b], tol=1e-6)
+        assert abs(infos[b]["iters"] - o["iters"]) <= 1
+        if infos[b]["iters"] == o["iters"]:
+            assert rel(U[b].cpu().numpy(), o["U"]) <= 1e-9
+    # graph replay length does not change the result
+    s.set_options(check_every=1)
+    rc2, X2, U2, L2, infos2 = s.solve_batch(torch.tensor(x0, device="cuda"),
+                                            torch.tensor(xref, device="cuda"))
+    assert torch.equal(U2, U) and torch.equal(X2, X) and torch.equal(L2, L)
+    assert [i["iters"] for i in infos2] == [i["iters"] for i in infos]
+
+
+def test_residual_batch_matches_oracle(nm):
+    import torch
+    P = make_problem("c1")
+    x0, xref = make_batch(P, [1, 2])
+    rng = np.random.default_rng(0)
+    X = rng.uniform(0, 0.2, (2, P.N, P.n)); U = rng.normal(size=(2, P.N, P.m))
+    L = rng.normal(size=(2, P.N, P.n)) * 1e-3
+    s = nm.Solver(P, max_batch=2)
+    t = lambda a: torch.tensor(a, device="cuda")
+    rs, rp = s.residual_batch(t(x0), t(xref), t(X), t(U), t(L))
+    for b in range(2):
+        ors, orp = oracle.residual(P, x0[b], xref[b], X[b], U[b], L[b])
+        assert abs(rs[b] - ors) <= 1e-12 * ors and abs(rp[b] - orp) <= 1e-12 * orp
+
+
+def test_fp32_sweeps_reach_fp64_fixed_point(nm):
+    P = make_problem("c1")
+    x0, xref = make_instance(P, 6)
+    s = nm.Solver(P, precision=nm.NMPC_FP32_SWEEP)
+    rc, X, U, L, info = s.solve(x0, xref)
+    assert rc == nm.NMPC_OK and info["fp32_iters"] > 0 and info["r_scaled"] <= 1e-6
+    rs, _ = oracle.residual(P, x0, xref, X, U, L)
+    assert rs <= 1e-6
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    err = rel(U, ex["U"])
+    print(f"fp32 sweeps: iters {info['iters']} (fp32 {info['fp32_iters']}), "
+          f"control rel. error vs exact {err:.2e}")
+    assert err <= 1e-4
+
+
+def test_warm_start_and_failure_statuses(nm):
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 7)
+    ex = oracle.solve(P, x0, xref, tol=1e-10)
+    s = nm.Solver(P)
+    rc, X, U, L, info = s.solve(x0, xref, warm=(ex["X"], ex["U"], ex["LAM"]))
+    assert rc == nm.NMPC_OK and info["iters"] == 0
+    np.testing.assert_array_equal(U, ex["U"])
+    bad = ex["U"].copy(); bad[2, 1] = np.nan
+    rc, X, U, L, info = s.solve(x0, xref, warm=(ex["X"], bad, ex["LAM"]))
+    assert rc == nm.NMPC_E_NONFINITE and info["iters"] == 0
+    s.set_options(max_iter=3)
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-6, max_iter=3)
+    assert rc == nm.NMPC_E_NOCONV and info["iters"] == 3 and rel(U, o["U"]) <= REL
+
+
+def test_time_varying_reference(nm):
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 8)
+    xr = np.stack([xref * (1.0 - 0.02 * i) for i in range(P.N)])
+    s = nm.Solver(P, xref_per_stage=1, tol=0.0, max_iter=6)
+    rc, X, U, L, info = s.solve(x0, xr)
+    o = oracle.solve(P, x0, xr, tol=0.0, max_iter=6)
+    assert rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
