@@ -159,6 +159,18 @@ const char *nmpc_last_error(void);
 int nmpc_kernel_config(const nmpc_handle *hd, int32_t *rows_per_lane, int32_t *waves,
                        int32_t *workgroups);
 
+/* Kernel timing of later solves on this handle (not thread-safe). enable != 0
+ * resets the counters and brackets every replay of the captured iteration
+ * graph with HIP events on the handle's stream; enable == 0 stops timing. */
+int nmpc_timing_enable(nmpc_handle *hd, int32_t enable);
+
+/* Read the counters since the last enable: GPU milliseconds spent in the
+ * iteration kernels, number of iteration-kernel launches, and number of
+ * (instance, stage) units that were evaluated and updated. NULL pointers are
+ * skipped. */
+int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches,
+                     int64_t *units);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,4 +30,6 @@ from ._binding import (  # noqa: F401
     nmpc_solve,
     nmpc_solve_batch,
     nmpc_strerror,
+    nmpc_timing_enable,
+    nmpc_timing_read,
 )

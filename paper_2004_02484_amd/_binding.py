@@ -94,6 +94,12 @@ def _load():
                                        ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]
     lib.nmpc_kernel_config.restype = ctypes.c_int
+    lib.nmpc_timing_enable.argtypes = [vp, ctypes.c_int32]
+    lib.nmpc_timing_enable.restype = ctypes.c_int
+    lib.nmpc_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(ctypes.c_int64)]
+    lib.nmpc_timing_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -241,6 +247,20 @@ def nmpc_kernel_config(hd):
     return {"rows_per_lane": r.value, "waves": w.value, "workgroups": g.value}
 
 
+def nmpc_timing_enable(hd, enable: bool = True) -> None:
+    rc = _load().nmpc_timing_enable(hd, 1 if enable else 0)
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_timing_enable")
+
+
+def nmpc_timing_read(hd):
+    ms = ctypes.c_double(); la = ctypes.c_int64(); un = ctypes.c_int64()
+    rc = _load().nmpc_timing_read(hd, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_timing_read")
+    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
+
+
 # ------------------------------------------------------------- convenience
 
 class Solver:
@@ -276,6 +296,12 @@ class Solver:
 
     def kernel_config(self):
         return nmpc_kernel_config(self.hd)
+
+    def timing_enable(self, enable: bool = True):
+        nmpc_timing_enable(self.hd, enable)
+
+    def timing_read(self):
+        return nmpc_timing_read(self.hd)
 
     def close(self):
         if getattr(self, "hd", None):

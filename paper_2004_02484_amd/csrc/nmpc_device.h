@@ -49,6 +49,7 @@ struct IterArgs {
     double *rfin;                   // [B][2] residuals of the returned iterate
     int *ctr;                       // [0] kernel index, [2] finished instances
     unsigned *wgdone;               // workgroups finished in the current kernel
+    unsigned long long *work_units; // (instance, stage) units evaluated
     int B, units, per_xcd;
     double tol;
     int max_iter, n_sw, n_schur;

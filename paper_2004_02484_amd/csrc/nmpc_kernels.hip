@@ -544,6 +544,7 @@ __global__ void __launch_bounds__(kWave * kMaxWaves) k_iterate(const IterArgs a)
             for (int aa = 0; aa < LX; ++aa)
                 gxr[aa] = c.lane < a.P.nsx ? a.gx[aa * a.P.nsx + c.lane] : 0.0;
             const int slot = a.residual_only ? 0 : k % 3;
+            if (tid == 0 && !a.residual_only) atomicAdd(a.work_units, 1ull);
             if (PREC == 1 && d.fp32)
                 stage_body<float, R, LX, LY>(a, c, gxr, b, i, d.j, slot, tid);
             else

@@ -60,6 +60,12 @@ struct nmpc_handle {
     int *d_ctr = nullptr;                  // [4]
     unsigned *d_wgdone = nullptr;
     int *h_poll = nullptr;                 // pinned
+    unsigned long long *d_units = nullptr; // evaluated (instance, stage) units
+    bool timing = false;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    double kernel_ms = 0.0;
+    long long launches = 0;
+    unsigned long long units0 = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_count = -1, graph_len = 0, graph_prec = -1;
@@ -129,10 +135,12 @@ void release(nmpc_handle *h)
     for (void *p : {(void *)h->d_gx, (void *)h->d_gy, (void *)h->d_S[0], (void *)h->d_S[1],
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_acc,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
-                    (void *)h->d_wgdone})
+                    (void *)h->d_wgdone, (void *)h->d_units})
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
     if (h->ev) (void)hipEventDestroy(h->ev);
+    if (h->t0) (void)hipEventDestroy(h->t0);
+    if (h->t1) (void)hipEventDestroy(h->t1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
 }
@@ -156,7 +164,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.racc = h->d_acc;
     a.pacc = h->d_acc + 3 * (size_t)h->max_batch;
     a.st = h->d_st; a.iters = h->d_iters; a.rfin = h->d_rfin;
-    a.ctr = h->d_ctr; a.wgdone = h->d_wgdone;
+    a.ctr = h->d_ctr; a.wgdone = h->d_wgdone; a.work_units = h->d_units;
     a.B = h->max_batch;
     a.units = count * h->N;
     a.per_xcd = (a.units + 7) / 8;
@@ -222,11 +230,19 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
     const long long cap = (long long)h->opt.max_iter + 8 + h->graph_len;
     long long launched = 0;
     for (;;) {
+        if (h->timing) HIP_TRY(hipEventRecord(h->t0, h->stream));
         HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+        if (h->timing) HIP_TRY(hipEventRecord(h->t1, h->stream));
         launched += h->graph_len;
         HIP_TRY(hipMemcpyAsync(h->h_poll, h->d_ctr + 2, sizeof(int), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
+        if (h->timing) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
+            h->kernel_ms += ms;
+            h->launches += h->graph_len;
+        }
         if (*h->h_poll >= count) break;
         if (launched > cap)
             return fail(NMPC_E_DEVICE, "instances did not finish within max_iter launches");
@@ -340,10 +356,14 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
     ALLOC(h->d_wgdone, sizeof(unsigned));
+    ALLOC(h->d_units, sizeof(unsigned long long));
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_poll, sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&h->t0);
+    if (e == hipSuccess) e = hipEventCreate(&h->t1);
+    if (e == hipSuccess) e = hipMemset(h->d_units, 0, sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMemcpy(h->d_gx, h->gx.data(), sizeof(double) * h->gx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
@@ -481,6 +501,32 @@ const char *nmpc_strerror(int code)
 }
 
 const char *nmpc_last_error(void) { return g_err.c_str(); }
+
+int nmpc_timing_enable(nmpc_handle *h, int32_t enable)
+{
+    g_err.clear();
+    if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->timing = enable != 0;
+    if (h->timing) {
+        h->kernel_ms = 0.0;
+        h->launches = 0;
+        HIP_TRY(hipMemcpy(&h->units0, h->d_units, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    }
+    return NMPC_OK;
+}
+
+int nmpc_timing_read(const nmpc_handle *h, double *kernel_ms, int64_t *launches, int64_t *units)
+{
+    g_err.clear();
+    if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    unsigned long long u = 0;
+    HIP_TRY(hipMemcpy(&u, h->d_units, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    if (kernel_ms) *kernel_ms = h->kernel_ms;
+    if (launches) *launches = h->launches;
+    if (units) *units = (int64_t)(u - h->units0);
+    return NMPC_OK;
+}
 
 int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *waves,
                        int32_t *workgroups)
