@@ -88,6 +88,11 @@ typedef struct nmpc_options {
                              step's result passes it (final FP64 correction) */
     int32_t check_every;  /* iterations between host convergence polls (>= 1) */
     int32_t xref_per_stage; /* 0: xref is [n] per instance; 1: [N][n] */
+    int32_t tile_rows;    /* grid rows per lane of the stage kernel's register
+                             tile for the main precision; 0 = default. Other
+                             values select alternative kernel instances (as
+                             chosen by the tile autotuner); unsupported values
+                             give NMPC_E_UNSUPPORTED */
 } nmpc_options;
 
 /* Per-instance result information. */
@@ -103,7 +108,8 @@ typedef struct nmpc_info {
 typedef struct nmpc_handle nmpc_handle;
 
 /* Fill options with the paper's lower-layer settings (2 sweeps, 2 Schur
- * iterations), tol 1e-6, max_iter 2000, FP64, check_every 16. */
+ * iterations), tol 1e-6, max_iter 2000, FP64, check_every 16, default
+ * tile. */
 void nmpc_default_options(nmpc_options *opt);
 
 /* Create a solver for one problem shape and up to max_batch instances on the

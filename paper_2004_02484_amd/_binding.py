@@ -35,7 +35,7 @@ class nmpc_options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("n_sweep", ctypes.c_int32), ("n_schur", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("xref_per_stage", ctypes.c_int32)]
+                ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
 
 
 class nmpc_info(ctypes.Structure):

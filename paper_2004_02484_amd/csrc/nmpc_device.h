@@ -2,6 +2,7 @@
 // runtime of the double-layer Jacobi NMPC library (internal header).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -9,17 +10,22 @@ namespace nmpc {
 
 constexpr int kWave = 64;       // CDNA wavefront width
 constexpr int kMaxWaves = 16;   // waves per workgroup (1024 threads)
-constexpr int kMaxRows = 64;    // rows per stage held by one workgroup
-constexpr int kMaxLy = 8;       // input lattice rows
 constexpr int kMaxM = 64;       // inputs per stage
+constexpr int kMaxLy = 8;       // input lattice rows
+constexpr int kMaxCx = 6;       // columns per lane: nsx <= 16 * 6 = 96
 
 constexpr int kActive = -1;
 constexpr int kStatusOk = 0;        // == NMPC_OK
 constexpr int kStatusNoconv = 2;    // == NMPC_E_NOCONV
 constexpr int kStatusNonfinite = 3; // == NMPC_E_NONFINITE
 
+// Instance modes; kModeFp32 / kModeFp64 double as kernel precision tags.
+constexpr int kModeFp64 = 0;
+constexpr int kModeFp32 = 1;
+constexpr int kModeFp64Redo = 2;   // FP32 test passed: redo that iterate in FP64
+
 struct DevProblem {
-    int nsx, nsy, n, N, m, lx, ly;
+    int nsx, nsy, n, N, m, lx, ly;   // n: padded points per stage, nsy * 16 * CX
     double h, k0, k1, q, r, gamma;
     double idx2, idy2, c0;   // 1/dx^2, 1/dy^2 (0 in 1D), 2/dx^2 + 2/dy^2
 };
@@ -27,11 +33,12 @@ struct DevProblem {
 // Per-instance iteration state; two copies, indexed by kernel parity.
 struct InstState {
     int status;   // kActive or a final status
-    int mode;     // 1: lower layer in FP32, 0: FP64
-    int off;      // iterate index j = kernel index - off
+    int mode;     // kModeFp32, kModeFp64 or kModeFp64Redo
+    int e;        // evaluations done (residual slot of evaluation e is e % 3)
+    int j;        // index of the last evaluated iterate S^j
     int pending;  // 1: an FP64 correction step is still owed
-    int f32;      // iterations run with FP32 sweeps
-    int pad[3];
+    int f32;      // evaluations run with FP32 sweeps
+    int pad[2];
 };
 
 struct IterArgs {
@@ -42,14 +49,13 @@ struct IterArgs {
     long long xref_inst_stride;     // elements between instances
     int xref_stage_stride;          // 0 or n
     double *X[2], *U[2], *LAM[2];   // trajectory double buffer [B][N][n] / [B][N][m]
-    unsigned long long *racc;       // [3][B] r_scaled bit patterns
-    unsigned long long *pacc;       // [3][B] r_paper bit patterns
+    unsigned long long *rst;        // [3][B][N] per-stage r_scaled bit patterns
+    unsigned long long *pst;        // [3][B][N] per-stage r_paper bit patterns
     InstState *st;                  // [2][B]
     int *iters;                     // [B] index of the returned iterate
     double *rfin;                   // [B][2] residuals of the returned iterate
-    int *ctr;                       // [0] kernel index, [2] finished instances
-    unsigned *wgdone;               // workgroups finished in the current kernel
-    unsigned long long *work_units; // (instance, stage) units evaluated
+    int *ctr;                       // [0] kernel base index, [2] finished, [3] in FP32 phase
+    int kofs;                       // this launch's index within a captured sequence
     int B, units, per_xcd;
     double tol;
     int max_iter, n_sw, n_schur;
@@ -57,24 +63,59 @@ struct IterArgs {
 };
 
 struct InitArgs {
-    int count, B, N, n, m, mode;
+    int count, B, N, nsx, nsy, sx, m, mode;
     const double *x0, *wx, *wu, *wl;
     double *X, *U, *LAM;
     InstState *st;
-    unsigned long long *racc, *pacc;
     int *iters, *ctr;
-    unsigned *wgdone;
 };
 
 struct OutArgs {
-    int count, N, n, m;
+    int count, N, nsx, nsy, sx, m;
     const int *iters;
     const double *X[2], *U[2], *LAM[2];
     double *ox, *ou, *ol;
 };
 
-const void *iterate_kernel(int prec, int rows, int lx, int ly);
+// Tile configuration of one iteration-kernel instance.
+struct TileCfg {
+    int cx, rows, max_waves;
+};
+
+// Byte offsets into a workgroup's dynamic LDS.
+struct LdsOff {
+    size_t edge, gx, gy, gxf, gyf, uvec, v3, kun, red, nrm, total;
+};
+
+__host__ __device__ inline size_t lds_align16(size_t p) { return (p + 15) & ~(size_t)15; }
+
+// GT tile rows (16-lane groups) per workgroup, W waves, CX columns and RY rows
+// per lane, tsize bytes per sweep value, LX x LY input lattice.
+__host__ __device__ inline LdsOff lds_layout(int GT, int W, int CX, int tsize, int LX, int LY,
+                                             int RY)
+{
+    LdsOff o;
+    size_t p = 0;
+    // edges hold FP64 values for the residual stencils and T values later
+    o.edge = p; p = lds_align16(p + (size_t)2 * 2 * GT * 16 * CX * (tsize > 8 ? tsize : 8));
+    o.gx = p;   p = lds_align16(p + (size_t)LX * 16 * CX * 8);
+    o.gy = p;   p = lds_align16(p + (size_t)LY * GT * RY * 8);
+    o.gxf = p;  p = lds_align16(p + (size_t)LX * 16 * CX * 4);
+    o.gyf = p;  p = lds_align16(p + (size_t)LY * GT * RY * 4);
+    o.uvec = p; p = lds_align16(p + (size_t)kMaxM * 8);
+    o.v3 = p;   p = lds_align16(p + (size_t)kMaxM * 8);
+    o.kun = p;  p = lds_align16(p + (size_t)kMaxM * 8);
+    o.red = p;  p = lds_align16(p + (size_t)W * kMaxM * 8);
+    o.nrm = p;  p = lds_align16(p + (size_t)W * 4 * 8);
+    o.total = p;
+    return o;
+}
+
+// ry = 0 selects the default tile height for (prec, cx).
+const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);
 const void *init_kernel();
+const void *pad_kernel();
+const void *advance_kernel();
 const void *output_kernel();
 
 }  // namespace nmpc

@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -18,6 +19,7 @@ using nmpc::InitArgs;
 using nmpc::InstState;
 using nmpc::IterArgs;
 using nmpc::OutArgs;
+using nmpc::TileCfg;
 
 namespace {
 
@@ -46,43 +48,68 @@ struct nmpc_handle {
     nmpc_options opt{};
     int max_batch = 0;
     int n = 0, m = 0, N = 0;
-    int rows = 1, waves = 1;
+    int sx = 0, np = 0;                    // padded row stride (16 * CX), padded points per stage
+    struct Kern {
+        const void *fn = nullptr;
+        TileCfg cfg{};
+        int waves = 0;
+        size_t lds = 0;
+    } kern[2];                             // [kModeFp64], [kModeFp32]
     std::vector<double> gx, gy;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     double *d_gx = nullptr, *d_gy = nullptr;
     double *d_S[2] = {nullptr, nullptr};
     double *d_x0 = nullptr, *d_xref = nullptr, *d_out = nullptr;
-    unsigned long long *d_acc = nullptr;   // racc [3][B] then pacc [3][B]
+    unsigned long long *d_rst = nullptr;   // per-stage residual bits [2][3][B][N]
     InstState *d_st = nullptr;             // [2][B]
     int *d_iters = nullptr;                // [B]
     double *d_rfin = nullptr;              // [B][2]
     int *d_ctr = nullptr;                  // [4]
-    unsigned *d_wgdone = nullptr;
     int *h_poll = nullptr;                 // pinned
-    unsigned long long *d_units = nullptr; // evaluated (instance, stage) units
     bool timing = false;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double kernel_ms = 0.0;
     long long launches = 0;
-    unsigned long long units0 = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int graph_count = -1, graph_len = 0, graph_prec = -1;
-    size_t xref_len = 0;                   // elements of xref per instance
+    long long units = 0;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_count[2] = {-1, -1}, graph_len[2] = {0, 0};
+    size_t xref_len = 0;                   // padded xref elements per instance (device)
 
     double *X(int b) const { return d_S[b]; }
-    double *L(int b) const { return d_S[b] + (size_t)max_batch * N * n; }
-    double *U(int b) const { return d_S[b] + (size_t)2 * max_batch * N * n; }
+    double *L(int b) const { return d_S[b] + (size_t)max_batch * N * np; }
+    double *U(int b) const { return d_S[b] + (size_t)2 * max_batch * N * np; }
+    size_t xref_dense() const { return (size_t)n * (opt.xref_per_stage ? N : 1); }
 };
 
 namespace {
 
-int choose_rows(int nsy)
+int tile_cx(int nsx)
 {
-    for (int r : {1, 2, 4})
-        if ((nsy + r - 1) / r <= nmpc::kMaxWaves) return r;
-    return -1;
+    const int cx = (nsx + 15) / 16;
+    return cx == 5 ? 6 : cx;
+}
+
+// Pick the iteration kernel of precision `prec` for this grid and lattice.
+int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k)
+{
+    TileCfg cfg{};
+    const void *fn = nmpc::iterate_kernel(prec, tile_cx(p->nsx), ry, p->lx, p->ly, &cfg);
+    if (!fn && ry) return fail(NMPC_E_UNSUPPORTED, "no kernel instance with this tile height");
+    if (!fn) return fail(NMPC_E_UNSUPPORTED, "no kernel instance for this grid width / input lattice");
+    const int groups = (p->nsy + cfg.rows - 1) / cfg.rows;
+    const int waves = (groups + 3) / 4;
+    if (waves > cfg.max_waves)
+        return fail(NMPC_E_UNSUPPORTED, "grid too tall for the fused stage kernel");
+    if (k) {
+        k->fn = fn;
+        k->cfg = cfg;
+        k->waves = waves;
+        k->lds = nmpc::lds_layout(waves * 4, waves, cfg.cx, prec == nmpc::kModeFp32 ? 4 : 8,
+                                  p->lx, p->ly, cfg.rows).total;
+    }
+    return NMPC_OK;
 }
 
 int check_problem(const nmpc_problem *p)
@@ -102,13 +129,12 @@ int check_problem(const nmpc_problem *p)
         if (!std::isfinite(p->gx[t])) return fail(NMPC_E_ARG, "gx not finite");
     for (long long t = 0; t < (long long)p->ly * p->nsy; ++t)
         if (!std::isfinite(p->gy[t])) return fail(NMPC_E_ARG, "gy not finite");
-    if (p->nsx > nmpc::kWave || p->nsy > nmpc::kMaxRows || p->ly > nmpc::kMaxLy ||
-        p->lx * p->ly > nmpc::kMaxM)
-        return fail(NMPC_E_UNSUPPORTED, "fused stage kernel needs nsx <= 64, nsy <= 64, m <= 64");
-    const int rows = choose_rows(p->nsy);
-    if (rows < 0 || !nmpc::iterate_kernel(0, rows, p->lx, p->ly) ||
-        !nmpc::iterate_kernel(1, rows, p->lx, p->ly))
-        return fail(NMPC_E_UNSUPPORTED, "no kernel instance for this input lattice");
+    if (p->nsx > 16 * nmpc::kMaxCx || p->ly > nmpc::kMaxLy || p->lx * p->ly > nmpc::kMaxM)
+        return fail(NMPC_E_UNSUPPORTED, "fused stage kernel needs nsx <= 96, m <= 64");
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
+        const int rc = select_kernel(p, prec, 0, nullptr);
+        if (rc) return rc;
+    }
     return NMPC_OK;
 }
 
@@ -124,18 +150,21 @@ int check_options(const nmpc_options *o)
     if (o->check_every < 1 || o->check_every > 4096) return fail(NMPC_E_ARG, "bad check_every");
     if (o->xref_per_stage != 0 && o->xref_per_stage != 1)
         return fail(NMPC_E_ARG, "xref_per_stage must be 0 or 1");
+    if (o->tile_rows < 0 || o->tile_rows > 16) return fail(NMPC_E_ARG, "tile_rows must be 0..16");
     return NMPC_OK;
 }
 
 void release(nmpc_handle *h)
 {
     if (!h) return;
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (int q = 0; q < 2; ++q) {
+        if (h->gexec[q]) (void)hipGraphExecDestroy(h->gexec[q]);
+        if (h->graph[q]) (void)hipGraphDestroy(h->graph[q]);
+    }
     for (void *p : {(void *)h->d_gx, (void *)h->d_gy, (void *)h->d_S[0], (void *)h->d_S[1],
-                    (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_acc,
+                    (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
-                    (void *)h->d_wgdone, (void *)h->d_units})
+                    })
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -149,7 +178,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
 {
     IterArgs a{};
     const nmpc_problem &p = h->prob;
-    a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->n; a.P.N = h->N; a.P.m = h->m;
+    a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->np; a.P.N = h->N; a.P.m = h->m;
     a.P.lx = p.lx; a.P.ly = p.ly;
     a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
     const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
@@ -159,12 +188,12 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.gx = h->d_gx; a.gy = h->d_gy;
     a.x0 = h->d_x0; a.xref = h->d_xref;
     a.xref_inst_stride = (long long)h->xref_len;
-    a.xref_stage_stride = h->opt.xref_per_stage ? h->n : 0;
+    a.xref_stage_stride = h->opt.xref_per_stage ? h->np : 0;
     for (int b = 0; b < 2; ++b) { a.X[b] = h->X(b); a.U[b] = h->U(b); a.LAM[b] = h->L(b); }
-    a.racc = h->d_acc;
-    a.pacc = h->d_acc + 3 * (size_t)h->max_batch;
+    a.rst = h->d_rst;
+    a.pst = h->d_rst + 3 * (size_t)h->max_batch * h->N;
     a.st = h->d_st; a.iters = h->d_iters; a.rfin = h->d_rfin;
-    a.ctr = h->d_ctr; a.wgdone = h->d_wgdone; a.work_units = h->d_units;
+    a.ctr = h->d_ctr; a.kofs = 0;
     a.B = h->max_batch;
     a.units = count * h->N;
     a.per_xcd = (a.units + 7) / 8;
@@ -174,88 +203,125 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     return a;
 }
 
-int launch_iterate(nmpc_handle *h, const IterArgs &a, hipStream_t s)
+int launch_iterate(nmpc_handle *h, int prec, const IterArgs &a, hipStream_t s)
 {
-    const void *fn = nmpc::iterate_kernel(h->opt.precision, h->rows, h->prob.lx, h->prob.ly);
-    if (!fn) return fail(NMPC_E_UNSUPPORTED, "no kernel instance");
+    const nmpc_handle::Kern &k = h->kern[prec];
     void *args[] = {(void *)&a};
-    HIP_TRY(hipLaunchKernel(fn, dim3(8 * a.per_xcd), dim3(nmpc::kWave * h->waves), args, 0, s));
+    HIP_TRY(hipLaunchKernel(k.fn, dim3(8 * a.per_xcd), dim3(nmpc::kWave * k.waves), args, k.lds, s));
     return NMPC_OK;
 }
 
-int ensure_graph(nmpc_handle *h, int count)
+// Captured sequence of check_every launches of the precision-`prec` kernel.
+int ensure_graph(nmpc_handle *h, int prec, int count)
 {
     const int len = h->opt.check_every;
-    if (h->gexec && h->graph_count == count && h->graph_len == len &&
-        h->graph_prec == h->opt.precision)
+    if (h->gexec[prec] && h->graph_count[prec] == count && h->graph_len[prec] == len)
         return NMPC_OK;
-    if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
-    if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+    if (h->gexec[prec]) { (void)hipGraphExecDestroy(h->gexec[prec]); h->gexec[prec] = nullptr; }
+    if (h->graph[prec]) { (void)hipGraphDestroy(h->graph[prec]); h->graph[prec] = nullptr; }
     IterArgs a = iter_args(h, count);
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     int rc = NMPC_OK;
-    for (int t = 0; t < len && rc == NMPC_OK; ++t) rc = launch_iterate(h, a, h->stream);
+    for (int t = 0; t < len && rc == NMPC_OK; ++t) {
+        a.kofs = t;
+        rc = launch_iterate(h, prec, a, h->stream);
+    }
+    if (rc == NMPC_OK) {
+        int *ctr = h->d_ctr;
+        void *args[] = {(void *)&ctr, (void *)&len};
+        const hipError_t e = hipLaunchKernel(nmpc::advance_kernel(), dim3(1), dim3(64), args, 0,
+                                             h->stream);
+        if (e != hipSuccess) rc = fail(NMPC_E_DEVICE, std::string("advance: ") + hipGetErrorString(e));
+    }
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->stream, &g);
     if (rc != NMPC_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(NMPC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    h->graph = g;
-    HIP_TRY(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
-    h->graph_count = count; h->graph_len = len; h->graph_prec = h->opt.precision;
+    h->graph[prec] = g;
+    HIP_TRY(hipGraphInstantiate(&h->gexec[prec], g, nullptr, nullptr, 0));
+    h->graph_count[prec] = count; h->graph_len[prec] = len;
     return NMPC_OK;
 }
 
+int launch_grid(size_t tot) { return (int)std::min<size_t>((tot + 255) / 256 + 1, 8192); }
+
+// Dense device rows [rows][nsx] -> padded rows [rows][sx] in dst.
+int pad_rows(nmpc_handle *h, const double *src, double *dst, long long rows)
+{
+    int nsx = h->prob.nsx, sx = h->sx;
+    void *args[] = {(void *)&src, (void *)&dst, (void *)&rows, (void *)&nsx, (void *)&sx};
+    HIP_TRY(hipLaunchKernel(nmpc::pad_kernel(), dim3(launch_grid((size_t)rows * sx)), dim3(256),
+                            args, 0, h->stream));
+    return NMPC_OK;
+}
+
+// x0 [count][n] and xref [count][n or N*n] (dense, device) into the handle's
+// padded input buffers.
+int stage_inputs(nmpc_handle *h, int count, const double *x0, const double *xref)
+{
+    int rc = pad_rows(h, x0, h->d_x0, (long long)count * h->prob.nsy);
+    if (rc) return rc;
+    return pad_rows(h, xref, h->d_xref,
+                    (long long)count * h->prob.nsy * (h->opt.xref_per_stage ? h->N : 1));
+}
+
 // Run the upper iteration for `count` instances whose x0/xref already sit in
-// the handle's buffers; S^0 from the warm pointers (device) or cold.
+// the handle's buffers; S^0 from the warm pointers (device, dense) or cold.
 int run(nmpc_handle *h, int count, const double *wx, const double *wu, const double *wl,
         double *ox, double *ou, double *ol)
 {
     InitArgs ia{};
-    ia.count = count; ia.B = h->max_batch; ia.N = h->N; ia.n = h->n; ia.m = h->m;
-    ia.mode = h->opt.precision == NMPC_FP32_SWEEP ? 1 : 0;
+    ia.count = count; ia.B = h->max_batch; ia.N = h->N; ia.m = h->m;
+    ia.nsx = h->prob.nsx; ia.nsy = h->prob.nsy; ia.sx = h->sx;
+    ia.mode = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
     ia.x0 = h->d_x0; ia.wx = wx; ia.wu = wu; ia.wl = wl;
     ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
-    ia.st = h->d_st; ia.racc = h->d_acc; ia.pacc = h->d_acc + 3 * (size_t)h->max_batch;
-    ia.iters = h->d_iters; ia.ctr = h->d_ctr; ia.wgdone = h->d_wgdone;
+    ia.st = h->d_st;
+    ia.iters = h->d_iters; ia.ctr = h->d_ctr;
     {
         void *args[] = {(void *)&ia};
-        const size_t tot = (size_t)count * h->N * h->n;
-        const unsigned grid = (unsigned)std::min<size_t>((tot + 255) / 256 + 1, 8192);
-        HIP_TRY(hipLaunchKernel(nmpc::init_kernel(), dim3(grid), dim3(256), args, 0, h->stream));
+        HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
+                                dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
+                                0, h->stream));
     }
-    int rc = ensure_graph(h, count);
-    if (rc != NMPC_OK) return rc;
-    // Every instance finishes by kernel max_iter + 1 (+3 for the FP32 -> FP64
-    // switch and the correction step); later launches are no-ops.
-    const long long cap = (long long)h->opt.max_iter + 8 + h->graph_len;
+    // Phase FP32 (FP32-sweep precision) runs until no instance is left in
+    // FP32 mode, then phase FP64 until every instance has finished. Each
+    // phase ends by max_iter + 4 launches; launches after an instance has
+    // finished (or while it waits for the other phase) are no-ops for it.
+    int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
+    const long long cap = 2 * ((long long)h->opt.max_iter + 8 + h->opt.check_every);
     long long launched = 0;
     for (;;) {
+        int rc = ensure_graph(h, prec, count);
+        if (rc != NMPC_OK) return rc;
         if (h->timing) HIP_TRY(hipEventRecord(h->t0, h->stream));
-        HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+        HIP_TRY(hipGraphLaunch(h->gexec[prec], h->stream));
         if (h->timing) HIP_TRY(hipEventRecord(h->t1, h->stream));
-        launched += h->graph_len;
-        HIP_TRY(hipMemcpyAsync(h->h_poll, h->d_ctr + 2, sizeof(int), hipMemcpyDeviceToHost,
+        launched += h->graph_len[prec];
+        HIP_TRY(hipMemcpyAsync(h->h_poll, h->d_ctr + 2, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         if (h->timing) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
             h->kernel_ms += ms;
-            h->launches += h->graph_len;
+            h->launches += h->graph_len[prec];
         }
-        if (*h->h_poll >= count) break;
+        if (h->h_poll[0] >= count) break;
+        if (prec == nmpc::kModeFp32 && h->h_poll[1] <= 0) prec = nmpc::kModeFp64;
         if (launched > cap)
             return fail(NMPC_E_DEVICE, "instances did not finish within max_iter launches");
     }
     OutArgs oa{};
-    oa.count = count; oa.N = h->N; oa.n = h->n; oa.m = h->m; oa.iters = h->d_iters;
+    oa.count = count; oa.N = h->N; oa.m = h->m; oa.iters = h->d_iters;
+    oa.nsx = h->prob.nsx; oa.nsy = h->prob.nsy; oa.sx = h->sx;
     for (int b = 0; b < 2; ++b) { oa.X[b] = h->X(b); oa.U[b] = h->U(b); oa.LAM[b] = h->L(b); }
     oa.ox = ox; oa.ou = ou; oa.ol = ol;
     {
         void *args[] = {(void *)&oa};
-        const size_t tot = (size_t)count * h->N * h->n;
-        const unsigned grid = (unsigned)std::min<size_t>((tot + 255) / 256 + 1, 8192);
-        HIP_TRY(hipLaunchKernel(nmpc::output_kernel(), dim3(grid), dim3(256), args, 0, h->stream));
+        HIP_TRY(hipLaunchKernel(nmpc::output_kernel(),
+                                dim3(launch_grid((size_t)count * h->N * h->n)), dim3(256), args,
+                                0, h->stream));
     }
     return NMPC_OK;
 }
@@ -277,6 +343,7 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
     int worst = NMPC_OK;
     for (int b = 0; b < count; ++b) {
         const InstState &s = st[b].status != nmpc::kActive ? st[b] : st2[b];
+        if (h->timing) h->units += (long long)s.e * h->N;
         const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
         if (info) {
             info[b].r_scaled = rf[2 * b];
@@ -326,14 +393,21 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->n = prob->nsx * prob->nsy;
     h->m = prob->lx * prob->ly;
     h->N = prob->horizon;
-    h->rows = choose_rows(prob->nsy);
-    h->waves = (prob->nsy + h->rows - 1) / h->rows;
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
+        const int ry = prec == (opt->precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32
+                                                                   : nmpc::kModeFp64)
+                           ? opt->tile_rows : 0;
+        rc = select_kernel(prob, prec, ry, &h->kern[prec]);
+        if (rc) { delete h; return rc; }
+    }
     h->gx.assign(prob->gx, prob->gx + (size_t)prob->lx * prob->nsx);
     h->gy.assign(prob->gy, prob->gy + (size_t)prob->ly * prob->nsy);
     h->prob.gx = h->gx.data();
     h->prob.gy = h->gy.data();
-    h->xref_len = (size_t)h->n * (opt->xref_per_stage ? h->N : 1);
-    const size_t B = max_batch, S = B * h->N * (2 * (size_t)h->n + h->m);
+    h->sx = 16 * h->kern[nmpc::kModeFp64].cfg.cx;
+    h->np = h->sx * prob->nsy;
+    h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
+    const size_t B = max_batch, S = B * h->N * (2 * (size_t)h->np + h->m);
 #define ALLOC(ptr, bytes)                                                          \
     do {                                                                           \
         hipError_t e_ = hipMalloc((void **)&(ptr), (bytes));                       \
@@ -347,29 +421,33 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_gy, sizeof(double) * h->gy.size());
     ALLOC(h->d_S[0], sizeof(double) * S);
     ALLOC(h->d_S[1], sizeof(double) * S);
-    ALLOC(h->d_x0, sizeof(double) * B * h->n);
-    ALLOC(h->d_xref, sizeof(double) * B * (size_t)h->n * h->N);   // room for per-stage xref
+    ALLOC(h->d_x0, sizeof(double) * B * h->np);
+    ALLOC(h->d_xref, sizeof(double) * B * (size_t)h->np * h->N);   // room for per-stage xref
+    // dense staging of one instance (host-buffer solves): outputs, or x0 + xref
     ALLOC(h->d_out, sizeof(double) * (size_t)h->N * (2 * (size_t)h->n + h->m));
-    ALLOC(h->d_acc, sizeof(unsigned long long) * 6 * B);
+    ALLOC(h->d_rst, sizeof(unsigned long long) * 6 * B * h->N);
     ALLOC(h->d_st, sizeof(InstState) * 2 * B);
     ALLOC(h->d_iters, sizeof(int) * B);
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
-    ALLOC(h->d_wgdone, sizeof(unsigned));
-    ALLOC(h->d_units, sizeof(unsigned long long));
+
 #undef ALLOC
-    hipError_t e = hipHostMalloc((void **)&h->h_poll, sizeof(int), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(int), hipHostMallocDefault);
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32})
+        if (e == hipSuccess && h->kern[prec].lds > 48 * 1024)
+            e = hipFuncSetAttribute(h->kern[prec].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)h->kern[prec].lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&h->t0);
     if (e == hipSuccess) e = hipEventCreate(&h->t1);
-    if (e == hipSuccess) e = hipMemset(h->d_units, 0, sizeof(unsigned long long));
+
     if (e == hipSuccess)
         e = hipMemcpy(h->d_gx, h->gx.data(), sizeof(double) * h->gx.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(h->d_gy, h->gy.data(), sizeof(double) * h->gy.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(h->d_ctr, 0, sizeof(int) * 4);
-    if (e == hipSuccess) e = hipMemset(h->d_wgdone, 0, sizeof(unsigned));
+
     if (e != hipSuccess) {
         release(h);
         return fail(NMPC_E_DEVICE, std::string("create: ") + hipGetErrorString(e));
@@ -384,10 +462,24 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
     int rc = check_options(opt);
     if (rc) return rc;
+    nmpc_handle::Kern kn[2];
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
+        const int ry = prec == (opt->precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32
+                                                                   : nmpc::kModeFp64)
+                           ? opt->tile_rows : 0;
+        rc = select_kernel(&h->prob, prec, ry, &kn[prec]);
+        if (rc) return rc;
+    }
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32})
+        if (kn[prec].lds > 48 * 1024)
+            HIP_TRY(hipFuncSetAttribute(kn[prec].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)kn[prec].lds));
+    h->kern[0] = kn[0];
+    h->kern[1] = kn[1];
     if (opt->xref_per_stage != h->opt.xref_per_stage)
-        h->xref_len = (size_t)h->n * (opt->xref_per_stage ? h->N : 1);
+        h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
     h->opt = *opt;
-    h->graph_count = -1;   // recapture: tolerances and counts are kernel arguments
+    h->graph_count[0] = h->graph_count[1] = -1;   // recapture: options are kernel arguments
     return NMPC_OK;
 }
 
@@ -401,11 +493,16 @@ int nmpc_solve(nmpc_handle *h, const double *x0, const double *xref, const doubl
     const int nw = (warm_x != nullptr) + (warm_u != nullptr) + (warm_lam != nullptr);
     if (nw != 0 && nw != 3) return fail(NMPC_E_ARG, "warm start needs x, u and lambda");
     const size_t n = h->n, m = h->m, N = h->N;
-    HIP_TRY(hipMemcpyAsync(h->d_x0, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->d_xref, xref, sizeof(double) * h->xref_len, hipMemcpyHostToDevice,
-                           h->stream));
+    // dense x0 | xref staged in d_out, then padded into the input buffers
+    HIP_TRY(hipMemcpyAsync(h->d_out, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->d_out + n, xref, sizeof(double) * h->xref_dense(),
+                           hipMemcpyHostToDevice, h->stream));
+    {
+        const int rc = stage_inputs(h, 1, h->d_out, h->d_out + n);
+        if (rc) return rc;
+    }
     const double *wx = nullptr, *wu = nullptr, *wl = nullptr;
-    if (nw == 3) {   // stage the start in buffer 1 (overwritten by the first update)
+    if (nw == 3) {   // stage the dense start in buffer 1 (overwritten by the first update)
         HIP_TRY(hipMemcpyAsync(h->X(1), warm_x, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(h->L(1), warm_lam, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipMemcpyAsync(h->U(1), warm_u, sizeof(double) * N * m, hipMemcpyHostToDevice, h->stream));
@@ -435,11 +532,9 @@ int nmpc_solve_batch(nmpc_handle *h, int32_t count, const double *x0, const doub
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
-    HIP_TRY(hipMemcpyAsync(h->d_x0, x0, sizeof(double) * count * (size_t)h->n,
-                           hipMemcpyDeviceToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(h->d_xref, xref, sizeof(double) * count * h->xref_len,
-                           hipMemcpyDeviceToDevice, h->stream));
-    int rc = run(h, count, warm_x, warm_u, warm_lam, out_x, out_u, out_lam);
+    int rc = stage_inputs(h, count, x0, xref);
+    if (rc) return rc;
+    rc = run(h, count, warm_x, warm_u, warm_lam, out_x, out_u, out_lam);
     if (rc) return rc;
     std::vector<nmpc_info> tmp;
     if (!info) { tmp.resize(count); info = tmp.data(); }
@@ -457,24 +552,38 @@ int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const d
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
-    IterArgs a = iter_args(h, count);
-    a.x0 = x0; a.xref = xref;
-    a.X[0] = const_cast<double *>(x);
-    a.U[0] = const_cast<double *>(u);
-    a.LAM[0] = const_cast<double *>(lam);
-    a.residual_only = 1;
-    HIP_TRY(hipMemsetAsync(h->d_acc, 0, sizeof(unsigned long long) * 6 * h->max_batch, h->stream));
-    int rc = launch_iterate(h, a, h->stream);
+    int rc = stage_inputs(h, count, x0, xref);
     if (rc) return rc;
-    std::vector<unsigned long long> bits(2 * (size_t)count);
-    HIP_TRY(hipMemcpyAsync(bits.data(), a.racc, sizeof(unsigned long long) * count,
+    {   // trajectories into buffer 0 (padded), via the warm-start path of k_init
+        InitArgs ia{};
+        ia.count = count; ia.B = h->max_batch; ia.N = h->N; ia.m = h->m;
+        ia.nsx = h->prob.nsx; ia.nsy = h->prob.nsy; ia.sx = h->sx; ia.mode = nmpc::kModeFp64;
+        ia.x0 = h->d_x0; ia.wx = x; ia.wu = u; ia.wl = lam;
+        ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
+        ia.st = h->d_st; ia.iters = h->d_iters; ia.ctr = h->d_ctr;
+        void *args[] = {(void *)&ia};
+        HIP_TRY(hipLaunchKernel(nmpc::init_kernel(), dim3(launch_grid((size_t)count * h->N * h->np)),
+                                dim3(256), args, 0, h->stream));
+    }
+    IterArgs a = iter_args(h, count);
+    a.residual_only = 1;
+    rc = launch_iterate(h, nmpc::kModeFp64, a, h->stream);
+    if (rc) return rc;
+    const size_t per = (size_t)count * h->N;   // slot 0 of both arrays
+    std::vector<unsigned long long> bits(2 * per);
+    HIP_TRY(hipMemcpyAsync(bits.data(), a.rst, sizeof(unsigned long long) * per,
                            hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(bits.data() + count, a.pacc, sizeof(unsigned long long) * count,
+    HIP_TRY(hipMemcpyAsync(bits.data() + per, a.pst, sizeof(unsigned long long) * per,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int b = 0; b < count; ++b) {
-        std::memcpy(&r_scaled[b], &bits[b], sizeof(double));
-        std::memcpy(&r_paper[b], &bits[count + b], sizeof(double));
+        unsigned long long ms = 0, mp = 0;   // bit-pattern max: NaN above all finite values
+        for (int i = 0; i < h->N; ++i) {
+            ms = std::max(ms, bits[(size_t)b * h->N + i]);
+            mp = std::max(mp, bits[per + (size_t)b * h->N + i]);
+        }
+        std::memcpy(&r_scaled[b], &ms, sizeof(double));
+        std::memcpy(&r_paper[b], &mp, sizeof(double));
     }
     return NMPC_OK;
 }
@@ -511,7 +620,7 @@ int nmpc_timing_enable(nmpc_handle *h, int32_t enable)
     if (h->timing) {
         h->kernel_ms = 0.0;
         h->launches = 0;
-        HIP_TRY(hipMemcpy(&h->units0, h->d_units, sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        h->units = 0;
     }
     return NMPC_OK;
 }
@@ -520,11 +629,9 @@ int nmpc_timing_read(const nmpc_handle *h, double *kernel_ms, int64_t *launches,
 {
     g_err.clear();
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
-    unsigned long long u = 0;
-    HIP_TRY(hipMemcpy(&u, h->d_units, sizeof(unsigned long long), hipMemcpyDeviceToHost));
     if (kernel_ms) *kernel_ms = h->kernel_ms;
     if (launches) *launches = h->launches;
-    if (units) *units = (int64_t)(u - h->units0);
+    if (units) *units = (int64_t)h->units;
     return NMPC_OK;
 }
 
@@ -532,8 +639,9 @@ int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *wa
                        int32_t *workgroups)
 {
     if (!h) return NMPC_E_ARG;
-    if (rows_per_lane) *rows_per_lane = h->rows;
-    if (waves) *waves = h->waves;
+    const int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
+    if (rows_per_lane) *rows_per_lane = h->kern[prec].cfg.rows;
+    if (waves) *waves = h->kern[prec].waves;
     if (workgroups) *workgroups = 8 * ((h->max_batch * h->N + 7) / 8);
     return NMPC_OK;
 }

@@ -52,7 +52,7 @@ def test_1d_needs_single_row():
 
 
 def test_unsupported_shapes_reported():
-    p = make_problem("grid", ns=96, N=4)   # wider than one wavefront of columns
+    p = make_problem("grid", ns=100, N=4)   # wider than 16 lanes x 6 columns
     with pytest.raises(nm.NmpcError) as e:
         nm.nmpc_create(p, nm.nmpc_default_options(), 1)
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
@@ -64,7 +64,8 @@ def test_unsupported_shapes_reported():
 
 @pytest.mark.parametrize("field,value", [("n_sweep", 0), ("n_sweep", 17), ("n_schur", -1),
                                          ("precision", 7), ("check_every", 0),
-                                         ("max_iter", -1), ("tol", -1.0)])
+                                         ("max_iter", -1), ("tol", -1.0), ("tile_rows", -1),
+                                         ("tile_rows", 17)])
 def test_invalid_options_rejected(field, value):
     o = nm.nmpc_default_options(**{field: value})
     with pytest.raises(nm.NmpcError) as e:
@@ -78,3 +79,10 @@ def test_null_handle_calls():
     assert lib.nmpc_kernel_config(None, None, None, None) == nm.NMPC_E_ARG
     lib.nmpc_strerror.restype = ctypes.c_char_p
     assert b"argument" in lib.nmpc_strerror(1)
+
+
+def test_unknown_tile_height_is_unsupported():
+    o = nm.nmpc_default_options(tile_rows=3)
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(make_problem("c1"), o, 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
