@@ -93,6 +93,11 @@ typedef struct nmpc_options {
                              values select alternative kernel instances (as
                              chosen by the tile autotuner); unsupported values
                              give NMPC_E_UNSUPPORTED */
+    int32_t warm_sweeps;  /* point-Jacobi sweeps per stage when a start is
+                             built from an input trajectory (0 = 24) */
+    int32_t fallback;     /* 1: for a warm start, compare its residual with the
+                             cold start's per instance and keep the smaller
+                             (non-finite counts as larger) */
 } nmpc_options;
 
 /* Per-instance result information. */
@@ -102,7 +107,7 @@ typedef struct nmpc_info {
     int32_t iters;        /* k of the returned iterate S^k */
     int32_t status;       /* NMPC_OK, NMPC_E_NOCONV or NMPC_E_NONFINITE */
     int32_t fp32_iters;   /* iterations run with FP32 sweeps */
-    int32_t reserved;
+    int32_t start_used;   /* 0 cold, 1 given (x, u, lambda), 2 built from u */
 } nmpc_info;
 
 typedef struct nmpc_handle nmpc_handle;
@@ -125,7 +130,10 @@ int nmpc_set_options(nmpc_handle *hd, const nmpc_options *opt);
 /* Solve one instance, host buffers. x0, xref: [n] (xref [N][n] with
  * xref_per_stage). warm_x/warm_u/warm_lam: a start S^0 ([N][n], [N][m],
  * [N][n]); all three NULL selects the cold start x_i = x0, u_i = 0,
- * lambda_i = 0; any other mix is NMPC_E_ARG. out_* receive the returned
+ * lambda_i = 0. warm_x NULL with warm_u given builds the start from the
+ * input trajectory: states by the backward-Euler model (K^x = 0), costates by
+ * the adjoint recursion (K^lambda = 0, warm_lam, if given, is the sweeps'
+ * initial guess). warm_x without warm_u is NMPC_E_ARG. out_* receive the returned
  * iterate; info may be NULL. Returns the instance status (NMPC_OK,
  * NMPC_E_NOCONV, NMPC_E_NONFINITE) or an error code. Blocks until done. */
 int nmpc_solve(nmpc_handle *hd, const double *x0, const double *xref,
@@ -134,7 +142,7 @@ int nmpc_solve(nmpc_handle *hd, const double *x0, const double *xref,
 
 /* Solve count <= max_batch instances, DEVICE buffers with a leading instance
  * index (x0 [count][n], xref [count][n] or [count][N][n], warm_* and out_*
- * [count][N][...]; warm pointers all NULL = cold). Work is ordered after
+ * [count][N][...]; warm pointers as in nmpc_solve). Work is ordered after
  * everything already queued on `stream` (a hipStream_t, NULL = null stream)
  * and the call returns when the results are written. info: HOST array
  * [count] (may be NULL). Returns NMPC_OK if every instance converged,

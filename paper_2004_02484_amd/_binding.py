@@ -35,17 +35,19 @@ class nmpc_options(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("n_sweep", ctypes.c_int32), ("n_schur", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
-                ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32)]
+                ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32)]
 
 
 class nmpc_info(ctypes.Structure):
     _fields_ = [("r_scaled", ctypes.c_double), ("r_paper", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("fp32_iters", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("fp32_iters", ctypes.c_int32), ("start_used", ctypes.c_int32)]
 
     def as_dict(self):
         return {"r_scaled": self.r_scaled, "r_paper": self.r_paper, "iters": self.iters,
-                "status": self.status, "fp32_iters": self.fp32_iters}
+                "status": self.status, "fp32_iters": self.fp32_iters,
+                "start_used": self.start_used}
 
 
 class NmpcError(RuntimeError):
@@ -170,8 +172,9 @@ def nmpc_solve(hd, x0, xref, warm=None, *, n: int, m: int, N: int, xref_stages: 
     X = np.empty((N, n)); U = np.empty((N, m)); L = np.empty((N, n))
     ws = [None, None, None]
     if warm is not None:
-        ws = [_host(warm[0], N * n, "warm x"), _host(warm[1], N * m, "warm u"),
-              _host(warm[2], N * n, "warm lam")]
+        ws = [None if warm[0] is None else _host(warm[0], N * n, "warm x"),
+              None if warm[1] is None else _host(warm[1], N * m, "warm u"),
+              None if warm[2] is None else _host(warm[2], N * n, "warm lam")]
     info = nmpc_info()
     ptr = lambda a: None if a is None else a.ctypes.data
     rc = _load().nmpc_solve(hd, x0.ctypes.data, xref.ctypes.data, ptr(ws[0]), ptr(ws[1]),
@@ -214,8 +217,9 @@ def nmpc_solve_batch(hd, x0, xref, warm=None, out=None, *, n: int, m: int, N: in
           _dev(out[2], (B, N, n), "out lam")]
     pw = [None, None, None]
     if warm is not None:
-        pw = [_dev(warm[0], (B, N, n), "warm x"), _dev(warm[1], (B, N, m), "warm u"),
-              _dev(warm[2], (B, N, n), "warm lam")]
+        pw = [None if warm[0] is None else _dev(warm[0], (B, N, n), "warm x"),
+              None if warm[1] is None else _dev(warm[1], (B, N, m), "warm u"),
+              None if warm[2] is None else _dev(warm[2], (B, N, n), "warm lam")]
     infos = (nmpc_info * B)()
     rc = _load().nmpc_solve_batch(hd, B, px0, pxr, pw[0], pw[1], pw[2], po[0], po[1], po[2],
                                   infos, _stream())

@@ -59,11 +59,12 @@ struct IterArgs {
     int B, units, per_xcd;
     double tol;
     int max_iter, n_sw, n_schur;
-    int residual_only;
+    int residual_only, res_slot;
 };
 
 struct InitArgs {
     int count, B, N, nsx, nsy, sx, m, mode;
+    int trajectory_only;            // 1: write S^0 only, keep the iteration state
     const double *x0, *wx, *wu, *wl;
     double *X, *U, *LAM;
     InstState *st;
@@ -114,6 +115,9 @@ __host__ __device__ inline LdsOff lds_layout(int GT, int W, int CX, int tsize, i
 // ry = 0 selects the default tile height for (prec, cx).
 const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);
 const void *init_kernel();
+const void *choose_flags_kernel();
+const void *choose_copy_kernel();
+const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg);
 const void *pad_kernel();
 const void *advance_kernel();
 const void *output_kernel();

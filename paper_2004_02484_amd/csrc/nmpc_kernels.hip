@@ -684,7 +684,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
         const int b = unit / a.P.N, i = unit % a.P.N;
         Decision d;
         if (a.residual_only) {
-            d.work = true; d.j = 0; d.slot = 0;
+            d.work = true; d.j = 0; d.slot = a.res_slot;
         } else {
             d = decide<PREC>(a, c, b, i, k);
         }
@@ -707,6 +707,185 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             }
             __syncthreads();
             stage_body<T, CX, RY, LX, LY>(a, c, b, i, d.j, d.slot);
+        }
+    }
+}
+
+// Consistent start from an input trajectory u (already in buffer 0): the
+// states follow the backward-Euler model of eq. nlp, x_i = x_{i-1} + h f(u_i,
+// x_i), solved stage by stage (K^x_i = 0), and the costates follow the
+// adjoint recursion K^lam_i = 0 of Sec. 3.2 solved from i = N down to 1, i.e.
+// F_x^T lam_i = -(lam_{i+1} + h q (x_i - xref_i)). Both solves are point-Jacobi
+// sweeps in FP64 (for the state: on the implicit equation with k(x) taken at
+// the current sweep). The costate sweeps start from the lambda already in
+// buffer 0 (a supplied guess, or 0). One workgroup per instance.
+template <int CX, int RY, int WB, int LX, int LY>
+__global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Ctx c;
+    c.lds = lds_raw;
+    c.tid = threadIdx.x;
+    c.lane = c.tid & (kWave - 1);
+    c.cl = c.lane & 15;
+    c.w = c.tid / kWave;
+    c.W = blockDim.x / kWave;
+    c.G = c.w * 4 + (c.lane >> 4);
+    c.GT = c.W * 4;
+    c.Gv = (a.P.nsy + RY - 1) / RY;
+    c.flip = 0;
+    c.ax = a.P.idx2;
+    c.ay = a.P.idy2;
+    c.off = lds_layout(c.GT, c.W, CX, 8, LX, LY, RY);
+    const DevProblem &P = a.P;
+    constexpr int M = LX * LY;
+    const int b = blockIdx.x;
+    if (b >= a.units) return;
+    double *gx = lds_ptr<double>(c, c.off.gx);
+    double *gy = lds_ptr<double>(c, c.off.gy);
+    double *uvec = lds_ptr<double>(c, c.off.uvec);
+    for (int t = c.tid; t < LX * 16 * CX; t += blockDim.x) {
+        const int aa = t / (16 * CX), ix = t % (16 * CX);
+        gx[t] = ix < P.nsx ? a.gx[aa * P.nsx + ix] : 0.0;
+    }
+    for (int t = c.tid; t < LY * c.GT * RY; t += blockDim.x) {
+        const int bb = t / (c.GT * RY), iy = t % (c.GT * RY);
+        gy[t] = iy < P.nsy ? a.gy[bb * P.nsy + iy] : 0.0;
+    }
+    const int n = P.n, sx = 16 * CX;
+    const int ix0 = c.cl * CX, iy0 = c.G * RY;
+    auto valid = [&](int t, int q) { return ix0 + q < P.nsx && iy0 + t < P.nsy; };
+    auto pidx = [&](int t, int q) { return (iy0 + t) * sx + ix0 + q; };
+    const double h = P.h, kp = P.k0 * P.k1;
+    const int nsw = a.n_sw;
+
+    // ---- states, forward in the horizon
+    double xp[RY][CX];
+#pragma unroll
+    for (int t = 0; t < RY; ++t)
+#pragma unroll
+        for (int q = 0; q < CX; ++q) xp[t][q] = valid(t, q) ? a.x0[(size_t)b * n + pidx(t, q)] : 0.0;
+    for (int i = 0; i < P.N; ++i) {
+        const size_t unit = (size_t)b * P.N + i;
+        __syncthreads();   // previous stage's readers of uvec are done
+        if (c.tid < M) uvec[c.tid] = a.U[0][unit * M + c.tid];
+        __syncthreads();
+        double Bu[RY][CX], x[RY][CX];
+        b_apply<double, CX, RY, LX, LY>(uvec, c, Bu);
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) x[t][q] = xp[t][q];
+        for (int s = 0; s < nsw; ++s) {
+            double nb[RY][CX];
+            nbsum<double, CX, RY>(x, nb, c);
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q) {
+                    const double kk = P.k0 * (1.0 + P.k1 * x[t][q]);
+                    const double v = (xp[t][q] + h * kk * nb[t][q] + h * Bu[t][q]) /
+                                     (1.0 + h * kk * P.c0);
+                    x[t][q] = valid(t, q) ? v : 0.0;
+                }
+        }
+        double *Xo = a.X[0] + unit * n;
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) {
+                if (valid(t, q)) Xo[pidx(t, q)] = x[t][q];
+                xp[t][q] = x[t][q];
+            }
+    }
+    // ---- costates, backward in the horizon
+    double ln[RY][CX];
+#pragma unroll
+    for (int t = 0; t < RY; ++t)
+#pragma unroll
+        for (int q = 0; q < CX; ++q) ln[t][q] = 0.0;
+    for (int i = P.N - 1; i >= 0; --i) {
+        const size_t unit = (size_t)b * P.N + i;
+        const double *Xi = a.X[0] + unit * n;
+        double *Li = a.LAM[0] + unit * n;
+        const double *Xr = a.xref + (size_t)b * a.xref_inst_stride + (size_t)i * a.xref_stage_stride;
+        double x[RY][CX], Lx[RY][CX], lam[RY][CX];
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) {
+                x[t][q] = valid(t, q) ? Xi[pidx(t, q)] : 0.0;
+                lam[t][q] = valid(t, q) ? Li[pidx(t, q)] : 0.0;
+            }
+        nbsum<double, CX, RY>(x, Lx, c);
+        double cc[RY][CX], invd[RY][CX], cpk[RY][CX];
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) {
+                Lx[t][q] -= P.c0 * x[t][q];
+                const double kk = P.k0 * (1.0 + P.k1 * x[t][q]);
+                const double d = -1.0 - h * kk * P.c0 + h * kp * Lx[t][q];
+                invd[t][q] = valid(t, q) ? 1.0 / d : 0.0;
+                cpk[t][q] = h * kk;
+                const double xr = valid(t, q) ? Xr[pidx(t, q)] : 0.0;
+                cc[t][q] = valid(t, q) ? -(ln[t][q] + h * P.q * (x[t][q] - xr)) : 0.0;
+            }
+        for (int s = 0; s < nsw; ++s) {
+            double z[RY][CX], nb[RY][CX];
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q) z[t][q] = cpk[t][q] * lam[t][q];
+            nbsum<double, CX, RY>(z, nb, c);
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q) lam[t][q] = (cc[t][q] - nb[t][q]) * invd[t][q];
+        }
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) {
+                if (valid(t, q)) Li[pidx(t, q)] = lam[t][q];
+                ln[t][q] = lam[t][q];
+            }
+    }
+}
+
+// Fallback between two starts, per instance: keep buffer 0's start unless its
+// residual (slot 0) is non-finite or larger than that of the start in buffer
+// 1 (slot 1). start_used[b] = used_if_kept, or 0 (the buffer-1 start).
+__global__ void k_choose_flags(const IterArgs a, int *start_used, int used_if_kept)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.units) return;
+    const size_t N = a.P.N;
+    unsigned long long mw = 0, mc = 0;
+    for (size_t i = 0; i < N; ++i) {
+        mw = umax64(mw, a.rst[(size_t)b * N + i]);
+        mc = umax64(mc, a.rst[((size_t)a.B + b) * N + i]);
+    }
+    start_used[b] = (bits2d(mw) <= bits2d(mc)) ? used_if_kept : 0;
+}
+
+// Copy buffer 1's start over buffer 0 for the instances that fell back.
+__global__ void k_choose_copy(const IterArgs a, const int *start_used)
+{
+    const size_t np = a.P.n, N = a.P.N, m = a.P.m;
+    const size_t per = N * (2 * np + m);
+    const size_t tot = (size_t)a.units * per, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+        const size_t b = t / per, r = t % per;
+        if (start_used[b] != 0) continue;
+        if (r < N * np) {
+            a.X[0][b * N * np + r] = a.X[1][b * N * np + r];
+        } else if (r < 2 * N * np) {
+            const size_t q = r - N * np;
+            a.LAM[0][b * N * np + q] = a.LAM[1][b * N * np + q];
+        } else {
+            const size_t q = r - 2 * N * np;
+            a.U[0][b * N * m + q] = a.U[1][b * N * m + q];
         }
     }
 }
@@ -742,6 +921,7 @@ __global__ void k_init(const InitArgs a)
     }
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < mN; t += stride)
         a.U[t] = a.wu ? a.wu[t] : 0.0;
+    if (a.trajectory_only) return;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.count;
          t += stride) {
         InstState s;
@@ -844,7 +1024,45 @@ const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cf
 #undef NMPC_TILE
 #undef NMPC_OCC
 
+#define NMPC_ROLL(CX_, RY_, WB_)                                                    \
+    if (cx == CX_ && lx == LX_ && ly == LY_) {                                      \
+        cfg->cx = CX_; cfg->rows = RY_; cfg->max_waves = WB_;                       \
+        return (const void *)&k_rollout<CX_, RY_, WB_, LX_, LY_>;                    \
+    }
+#define NMPC_ROLL_LATTICE()                                                         \
+    NMPC_ROLL(1, 4, 4) NMPC_ROLL(2, 2, 8) NMPC_ROLL(3, 2, 8) NMPC_ROLL(4, 2, 8)     \
+    NMPC_ROLL(6, 2, 12)
+
+const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg)
+{
+#define LX_ 1
+#define LY_ 1
+    NMPC_ROLL_LATTICE()
+#undef LX_
+#undef LY_
+#define LX_ 2
+#define LY_ 1
+    NMPC_ROLL_LATTICE()
+#undef LX_
+#undef LY_
+#define LX_ 2
+#define LY_ 2
+    NMPC_ROLL_LATTICE()
+#undef LX_
+#undef LY_
+#define LX_ 4
+#define LY_ 4
+    NMPC_ROLL_LATTICE()
+#undef LX_
+#undef LY_
+    return nullptr;
+}
+#undef NMPC_ROLL_LATTICE
+#undef NMPC_ROLL
+
 const void *init_kernel() { return (const void *)&k_init; }
+const void *choose_flags_kernel() { return (const void *)&k_choose_flags; }
+const void *choose_copy_kernel() { return (const void *)&k_choose_copy; }
 const void *pad_kernel() { return (const void *)&k_pad; }
 const void *advance_kernel() { return (const void *)&k_advance; }
 const void *output_kernel() { return (const void *)&k_output; }

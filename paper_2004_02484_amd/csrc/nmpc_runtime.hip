@@ -55,6 +55,10 @@ struct nmpc_handle {
         int waves = 0;
         size_t lds = 0;
     } kern[2];                             // [kModeFp64], [kModeFp32]
+    Kern roll;                             // start built from an input trajectory
+    int *d_start = nullptr;                // [B] start used per instance
+    int last_start_kind = 0;
+    bool last_fallback = false;
     std::vector<double> gx, gy;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
@@ -151,6 +155,8 @@ int check_options(const nmpc_options *o)
     if (o->xref_per_stage != 0 && o->xref_per_stage != 1)
         return fail(NMPC_E_ARG, "xref_per_stage must be 0 or 1");
     if (o->tile_rows < 0 || o->tile_rows > 16) return fail(NMPC_E_ARG, "tile_rows must be 0..16");
+    if (o->warm_sweeps < 0 || o->warm_sweeps > 1000) return fail(NMPC_E_ARG, "warm_sweeps must be 0..1000");
+    if (o->fallback != 0 && o->fallback != 1) return fail(NMPC_E_ARG, "fallback must be 0 or 1");
     return NMPC_OK;
 }
 
@@ -164,6 +170,7 @@ void release(nmpc_handle *h)
     for (void *p : {(void *)h->d_gx, (void *)h->d_gy, (void *)h->d_S[0], (void *)h->d_S[1],
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
+                    (void *)h->d_start,
                     })
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
@@ -265,11 +272,33 @@ int stage_inputs(nmpc_handle *h, int count, const double *x0, const double *xref
                     (long long)count * h->prob.nsy * (h->opt.xref_per_stage ? h->N : 1));
 }
 
-// Run the upper iteration for `count` instances whose x0/xref already sit in
-// the handle's buffers; S^0 from the warm pointers (device, dense) or cold.
-int run(nmpc_handle *h, int count, const double *wx, const double *wu, const double *wl,
-        double *ox, double *ou, double *ol)
+enum { kStartCold = 0, kStartGiven = 1, kStartInputs = 2 };
+
+int start_kind(const double *wx, const double *wu, const double *wl)
 {
+    if (!wx && !wu && !wl) return kStartCold;
+    if (wx && wu && wl) return kStartGiven;
+    if (!wx && wu) return kStartInputs;
+    return -1;
+}
+
+int launch_residual(nmpc_handle *h, int count, int buf, int slot)
+{
+    IterArgs a = iter_args(h, count);
+    a.residual_only = 1;
+    a.res_slot = slot;
+    a.X[0] = h->X(buf); a.U[0] = h->U(buf); a.LAM[0] = h->L(buf);
+    return launch_iterate(h, nmpc::kModeFp64, a, h->stream);
+}
+
+// S^0 for `count` instances in buffer 0 (and the iteration state reset):
+// cold, given, or built from an input trajectory; with the fallback option a
+// warm start is replaced per instance by the cold one when its residual is
+// not smaller.
+int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
+                const double *wl)
+{
+    const int kind = start_kind(wx, wu, wl);
     InitArgs ia{};
     ia.count = count; ia.B = h->max_batch; ia.N = h->N; ia.m = h->m;
     ia.nsx = h->prob.nsx; ia.nsy = h->prob.nsy; ia.sx = h->sx;
@@ -283,6 +312,60 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
                                 dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
                                 0, h->stream));
+    }
+    if (kind == kStartInputs) {
+        IterArgs a = iter_args(h, count);
+        a.units = count;
+        a.n_sw = h->opt.warm_sweeps > 0 ? h->opt.warm_sweeps : 24;
+        void *args[] = {(void *)&a};
+        HIP_TRY(hipLaunchKernel(h->roll.fn, dim3(count), dim3(nmpc::kWave * h->roll.waves), args,
+                                h->roll.lds, h->stream));
+    }
+    h->last_start_kind = kind;
+    h->last_fallback = false;
+    if (kind != kStartCold && h->opt.fallback) {
+        int rc = launch_residual(h, count, 0, 0);
+        if (rc) return rc;
+        InitArgs ic = ia;   // cold start into buffer 1, iteration state untouched
+        ic.wx = ic.wu = ic.wl = nullptr;
+        ic.X = h->X(1); ic.U = h->U(1); ic.LAM = h->L(1);
+        ic.trajectory_only = 1;
+        {
+            void *args[] = {(void *)&ic};
+            HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
+                                    dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256),
+                                    args, 0, h->stream));
+        }
+        rc = launch_residual(h, count, 1, 1);
+        if (rc) return rc;
+        IterArgs a = iter_args(h, count);
+        a.units = count;
+        int *st = h->d_start;
+        int used = kind;
+        {
+            void *args[] = {(void *)&a, (void *)&st, (void *)&used};
+            HIP_TRY(hipLaunchKernel(nmpc::choose_flags_kernel(), dim3((count + 255) / 256),
+                                    dim3(256), args, 0, h->stream));
+        }
+        {
+            void *args[] = {(void *)&a, (void *)&st};
+            HIP_TRY(hipLaunchKernel(nmpc::choose_copy_kernel(),
+                                    dim3(launch_grid((size_t)count * h->N * (2 * h->np + h->m))),
+                                    dim3(256), args, 0, h->stream));
+        }
+        h->last_fallback = true;
+    }
+    return NMPC_OK;
+}
+
+// Run the upper iteration for `count` instances whose x0/xref already sit in
+// the handle's buffers; S^0 from the warm pointers (device, dense) or cold.
+int run(nmpc_handle *h, int count, const double *wx, const double *wu, const double *wl,
+        double *ox, double *ou, double *ol)
+{
+    {
+        const int rc = build_start(h, count, wx, wu, wl);
+        if (rc) return rc;
     }
     // Phase FP32 (FP32-sweep precision) runs until no instance is left in
     // FP32 mode, then phase FP64 until every instance has finished. Each
@@ -334,6 +417,10 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
     // the final state lives in the parity slot of the last kernel + 1; the
     // status is sticky once set, so read both slots and take the final one.
     std::vector<InstState> st2(count);
+    std::vector<int> used(count, h->last_start_kind);
+    if (h->last_fallback)
+        HIP_TRY(hipMemcpyAsync(used.data(), h->d_start, sizeof(int) * count, hipMemcpyDeviceToHost,
+                               h->stream));
     HIP_TRY(hipMemcpyAsync(iters.data(), h->d_iters, sizeof(int) * count, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(rf.data(), h->d_rfin, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(st.data(), h->d_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, h->stream));
@@ -351,7 +438,7 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
             info[b].iters = iters[b];
             info[b].status = status;
             info[b].fp32_iters = s.f32;
-            info[b].reserved = 0;
+            info[b].start_used = used[b];
         }
         if (status != NMPC_OK && worst == NMPC_OK) worst = status;
     }
@@ -372,6 +459,9 @@ void nmpc_default_options(nmpc_options *opt)
     opt->precision = NMPC_FP64;
     opt->check_every = 16;
     opt->xref_per_stage = 0;
+    opt->tile_rows = 0;
+    opt->warm_sweeps = 0;
+    opt->fallback = 0;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
@@ -404,6 +494,16 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->gy.assign(prob->gy, prob->gy + (size_t)prob->ly * prob->nsy);
     h->prob.gx = h->gx.data();
     h->prob.gy = h->gy.data();
+    {
+        TileCfg cfg{};
+        h->roll.fn = nmpc::rollout_kernel(tile_cx(prob->nsx), prob->lx, prob->ly, &cfg);
+        if (!h->roll.fn) { delete h; return fail(NMPC_E_UNSUPPORTED, "no rollout kernel instance"); }
+        h->roll.cfg = cfg;
+        h->roll.waves = (((prob->nsy + cfg.rows - 1) / cfg.rows) + 3) / 4;
+        if (h->roll.waves > cfg.max_waves) { delete h; return fail(NMPC_E_UNSUPPORTED, "grid too tall"); }
+        h->roll.lds = nmpc::lds_layout(h->roll.waves * 4, h->roll.waves, cfg.cx, 8, prob->lx,
+                                       prob->ly, cfg.rows).total;
+    }
     h->sx = 16 * h->kern[nmpc::kModeFp64].cfg.cx;
     h->np = h->sx * prob->nsy;
     h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
@@ -430,6 +530,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_iters, sizeof(int) * B);
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
+    ALLOC(h->d_start, sizeof(int) * B);
 
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(int), hipHostMallocDefault);
@@ -437,6 +538,9 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
         if (e == hipSuccess && h->kern[prec].lds > 48 * 1024)
             e = hipFuncSetAttribute(h->kern[prec].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)h->kern[prec].lds);
+    if (e == hipSuccess && h->roll.lds > 48 * 1024)
+        e = hipFuncSetAttribute(h->roll.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)h->roll.lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&h->t0);
@@ -490,8 +594,8 @@ int nmpc_solve(nmpc_handle *h, const double *x0, const double *xref, const doubl
     g_err.clear();
     if (!h || !x0 || !xref || !out_x || !out_u || !out_lam)
         return fail(NMPC_E_ARG, "NULL argument");
-    const int nw = (warm_x != nullptr) + (warm_u != nullptr) + (warm_lam != nullptr);
-    if (nw != 0 && nw != 3) return fail(NMPC_E_ARG, "warm start needs x, u and lambda");
+    if (start_kind(warm_x, warm_u, warm_lam) < 0)
+        return fail(NMPC_E_ARG, "warm start needs (x, u, lambda), u alone, or (u, lambda)");
     const size_t n = h->n, m = h->m, N = h->N;
     // dense x0 | xref staged in d_out, then padded into the input buffers
     HIP_TRY(hipMemcpyAsync(h->d_out, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
@@ -502,11 +606,20 @@ int nmpc_solve(nmpc_handle *h, const double *x0, const double *xref, const doubl
         if (rc) return rc;
     }
     const double *wx = nullptr, *wu = nullptr, *wl = nullptr;
-    if (nw == 3) {   // stage the dense start in buffer 1 (overwritten by the first update)
-        HIP_TRY(hipMemcpyAsync(h->X(1), warm_x, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(hipMemcpyAsync(h->L(1), warm_lam, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
-        HIP_TRY(hipMemcpyAsync(h->U(1), warm_u, sizeof(double) * N * m, hipMemcpyHostToDevice, h->stream));
-        wx = h->X(1); wu = h->U(1); wl = h->L(1);
+    // stage the dense start in the output staging area (read by k_init
+    // before anything writes d_out again)
+    double *stg = h->d_out;
+    if (warm_x) {
+        HIP_TRY(hipMemcpyAsync(stg, warm_x, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+        wx = stg;
+    }
+    if (warm_lam) {
+        HIP_TRY(hipMemcpyAsync(stg + N * n, warm_lam, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+        wl = stg + N * n;
+    }
+    if (warm_u) {
+        HIP_TRY(hipMemcpyAsync(stg + 2 * N * n, warm_u, sizeof(double) * N * m, hipMemcpyHostToDevice, h->stream));
+        wu = stg + 2 * N * n;
     }
     double *ox = h->d_out, *ol = h->d_out + N * n, *ou = h->d_out + 2 * N * n;
     int rc = run(h, 1, wx, wu, wl, ox, ou, ol);
@@ -527,8 +640,8 @@ int nmpc_solve_batch(nmpc_handle *h, int32_t count, const double *x0, const doub
     if (!h || !x0 || !xref || !out_x || !out_u || !out_lam)
         return fail(NMPC_E_ARG, "NULL argument");
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
-    const int nw = (warm_x != nullptr) + (warm_u != nullptr) + (warm_lam != nullptr);
-    if (nw != 0 && nw != 3) return fail(NMPC_E_ARG, "warm start needs x, u and lambda");
+    if (start_kind(warm_x, warm_u, warm_lam) < 0)
+        return fail(NMPC_E_ARG, "warm start needs (x, u, lambda), u alone, or (u, lambda)");
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));

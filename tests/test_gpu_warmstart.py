@@ -1,0 +1,102 @@
+"""GPU tests of starts built from an input trajectory and of the fallback.
+
+A start built from u must satisfy the state rows (backward-Euler model) and
+the costate rows (adjoint recursion) of the KKT conditions, checked with the
+oracle's KKT evaluation; only the input rows remain. From such a start the
+iteration reaches the same solution as from the cold start.
+"""
+import numpy as np
+import pytest
+
+from nmpc_inputs import make_instance, make_problem
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_02484_amd as nm
+    return nm
+
+
+@pytest.fixture(scope="module")
+def c1_case():
+    P = make_problem("c1")
+    x0, xref = make_instance(P, 21)
+    ex = oracle.solve(P, x0, xref, tol=1e-11, max_iter=20000)
+    assert ex["status"] == "converged"
+    return P, x0, xref, ex
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_input_built_start_satisfies_state_and_costate_rows(nm, name, c1_case):
+    if name == "c1":
+        P, x0, xref, ex = c1_case
+    else:
+        P = make_problem("c0")
+        x0, xref = make_instance(P, 4)
+        ex = oracle.solve(P, x0, xref, tol=1e-11, max_iter=20000)
+    rng = np.random.default_rng(3)
+    U = ex["U"] * (1.0 + 1e-2 * rng.standard_normal(ex["U"].shape))
+    s = nm.Solver(P, tol=0.0, max_iter=0, warm_sweeps=40)
+    rc, X, Uo, L, info = s.solve(x0, xref, warm=(None, U, None))
+    assert rc == nm.NMPC_E_NOCONV and info["iters"] == 0 and info["start_used"] == 2
+    np.testing.assert_array_equal(Uo, U)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, Uo, L)
+    assert np.abs(KX).max() <= 1e-12
+    assert np.abs(KL).max() / P.h <= 1e-10
+    # the input rows carry the perturbation: |K^u|/(h r) ~ |u - u*|
+    assert np.abs(KU).max() / (P.h * P.r) > 1e-4
+
+
+def test_input_start_converges_to_the_solution_faster(nm, c1_case):
+    P, x0, xref, ex = c1_case
+    rng = np.random.default_rng(4)
+    U = ex["U"] * (1.0 + 1e-3 * rng.standard_normal(ex["U"].shape))
+    s = nm.Solver(P)
+    rc_c, Xc, Uc, Lc, info_c = s.solve(x0, xref)
+    rc, X, Uw, L, info = s.solve(x0, xref, warm=(None, U, None))
+    assert rc == nm.NMPC_OK and rc_c == nm.NMPC_OK
+    err = np.abs(Uw - ex["U"]).max() / np.abs(ex["U"]).max()
+    print(f"cold {info_c['iters']} iterations, start from u (1e-3 noise) {info['iters']}, "
+          f"control rel. error vs exact {err:.2e}")
+    assert info["iters"] < info_c["iters"] // 2
+    assert err <= 1e-4
+    rs, _ = oracle.residual(P, x0, xref, X, Uw, L)
+    assert rs <= 1e-6
+
+
+def test_fallback_keeps_the_better_start(nm, c1_case):
+    P, x0, xref, ex = c1_case
+    s = nm.Solver(P, fallback=1)
+    bad = np.full_like(ex["U"], np.nan)
+    rc, X, U, L, info = s.solve(x0, xref, warm=(None, bad, None))
+    assert rc == nm.NMPC_OK and info["start_used"] == 0
+    huge = np.full_like(ex["U"], 1e6)
+    rc, X, U, L, info = s.solve(x0, xref, warm=(None, huge, None))
+    assert rc == nm.NMPC_OK and info["start_used"] == 0
+    good = ex["U"] * (1 + 1e-4)
+    rc, X, U, L, info = s.solve(x0, xref, warm=(None, good, None))
+    assert rc == nm.NMPC_OK and info["start_used"] == 2
+    rc, X, U, L, info = s.solve(x0, xref, warm=(ex["X"], ex["U"], ex["LAM"]))
+    assert rc == nm.NMPC_OK and info["start_used"] == 1 and info["iters"] == 0
+
+
+def test_batch_input_start_with_fallback(nm, c1_case):
+    import torch
+    P, x0, xref, ex = c1_case
+    B = 3
+    X0 = torch.tensor(np.stack([x0] * B), device="cuda")
+    XR = torch.tensor(np.stack([xref] * B), device="cuda")
+    U = np.stack([ex["U"] * (1 + 1e-3), np.full_like(ex["U"], np.nan), ex["U"]])
+    s = nm.Solver(P, max_batch=B, fallback=1)
+    rc, X, Uo, L, infos = s.solve_batch(X0, XR, warm=(None, torch.tensor(U, device="cuda"), None))
+    assert rc == nm.NMPC_OK
+    assert [i["start_used"] for i in infos] == [2, 0, 2]
+    for b in range(B):
+        err = np.abs(Uo[b].cpu().numpy() - ex["U"]).max() / np.abs(ex["U"]).max()
+        assert err <= 1e-4
