@@ -185,6 +185,67 @@ int nmpc_timing_enable(nmpc_handle *hd, int32_t enable);
 int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches,
                      int64_t *units);
 
+/* Set the calling thread's last-error text (used by the network calls). */
+void nmpc_set_last_error(const char *msg);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start: kernels of the patch-encoder network (trained on the
+ * GPU on solutions of the method itself). All pointers are DEVICE memory,
+ * work is queued on `stream` (hipStream_t, NULL = null stream) and the calls
+ * return without waiting. bf16 values are raw 16-bit patterns (uint16_t).
+ * Errors: NMPC_E_ARG for bad sizes/NULLs, NMPC_E_DEVICE for launch failures.
+ * ------------------------------------------------------------------------ */
+
+/* C[m][n] = beta C[m][n] + sum_k A(m,k) B(k,n) (+ bias[n]) (ReLU if relu),
+ * bf16 operands on the matrix cores with fp32 accumulation. A(m,k) is
+ * A[m*lda + k] (trans_a = 0) or A[k*lda + m]; B(k,n) is B[k*ldb + n]
+ * (trans_b = 0) or B[n*ldb + k]. C (fp32, may be NULL if Cb is given) and Cb
+ * (bf16 copy of the result, may be NULL). Forward layers use (0,0), data
+ * gradients (0,1), weight gradients (1,0). */
+int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
+                   const uint16_t *A, int32_t lda, const uint16_t *B, int32_t ldb, float beta,
+                   float *C, int32_t ldc, const float *bias, int32_t relu, uint16_t *Cb,
+                   int32_t ldcb, void *stream);
+
+/* Network input rows: for each instance and each actuator p = pb*L + pa of an
+ * L x L lattice on an ns x ns grid, a win x win window of x0/0.1 - 1 and of
+ * xref/0.3 (2 win^2 values, zero outside the grid) starting (win - ns/L)/2
+ * nodes before the actuator's cell, then a one-hot of p (L^2 values), then
+ * zeros up to ld. x0, xref: [count][ns*ns]; out: [count*L^2][ld] bf16;
+ * out_lo (may be NULL): bf16 of (value - out), the low part of a split. */
+int nmpc_net_windows(const double *x0, const double *xref, int32_t count, int32_t ns,
+                     int32_t lattice, int32_t win, uint16_t *out, uint16_t *out_lo, int32_t ld,
+                     void *stream);
+
+/* hi = bf16(x), lo = bf16(x - hi) (split operands for higher-precision products). */
+int nmpc_split_bf16(const float *x, uint16_t *hi, uint16_t *lo, int64_t n, void *stream);
+
+/* dh[i] = h[i] > 0 ? dh[i] : 0 (in place), dhb = bf16(dh). */
+int nmpc_relu_grad(float *dh, const float *h, uint16_t *dhb, int64_t n, void *stream);
+
+/* out[n] = sum_m A[m*lda + n] for n < N (bias gradients). */
+int nmpc_colsum(const float *A, int32_t M, int32_t N, int32_t lda, float *out, void *stream);
+
+/* dY = scale (Y - T) (fp32 and bf16, row stride lddy) and row_sse[m] =
+ * sum_n (Y - T)^2 for the M x N block. */
+int nmpc_mse_grad(const float *Y, int32_t ldy, const float *T, int32_t ldt, int32_t M, int32_t N,
+                  float scale, float *dY, uint16_t *dYb, int32_t lddy, float *row_sse, void *stream);
+
+/* Adam step `step` (>= 1) on fp32 weights w with gradient g and moments m, v
+ * (decoupled weight decay); wb (may be NULL) receives the bf16 copy of w. */
+int nmpc_adam(float *w, const float *g, float *m, float *v, uint16_t *wb, int64_t n, float lr,
+              float beta1, float beta2, float eps, float weight_decay, int32_t step, void *stream);
+
+/* y = bf16(x). */
+int nmpc_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream);
+
+/* Input trajectories u [count][N][m] (double) <-> per-actuator rows
+ * rows[(b*m + j)*ldr + i] = scale * u[b][i][j] (float). */
+int nmpc_pack_inputs(const double *u, int32_t count, int32_t N, int32_t m, float scale, float *rows,
+                     int32_t ldr, void *stream);
+int nmpc_unpack_inputs(const float *rows, int32_t ldr, int32_t count, int32_t N, int32_t m,
+                       float scale, double *u, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,52 @@
+// nmpc_net.h -- argument blocks of the warm-start network kernels (internal).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nmpc {
+
+struct GemmArgs {
+    int M, N, K;
+    const unsigned short *A;   // bf16
+    int lda;
+    const unsigned short *B;   // bf16
+    int ldb;
+    float beta;
+    float *C;                  // fp32 output (may be null)
+    int ldc;
+    const float *bias;         // [N] or null
+    int relu;
+    unsigned short *Cb;        // bf16 output (may be null)
+    int ldcb;
+};
+
+struct WinArgs {
+    const double *x0, *xref;   // [count][ns * ns]
+    int count, ns, L, win, ld;
+    unsigned short *out;       // [count * L * L][ld] bf16
+    unsigned short *out_lo;    // bf16 residual (value - out), may be null
+};
+
+struct AdamArgs {
+    float *w;
+    const float *g;
+    float *m, *v;
+    unsigned short *wb;        // bf16 copy (may be null)
+    long long n;
+    float lr, b1, b2, eps, wd;
+    int step;
+};
+
+const void *gemm_kernel(int ta, int tb);
+const void *windows_kernel();
+const void *relu_grad_kernel();
+const void *colsum_kernel();
+const void *mse_kernel();
+const void *adam_kernel();
+const void *to_bf16_kernel();
+const void *split_bf16_kernel();
+const void *pack_u_kernel();
+const void *unpack_u_kernel();
+
+}  // namespace nmpc

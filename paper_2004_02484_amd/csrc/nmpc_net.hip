@@ -1,0 +1,266 @@
+// nmpc_net.hip -- kernels of the learned warm start: a patch encoder mapping
+// (x0, xref) windows around each actuator to that actuator's input trajectory.
+//
+// Every layer is a GEMM on bf16 operands with fp32 accumulation on the matrix
+// cores (v_mfma_f32_16x16x16_bf16), so forward, data gradient and weight
+// gradient are the three operand layouts of one kernel:
+//   forward  C = X W          (A [M][K], B [K][N])
+//   dgrad    C = dY W^T       (B stored [N][K])
+//   wgrad    C = X^T dY       (A stored [K][M])
+// The small elementwise kernels (window gather, ReLU gradient, column sums,
+// squared-error gradient, Adam, layout packing) complete the training step.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nmpc_net.h"
+
+namespace nmpc {
+
+using bf16x4 = __attribute__((ext_vector_type(4))) short;
+using f32x4 = __attribute__((ext_vector_type(4))) float;
+
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    // round to nearest even; NaN stays NaN
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float((unsigned int)b << 16); }
+
+// ------------------------------------------------------------------- GEMM
+
+constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
+
+// C[m][n] = beta C + sum_k A(m, k) B(k, n) (+ bias[n]) (ReLU); outputs fp32 C
+// and/or bf16 Cb. A(m, k) = TA ? A[k lda + m] : A[m lda + k];
+// B(k, n) = TB ? B[n ldb + k] : B[k ldb + n]. Tails are zero-filled.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
+{
+    __shared__ unsigned short As[kBM][kBK + kPad];   // [m][k]
+    __shared__ unsigned short Bs[kBN][kBK + kPad];   // [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        // stage a 64 x 32 tile of A and of B^T (8 elements per thread each)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid * 8 + e;
+            int r, kk;
+            if (TA) { kk = idx / kBM; r = idx % kBM; }   // consecutive threads walk m
+            else    { r = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
+            const int gm = m0 + r, gk = k0 + kk;
+            unsigned short v = 0;
+            if (gm < g.M && gk < g.K) v = TA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
+            As[r][kk] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid * 8 + e;
+            int c, kk;
+            if (TB) { c = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
+            else    { kk = idx / kBN; c = idx % kBN; }   // consecutive threads walk n
+            const int gn = n0 + c, gk = k0 + kk;
+            unsigned short v = 0;
+            if (gn < g.N && gk < g.K) v = TB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
+            Bs[c][kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kBK; ks += 16) {
+            // fragments: lane l holds rows/cols l % 16, k = 4 (l / 16) .. +3
+            const int kq = ks + 4 * (lane >> 4);
+            bf16x4 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const unsigned short *p = &As[wm + i * 16 + (lane & 15)][kq];
+                af[i] = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const unsigned short *p = &Bs[wn + j * 16 + (lane & 15)][kq];
+                bfr[j] = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // result: lane l holds rows 4 (l / 16) + r, column l % 16 of each 16 x 16 block
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r;
+                const int gn = n0 + wn + j * 16 + (lane & 15);
+                if (gm >= g.M || gn >= g.N) continue;
+                float v = acc[i][j][r];
+                if (g.C && g.beta != 0.f) v += g.beta * g.C[(size_t)gm * g.ldc + gn];
+                if (g.bias) v += g.bias[gn];
+                if (g.relu) v = v > 0.f ? v : 0.f;
+                if (g.C) g.C[(size_t)gm * g.ldc + gn] = v;
+                if (g.Cb) g.Cb[(size_t)gm * g.ldcb + gn] = f2bf(v);
+            }
+}
+
+// ------------------------------------------------------------ elementwise
+
+// Windows of (x0 / 0.1 - 1, xref / 0.3) around each actuator of an L x L
+// lattice on an ns x ns grid (spacing s = ns / L, window win = 1.5 s, so a
+// window starts s/4 before the actuator's cell), followed by a one-hot
+// actuator index; zero outside the grid and in the padding up to ld.
+// Row (b, p) with p = pb * L + pa (the input index) of out [count * L^2][ld].
+__global__ void k_windows(const WinArgs a)
+{
+    const int rows = a.count * a.L * a.L;
+    const int feat = 2 * a.win * a.win;
+    const size_t tot = (size_t)rows * a.ld, stride = (size_t)gridDim.x * blockDim.x;
+    const int s = a.ns / a.L, off = (a.win - s) / 2;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+        const int row = (int)(t / a.ld), col = (int)(t % a.ld);
+        const int b = row / (a.L * a.L), p = row % (a.L * a.L);
+        float v = 0.f;
+        if (col < feat) {
+            const int ch = col / (a.win * a.win), r = col % (a.win * a.win);
+            const int wy = r / a.win, wx = r % a.win;
+            const int iy = (p / a.L) * s - off + wy, ix = (p % a.L) * s - off + wx;
+            if (iy >= 0 && iy < a.ns && ix >= 0 && ix < a.ns) {
+                const size_t g = (size_t)b * a.ns * a.ns + (size_t)iy * a.ns + ix;
+                v = ch == 0 ? float(a.x0[g] / 0.1 - 1.0) : float(a.xref[g] / 0.3);
+            }
+        } else if (col < feat + a.L * a.L) {
+            v = (col - feat) == p ? 1.f : 0.f;
+        }
+        const unsigned short hi = f2bf(v);
+        a.out[t] = hi;
+        if (a.out_lo) a.out_lo[t] = f2bf(v - bf2f(hi));
+    }
+}
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): products of split
+// operands (hi*hi + hi*lo + lo*hi) carry about 16 significant bits.
+__global__ void k_split_bf16(const float *x, unsigned short *hi, unsigned short *lo, long long n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n; t += stride) {
+        const unsigned short h = f2bf(x[t]);
+        hi[t] = h;
+        lo[t] = f2bf(x[t] - bf2f(h));
+    }
+}
+
+// dH = dH * (H > 0), also as bf16.
+__global__ void k_relu_grad(float *dh, const float *hact, unsigned short *dhb, long long n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n; t += stride) {
+        const float v = hact[t] > 0.f ? dh[t] : 0.f;
+        dh[t] = v;
+        dhb[t] = f2bf(v);
+    }
+}
+
+// out[n] = sum_m A[m][n] (one thread per column, fixed summation order).
+__global__ void k_colsum(const float *A, int M, int N, int lda, float *out)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += A[(size_t)m * lda + n];
+    out[n] = s;
+}
+
+// dY = scale (Y - T) (fp32 and bf16) and per-row squared-error partials.
+__global__ void k_mse(const float *Y, int ldy, const float *T, int ldt, int M, int N, float scale,
+                      float *dY, unsigned short *dYb, int lddy, float *row_sse)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    float s = 0.f;
+    for (int n = 0; n < N; ++n) {
+        const float e = Y[(size_t)m * ldy + n] - T[(size_t)m * ldt + n];
+        s += e * e;
+        const float g = scale * e;
+        dY[(size_t)m * lddy + n] = g;
+        dYb[(size_t)m * lddy + n] = f2bf(g);
+    }
+    row_sse[m] = s;
+}
+
+// Adam on fp32 master weights (decoupled weight decay), refreshing the bf16 copy.
+__global__ void k_adam(const AdamArgs a)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const float c1 = 1.f - powf(a.b1, (float)a.step), c2 = 1.f - powf(a.b2, (float)a.step);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.n; t += stride) {
+        const float g = a.g[t];
+        const float m = a.b1 * a.m[t] + (1.f - a.b1) * g;
+        const float v = a.b2 * a.v[t] + (1.f - a.b2) * g * g;
+        a.m[t] = m;
+        a.v[t] = v;
+        float w = a.w[t] * (1.f - a.lr * a.wd);
+        w -= a.lr * (m / c1) / (sqrtf(v / c2) + a.eps);
+        a.w[t] = w;
+        if (a.wb) a.wb[t] = f2bf(w);
+    }
+}
+
+__global__ void k_to_bf16(const float *x, unsigned short *y, long long n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n; t += stride)
+        y[t] = f2bf(x[t]);
+}
+
+// u [count][N][m] (double) <-> rows [count * m][ldr] of N values (float), scaled.
+__global__ void k_pack_u(const double *u, int count, int N, int m, float scale, float *rows, int ldr)
+{
+    const size_t tot = (size_t)count * N * m, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+        const size_t b = t / ((size_t)N * m), r = t % ((size_t)N * m);
+        const int i = (int)(r / m), j = (int)(r % m);
+        rows[(b * m + j) * ldr + i] = float(u[t]) * scale;
+    }
+}
+__global__ void k_unpack_u(const float *rows, int ldr, int count, int N, int m, float scale, double *u)
+{
+    const size_t tot = (size_t)count * N * m, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
+        const size_t b = t / ((size_t)N * m), r = t % ((size_t)N * m);
+        const int i = (int)(r / m), j = (int)(r % m);
+        u[t] = double(rows[(b * m + j) * ldr + i]) * scale;
+    }
+}
+
+const void *gemm_kernel(int ta, int tb)
+{
+    if (!ta && !tb) return (const void *)&k_gemm<false, false>;
+    if (!ta && tb) return (const void *)&k_gemm<false, true>;
+    if (ta && !tb) return (const void *)&k_gemm<true, false>;
+    return (const void *)&k_gemm<true, true>;
+}
+const void *windows_kernel() { return (const void *)&k_windows; }
+const void *relu_grad_kernel() { return (const void *)&k_relu_grad; }
+const void *colsum_kernel() { return (const void *)&k_colsum; }
+const void *mse_kernel() { return (const void *)&k_mse; }
+const void *adam_kernel() { return (const void *)&k_adam; }
+const void *to_bf16_kernel() { return (const void *)&k_to_bf16; }
+const void *split_bf16_kernel() { return (const void *)&k_split_bf16; }
+const void *pack_u_kernel() { return (const void *)&k_pack_u; }
+const void *unpack_u_kernel() { return (const void *)&k_unpack_u; }
+
+}  // namespace nmpc

@@ -724,6 +724,8 @@ const char *nmpc_strerror(int code)
 
 const char *nmpc_last_error(void) { return g_err.c_str(); }
 
+void nmpc_set_last_error(const char *msg) { g_err = msg ? msg : ""; }
+
 int nmpc_timing_enable(nmpc_handle *h, int32_t enable)
 {
     g_err.clear();
