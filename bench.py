@@ -1,15 +1,21 @@
-"""Benchmark: NMPC solves/s to KKT residual 1e-6 on the 64x64 grid, N = 40.
+"""Benchmark: NMPC solves/s to KKT residual 1e-6 on the 64x64 grid, N = 40,
+learned warm start vs the plain (cold) start.
 
 One step = one batch of 256 synthetic heat-process instances (64x64 interior
-nodes, 4x4 Gaussian actuator lattice, horizon 40, seeded x0 and reference),
-solved from the cold start to r_scaled <= 1e-6 by the double-layer Jacobi
-method on one GPU. Inputs for every step are generated and copied to HBM
-before the timed region; each step uses its own seeds.
+nodes, 4x4 Gaussian actuator lattice, horizon 40, seeded x0 and reference)
+solved to r_scaled <= 1e-6 by the double-layer Jacobi method on one GPU. With
+the learned start (the timed value) a step is: network inference on the
+matrix cores -> predicted input trajectories -> states by the backward-Euler
+rollout and costates by the adjoint recursion -> per-instance fallback to the
+cold start if that start's residual is worse -> Jacobi refinement. The same
+batches are then solved from the cold start for the comparison. Inputs for
+every step are generated and copied to HBM before the timed region; each step
+uses its own seeds, disjoint from the network's training seeds.
 
 Prints one JSON line with the metric, the roofline of the dominant kernel
 (the fused upper-iteration kernel, measured with HIP events on the library's
-stream over the timed region) and the CPU oracle timed on a bounded sample of
-the same workload.
+stream over the timed region), the network's matrix-core rate and the CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -29,6 +35,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 KERNEL_SRC = os.path.join(ROOT, "paper_2004_02484_amd", "csrc", "nmpc_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_c1_b256_traffic.json")
+WEIGHTS = os.path.join(ROOT, "paper_2004_02484_amd", "weights", "c1_patchnet.npz")
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 EVAL_SEED0 = 1_000_000         # disjoint from any training seeds
 
 
@@ -79,20 +87,51 @@ def cpu_baseline(P, x0s, xrefs, budget_s: float):
                       f"{dt:.1f} s"}
 
 
+def net_flops(net, count: int) -> float:
+    """Dense-layer flops of one inference over `count` instances (2 per MAC;
+    the split skip product counts its three bf16 products)."""
+    rows = count * net.m
+    return 2.0 * rows * (net.K0p * net.H + 2 * net.H * net.H + net.H * net.N + 3 * net.K0p * net.N)
+
+
+def timed_steps(solver, batches, out, net=None, ubuf=None):
+    """Solve each batch once (learned start if `net` is given); return per-step
+    wall times, iteration counts, starts used and the worst status."""
+    import torch
+    times, iters, used, worst = [], [], [], 0
+    torch.cuda.synchronize()
+    for x0, xr in batches:
+        t = time.perf_counter()
+        if net is not None:
+            up = net.predict(x0, xr, out=ubuf)
+            rc, X, U, L, infos = solver.solve_batch(x0, xr, warm=(None, up, None), out=out)
+        else:
+            rc, X, U, L, infos = solver.solve_batch(x0, xr, out=out)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        worst = max(worst, rc)
+        iters += [i["iters"] for i in infos]
+        used += [i["start_used"] for i in infos]
+    return times, iters, used, worst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--start", choices=["learned", "cold"], default="learned",
+                    help="start timed for the value (the other one is reported beside it)")
+    ap.add_argument("--weights", default=WEIGHTS)
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 disables)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -106,7 +145,14 @@ def main():
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
-                       check_every=16)
+                       check_every=16, fallback=1)
+    net = None
+    if args.start == "learned":
+        if not os.path.exists(args.weights):
+            raise SystemExit(f"{args.weights}: no trained network; run "
+                             f"python -m paper_2004_02484_amd.train_warmstart --out {args.weights}")
+        from paper_2004_02484_amd.warmstart import PatchNet
+        net = PatchNet.load(args.weights, device="cuda")
 
     nb = args.warmup + args.steps
     host = [make_batch(P, range(EVAL_SEED0 + s * B, EVAL_SEED0 + (s + 1) * B)) for s in range(nb)]
@@ -114,26 +160,23 @@ def main():
     out = (torch.empty((B, P.N, P.n), dtype=torch.float64, device=dev),
            torch.empty((B, P.N, P.m), dtype=torch.float64, device=dev),
            torch.empty((B, P.N, P.n), dtype=torch.float64, device=dev))
+    ubuf = torch.empty((B, P.N, P.m), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    for s in range(args.warmup):
-        solver.solve_batch(*dev_in[s], out=out)
-    torch.cuda.synchronize()
+    # warmup: graphs, network buffers, both starts
+    timed_steps(solver, dev_in[:args.warmup], out, net, ubuf)
+    if net is not None:
+        timed_steps(solver, dev_in[:args.warmup], out)
 
+    # timed region: exactly K steps with the selected start
     solver.timing_enable(True)
-    iters = []
-    worst = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.warmup, nb):
-        rc, X, U, L, infos = solver.solve_batch(*dev_in[s], out=out)
-        worst = max(worst, rc)
-        iters += [i["iters"] for i in infos]
+    times, iters, used, worst = timed_steps(solver, dev_in[args.warmup:], out, net, ubuf)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    elapsed = time.perf_counter() - t0
     tm = solver.timing_read()
     solver.timing_enable(False)
-    elapsed = t1 - t0
 
     if args.copy_calibration:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
@@ -156,19 +199,52 @@ def main():
             "units_per_launch": round(units_per_launch, 1),
             "bytes_per_unit": bpu}
 
+    start_desc = "learned warm start (network + rollout + adjoint, cold fallback)" \
+        if net is not None else "cold start"
+    cfg = {"workload": "2D nonlinear heat 64x64, N=40, 16 Gaussian inputs, batch 256, "
+                       f"{start_desc}, tol 1e-6",
+           "global_batch": B, "grid": "64x64", "horizon": P.N, "start": args.start,
+           "iters_min": int(min(iters)), "iters_max": int(max(iters)),
+           "iters_mean": round(float(np.mean(iters)), 1), "status_worst": worst,
+           "step_ms_median": round(1e3 * float(np.median(times)), 2),
+           "step_ms_min": round(1e3 * min(times), 2)}
+    if net is not None:
+        # the plain (cold) start on the same batches, same solver settings
+        ct, citers, _, cworst = timed_steps(solver, dev_in[args.warmup:], out)
+        plain = solves / sum(ct)
+        cfg.update({"starts_used": {k: int(v) for k, v in
+                                    zip(("cold", "given", "from_inputs"),
+                                        np.bincount(used, minlength=3))},
+                    "plain_solves_per_s": round(plain, 2),
+                    "plain_iters_mean": round(float(np.mean(citers)), 1),
+                    "plain_status_worst": cworst,
+                    "speedup_vs_plain": round(value / plain, 3)})
+        # network rate on the matrix cores (inference only)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            net.predict(*dev_in[args.warmup], out=ubuf)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = net_flops(net, B) / (ms * 1e-3) / 1e12
+        cfg["network"] = {"inference_ms": round(ms, 3), "params": int(sum(v.numel() for v in net.params.values())),
+                          "mfma": {"bound": "mfma", "achieved": round(tf, 2),
+                                   "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)},
+                          "weights": os.path.relpath(args.weights, ROOT),
+                          "val_rel_err_median": net.meta.get("val_rel_err_median")}
+
     result = {
-        "metric": "NMPC solves/s to KKT res 1e-6, 64x64 grid N=40 (batch 256, cold start)",
+        "metric": "NMPC solves/s to KKT res 1e-6, 64x64 grid N=40: learned warm start vs plain",
         "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32 sweeps, f64 state/residual" if prec == nm.NMPC_FP32_SWEEP else "f64",
         "data": "synthetic",
-        "config": {"workload": "2D nonlinear heat 64x64, N=40, 16 Gaussian inputs, "
-                               "batch 256, cold start, tol 1e-6",
-                   "global_batch": B, "grid": "64x64", "horizon": P.N,
-                   "iters_min": int(min(iters)), "iters_max": int(max(iters)),
-                   "iters_mean": round(float(np.mean(iters)), 1), "status_worst": worst},
+        "config": cfg,
         "roofline": roof,
     }
     if args.cpu_budget > 0:

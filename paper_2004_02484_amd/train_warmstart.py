@@ -1,6 +1,6 @@
 """Train the warm-start network on solutions computed by the solver itself.
 
-    python -m paper_2004_02484_amd.train_warmstart --samples 20480 --epochs 40 \\
+    python -m paper_2004_02484_amd.train_warmstart --samples 40960 --epochs 120 \\
         --out paper_2004_02484_amd/weights/c1_patchnet.npz
 
 Data: instances of the 64x64, N=40 workload (seeds 0..samples-1) solved on the
@@ -46,7 +46,7 @@ def rel_errors(net, x0, xr, u, batch=256):
     return np.concatenate(errs)
 
 
-def train(samples=20480, val=1024, epochs=40, batch=256, lr=1e-3, wd=1e-5, hidden=512, seed=0,
+def train(samples=40960, val=1024, epochs=120, batch=256, lr=1e-3, wd=1e-5, hidden=512, seed=0,
           log=print):
     import torch
     from nmpc_inputs import make_problem
@@ -86,9 +86,9 @@ def train(samples=20480, val=1024, epochs=40, batch=256, lr=1e-3, wd=1e-5, hidde
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--samples", type=int, default=20480)
+    ap.add_argument("--samples", type=int, default=40960)
     ap.add_argument("--val", type=int, default=1024)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=120)
     ap.add_argument("--hidden", type=int, default=512)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--out", required=True)

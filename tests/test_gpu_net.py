@@ -109,3 +109,38 @@ def test_training_steps_reduce_the_loss(ws):
         loss, g = net.loss_and_grads(dx0, dxr, u_t)
         net.adam_step(g, lr=2e-3)
     assert loss < 0.2 * first
+
+
+def test_trained_network_cuts_iterations_without_moving_the_solution(ws):
+    """The committed network on unseen instances: the learned start needs far
+    fewer upper iterations than the cold start, is never replaced by the
+    fallback, and the converged inputs agree with the cold-start solution and
+    with the oracle's exact solution."""
+    import os
+    import torch
+    import paper_2004_02484_amd as nm
+    import oracle
+    path = os.path.join(os.path.dirname(ws.__file__), "weights", "c1_patchnet.npz")
+    net = ws.PatchNet.load(path)
+    P = make_problem("c1")
+    seeds = list(range(2_000_000, 2_000_016))          # disjoint from the training seeds
+    x0, xr = make_batch(P, seeds)
+    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
+    s = nm.Solver(P, max_batch=len(seeds), precision=nm.NMPC_FP32_SWEEP, fallback=1)
+    rc_c, Xc, Uc, Lc, ic = s.solve_batch(dx0, dxr)
+    up = net.predict(dx0, dxr)
+    rc_l, Xl, Ul, Ll, il = s.solve_batch(dx0, dxr, warm=(None, up, None))
+    assert rc_c == nm.NMPC_OK and rc_l == nm.NMPC_OK
+    itc = np.array([i["iters"] for i in ic]); itl = np.array([i["iters"] for i in il])
+    pred = ((up - Uc).abs().amax(dim=(1, 2)) / Uc.abs().amax(dim=(1, 2))).cpu().numpy()
+    print(f"cold iterations {itc.mean():.1f}, learned {itl.mean():.1f} "
+          f"(min {itl.min()}, max {itl.max()}); prediction error median {np.median(pred):.2e}")
+    assert all(i["start_used"] == 2 for i in il)
+    assert np.median(pred) <= 1e-2
+    assert itl.mean() <= 0.6 * itc.mean()
+    du = ((Ul - Uc).abs().amax(dim=(1, 2)) / Uc.abs().amax(dim=(1, 2))).max().item()
+    assert du <= 1e-4
+    ex = oracle.solve(P, x0[0], xr[0], tol=1e-11, max_iter=20000)
+    assert ex["status"] == "converged"
+    err = np.abs(Ul[0].cpu().numpy() - ex["U"]).max() / np.abs(ex["U"]).max()
+    assert err <= 1e-4
