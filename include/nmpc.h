@@ -188,6 +188,62 @@ int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches
 /* Set the calling thread's last-error text (used by the network calls). */
 void nmpc_set_last_error(const char *msg);
 
+/* Tile autotuner: time `iters` upper iterations (1..1000) of this batch from
+ * the cold start (DEVICE x0 [count][n], xref [count][n]) with every tile
+ * height that the kernel table holds for the problem's grid width in the
+ * handle's main precision, keep the fastest as the handle's tile_rows and
+ * return it in *tile_rows (may be NULL). The timing runs' results are
+ * discarded; stream as in nmpc_solve_batch. */
+int nmpc_autotune(nmpc_handle *hd, int32_t count, const double *x0, const double *xref,
+                  int32_t iters, void *stream, int32_t *tile_rows);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches: instances of several problem classes (grid sizes,
+ * horizons, steps, input factors) solved together, one kernel launch per
+ * upper iteration over all of their (instance, stage) units, replayed as a
+ * captured graph of check_every launches; each instance keeps its own
+ * convergence state (as in nmpc_solve_batch). Classes are 2D problems with the
+ * 4 x 4 input lattice and nsx, nsy <= 96.
+ * ------------------------------------------------------------------------ */
+typedef struct nmpc_ragged nmpc_ragged;
+
+/* Create for nclass (1..64) classes (copied) and up to max_instances
+ * instances per solve. opt as for nmpc_create; xref_per_stage must be 0;
+ * tile_rows, warm_sweeps and fallback are not used. Device trajectory
+ * buffers are sized at the first solve and grow on demand. */
+int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_options *opt,
+                       int32_t max_instances, nmpc_ragged **out);
+
+/* Solve count instances; cls: HOST [count] class of each instance. DEVICE
+ * buffers, packed in instance order: x0 and xref n_b values per instance
+ * (n_b = nsx * nsy of its class), warm_x / warm_lam / out_x / out_lam N_b * n_b,
+ * warm_u / out_u N_b * m. The warm pointers are all NULL (cold start) or all
+ * given. info: HOST [count] or NULL. Ordering, blocking and return value as
+ * in nmpc_solve_batch. */
+int nmpc_ragged_solve(nmpc_ragged *rg, int32_t count, const int32_t *cls, const double *x0,
+                      const double *xref, const double *warm_x, const double *warm_u,
+                      const double *warm_lam, double *out_x, double *out_u, double *out_lam,
+                      nmpc_info *info, void *stream);
+
+/* Workgroup-size autotuner: for the set of classes in this batch, time
+ * `iters` (1..1000) upper iterations from the cold start with each
+ * workgroup size of the ragged kernel (8, 12 or 16 waves) whose tiles fit
+ * every class, remember the fastest for later solves of batches with the
+ * same class set and return it in *waves (may be NULL). */
+int nmpc_ragged_autotune(nmpc_ragged *rg, int32_t count, const int32_t *cls, const double *x0,
+                         const double *xref, int32_t iters, void *stream, int32_t *waves);
+
+/* Workgroup size (waves) a solve of a batch with these classes would use. */
+int nmpc_ragged_config(const nmpc_ragged *rg, int32_t count, const int32_t *cls, int32_t *waves);
+
+/* Kernel timing of later ragged solves, as nmpc_timing_enable/read. */
+int nmpc_ragged_timing_enable(nmpc_ragged *rg, int32_t enable);
+int nmpc_ragged_timing_read(const nmpc_ragged *rg, double *kernel_ms, int64_t *launches,
+                            int64_t *units);
+
+/* Release the ragged solver. NULL is ignored. */
+void nmpc_ragged_destroy(nmpc_ragged *rg);
+
 /* ---------------------------------------------------------------------------
  * Learned warm start: kernels of the patch-encoder network (trained on the
  * GPU on solutions of the method itself). All pointers are DEVICE memory,

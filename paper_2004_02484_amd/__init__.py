@@ -18,13 +18,22 @@ from ._binding import (  # noqa: F401
     NMPC_FP64,
     NMPC_OK,
     NmpcError,
+    RaggedSolver,
     Solver,
     library_path,
+    nmpc_autotune,
     nmpc_create,
     nmpc_default_options,
     nmpc_destroy,
     nmpc_kernel_config,
     nmpc_last_error,
+    nmpc_ragged_autotune,
+    nmpc_ragged_config,
+    nmpc_ragged_create,
+    nmpc_ragged_destroy,
+    nmpc_ragged_solve,
+    nmpc_ragged_timing_enable,
+    nmpc_ragged_timing_read,
     nmpc_residual_batch,
     nmpc_set_options,
     nmpc_solve,

@@ -102,6 +102,29 @@ def _load():
                                      ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.nmpc_timing_read.restype = ctypes.c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.nmpc_autotune.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, i32p]
+    lib.nmpc_autotune.restype = ctypes.c_int
+    lib.nmpc_ragged_create.argtypes = [ctypes.POINTER(nmpc_problem), ctypes.c_int32,
+                                       ctypes.POINTER(nmpc_options), ctypes.c_int32,
+                                       ctypes.POINTER(vp)]
+    lib.nmpc_ragged_create.restype = ctypes.c_int
+    lib.nmpc_ragged_solve.argtypes = [vp, ctypes.c_int32, i32p, vp, vp, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(nmpc_info), vp]
+    lib.nmpc_ragged_solve.restype = ctypes.c_int
+    lib.nmpc_ragged_autotune.argtypes = [vp, ctypes.c_int32, i32p, vp, vp, ctypes.c_int32, vp,
+                                         i32p]
+    lib.nmpc_ragged_autotune.restype = ctypes.c_int
+    lib.nmpc_ragged_config.argtypes = [vp, ctypes.c_int32, i32p, i32p]
+    lib.nmpc_ragged_config.restype = ctypes.c_int
+    lib.nmpc_ragged_timing_enable.argtypes = [vp, ctypes.c_int32]
+    lib.nmpc_ragged_timing_enable.restype = ctypes.c_int
+    lib.nmpc_ragged_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(ctypes.c_int64)]
+    lib.nmpc_ragged_timing_read.restype = ctypes.c_int
+    lib.nmpc_ragged_destroy.argtypes = [vp]
+    lib.nmpc_ragged_destroy.restype = None
     _lib = lib
     return lib
 
@@ -265,6 +288,97 @@ def nmpc_timing_read(hd):
     return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
 
 
+def nmpc_autotune(hd, x0, xref, iters: int = 8, *, n: int, m: int, N: int,
+                  xref_stages: bool = False) -> int:
+    """Time the tile heights on this batch; returns the chosen tile_rows."""
+    B = x0.shape[0]
+    if xref_stages:
+        raise ValueError("nmpc_autotune takes one xref per instance")
+    tr = ctypes.c_int32()
+    rc = _load().nmpc_autotune(hd, B, _dev(x0, (B, n), "x0"), _dev(xref, (B, n), "xref"),
+                               int(iters), _stream(), ctypes.byref(tr))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_autotune")
+    return tr.value
+
+
+def nmpc_ragged_create(classes, options: nmpc_options, max_instances: int):
+    """classes: problem objects as for nmpc_create. Returns (handle, keep-alive)."""
+    prs = [_Problem(c) for c in classes]
+    arr = (nmpc_problem * len(prs))(*[p.s for p in prs])
+    hd = ctypes.c_void_p()
+    rc = _load().nmpc_ragged_create(arr, len(prs), ctypes.byref(options), int(max_instances),
+                                    ctypes.byref(hd))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_ragged_create")
+    return hd, prs
+
+
+def _cls_array(cls):
+    c = np.ascontiguousarray(cls, dtype=np.int32)
+    return c, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def nmpc_ragged_solve(hd, cls, x0, xref, warm, out, sizes):
+    """Packed device tensors (1-D float64): x0, xref, out = (x, u, lam), warm
+    None or (x, u, lam). sizes = (sum n_b, sum N_b n_b, sum N_b m)."""
+    nx, nS, nU = sizes
+    c, cp = _cls_array(cls)
+    px0 = _dev(x0, (nx,), "x0")
+    pxr = _dev(xref, (nx,), "xref")
+    po = [_dev(out[0], (nS,), "out x"), _dev(out[1], (nU,), "out u"),
+          _dev(out[2], (nS,), "out lam")]
+    pw = [None, None, None]
+    if warm is not None:
+        pw = [_dev(warm[0], (nS,), "warm x"), _dev(warm[1], (nU,), "warm u"),
+              _dev(warm[2], (nS,), "warm lam")]
+    infos = (nmpc_info * len(c))()
+    rc = _load().nmpc_ragged_solve(hd, len(c), cp, px0, pxr, pw[0], pw[1], pw[2], po[0], po[1],
+                                   po[2], infos, _stream())
+    if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
+        raise NmpcError(rc, "nmpc_ragged_solve")
+    return rc, [i.as_dict() for i in infos]
+
+
+def nmpc_ragged_autotune(hd, cls, x0, xref, nx: int, iters: int = 8) -> int:
+    c, cp = _cls_array(cls)
+    w = ctypes.c_int32()
+    rc = _load().nmpc_ragged_autotune(hd, len(c), cp, _dev(x0, (nx,), "x0"),
+                                      _dev(xref, (nx,), "xref"), int(iters), _stream(),
+                                      ctypes.byref(w))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_ragged_autotune")
+    return w.value
+
+
+def nmpc_ragged_config(hd, cls) -> int:
+    c, cp = _cls_array(cls)
+    w = ctypes.c_int32()
+    rc = _load().nmpc_ragged_config(hd, len(c), cp, ctypes.byref(w))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_ragged_config")
+    return w.value
+
+
+def nmpc_ragged_timing_enable(hd, enable: bool = True) -> None:
+    rc = _load().nmpc_ragged_timing_enable(hd, 1 if enable else 0)
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_ragged_timing_enable")
+
+
+def nmpc_ragged_timing_read(hd):
+    ms = ctypes.c_double(); la = ctypes.c_int64(); un = ctypes.c_int64()
+    rc = _load().nmpc_ragged_timing_read(hd, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_ragged_timing_read")
+    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
+
+
+def nmpc_ragged_destroy(hd) -> None:
+    if hd:
+        _load().nmpc_ragged_destroy(hd)
+
+
 # ------------------------------------------------------------- convenience
 
 class Solver:
@@ -298,6 +412,11 @@ class Solver:
     def residual_batch(self, x0, xref, X, U, LAM):
         return nmpc_residual_batch(self.hd, x0, xref, X, U, LAM, **self._dims)
 
+    def autotune(self, x0, xref, iters: int = 8) -> int:
+        tr = nmpc_autotune(self.hd, x0, xref, iters, **self._dims)
+        self.options.tile_rows = tr
+        return tr
+
     def kernel_config(self):
         return nmpc_kernel_config(self.hd)
 
@@ -310,6 +429,87 @@ class Solver:
     def close(self):
         if getattr(self, "hd", None):
             nmpc_destroy(self.hd)
+            self.hd = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RaggedSolver:
+    """Instances of several problem classes in one launch per iteration.
+
+    solve() takes per-instance lists (class index, x0, xref as device tensors
+    or host arrays), packs them into the library's instance-order layout and
+    returns per-instance (X [N,n], U [N,m], LAM [N,n]) device views."""
+
+    def __init__(self, classes, *, max_instances: int, **options):
+        _load()
+        self.classes = list(classes)
+        self.options = nmpc_default_options(**options)
+        self.max_instances = max_instances
+        self.hd, self._keep = nmpc_ragged_create(self.classes, self.options, max_instances)
+
+    def _sizes(self, cls):
+        n = [int(self.classes[c].nsx) * int(self.classes[c].nsy) for c in cls]
+        N = [int(self.classes[c].N) for c in cls]
+        m = [int(self.classes[c].lx) * int(self.classes[c].ly) for c in cls]
+        return n, N, m
+
+    def pack(self, cls, arrays):
+        """Concatenate per-instance device tensors (any shape) into one 1-D tensor."""
+        import torch
+        return torch.cat([a.reshape(-1) for a in arrays]).contiguous()
+
+    def solve(self, cls, x0, xref, warm=None):
+        """cls: class per instance; x0, xref: packed 1-D device tensors or lists
+        of per-instance device tensors; warm: None or packed (x, u, lam)."""
+        import torch
+        cls = [int(c) for c in cls]
+        n, N, m = self._sizes(cls)
+        if isinstance(x0, (list, tuple)):
+            x0 = self.pack(cls, x0)
+        if isinstance(xref, (list, tuple)):
+            xref = self.pack(cls, xref)
+        nx = sum(n)
+        nS = sum(a * b for a, b in zip(n, N))
+        nU = sum(a * b for a, b in zip(m, N))
+        dev = x0.device
+        out = (torch.empty(nS, dtype=torch.float64, device=dev),
+               torch.empty(nU, dtype=torch.float64, device=dev),
+               torch.empty(nS, dtype=torch.float64, device=dev))
+        rc, infos = nmpc_ragged_solve(self.hd, cls, x0, xref, warm, out, (nx, nS, nU))
+        res, so, uo = [], 0, 0
+        for b in range(len(cls)):
+            k, ku = N[b] * n[b], N[b] * m[b]
+            res.append((out[0][so:so + k].view(N[b], n[b]), out[1][uo:uo + ku].view(N[b], m[b]),
+                        out[2][so:so + k].view(N[b], n[b])))
+            so += k
+            uo += ku
+        return rc, res, infos, out
+
+    def autotune(self, cls, x0, xref, iters: int = 8) -> int:
+        cls = [int(c) for c in cls]
+        if isinstance(x0, (list, tuple)):
+            x0 = self.pack(cls, x0)
+        if isinstance(xref, (list, tuple)):
+            xref = self.pack(cls, xref)
+        return nmpc_ragged_autotune(self.hd, cls, x0, xref, x0.numel(), iters)
+
+    def config(self, cls) -> int:
+        return nmpc_ragged_config(self.hd, [int(c) for c in cls])
+
+    def timing_enable(self, enable: bool = True):
+        nmpc_ragged_timing_enable(self.hd, enable)
+
+    def timing_read(self):
+        return nmpc_ragged_timing_read(self.hd)
+
+    def close(self):
+        if getattr(self, "hd", None):
+            nmpc_ragged_destroy(self.hd)
             self.hd = None
 
     def __del__(self):

@@ -1,6 +1,7 @@
 """Build libnmpc.so (HIP, gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -9,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmpc.so")
-SOURCES = ["nmpc_kernels.hip", "nmpc_runtime.hip", "nmpc_net.hip", "nmpc_net_runtime.hip"]
+SOURCES = ["nmpc_kernels.hip", "nmpc_ragged.hip", "nmpc_runtime.hip", "nmpc_ragged_runtime.hip",
+           "nmpc_net.hip", "nmpc_net_runtime.hip"]
 
 # Packed FP32 ops are disabled: code is written for scalar FP32/FP64 VALU.
 HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
@@ -19,15 +21,20 @@ HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc, *HIPFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-               "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([hipcc, *HIPFLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+                     "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    # the translation units compile independently: run them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", "0")) or (os.cpu_count() or 1)))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for cmd in cmds:
+            if verbose:
+                print(" ".join(cmd), flush=True)
+        for f in [pool.submit(subprocess.check_call, cmd) for cmd in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -57,6 +57,7 @@ struct IterArgs {
     int *ctr;                       // [0] kernel base index, [2] finished, [3] in FP32 phase
     int kofs;                       // this launch's index within a captured sequence
     int B, units, per_xcd;
+    long long rslot;                // residual slot stride of rst / pst
     double tol;
     int max_iter, n_sw, n_schur;
     int residual_only, res_slot;
@@ -76,6 +77,28 @@ struct OutArgs {
     const int *iters;
     const double *X[2], *U[2], *LAM[2];
     double *ox, *ou, *ol;
+};
+
+// One problem class of a ragged batch, as the ragged kernel sees it.
+struct RgClass {
+    DevProblem P;             // P.n = nsy * 16 * cx (padded points per stage)
+    const double *gx, *gy;    // [lx][nsx], [ly][nsy]
+    int tile;                 // tile case of the ragged kernel: 3 * (cx case) + ry - 1
+    int sx;                   // padded row stride 16 * cx
+};
+
+// Per-instance layout of a ragged batch (device arrays, instance order).
+struct RgArgs {
+    const RgClass *cls;       // [classes]
+    const int *icls;          // class of each instance
+    const long long *xoff;    // padded x0 / xref offset (one stage)
+    const long long *soff;    // padded X / LAM trajectory offset
+    const long long *uoff;    // U trajectory offset (dense == padded)
+    const long long *dxoff;   // dense x0 / xref offset
+    const long long *dsoff;   // dense X / LAM trajectory offset
+    const long long *ustart;  // first stage-residual index (sum of earlier horizons)
+    const int2 *umap;         // per unit: (instance, stage); instance < 0: no work
+    int count;
 };
 
 // Tile configuration of one iteration-kernel instance.
@@ -121,5 +144,13 @@ const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg);
 const void *pad_kernel();
 const void *advance_kernel();
 const void *output_kernel();
+
+// Ragged batch kernels (4 x 4 input lattice); waves: 8, 12 or 16.
+const void *ragged_iterate_kernel(int prec, int waves);
+const void *ragged_pad_kernel();
+const void *ragged_init_kernel();
+const void *ragged_output_kernel();
+// tile case of a class for a launch of `waves` waves, or -1
+int ragged_tile(int nsx, int nsy, int waves, int *cx, int *ry);
 
 }  // namespace nmpc

@@ -1,0 +1,208 @@
+// nmpc_ragged.hip -- one launch per upper iteration over a ragged batch:
+// instances of different grid sizes and horizons (each instance belongs to a
+// problem class with its own grid, horizon, step and input factors).
+//
+// The work list holds one entry per (instance, stage) unit, grouped into
+// eight runs, one per XCD (consecutive workgroup ids go to different XCDs), each
+// run balanced by stage-points and holding whole instances, so that the
+// x_{i-1} / lambda_{i+1} reads of neighbouring stages hit that XCD's L2. All
+// classes share the workgroup size of the launch; each class gets the tile
+// (CX columns x RY rows per lane) that covers its grid with the fewest rows,
+// and the workgroup branches once, uniformly, to that tile's stage code. The
+// per-instance convergence state machine is the one of the batch kernel, with
+// the instance's own horizon.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "nmpc_device.h"
+#include "nmpc_stage.h"
+
+namespace nmpc {
+
+constexpr int kRgLx = 4, kRgLy = 4;
+constexpr int kRgCx[5] = {1, 2, 3, 4, 6};
+
+template <int PREC, int WB, int CX, int RY>
+__device__ __noinline__ void rg_unit(const IterArgs &a, const RgArgs &r, const RgClass &cl,
+                                        Ctx &c, int b, int i, int k)
+{
+    using T = typename std::conditional<PREC == kModeFp32, float, double>::type;
+    tile_setup<T, CX, RY, kRgLx, kRgLy>(c, cl.P);
+    const int N = cl.P.N;
+    const long long us = r.ustart[b];
+    Decision d;
+    if (a.residual_only) {
+        d.work = true; d.j = 0; d.slot = a.res_slot;
+    } else {
+        d = decide<PREC>(a, c, b, i, k, N, us);
+    }
+    if (!d.work) return;
+    load_tables<CX, RY, kRgLx, kRgLy>(c, cl.gx, cl.gy, cl.P.nsx, cl.P.nsy);
+    StageLoc v;
+    v.so = r.soff[b];
+    v.uo = r.uoff[b];
+    v.xo = r.xoff[b];
+    v.xro = r.xoff[b];
+    v.res_at = (long long)d.slot * a.rslot + us + i;
+    v.i = i;
+    v.cur = d.j & 1;
+    v.last = i == N - 1;
+    stage_body<T, CX, RY, kRgLx, kRgLy>(a, cl.P, v, c);
+}
+
+// Rows covered by a tile of RY rows per lane with WB waves: 4 * WB * RY. A
+// case is instantiated only where it is the smallest cover of some grid
+// height <= 96 and has at most 18 (8 waves) or 12 (12, 16 waves) points per
+// lane. Each case is a separate function, so only the large tiles spill when
+// the register file that WB waves leave a lane (512 / (WB / 4) VGPRs, at most
+// 256) is too small for them; the autotuner weighs that against occupancy.
+__host__ __device__ constexpr int rg_max_points(int wb) { return wb <= 8 ? 18 : 12; }
+template <int WB, int CX, int RY>
+constexpr bool rg_case() { return 4 * WB * (RY - 1) < 96 && CX * RY <= rg_max_points(WB); }
+
+template <int PREC, int WB>
+__global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, const RgArgs r)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Ctx c;
+    c.lds = lds_raw;
+    const int k = a.residual_only ? 0 : *(volatile const int *)(a.ctr) + a.kofs;
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (unit >= a.units) return;
+    const int2 bi = r.umap[unit];
+    if (bi.x < 0) return;
+    const RgClass &cl = r.cls[r.icls[bi.x]];
+#define NMPC_RG_CASE(CI, RY)                                                       \
+    case 3 * CI + RY - 1:                                                           \
+        if constexpr (rg_case<WB, kRgCx[CI], RY>())                                 \
+            rg_unit<PREC, WB, kRgCx[CI], RY>(a, r, cl, c, bi.x, bi.y, k);            \
+        break;
+    switch (cl.tile) {
+        NMPC_RG_CASE(0, 1) NMPC_RG_CASE(0, 2) NMPC_RG_CASE(0, 3)
+        NMPC_RG_CASE(1, 1) NMPC_RG_CASE(1, 2) NMPC_RG_CASE(1, 3)
+        NMPC_RG_CASE(2, 1) NMPC_RG_CASE(2, 2) NMPC_RG_CASE(2, 3)
+        NMPC_RG_CASE(3, 1) NMPC_RG_CASE(3, 2) NMPC_RG_CASE(3, 3)
+        NMPC_RG_CASE(4, 1) NMPC_RG_CASE(4, 2) NMPC_RG_CASE(4, 3)
+    default: break;
+    }
+#undef NMPC_RG_CASE
+}
+
+// Dense inputs [count][n_b] (packed) -> padded rows (stride sx of the
+// instance's class, zero padding). One workgroup per instance.
+__global__ void k_rg_pad(const RgArgs r, const double *src, double *dst)
+{
+    const int b = blockIdx.x;
+    if (b >= r.count) return;
+    const RgClass &cl = r.cls[r.icls[b]];
+    const int nsx = cl.P.nsx, sx = cl.sx, tot = cl.P.nsy * sx;
+    const double *s = src + r.dxoff[b];
+    double *d = dst + r.xoff[b];
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        const int row = t / sx, col = t % sx;
+        d[t] = col < nsx ? s[row * nsx + col] : 0.0;
+    }
+}
+
+// S^0 of each instance into buffer 0: cold (x_i = x0, u_i = 0, lambda_i = 0)
+// or the given dense start; iteration state reset. One workgroup per instance.
+__global__ void k_rg_init(const IterArgs a, const RgArgs r, int mode, const double *wx,
+                          const double *wu, const double *wl)
+{
+    const int b = blockIdx.x;
+    if (b >= r.count) return;
+    const RgClass &cl = r.cls[r.icls[b]];
+    const int nsx = cl.P.nsx, sx = cl.sx, np = cl.P.n, N = cl.P.N, m = cl.P.m;
+    const int nd = nsx * cl.P.nsy;
+    const double *x0 = a.x0 + r.xoff[b];
+    double *X = a.X[0] + r.soff[b];
+    double *L = a.LAM[0] + r.soff[b];
+    double *U = a.U[0] + r.uoff[b];
+    const long long ds = r.dsoff[b];
+    for (long long t = threadIdx.x; t < (long long)N * np; t += blockDim.x) {
+        const int i = (int)(t / np), p = (int)(t % np);
+        const int row = p / sx, col = p % sx;
+        double x = 0.0, l = 0.0;
+        if (col < nsx) {
+            const long long dense = ds + (long long)i * nd + row * nsx + col;
+            x = wx ? wx[dense] : x0[p];
+            l = wl ? wl[dense] : 0.0;
+        }
+        X[t] = x;
+        L[t] = l;
+    }
+    for (int t = threadIdx.x; t < N * m; t += blockDim.x) U[t] = wu ? wu[r.uoff[b] + t] : 0.0;
+    if (threadIdx.x == 0) {
+        InstState s;
+        s.status = kActive; s.mode = mode; s.e = 0; s.j = 0; s.pending = 0; s.f32 = 0;
+        s.pad[0] = s.pad[1] = 0;
+        a.st[b] = s;
+        a.st[a.B + b] = s;
+        a.iters[b] = 0;
+    }
+    if (b == 0 && threadIdx.x == 0) {
+        a.ctr[0] = 0;
+        a.ctr[2] = 0;
+        a.ctr[3] = mode == kModeFp32 ? r.count : 0;
+    }
+}
+
+// Each instance's returned iterate (buffer iters[b] & 1) to the dense packed
+// outputs. One workgroup per instance.
+__global__ void k_rg_output(const IterArgs a, const RgArgs r, double *ox, double *ou, double *ol)
+{
+    const int b = blockIdx.x;
+    if (b >= r.count) return;
+    const RgClass &cl = r.cls[r.icls[b]];
+    const int nsx = cl.P.nsx, sx = cl.sx, np = cl.P.n, N = cl.P.N, m = cl.P.m;
+    const int nd = nsx * cl.P.nsy;
+    const int buf = a.iters[b] & 1;
+    const double *X = a.X[buf] + r.soff[b];
+    const double *L = a.LAM[buf] + r.soff[b];
+    const double *U = a.U[buf] + r.uoff[b];
+    const long long ds = r.dsoff[b];
+    for (long long t = threadIdx.x; t < (long long)N * nd; t += blockDim.x) {
+        const int i = (int)(t / nd), p = (int)(t % nd);
+        const long long src = (long long)i * np + (p / nsx) * sx + p % nsx;
+        ox[ds + t] = X[src];
+        ol[ds + t] = L[src];
+    }
+    for (int t = threadIdx.x; t < N * m; t += blockDim.x) ou[r.uoff[b] + t] = U[t];
+}
+
+const void *ragged_iterate_kernel(int prec, int waves)
+{
+    if (prec == kModeFp32) {
+        if (waves == 8) return (const void *)&k_iterate_rg<kModeFp32, 8>;
+        if (waves == 12) return (const void *)&k_iterate_rg<kModeFp32, 12>;
+        if (waves == 16) return (const void *)&k_iterate_rg<kModeFp32, 16>;
+    } else {
+        if (waves == 8) return (const void *)&k_iterate_rg<kModeFp64, 8>;
+        if (waves == 12) return (const void *)&k_iterate_rg<kModeFp64, 12>;
+        if (waves == 16) return (const void *)&k_iterate_rg<kModeFp64, 16>;
+    }
+    return nullptr;
+}
+
+int ragged_tile(int nsx, int nsy, int waves, int *cx, int *ry)
+{
+    int ci = -1;
+    for (int q = 0; q < 5; ++q)
+        if (16 * kRgCx[q] >= nsx) { ci = q; break; }
+    if (ci < 0 || nsy < 1 || nsx < 1) return -1;
+    const int rows = 4 * waves;
+    const int r_ = (nsy + rows - 1) / rows;
+    if (r_ > 3 || 4 * waves * (r_ - 1) >= 96 || kRgCx[ci] * r_ > rg_max_points(waves)) return -1;
+    if (cx) *cx = kRgCx[ci];
+    if (ry) *ry = r_;
+    return 3 * ci + r_ - 1;
+}
+
+const void *ragged_pad_kernel() { return (const void *)&k_rg_pad; }
+const void *ragged_init_kernel() { return (const void *)&k_rg_init; }
+const void *ragged_output_kernel() { return (const void *)&k_rg_output; }
+
+}  // namespace nmpc

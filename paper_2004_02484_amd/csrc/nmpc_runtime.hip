@@ -204,6 +204,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.B = h->max_batch;
     a.units = count * h->N;
     a.per_xcd = (a.units + 7) / 8;
+    a.rslot = (long long)h->max_batch * h->N;
     a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
     a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
     a.residual_only = 0;
@@ -747,6 +748,55 @@ int nmpc_timing_read(const nmpc_handle *h, double *kernel_ms, int64_t *launches,
     if (kernel_ms) *kernel_ms = h->kernel_ms;
     if (launches) *launches = h->launches;
     if (units) *units = (int64_t)h->units;
+    return NMPC_OK;
+}
+
+int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double *xref,
+                  int32_t iters, void *stream, int32_t *tile_rows)
+{
+    g_err.clear();
+    if (!h || !x0 || !xref) return fail(NMPC_E_ARG, "NULL argument");
+    if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    if (iters < 1 || iters > 1000) return fail(NMPC_E_ARG, "iters must be 1..1000");
+    const int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
+    hipStream_t us = (hipStream_t)stream;
+    HIP_TRY(hipEventRecord(h->ev, us));
+    HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
+    int rc = stage_inputs(h, count, x0, xref);
+    if (rc) return rc;
+    const nmpc_handle::Kern keep = h->kern[prec];
+    int best_ry = -1;
+    float best_ms = 0.f;
+    nmpc_handle::Kern best{};
+    for (int ry = 1; ry <= 16; ++ry) {
+        nmpc_handle::Kern k;
+        if (select_kernel(&h->prob, prec, ry, &k) != NMPC_OK) continue;   // no such tile
+        if (k.lds > 48 * 1024)
+            HIP_TRY(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
+        h->kern[prec] = k;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {   // the first pass loads code and warms caches
+            rc = build_start(h, count, nullptr, nullptr, nullptr);
+            if (rc) { h->kern[prec] = keep; return rc; }
+            IterArgs a = iter_args(h, count);
+            HIP_TRY(hipEventRecord(h->t0, h->stream));
+            for (int t = 0; t < iters && rc == NMPC_OK; ++t) {
+                a.kofs = t;
+                rc = launch_iterate(h, prec, a, h->stream);
+            }
+            if (rc) { h->kern[prec] = keep; return rc; }
+            HIP_TRY(hipEventRecord(h->t1, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
+        }
+        if (best_ry < 0 || ms < best_ms) { best_ry = ry; best_ms = ms; best = k; }
+    }
+    g_err.clear();
+    if (best_ry < 0) { h->kern[prec] = keep; return fail(NMPC_E_UNSUPPORTED, "no tile to tune"); }
+    h->kern[prec] = best;
+    h->opt.tile_rows = best_ry;
+    h->graph_count[0] = h->graph_count[1] = -1;
+    if (tile_rows) *tile_rows = best_ry;
     return NMPC_OK;
 }
 

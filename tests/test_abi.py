@@ -86,3 +86,41 @@ def test_unknown_tile_height_is_unsupported():
     with pytest.raises(nm.NmpcError) as e:
         nm.nmpc_create(make_problem("c1"), o, 1)
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
+
+
+def _grid(ns, N, lattice=4):
+    return make_problem("grid", ns=ns, N=N, lattice=lattice)
+
+
+@pytest.mark.parametrize("classes,opts,code", [
+    ([], {}, nm.NMPC_E_ARG),                                             # no class
+    ([("grid", 32, 4, 2)], {}, nm.NMPC_E_UNSUPPORTED),                   # 2x2 lattice
+    ([("grid", 100, 4, 4)], {}, nm.NMPC_E_UNSUPPORTED),                  # wider than 96
+    ([("c0",)], {}, nm.NMPC_E_UNSUPPORTED),                              # 1D class
+    ([("grid", 32, 4, 4)], {"xref_per_stage": 1}, nm.NMPC_E_UNSUPPORTED),
+    ([("grid", 32, 4, 4)], {"n_sweep": 0}, nm.NMPC_E_ARG),
+    ([("grid", 32, 0, 4)], {}, nm.NMPC_E_ARG),                           # horizon 0
+])
+def test_ragged_create_validates_before_any_device_call(classes, opts, code):
+    cl = [make_problem("c0") if c[0] == "c0" else _grid(c[1], c[2], c[3]) for c in classes]
+    if not cl:
+        o = nm.nmpc_default_options()
+        lib = _binding._load()
+        hd = ctypes.c_void_p()
+        assert lib.nmpc_ragged_create(None, 0, ctypes.byref(o), 4, ctypes.byref(hd)) == code
+        return
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_ragged_create(cl, nm.nmpc_default_options(**opts), 4)
+    assert e.value.code == code
+
+
+def test_ragged_null_handle_calls():
+    lib = _binding._load()
+    lib.nmpc_ragged_destroy(None)
+    c = (ctypes.c_int32 * 1)(0)
+    w = ctypes.c_int32()
+    assert lib.nmpc_ragged_config(None, 1, c, ctypes.byref(w)) == nm.NMPC_E_ARG
+    assert lib.nmpc_ragged_timing_enable(None, 1) == nm.NMPC_E_ARG
+    assert lib.nmpc_ragged_solve(None, 1, c, None, None, None, None, None, None, None, None,
+                                 None, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_autotune(None, 1, None, None, 4, None, None) == nm.NMPC_E_ARG
