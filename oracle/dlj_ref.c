@@ -114,33 +114,41 @@ static void dfx_T_apply(const ref_problem *P, const double *x, const double *lam
  * xref has xref_stride = 0 (one reference for all stages) or n (per stage).
  * ut (the regularization reference) may be NULL, meaning ut = u.
  */
+static void stage_kkt(const ref_problem *P, int i, const double *x0, const double *xref,
+                      int xref_stride, const double *X, const double *U, const double *LAM,
+                      const double *UT, double *kx, double *ku, double *kl)
+{
+    int n = ref_n(P), m = P->m, N = P->N;
+    const double *xprev = (i == 0) ? x0 : X + (size_t)(i - 1) * n;
+    const double *x = X + (size_t)i * n, *u = U + (size_t)i * m, *lam = LAM + (size_t)i * n;
+    const double *xr = xref + (size_t)i * xref_stride;
+    double *f = (double *)malloc(sizeof(double) * n);
+    double *g = (double *)malloc(sizeof(double) * n);
+    dyn_f(P, x, u, f);
+    for (int p = 0; p < n; ++p) kx[p] = xprev[p] - x[p] + P->h * f[p];
+    for (int j = 0; j < m; ++j) {
+        double btl = 0.0;
+        for (int p = 0; p < n; ++p) btl += P->B[(size_t)p * m + j] * lam[p];
+        double reg = UT ? P->gamma * (u[j] - UT[(size_t)i * m + j]) : 0.0;
+        ku[j] = P->h * (P->r * u[j] + btl) + reg;
+    }
+    dfx_T_apply(P, x, lam, g);
+    for (int p = 0; p < n; ++p) {
+        double lnext = (i == N - 1) ? 0.0 : LAM[(size_t)(i + 1) * n + p];
+        kl[p] = lnext - lam[p] + P->h * (P->q * (x[p] - xr[p]) + g[p]);
+    }
+    free(f); free(g);
+}
+
 void ref_kkt(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
              const double *X, const double *U, const double *LAM, const double *UT,
              double *KX, double *KU, double *KL)
 {
     int n = ref_n(P), m = P->m, N = P->N;
     #pragma omp parallel for schedule(static)
-    for (int i = 0; i < N; ++i) {
-        const double *xprev = (i == 0) ? x0 : X + (size_t)(i - 1) * n;
-        const double *x = X + (size_t)i * n, *u = U + (size_t)i * m, *lam = LAM + (size_t)i * n;
-        const double *xr = xref + (size_t)i * xref_stride;
-        double *f = (double *)malloc(sizeof(double) * n);
-        double *g = (double *)malloc(sizeof(double) * n);
-        dyn_f(P, x, u, f);
-        for (int p = 0; p < n; ++p) KX[(size_t)i * n + p] = xprev[p] - x[p] + P->h * f[p];
-        for (int j = 0; j < m; ++j) {
-            double btl = 0.0;
-            for (int p = 0; p < n; ++p) btl += P->B[(size_t)p * m + j] * lam[p];
-            double reg = UT ? P->gamma * (u[j] - UT[(size_t)i * m + j]) : 0.0;
-            KU[(size_t)i * m + j] = P->h * (P->r * u[j] + btl) + reg;
-        }
-        dfx_T_apply(P, x, lam, g);
-        for (int p = 0; p < n; ++p) {
-            double lnext = (i == N - 1) ? 0.0 : LAM[(size_t)(i + 1) * n + p];
-            KL[(size_t)i * n + p] = lnext - lam[p] + P->h * (P->q * (x[p] - xr[p]) + g[p]);
-        }
-        free(f); free(g);
-    }
+    for (int i = 0; i < N; ++i)
+        stage_kkt(P, i, x0, xref, xref_stride, X, U, LAM, UT, KX + (size_t)i * n,
+                  KU + (size_t)i * m, KL + (size_t)i * n);
 }
 
 /* Residual norms: r_paper = |K|_inf; r_scaled divides the input rows by h r
@@ -379,6 +387,89 @@ int ref_solve(const ref_problem *P, const double *x0, const double *xref, int xr
         ++k;
     }
     free(buf);
+    if (iters) *iters = k;
+    if (r_scaled) *r_scaled = rs;
+    if (r_paper) *r_paper = rp;
+    return status;
+}
+
+/* ------------------------------------------------ Gauss-Seidel upper layers */
+
+/*
+ * One Gauss-Seidel sweep over the stages (Sec. 4.4, Jacobi-type variants),
+ * in place: the stages are visited in turn (dir > 0: i = 1..N, forward;
+ * dir < 0: i = N..1, backward) and each stage block is solved from the
+ * current trajectory, in which the stages visited before already hold their
+ * new values. The regularization reference is the stage's current input
+ * (u~ = u^k), as in the Jacobi iteration.
+ *
+ * K_i depends on x_{i-1} and lambda_{i+1} only through the terms x_{i-1} and
+ * lambda_{i+1} themselves, and D_i only on s_i, so a forward sweep is exactly
+ * S - (D^k + L)^{-1} K^k (eq. fgs) and a backward sweep S - (D^k + U)^{-1} K^k
+ * (BGS), with L / U the blocks coupling a stage to the previous / next one.
+ * UT (may be NULL) is the regularization reference u~ of every stage: NULL
+ * means the stage's input at its visit, which is u^k in a single sweep.
+ */
+void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
+                  double *X, double *U, double *LAM, const double *UT, int dir, int n_sw,
+                  int n_schur)
+{
+    int n = ref_n(P), m = P->m, N = P->N;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(4 * n + 2 * m));
+    double *kx = w, *kl = w + n, *dx = w + 2 * n, *dl = w + 3 * n;
+    double *ku = w + 4 * n, *du = w + 4 * n + m;
+    for (int t = 0; t < N; ++t) {
+        int i = dir > 0 ? t : N - 1 - t;
+        stage_kkt(P, i, x0, xref, xref_stride, X, U, LAM, UT, kx, ku, kl);
+        ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n, kx, kl, ku, n_sw, n_schur,
+                        dx, du, dl);
+        for (int p = 0; p < n; ++p) {
+            X[(size_t)i * n + p] -= dx[p];
+            LAM[(size_t)i * n + p] -= dl[p];
+        }
+        for (int j = 0; j < m; ++j) U[(size_t)i * m + j] -= du[j];
+    }
+    free(w);
+}
+
+/*
+ * Upper layer by Gauss-Seidel sweeps: upper = 1 FGS (eq. fgs), 2 BGS,
+ * 3 SGS (eq. sgs, read as a backward sweep followed by a forward sweep, both
+ * with the regularization reference u~ = u^k of the iteration; in the linear
+ * case this is eq. sgs exactly). Every iteration first evaluates K(S^k) and
+ * its norms for the stopping test, exactly as ref_solve does; the returned
+ * trajectory is the last evaluated iterate S^k.
+ */
+int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
+                 double *X, double *U, double *LAM, int upper, double tol, int max_iter,
+                 int n_sw, int n_schur, int *iters, double *r_scaled, double *r_paper,
+                 double *rhist)
+{
+    int n = ref_n(P), m = P->m, N = P->N, k = 0, status = 1;
+    double *KX = (double *)malloc(sizeof(double) * (size_t)N * n);
+    double *KL = (double *)malloc(sizeof(double) * (size_t)N * n);
+    double *KU = (double *)malloc(sizeof(double) * (size_t)N * m);
+    double *UK = (double *)malloc(sizeof(double) * (size_t)N * m);
+    double rs = 0.0, rp = 0.0;
+    for (;;) {
+        ref_kkt(P, x0, xref, xref_stride, X, U, LAM, U, KX, KU, KL);
+        ref_norms(P, KX, KU, KL, &rs, &rp);
+        if (rhist) rhist[k] = rs;
+        if (!isfinite(rs)) { status = 2; break; }
+        if (rs <= tol) { status = 0; break; }
+        if (k >= max_iter) { status = 1; break; }
+        if (upper == 1) {
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, +1, n_sw, n_schur);
+        } else if (upper == 2) {
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur);
+        } else {
+            memcpy(UK, U, sizeof(double) * (size_t)N * m);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UK, +1, n_sw, n_schur);
+        }
+        ++k;
+    }
+    free(KX); free(KL); free(KU); free(UK);
     if (iters) *iters = k;
     if (r_scaled) *r_scaled = rs;
     if (r_paper) *r_paper = rp;

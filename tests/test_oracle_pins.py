@@ -365,3 +365,107 @@ def test_c0_solution_satisfies_kkt():
     assert o["status"] == "converged"
     rs, rp = dense.norms(P, *dense.kkt(P, x0, xref, o["X"], o["U"], o["LAM"]))
     assert rs <= 1e-6 and abs(rs - o["r_scaled"]) <= 1e-12
+
+
+# ------------------------- Gauss-Seidel upper layers (Sec. 4.4, eq. fgs, eq. sgs)
+
+def _tri_parts(J, P):
+    """Block-diagonal D, strictly lower L and strictly upper U block parts of
+    the stage-block-tridiagonal matrix J (J = D + L + U)."""
+    w = 2 * P.n + P.m
+    D = np.zeros_like(J); L = np.zeros_like(J); Up = np.zeros_like(J)
+    for i in range(P.N):
+        for k in range(P.N):
+            blk = J[i * w:(i + 1) * w, k * w:(k + 1) * w]
+            tgt = D if i == k else (L if k < i else Up)
+            tgt[i * w:(i + 1) * w, k * w:(k + 1) * w] = blk
+    return D, L, Up
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_gs_sweep_is_the_papers_fgs_bgs_step(direction):
+    """A forward sweep equals S - (D^k + L)^{-1} K^k (eq. fgs), a backward one
+    S - (D^k + U)^{-1} K^k, on a nonlinear instance: K_i is affine in x_{i-1}
+    and lambda_{i+1} with identity coefficients and D_i depends on s_i only, so
+    the sequential sweep and the block-triangular solve agree exactly."""
+    P = tiny2d(N=4)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=21)
+    Xn, Un, Ln = oracle.gs_sweep(P, x0, xref, X, U, LAM, direction, n_sw=400, n_schur=60)
+    J = dense.jacobian(P, X, U, LAM)
+    D, L, Up = _tri_parts(J, P)
+    K = dense.pack(*dense.kkt(P, x0, xref, X, U, LAM))
+    Sn = dense.pack(X, U, LAM) - np.linalg.solve(D + (L if direction > 0 else Up), K)
+    got = dense.pack(Xn, Un, Ln)
+    assert np.abs(got - Sn).max() <= 1e-9 * np.abs(Sn).max()
+    # and it differs from the Jacobi step (the coupling is really used)
+    Sj = dense.pack(X, U, LAM) - np.linalg.solve(D, K)
+    assert np.abs(got - Sj).max() > 1e-6 * np.abs(Sn).max()
+
+
+def test_sgs_iteration_is_eq_sgs_in_the_linear_case():
+    """With k1 = 0 the blocks do not depend on S, and one SGS iteration (a
+    backward sweep, then a forward sweep) equals eq. sgs:
+    S - (D + L)^{-1} (K - U (D + U)^{-1} K)."""
+    P = tiny2d(N=4, k1=0.0)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=22)
+    o = oracle.solve(P, x0, xref, start=(X, U, LAM), tol=0.0, max_iter=1, n_sw=400,
+                     n_schur=60, upper="sgs")
+    J = dense.jacobian(P, X, U, LAM)
+    D, L, Up = _tri_parts(J, P)
+    K = dense.pack(*dense.kkt(P, x0, xref, X, U, LAM))
+    Sn = dense.pack(X, U, LAM) - np.linalg.solve(D + L, K - Up @ np.linalg.solve(D + Up, K))
+    got = dense.pack(o["X"], o["U"], o["LAM"])
+    assert np.abs(got - Sn).max() <= 1e-9 * np.abs(Sn).max()
+
+
+def test_fgs_rate_is_the_square_of_jacobis():
+    """Theorem cor_cvg: the KKT matrix is block tridiagonal, hence consistently
+    ordered, so rho((D + L)^{-1} U) = rho(D^{-1}(L + U))^2. Checked on the
+    iteration matrices at the solution, and on the oracle's observed residual
+    decay (linear case, gamma = 0, exact lower layer, where the FGS map is
+    exactly affine)."""
+    P = tiny2d(nsx=5, nsy=4, N=5, lattice=2, sigma=0.2, k1=0.0, gamma_rel=0.0)
+    x0, xref = tiny_data(P, seed=23)[:2]
+    o = oracle.solve(P, x0, xref, tol=1e-13, max_iter=20000)
+    J = dense.jacobian(P, o["X"], o["U"], o["LAM"])
+    D, L, Up = _tri_parts(J, P)
+    rj = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D, L + Up))))
+    rf = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D + L, Up))))
+    rb = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D + Up, L))))
+    assert 0.0 < rj < 1.0
+    assert abs(rf - rj ** 2) <= 1e-8 and abs(rb - rj ** 2) <= 1e-8
+    # the oracle's sweep map has exactly that iteration matrix: its columns by
+    # differences (the map is affine here)
+    X, U, LAM = o["X"], o["U"], o["LAM"]
+    S0 = dense.pack(X, U, LAM)
+    base = dense.pack(*oracle.gs_sweep(P, x0, xref, X, U, LAM, 1, n_sw=400, n_schur=60))
+    G = np.zeros((S0.size, S0.size))
+    for j in range(S0.size):
+        e = np.zeros(S0.size); e[j] = 1e-3
+        Xe, Ue, Le = dense.unpack(P, S0 + e)
+        G[:, j] = (dense.pack(*oracle.gs_sweep(P, x0, xref, Xe, Ue, Le, 1, n_sw=400,
+                                               n_schur=60)) - base) / 1e-3
+    np.testing.assert_allclose(G, -np.linalg.solve(D + L, Up), atol=1e-8)
+    # observed residual decay over many iterations (the dominant eigenvalues
+    # are a complex pair, so single-step ratios oscillate)
+    t = oracle.solve(P, x0, xref, tol=1e-300, max_iter=80, n_sw=300, n_schur=40, trace=True,
+                     upper="fgs")
+    r = t["rhist"]
+    k0 = int(np.argmax(r < 1e-2 * r[0]))
+    k1 = int(np.nonzero(r > 1e-11 * r[0])[0].max())
+    assert k1 - k0 >= 15
+    rate = (r[k1] / r[k0]) ** (1.0 / (k1 - k0))
+    assert abs(rate - rj ** 2) <= 0.1 * rj ** 2
+
+
+@pytest.mark.parametrize("upper", ["fgs", "bgs", "sgs"])
+def test_gauss_seidel_fixed_point_is_jacobis(upper):
+    """Same KKT point as the Jacobi upper layer (the splitting changes only the
+    rate), in fewer iterations on the nonlinear 1D configuration."""
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 3)
+    oj = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    og = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000, upper=upper)
+    assert oj["status"] == og["status"] == "converged"
+    np.testing.assert_allclose(og["U"], oj["U"], atol=1e-9 * np.abs(oj["U"]).max())
+    assert og["iters"] < oj["iters"]
