@@ -62,6 +62,8 @@ enum { NMPC_FP64 = 0, NMPC_FP32_SWEEP = 1 };
 
 enum { NMPC_START_COLD = 0, NMPC_START_WARM = 1 };
 
+enum { NMPC_UPPER_JACOBI = 0, NMPC_UPPER_FGS = 1, NMPC_UPPER_BGS = 2, NMPC_UPPER_SGS = 3 };
+
 /* Problem data (Sec. 3 notation). gx/gy are host arrays, copied at create. */
 typedef struct nmpc_problem {
     int32_t dim;          /* 1 or 2 */
@@ -98,6 +100,15 @@ typedef struct nmpc_options {
     int32_t fallback;     /* 1: for a warm start, compare its residual with the
                              cold start's per instance and keep the smaller
                              (non-finite counts as larger) */
+    int32_t upper;        /* upper-layer splitting (Sec. 4.4): NMPC_UPPER_JACOBI
+                             (eq. 1st_jacobi, all stages in parallel; default),
+                             NMPC_UPPER_FGS (eq. fgs), NMPC_UPPER_BGS, or
+                             NMPC_UPPER_SGS (eq. sgs: a backward sweep, then a
+                             forward sweep). The Gauss-Seidel variants visit the
+                             stages of an instance in turn: one workgroup per
+                             instance runs the whole solve in one launch per
+                             precision phase. Every variant has the same
+                             solution; iterations count upper iterations */
 } nmpc_options;
 
 /* Per-instance result information. */
@@ -114,7 +125,7 @@ typedef struct nmpc_handle nmpc_handle;
 
 /* Fill options with the paper's lower-layer settings (2 sweeps, 2 Schur
  * iterations), tol 1e-6, max_iter 2000, FP64, check_every 16, default
- * tile. */
+ * tile, Jacobi upper layer. */
 void nmpc_default_options(nmpc_options *opt);
 
 /* Create a solver for one problem shape and up to max_batch instances on the
@@ -191,9 +202,9 @@ void nmpc_set_last_error(const char *msg);
 /* Tile autotuner: time `iters` upper iterations (1..1000) of this batch from
  * the cold start (DEVICE x0 [count][n], xref [count][n]) with every tile
  * height that the kernel table holds for the problem's grid width in the
- * handle's main precision, keep the fastest as the handle's tile_rows and
- * return it in *tile_rows (may be NULL). The timing runs' results are
- * discarded; stream as in nmpc_solve_batch. */
+ * handle's main precision and upper layer, keep the fastest as the handle's
+ * tile_rows and return it in *tile_rows (may be NULL). The timing runs'
+ * results are discarded; stream as in nmpc_solve_batch. */
 int nmpc_autotune(nmpc_handle *hd, int32_t count, const double *x0, const double *xref,
                   int32_t iters, void *stream, int32_t *tile_rows);
 
@@ -208,8 +219,8 @@ int nmpc_autotune(nmpc_handle *hd, int32_t count, const double *x0, const double
 typedef struct nmpc_ragged nmpc_ragged;
 
 /* Create for nclass (1..64) classes (copied) and up to max_instances
- * instances per solve. opt as for nmpc_create; xref_per_stage must be 0;
- * tile_rows, warm_sweeps and fallback are not used. Device trajectory
+ * instances per solve. opt as for nmpc_create; xref_per_stage must be 0 and
+ * upper NMPC_UPPER_JACOBI; tile_rows, warm_sweeps and fallback are not used. Device trajectory
  * buffers are sized at the first solve and grow on demand. */
 int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_options *opt,
                        int32_t max_instances, nmpc_ragged **out);

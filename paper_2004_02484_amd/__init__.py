@@ -17,6 +17,10 @@ from ._binding import (  # noqa: F401
     NMPC_FP32_SWEEP,
     NMPC_FP64,
     NMPC_OK,
+    NMPC_UPPER_BGS,
+    NMPC_UPPER_FGS,
+    NMPC_UPPER_JACOBI,
+    NMPC_UPPER_SGS,
     NmpcError,
     RaggedSolver,
     Solver,

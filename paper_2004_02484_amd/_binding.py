@@ -19,6 +19,10 @@ NMPC_E_OOM = 5
 NMPC_E_UNSUPPORTED = 6
 NMPC_FP64 = 0
 NMPC_FP32_SWEEP = 1
+NMPC_UPPER_JACOBI = 0
+NMPC_UPPER_FGS = 1
+NMPC_UPPER_BGS = 2
+NMPC_UPPER_SGS = 3
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -36,7 +40,8 @@ class nmpc_options(ctypes.Structure):
                 ("n_sweep", ctypes.c_int32), ("n_schur", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-                ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32)]
+                ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("upper", ctypes.c_int32)]
 
 
 class nmpc_info(ctypes.Structure):

@@ -24,6 +24,12 @@ constexpr int kModeFp64 = 0;
 constexpr int kModeFp32 = 1;
 constexpr int kModeFp64Redo = 2;   // FP32 test passed: redo that iterate in FP64
 
+// Upper-layer splittings (values of nmpc_options.upper).
+constexpr int kUpperJacobi = 0;
+constexpr int kUpperFgs = 1;
+constexpr int kUpperBgs = 2;
+constexpr int kUpperSgs = 3;
+
 struct DevProblem {
     int nsx, nsy, n, N, m, lx, ly;   // n: padded points per stage, nsy * 16 * CX
     double h, k0, k1, q, r, gamma;
@@ -137,6 +143,8 @@ __host__ __device__ inline LdsOff lds_layout(int GT, int W, int CX, int tsize, i
 
 // ry = 0 selects the default tile height for (prec, cx).
 const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);
+// Gauss-Seidel kernel (one workgroup per instance); arguments (IterArgs, int upper).
+const void *gs_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);
 const void *init_kernel();
 const void *choose_flags_kernel();
 const void *choose_copy_kernel();

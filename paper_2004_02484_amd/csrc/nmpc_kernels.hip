@@ -50,16 +50,16 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
         }
         if (d.work) {
             load_tables<CX, RY, LX, LY>(c, a.gx, a.gy, a.P.nsx, a.P.nsy);
-            StageLoc v;
+            StageLoc v = jacobi_loc(d.j & 1);
             v.so = (long long)b * N * n;
             v.uo = (long long)b * N * M;
             v.xo = (long long)b * n;
             v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
             v.res_at = (long long)d.slot * a.rslot + (long long)b * N + i;
             v.i = i;
-            v.cur = d.j & 1;
             v.last = i == N - 1;
-            stage_body<T, CX, RY, LX, LY>(a, a.P, v, c);
+            unsigned long long acc[2] = {0, 0};
+            stage_body<T, CX, RY, LX, LY>(a, a.P, v, c, acc);
         }
     }
 }

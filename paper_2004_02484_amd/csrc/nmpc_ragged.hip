@@ -40,16 +40,16 @@ __device__ __noinline__ void rg_unit(const IterArgs &a, const RgArgs &r, const R
     }
     if (!d.work) return;
     load_tables<CX, RY, kRgLx, kRgLy>(c, cl.gx, cl.gy, cl.P.nsx, cl.P.nsy);
-    StageLoc v;
+    StageLoc v = jacobi_loc(d.j & 1);
     v.so = r.soff[b];
     v.uo = r.uoff[b];
     v.xo = r.xoff[b];
     v.xro = r.xoff[b];
     v.res_at = (long long)d.slot * a.rslot + us + i;
     v.i = i;
-    v.cur = d.j & 1;
     v.last = i == N - 1;
-    stage_body<T, CX, RY, kRgLx, kRgLy>(a, cl.P, v, c);
+    unsigned long long acc[2] = {0, 0};
+    stage_body<T, CX, RY, kRgLx, kRgLy>(a, cl.P, v, c, acc);
 }
 
 // Rows covered by a tile of RY rows per lane with WB waves: 4 * WB * RY. A

@@ -444,6 +444,9 @@ int check_opts(const nmpc_options *o)
         return rg_fail(NMPC_E_ARG, "unknown precision");
     if (o->check_every < 1 || o->check_every > 4096) return rg_fail(NMPC_E_ARG, "bad check_every");
     if (o->xref_per_stage != 0) return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches take one xref per instance");
+    if (o->upper < 0 || o->upper > 3) return rg_fail(NMPC_E_ARG, "unknown upper layer");
+    if (o->upper != NMPC_UPPER_JACOBI)
+        return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches use the Jacobi upper layer");
     return NMPC_OK;
 }
 

@@ -55,6 +55,7 @@ struct nmpc_handle {
         int waves = 0;
         size_t lds = 0;
     } kern[2];                             // [kModeFp64], [kModeFp32]
+    Kern gs[2];                            // Gauss-Seidel kernels (upper != Jacobi)
     Kern roll;                             // start built from an input trajectory
     int *d_start = nullptr;                // [B] start used per instance
     int last_start_kind = 0;
@@ -95,11 +96,13 @@ int tile_cx(int nsx)
     return cx == 5 ? 6 : cx;
 }
 
-// Pick the iteration kernel of precision `prec` for this grid and lattice.
-int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k)
+// Pick the iteration kernel of precision `prec` for this grid and lattice:
+// the Jacobi kernel (gs = false) or the Gauss-Seidel kernel.
+int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k, bool gs = false)
 {
     TileCfg cfg{};
-    const void *fn = nmpc::iterate_kernel(prec, tile_cx(p->nsx), ry, p->lx, p->ly, &cfg);
+    const void *fn = gs ? nmpc::gs_kernel(prec, tile_cx(p->nsx), ry, p->lx, p->ly, &cfg)
+                        : nmpc::iterate_kernel(prec, tile_cx(p->nsx), ry, p->lx, p->ly, &cfg);
     if (!fn && ry) return fail(NMPC_E_UNSUPPORTED, "no kernel instance with this tile height");
     if (!fn) return fail(NMPC_E_UNSUPPORTED, "no kernel instance for this grid width / input lattice");
     const int groups = (p->nsy + cfg.rows - 1) / cfg.rows;
@@ -157,6 +160,39 @@ int check_options(const nmpc_options *o)
     if (o->tile_rows < 0 || o->tile_rows > 16) return fail(NMPC_E_ARG, "tile_rows must be 0..16");
     if (o->warm_sweeps < 0 || o->warm_sweeps > 1000) return fail(NMPC_E_ARG, "warm_sweeps must be 0..1000");
     if (o->fallback != 0 && o->fallback != 1) return fail(NMPC_E_ARG, "fallback must be 0 or 1");
+    if (o->upper < NMPC_UPPER_JACOBI || o->upper > NMPC_UPPER_SGS)
+        return fail(NMPC_E_ARG, "unknown upper layer");
+    return NMPC_OK;
+}
+
+int main_prec(const nmpc_options &o)
+{
+    return o.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
+}
+
+// Kernels of both precisions for the handle's upper layer (tile_rows applies
+// to the main precision), with their LDS limits raised where needed.
+int select_all(const nmpc_problem *p, const nmpc_options *o, nmpc_handle::Kern (&jk)[2],
+               nmpc_handle::Kern (&gk)[2])
+{
+    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
+        const int ry = prec == main_prec(*o) ? o->tile_rows : 0;
+        const bool gs = o->upper != NMPC_UPPER_JACOBI;
+        // the Jacobi kernel always exists: residual launches (fallback) use it
+        int rc = select_kernel(p, prec, gs ? 0 : ry, &jk[prec]);
+        if (rc) return rc;
+        if (gs) {
+            rc = select_kernel(p, prec, ry, &gk[prec], true);
+            if (rc) return rc;
+        }
+    }
+    return NMPC_OK;
+}
+
+int raise_lds(const nmpc_handle::Kern &k)
+{
+    if (k.fn && k.lds > 48 * 1024)
+        HIP_TRY(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
     return NMPC_OK;
 }
 
@@ -361,12 +397,59 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
 
 // Run the upper iteration for `count` instances whose x0/xref already sit in
 // the handle's buffers; S^0 from the warm pointers (device, dense) or cold.
+// Each instance's returned iterate (buffer iters[b] & 1) to the outputs.
+int launch_output(nmpc_handle *h, int count, double *ox, double *ou, double *ol)
+{
+    OutArgs oa{};
+    oa.count = count; oa.N = h->N; oa.m = h->m; oa.iters = h->d_iters;
+    oa.nsx = h->prob.nsx; oa.nsy = h->prob.nsy; oa.sx = h->sx;
+    for (int b = 0; b < 2; ++b) { oa.X[b] = h->X(b); oa.U[b] = h->U(b); oa.LAM[b] = h->L(b); }
+    oa.ox = ox; oa.ou = ou; oa.ol = ol;
+    void *args[] = {(void *)&oa};
+    HIP_TRY(hipLaunchKernel(nmpc::output_kernel(), dim3(launch_grid((size_t)count * h->N * h->n)),
+                            dim3(256), args, 0, h->stream));
+    return NMPC_OK;
+}
+
+// Gauss-Seidel upper layer: one launch per precision phase, one workgroup
+// per instance; the kernels take every decision themselves.
+int run_gs(nmpc_handle *h, int count)
+{
+    IterArgs a = iter_args(h, count);
+    a.units = count;
+    int upper = h->opt.upper;
+    void *args[] = {(void *)&a, (void *)&upper};
+    if (h->timing) HIP_TRY(hipEventRecord(h->t0, h->stream));
+    int launches = 0;
+    for (int prec : {nmpc::kModeFp32, nmpc::kModeFp64}) {
+        if (prec == nmpc::kModeFp32 && main_prec(h->opt) != nmpc::kModeFp32) continue;
+        const nmpc_handle::Kern &k = h->gs[prec];
+        HIP_TRY(hipLaunchKernel(k.fn, dim3(count), dim3(nmpc::kWave * k.waves), args, k.lds,
+                                h->stream));
+        ++launches;
+    }
+    if (h->timing) {
+        HIP_TRY(hipEventRecord(h->t1, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
+        h->kernel_ms += ms;
+        h->launches += launches;
+    }
+    return NMPC_OK;
+}
+
 int run(nmpc_handle *h, int count, const double *wx, const double *wu, const double *wl,
         double *ox, double *ou, double *ol)
 {
     {
         const int rc = build_start(h, count, wx, wu, wl);
         if (rc) return rc;
+    }
+    if (h->opt.upper != NMPC_UPPER_JACOBI) {
+        const int rc = run_gs(h, count);
+        if (rc) return rc;
+        return launch_output(h, count, ox, ou, ol);
     }
     // Phase FP32 (FP32-sweep precision) runs until no instance is left in
     // FP32 mode, then phase FP64 until every instance has finished. Each
@@ -396,18 +479,7 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
         if (launched > cap)
             return fail(NMPC_E_DEVICE, "instances did not finish within max_iter launches");
     }
-    OutArgs oa{};
-    oa.count = count; oa.N = h->N; oa.m = h->m; oa.iters = h->d_iters;
-    oa.nsx = h->prob.nsx; oa.nsy = h->prob.nsy; oa.sx = h->sx;
-    for (int b = 0; b < 2; ++b) { oa.X[b] = h->X(b); oa.U[b] = h->U(b); oa.LAM[b] = h->L(b); }
-    oa.ox = ox; oa.ou = ou; oa.ol = ol;
-    {
-        void *args[] = {(void *)&oa};
-        HIP_TRY(hipLaunchKernel(nmpc::output_kernel(),
-                                dim3(launch_grid((size_t)count * h->N * h->n)), dim3(256), args,
-                                0, h->stream));
-    }
-    return NMPC_OK;
+    return launch_output(h, count, ox, ou, ol);
 }
 
 int collect_info(nmpc_handle *h, int count, nmpc_info *info)
@@ -463,6 +535,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->tile_rows = 0;
     opt->warm_sweeps = 0;
     opt->fallback = 0;
+    opt->upper = NMPC_UPPER_JACOBI;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
@@ -484,13 +557,8 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->n = prob->nsx * prob->nsy;
     h->m = prob->lx * prob->ly;
     h->N = prob->horizon;
-    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
-        const int ry = prec == (opt->precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32
-                                                                   : nmpc::kModeFp64)
-                           ? opt->tile_rows : 0;
-        rc = select_kernel(prob, prec, ry, &h->kern[prec]);
-        if (rc) { delete h; return rc; }
-    }
+    rc = select_all(prob, opt, h->kern, h->gs);
+    if (rc) { delete h; return rc; }
     h->gx.assign(prob->gx, prob->gx + (size_t)prob->lx * prob->nsx);
     h->gy.assign(prob->gy, prob->gy + (size_t)prob->ly * prob->nsy);
     h->prob.gx = h->gx.data();
@@ -536,9 +604,10 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(int), hipHostMallocDefault);
     for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32})
-        if (e == hipSuccess && h->kern[prec].lds > 48 * 1024)
-            e = hipFuncSetAttribute(h->kern[prec].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)h->kern[prec].lds);
+        for (const nmpc_handle::Kern *k : {&h->kern[prec], &h->gs[prec]})
+            if (e == hipSuccess && k->fn && k->lds > 48 * 1024)
+                e = hipFuncSetAttribute(k->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)k->lds);
     if (e == hipSuccess && h->roll.lds > 48 * 1024)
         e = hipFuncSetAttribute(h->roll.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)h->roll.lds);
@@ -567,20 +636,17 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
     int rc = check_options(opt);
     if (rc) return rc;
-    nmpc_handle::Kern kn[2];
+    nmpc_handle::Kern kn[2], gn[2];
+    rc = select_all(&h->prob, opt, kn, gn);
+    if (rc) return rc;
     for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
-        const int ry = prec == (opt->precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32
-                                                                   : nmpc::kModeFp64)
-                           ? opt->tile_rows : 0;
-        rc = select_kernel(&h->prob, prec, ry, &kn[prec]);
-        if (rc) return rc;
+        if ((rc = raise_lds(kn[prec]))) return rc;
+        if ((rc = raise_lds(gn[prec]))) return rc;
     }
-    for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32})
-        if (kn[prec].lds > 48 * 1024)
-            HIP_TRY(hipFuncSetAttribute(kn[prec].fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)kn[prec].lds));
     h->kern[0] = kn[0];
     h->kern[1] = kn[1];
+    h->gs[0] = gn[0];
+    h->gs[1] = gn[1];
     if (opt->xref_per_stage != h->opt.xref_per_stage)
         h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
     h->opt = *opt;
@@ -764,27 +830,38 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
     int rc = stage_inputs(h, count, x0, xref);
     if (rc) return rc;
-    const nmpc_handle::Kern keep = h->kern[prec];
+    const bool gs = h->opt.upper != NMPC_UPPER_JACOBI;
+    nmpc_handle::Kern &slot = gs ? h->gs[prec] : h->kern[prec];
+    const nmpc_handle::Kern keep = slot;
     int best_ry = -1;
     float best_ms = 0.f;
     nmpc_handle::Kern best{};
     for (int ry = 1; ry <= 16; ++ry) {
         nmpc_handle::Kern k;
-        if (select_kernel(&h->prob, prec, ry, &k) != NMPC_OK) continue;   // no such tile
-        if (k.lds > 48 * 1024)
-            HIP_TRY(hipFuncSetAttribute(k.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)k.lds));
-        h->kern[prec] = k;
+        if (select_kernel(&h->prob, prec, ry, &k, gs) != NMPC_OK) continue;   // no such tile
+        if ((rc = raise_lds(k))) return rc;
+        slot = k;
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {   // the first pass loads code and warms caches
             rc = build_start(h, count, nullptr, nullptr, nullptr);
-            if (rc) { h->kern[prec] = keep; return rc; }
+            if (rc) { slot = keep; return rc; }
             IterArgs a = iter_args(h, count);
             HIP_TRY(hipEventRecord(h->t0, h->stream));
-            for (int t = 0; t < iters && rc == NMPC_OK; ++t) {
-                a.kofs = t;
-                rc = launch_iterate(h, prec, a, h->stream);
+            if (gs) {   // `iters` iterations of the main-precision kernel, no early exit
+                a.units = count;
+                a.tol = -1.0;
+                a.max_iter = iters;
+                int upper = h->opt.upper;
+                void *args[] = {(void *)&a, (void *)&upper};
+                HIP_TRY(hipLaunchKernel(k.fn, dim3(count), dim3(nmpc::kWave * k.waves), args,
+                                        k.lds, h->stream));
+            } else {
+                for (int t = 0; t < iters && rc == NMPC_OK; ++t) {
+                    a.kofs = t;
+                    rc = launch_iterate(h, prec, a, h->stream);
+                }
             }
-            if (rc) { h->kern[prec] = keep; return rc; }
+            if (rc) { slot = keep; return rc; }
             HIP_TRY(hipEventRecord(h->t1, h->stream));
             HIP_TRY(hipStreamSynchronize(h->stream));
             HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
@@ -792,8 +869,8 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
         if (best_ry < 0 || ms < best_ms) { best_ry = ry; best_ms = ms; best = k; }
     }
     g_err.clear();
-    if (best_ry < 0) { h->kern[prec] = keep; return fail(NMPC_E_UNSUPPORTED, "no tile to tune"); }
-    h->kern[prec] = best;
+    if (best_ry < 0) { slot = keep; return fail(NMPC_E_UNSUPPORTED, "no tile to tune"); }
+    slot = best;
     h->opt.tile_rows = best_ry;
     h->graph_count[0] = h->graph_count[1] = -1;
     if (tile_rows) *tile_rows = best_ry;
@@ -804,10 +881,12 @@ int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *wa
                        int32_t *workgroups)
 {
     if (!h) return NMPC_E_ARG;
-    const int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
-    if (rows_per_lane) *rows_per_lane = h->kern[prec].cfg.rows;
-    if (waves) *waves = h->kern[prec].waves;
-    if (workgroups) *workgroups = 8 * ((h->max_batch * h->N + 7) / 8);
+    const int prec = main_prec(h->opt);
+    const bool gs = h->opt.upper != NMPC_UPPER_JACOBI;
+    const nmpc_handle::Kern &k = gs ? h->gs[prec] : h->kern[prec];
+    if (rows_per_lane) *rows_per_lane = k.cfg.rows;
+    if (waves) *waves = k.waves;
+    if (workgroups) *workgroups = gs ? h->max_batch : 8 * ((h->max_batch * h->N + 7) / 8);
     return NMPC_OK;
 }
 

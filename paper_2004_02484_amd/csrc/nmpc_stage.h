@@ -430,23 +430,41 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
 
 // Where one unit's data lives: its instance's trajectories start at element
 // so (X, LAM) and uo (U) of the iterate buffers, its padded x0 at xo and its
-// xref_i at xro; i is the stage, cur the buffer of S^j. The pointers
+// xref_i at xro; i is the stage. The stage reads s_i from buffer src and
+// writes its new value to buffer dst; the neighbour values x_{i-1} and
+// lambda_{i+1} that enter the update come from buffers xpb / lnb, those that
+// enter the residual of S^j from xrb / lrb (they differ in Gauss-Seidel
+// sweeps, where the update sees neighbours already updated in this sweep).
+// utb >= 0 names the buffer of the regularization reference u~ when it is not
+// the stage's own input (then K^u carries gamma (u - u~)). The pointers
 // themselves stay in the kernel arguments, which the compiler may reload
 // instead of keeping them live.
 struct StageLoc {
     long long so, uo, xo, xro;
-    long long res_at;              // index into a.rst / a.pst
-    int i, cur;
+    long long res_at;              // >= 0: index into a.rst / a.pst; -1: accumulate into
+                                   // the caller's norms only; -2: no residual
+    int i, src, dst, xpb, xrb, lnb, lrb, utb;
     bool last;                     // i is the last stage
 };
 
+__device__ __forceinline__ StageLoc jacobi_loc(int cur)
+{
+    StageLoc v{};
+    v.src = v.xpb = v.xrb = v.lnb = v.lrb = cur;
+    v.dst = cur ^ 1;
+    v.utb = -1;
+    return v;
+}
+
+// acc (thread 0 only): running bit-pattern max of (r_scaled, r_paper) over
+// the stages processed with res_at == -1.
 template <typename T, int CX, int RY, int LX, int LY>
 __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &P,
-                                           const StageLoc &v, Ctx &c)
+                                           const StageLoc &v, Ctx &c,
+                                           unsigned long long (&acc)[2])
 {
     constexpr int M = LX * LY;
     const int n = P.n;
-    const int cur = v.cur, nxt = cur ^ 1;
     double *uvec = lds_ptr<double>(c, c.off.uvec);
     double *v3 = lds_ptr<double>(c, c.off.v3);
     double *kun = lds_ptr<double>(c, c.off.kun);
@@ -457,11 +475,16 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     // last stage), xref_i, all with the padded row stride sx = 16 * CX: a
     // lane's tile lies inside a row or entirely in its zero padding
     const bool last = v.last;
+    const bool want_res = v.res_at != -2;
     const size_t si = (size_t)v.so + (size_t)v.i * n;
-    const double *Xc = a.X[cur] + si;
-    const double *Lc = a.LAM[cur] + si;
-    const double *Xp = v.i == 0 ? a.x0 + v.xo : a.X[cur] + (si - n);
-    const double *Ln = a.LAM[cur] + (si + n);
+    const double *Xc = a.X[v.src] + si;
+    const double *Lc = a.LAM[v.src] + si;
+    const double *Xp = v.i == 0 ? a.x0 + v.xo : a.X[v.xpb] + (si - n);
+    const double *Xq = v.i == 0 ? Xp : a.X[v.xrb] + (si - n);
+    const double *Ln = a.LAM[v.lnb] + (si + n);
+    const double *Lq = a.LAM[v.lrb] + (si + n);
+    const bool xdiff = want_res && v.i > 0 && v.xrb != v.xpb;
+    const bool ldiff = want_res && !last && v.lrb != v.lnb;
     const double *Xr = a.xref + v.xro;
     const int ix0 = c.cl * CX, iy0 = c.G * RY;
     const int sx = 16 * CX;
@@ -485,7 +508,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 xc[t][q] = v ? Xc[pidx(t, q)] : 0.0;
                 lc[t][q] = v ? Lc[pidx(t, q)] : 0.0;
             }
-        if (c.tid < M) uvec[c.tid] = a.U[cur][v.uo + (size_t)v.i * M + c.tid];
+        if (c.tid < M) uvec[c.tid] = a.U[v.src][v.uo + (size_t)v.i * M + c.tid];
         nbsum<double, CX, RY>(xc, Lx, c);
 #pragma unroll
         for (int t = 0; t < RY; ++t)
@@ -504,16 +527,17 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 for (int q = 0; q < CX; ++q) {
                     // nodes off the grid have no KKT row: their stencil of a
                     // valid neighbour is dropped (norms, right-hand sides)
-                    double kl = 0.0;
+                    double kl = 0.0, klr = 0.0;
                     if (valid(t, q)) {
                         const double ln = last ? 0.0 : Ln[pidx(t, q)];
                         const double xr = Xr[pidx(t, q)];
                         const double gg = P.k0 * (1.0 + P.k1 * xc[t][q]) * lc[t][q];
-                        kl = ln - lc[t][q] +
-                             h * (P.q * (xc[t][q] - xr) + (Lg[t][q] - P.c0 * gg) +
-                                  kp * Lx[t][q] * lc[t][q]);
+                        const double rest = h * (P.q * (xc[t][q] - xr) + (Lg[t][q] - P.c0 * gg) +
+                                                 kp * Lx[t][q] * lc[t][q]);
+                        kl = ln - lc[t][q] + rest;
+                        klr = ldiff ? Lq[pidx(t, q)] - lc[t][q] + rest : kl;
                     }
-                    ml = umax64(ml, abits(kl));
+                    ml = umax64(ml, abits(klr));
                     b2[t][q] = T(kl);
                 }
         }
@@ -525,12 +549,14 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             for (int t = 0; t < RY; ++t)
 #pragma unroll
                 for (int q = 0; q < CX; ++q) {
-                    double kx = 0.0;
+                    double kx = 0.0, kxr = 0.0;
                     if (valid(t, q)) {
                         const double kk = P.k0 * (1.0 + P.k1 * xc[t][q]);
-                        kx = Xp[pidx(t, q)] - xc[t][q] + h * (kk * Lx[t][q] + Bu[t][q]);
+                        const double fx = h * (kk * Lx[t][q] + Bu[t][q]);
+                        kx = Xp[pidx(t, q)] - xc[t][q] + fx;
+                        kxr = xdiff ? Xq[pidx(t, q)] - xc[t][q] + fx : kx;
                     }
-                    mx = umax64(mx, abits(kx));
+                    mx = umax64(mx, abits(kxr));
                     b1[t][q] = T(kx);
                 }
         }
@@ -550,39 +576,52 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     }
     unsigned long long mu = 0;
     if (c.tid < M) {
-        const double ku = h * (P.r * uvec[c.tid] + red[c.tid]);   // u~ = u: no gamma term
-        kun[c.tid] = ku;
+        // with u~ = u^k the gamma term vanishes at evaluation; a stage whose
+        // reference is another buffer's input (second sweep of SGS) keeps it
+        const double ku = h * (P.r * uvec[c.tid] + red[c.tid]);
+        const double reg = v.utb >= 0
+            ? P.gamma * (uvec[c.tid] - a.U[v.utb][v.uo + (size_t)v.i * M + c.tid]) : 0.0;
+        kun[c.tid] = ku + reg;
         v3[c.tid] = 0.0;
         mu = abits(ku);
     }
-    mx = wave_max64(mx);
-    ml = wave_max64(ml);
-    mu = wave_max64(mu);
-    if (c.lane == 0) {
-        nrm[c.w * 4 + 0] = mx;
-        nrm[c.w * 4 + 1] = ml;
-        nrm[c.w * 4 + 2] = mu;
-    }
-    __syncthreads();
-    if (c.tid == 0) {
-        unsigned long long ax = 0, al = 0, au = 0;
-        for (int ww = 0; ww < c.W; ++ww) {
-            ax = umax64(ax, nrm[ww * 4 + 0]);
-            al = umax64(al, nrm[ww * 4 + 1]);
-            au = umax64(au, nrm[ww * 4 + 2]);
+    if (want_res) {
+        mx = wave_max64(mx);
+        ml = wave_max64(ml);
+        mu = wave_max64(mu);
+        if (c.lane == 0) {
+            nrm[c.w * 4 + 0] = mx;
+            nrm[c.w * 4 + 1] = ml;
+            nrm[c.w * 4 + 2] = mu;
         }
-        const double dx_ = bits2d(ax), dl_ = bits2d(al), du_ = bits2d(au);
-        double rp = dx_ > du_ ? dx_ : du_;
-        rp = rp > dl_ ? rp : dl_;
-        double rs = dx_, su = du_ / (h * P.r), sl = dl_ / h;
-        rs = rs > su ? rs : su;
-        rs = rs > sl ? rs : sl;
-        // NaN-propagating: any non-finite row makes both norms non-finite
-        const bool bad = (ax >= 0x7FF0000000000000ull) || (al >= 0x7FF0000000000000ull) ||
-                         (au >= 0x7FF0000000000000ull);
-        if (bad) { rs = __longlong_as_double(0x7FF8000000000000ll); rp = rs; }
-        a.rst[v.res_at] = abits(rs);
-        a.pst[v.res_at] = abits(rp);
+        __syncthreads();
+        if (c.tid == 0) {
+            unsigned long long ax = 0, al = 0, au = 0;
+            for (int ww = 0; ww < c.W; ++ww) {
+                ax = umax64(ax, nrm[ww * 4 + 0]);
+                al = umax64(al, nrm[ww * 4 + 1]);
+                au = umax64(au, nrm[ww * 4 + 2]);
+            }
+            const double dx_ = bits2d(ax), dl_ = bits2d(al), du_ = bits2d(au);
+            double rp = dx_ > du_ ? dx_ : du_;
+            rp = rp > dl_ ? rp : dl_;
+            double rs = dx_, su = du_ / (h * P.r), sl = dl_ / h;
+            rs = rs > su ? rs : su;
+            rs = rs > sl ? rs : sl;
+            // NaN-propagating: any non-finite row makes both norms non-finite
+            const bool bad = (ax >= 0x7FF0000000000000ull) || (al >= 0x7FF0000000000000ull) ||
+                             (au >= 0x7FF0000000000000ull);
+            if (bad) { rs = __longlong_as_double(0x7FF8000000000000ll); rp = rs; }
+            if (v.res_at >= 0) {
+                a.rst[v.res_at] = abits(rs);
+                a.pst[v.res_at] = abits(rp);
+            } else {
+                acc[0] = umax64(acc[0], abits(rs));
+                acc[1] = umax64(acc[1], abits(rp));
+            }
+        }
+    } else {
+        __syncthreads();   // publish kun / v3 (the norm path's barrier)
     }
     if (a.residual_only) return;
 
@@ -645,8 +684,8 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     }
 
     // ---- update S^{j+1} = S^j - ds (FP64); x_i, lam_i re-read (L2-resident)
-    double *Xn = a.X[nxt] + si;
-    double *Lw = a.LAM[nxt] + si;
+    double *Xn = a.X[v.dst] + si;
+    double *Lw = a.LAM[v.dst] + si;
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -656,7 +695,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 Xn[p] = Xc[p] - double(y5[t][q]);
                 Lw[p] = Lc[p] - double(y4[t][q]);
             }
-    if (c.tid < M) a.U[nxt][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - v3[c.tid];
+    if (c.tid < M) a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - v3[c.tid];
 }
 
 // The separable input factors gx [LX][nsx], gy [LY][nsy] into LDS (double and

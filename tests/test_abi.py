@@ -30,6 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_are_the_papers_lower_layer():
     o = nm.nmpc_default_options()
     assert (o.n_sweep, o.n_schur, o.precision) == (2, 2, nm.NMPC_FP64)
+    assert o.upper == nm.NMPC_UPPER_JACOBI
     assert o.tol == 1e-6 and o.check_every >= 1
 
 
@@ -65,7 +66,7 @@ def test_unsupported_shapes_reported():
 @pytest.mark.parametrize("field,value", [("n_sweep", 0), ("n_sweep", 17), ("n_schur", -1),
                                          ("precision", 7), ("check_every", 0),
                                          ("max_iter", -1), ("tol", -1.0), ("tile_rows", -1),
-                                         ("tile_rows", 17)])
+                                         ("tile_rows", 17), ("upper", 4), ("upper", -1)])
 def test_invalid_options_rejected(field, value):
     o = nm.nmpc_default_options(**{field: value})
     with pytest.raises(nm.NmpcError) as e:
@@ -100,6 +101,7 @@ def _grid(ns, N, lattice=4):
     ([("grid", 32, 4, 4)], {"xref_per_stage": 1}, nm.NMPC_E_UNSUPPORTED),
     ([("grid", 32, 4, 4)], {"n_sweep": 0}, nm.NMPC_E_ARG),
     ([("grid", 32, 0, 4)], {}, nm.NMPC_E_ARG),                           # horizon 0
+    ([("grid", 32, 4, 4)], {"upper": 3}, nm.NMPC_E_UNSUPPORTED),         # SGS not ragged
 ])
 def test_ragged_create_validates_before_any_device_call(classes, opts, code):
     cl = [make_problem("c0") if c[0] == "c0" else _grid(c[1], c[2], c[3]) for c in classes]
