@@ -12,8 +12,10 @@ batches are then solved from the cold start for the comparison. Inputs for
 every step are generated and copied to HBM before the timed region; each step
 uses its own seeds, disjoint from the network's training seeds.
 
-Prints one JSON line with the metric, the roofline of the dominant kernel
-(the fused upper-iteration kernel, measured with HIP events on the library's
+The upper layer is the paper's symmetric Gauss-Seidel (eq. sgs) by default
+(--upper jacobi|fgs|bgs|sgs). Prints one JSON line with the metric, the
+roofline of the dominant kernel (the persistent Gauss-Seidel kernel, or the
+fused Jacobi iteration kernel, measured with HIP events on the library's
 stream over the timed region), the network's matrix-core rate and the CPU
 oracle timed on a bounded sample of the same workload.
 """
@@ -33,8 +35,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-KERNEL_SRC = os.path.join(ROOT, "paper_2004_02484_amd", "csrc", "nmpc_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_c1_b256_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2004_02484_amd", "csrc")
+UPPER = {"jacobi": 0, "fgs": 1, "bgs": 2, "sgs": 3}
+# dominant kernel per upper layer: (name, sources it is built from, counter summary)
+KERNELS = {
+    "jacobi": ("k_iterate (fused upper iteration, all stages in parallel)",
+               ("nmpc_kernels.hip", "nmpc_stage.h"), "k_iterate_c1_b256_traffic.json"),
+    "gs": ("k_gs (persistent Gauss-Seidel sweeps, one workgroup per instance)",
+           ("nmpc_gs.hip", "nmpc_stage.h"), "k_gs_c1_b256_traffic.json"),
+}
 WEIGHTS = os.path.join(ROOT, "paper_2004_02484_amd", "weights", "c1_patchnet.npz")
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 EVAL_SEED0 = 1_000_000         # disjoint from any training seeds
@@ -47,34 +56,39 @@ def bytes_per_unit(n: int, m: int, N: int, word: int = 8) -> float:
     return word * (2.0 * (2 * n + m) + 2.0 * n / N)
 
 
-def kernel_digest() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_digest(sources) -> str:
+    h = hashlib.sha256()
+    for src in sources:
+        with open(os.path.join(CSRC, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def traffic_per_launch(units_per_launch: float):
+def traffic_per_launch(kind: str, units_per_launch: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source (else None)."""
+    _, sources, fname = KERNELS[kind]
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", fname)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_digest") != kernel_digest():
+    if t.get("kernel_digest") != kernel_digest(sources):
         return None
     return t["bytes_per_unit"] * units_per_launch
 
 
-def cpu_baseline(P, x0s, xrefs, budget_s: float):
-    """The oracle (plain C, FP64, OpenMP over stages) on a bounded sample of
-    the first timed batch: cold start, same tolerance and schedule."""
+def cpu_baseline(P, x0s, xrefs, budget_s: float, upper: str):
+    """The oracle (plain C, FP64; OpenMP over stages in its KKT evaluation and,
+    for Jacobi, its stage solves) on a bounded sample of the first timed batch:
+    cold start, same upper layer, tolerance and schedule."""
     import oracle
     oracle.build(force=False)
     t0 = time.perf_counter()
     done = 0
     iters = []
     for b in range(x0s.shape[0]):
-        o = oracle.solve(P, x0s[b], xrefs[b], tol=1e-6, max_iter=5000)
+        o = oracle.solve(P, x0s[b], xrefs[b], tol=1e-6, max_iter=5000, upper=upper)
         iters.append(o["iters"])
         done += 1
         if time.perf_counter() - t0 >= budget_s:
@@ -83,8 +97,8 @@ def cpu_baseline(P, x0s, xrefs, budget_s: float):
     return {"value": done / dt, "unit": "solves/s", "cores": oracle.threads(),
             "kind": "oracle",
             "sample": f"{done} of the 256 instances of the first timed batch, 64x64 N=40, "
-                      f"cold start, tol 1e-6, iterations {min(iters)}..{max(iters)}, "
-                      f"{dt:.1f} s"}
+                      f"cold start, {upper} upper layer, tol 1e-6, iterations "
+                      f"{min(iters)}..{max(iters)}, {dt:.1f} s"}
 
 
 def net_flops(net, count: int) -> float:
@@ -122,6 +136,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--upper", choices=list(UPPER), default="sgs",
+                    help="upper-layer splitting: the paper's SGS (default) or Jacobi, FGS, BGS")
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -145,7 +161,8 @@ def main():
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
-                       check_every=16, fallback=1)
+                       check_every=16, fallback=1, upper=UPPER[args.upper])
+    kind = "jacobi" if args.upper == "jacobi" else "gs"
     net = None
     if args.start == "learned":
         if not os.path.exists(args.weights):
@@ -193,8 +210,8 @@ def main():
     achieved = bpu * units_per_launch / avg_launch_s / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_per_launch(units_per_launch),
-            "kernel": "k_iterate (fused upper iteration)",
+            "traffic": traffic_per_launch(kind, units_per_launch),
+            "kernel": KERNELS[kind][0],
             "avg_launch_us": round(avg_launch_s * 1e6, 1),
             "units_per_launch": round(units_per_launch, 1),
             "bytes_per_unit": bpu}
@@ -202,8 +219,9 @@ def main():
     start_desc = "learned warm start (network + rollout + adjoint, cold fallback)" \
         if net is not None else "cold start"
     cfg = {"workload": "2D nonlinear heat 64x64, N=40, 16 Gaussian inputs, batch 256, "
-                       f"{start_desc}, tol 1e-6",
+                       f"{start_desc}, {args.upper.upper()} upper layer, tol 1e-6",
            "global_batch": B, "grid": "64x64", "horizon": P.N, "start": args.start,
+           "upper": args.upper,
            "iters_min": int(min(iters)), "iters_max": int(max(iters)),
            "iters_mean": round(float(np.mean(iters)), 1), "status_worst": worst,
            "step_ms_median": round(1e3 * float(np.median(times)), 2),
@@ -217,6 +235,7 @@ def main():
                                         np.bincount(used, minlength=3))},
                     "plain_solves_per_s": round(plain, 2),
                     "plain_iters_mean": round(float(np.mean(citers)), 1),
+                    "plain_iters_max": int(max(citers)),
                     "plain_status_worst": cworst,
                     "speedup_vs_plain": round(value / plain, 3)})
         # network rate on the matrix cores (inference only)
@@ -249,7 +268,7 @@ def main():
     }
     if args.cpu_budget > 0:
         result["cpu_baseline"] = cpu_baseline(P, host[args.warmup][0], host[args.warmup][1],
-                                              args.cpu_budget)
+                                              args.cpu_budget, args.upper)
     print(json.dumps(result), flush=True)
     solver.close()
 

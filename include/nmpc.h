@@ -85,9 +85,12 @@ typedef struct nmpc_options {
     int32_t n_sweep;      /* point-Jacobi sweeps per F_x / F_x^T solve, 1..16 */
     int32_t n_schur;      /* Schur input iterations, 0..16 */
     int32_t precision;    /* NMPC_FP64, or NMPC_FP32_SWEEP: lower layer in FP32,
-                             S, K, the norms and the test in FP64, and once the
-                             test passes, FP64 iterations continue until an FP64
-                             step's result passes it (final FP64 correction) */
+                             S, K, the norms and the test in FP64; once the
+                             test passes at S^j, one FP64 step is taken from S^j
+                             (Jacobi: one iteration; Gauss-Seidel: the first
+                             sweep of an iteration) and FP64 iterations continue
+                             until the test passes at an FP64-stepped iterate
+                             (final FP64 correction) */
     int32_t check_every;  /* iterations between host convergence polls (>= 1) */
     int32_t xref_per_stage; /* 0: xref is [n] per instance; 1: [N][n] */
     int32_t tile_rows;    /* grid rows per lane of the stage kernel's register

@@ -25,9 +25,12 @@
 
 namespace nmpc {
 
+// One sweep over the stages of instance b (dir > 0 forward). res: accumulate
+// the residual of the source iterate into acc; res_only: residual only.
 template <typename T, int CX, int RY, int LX, int LY>
 __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int dir, int src,
-                                         int dst, int utb, bool res, unsigned long long (&acc)[2])
+                                         int dst, int utb, bool res, bool res_only,
+                                         unsigned long long (&acc)[2])
 {
     const int N = a.P.N, n = a.P.n, M = LX * LY;
     StageLoc v{};
@@ -38,6 +41,7 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.dst = dst;
     v.utb = utb;
     v.res_at = res ? -1 : -2;
+    v.res_only = res_only;
     // forward: x_{i-1} updated (dst), lambda_{i+1} not yet (src); backward:
     // the reverse. The residual of S^j takes both from src.
     v.xpb = dir > 0 ? dst : src;
@@ -54,9 +58,11 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
 }
 
 // upper: kUpperFgs, kUpperBgs or kUpperSgs. The FP32 kernel runs an instance's
-// FP32-sweep iterations until its test passes (mode -> kModeFp64Redo); the
-// FP64 kernel then takes at least one FP64 iteration and continues until the
-// test passes at an iterate reached by an FP64 iteration.
+// FP32-sweep iterations until its test passes at S^j (mode -> kModeFp64Redo);
+// the FP64 kernel then takes one FP64 correction sweep from S^j (the first
+// sweep of the variant's iteration), checks the result with a residual-only
+// pass and returns it if the test passes, else continues with FP64
+// iterations.
 template <int PREC, int CX, int RY, int WB, int LX, int LY>
 __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const int upper)
 {
@@ -72,13 +78,21 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
     if (PREC == kModeFp32 && s.mode != kModeFp32) return;
     load_tables<CX, RY, LX, LY>(c, a.gx, a.gy, a.P.nsx, a.P.nsy);
     unsigned long long *bc = lds_ptr<unsigned long long>(c, c.off.nrm);
-    int owed = s.mode == kModeFp64Redo ? 1 : 0;   // FP64 iterations still owed
+    const int dir1 = upper == kUpperFgs ? 1 : -1;   // first sweep of an iteration
     int j = s.j, fin = -1;
+    bool check_only = false;
     double rs = 0.0, rp = 0.0;
+    if (PREC == kModeFp64 && s.mode == kModeFp64Redo) {
+        unsigned long long none[2] = {0, 0};
+        gs_sweep<T, CX, RY, LX, LY>(a, c, b, dir1, j & 1, (j & 1) ^ 1, -1, false, false, none);
+        ++s.e;
+        ++j;
+        check_only = true;
+    }
     for (;;) {
         const int p = j & 1, q = p ^ 1;
         unsigned long long acc[2] = {0, 0};
-        gs_sweep<T, CX, RY, LX, LY>(a, c, b, upper == kUpperFgs ? 1 : -1, p, q, -1, true, acc);
+        gs_sweep<T, CX, RY, LX, LY>(a, c, b, dir1, p, q, -1, true, check_only, acc);
         ++s.e;
         __syncthreads();
         if (c.tid == 0) { bc[0] = acc[0]; bc[1] = acc[1]; }
@@ -89,16 +103,20 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
         if (!(rs <= 1.7976931348623157e308)) { fin = kStatusNonfinite; break; }
         if (rs <= a.tol) {
             if (PREC == kModeFp32) { s.mode = kModeFp64Redo; break; }
-            if (owed <= 0) { fin = kStatusOk; break; }
+            fin = kStatusOk;
+            break;
         }
         if (j >= a.max_iter) { fin = kStatusNoconv; break; }
+        if (check_only) {   // the corrected iterate missed the test: iterate on in FP64
+            check_only = false;
+            continue;
+        }
         if (upper == kUpperSgs) {
-            gs_sweep<T, CX, RY, LX, LY>(a, c, b, 1, q, q, p, false, acc);
+            gs_sweep<T, CX, RY, LX, LY>(a, c, b, 1, q, q, p, false, false, acc);
             ++s.e;
         }
         ++j;
         if (PREC == kModeFp32) ++s.f32;
-        else --owed;
     }
     if (c.tid == 0) {
         s.j = j;

@@ -340,8 +340,9 @@ struct Decision {
 // state into the other parity slot. PREC is this kernel's precision (kModeFp32 or kModeFp64); an
 // instance in another mode waits for the kernel of its precision.
 //   FP32 mode, test passed at S^j  -> REDO (FP32-active count decremented)
-//   REDO (FP64 kernel)             -> re-evaluate S^j in FP64, owe one step
-//   FP64 mode, test passed, owed   -> take the FP64 step S^{j+1}
+//   REDO (FP64 kernel)             -> re-evaluate S^j in FP64: its update is the
+//                                     FP64 step S^{j+1}; owe the evaluation of S^{j+1}
+//   FP64 mode, test passed, owed   -> evaluate S^{j+1} (its own test decides)
 //   FP64 mode, test passed         -> finished, S^j returned
 // Nb: the instance's stages; rbase: offset of its stage residuals within a
 // residual slot (slot stride a.rslot).
@@ -445,6 +446,7 @@ struct StageLoc {
                                    // the caller's norms only; -2: no residual
     int i, src, dst, xpb, xrb, lnb, lrb, utb;
     bool last;                     // i is the last stage
+    bool res_only;                 // stop after the residual (no lower layer, no update)
 };
 
 __device__ __forceinline__ StageLoc jacobi_loc(int cur)
@@ -623,7 +625,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     } else {
         __syncthreads();   // publish kun / v3 (the norm path's barrier)
     }
-    if (a.residual_only) return;
+    if (a.residual_only || v.res_only) return;
 
     // ---- lower layer (T)
     const T hT = T(h), qT = T(P.q), c0T = T(P.c0);
