@@ -129,6 +129,40 @@ def timed_steps(solver, batches, out, net=None, ubuf=None):
     return times, iters, used, worst
 
 
+def closed_loop(solver, net, P, x0, xr, steps: int, ubuf):
+    """Closed loop of `steps` NMPC steps per instance of one batch (the plant
+    is one explicit-Euler step of the model with the applied first input).
+    Step 1 starts cold; steps 2..steps are solved three ways on the same
+    states: cold, shifted previous solution, learned. Returns per start kind
+    solves/s and iterations over steps 2..steps."""
+    import torch
+    B = x0.shape[0]
+    rc, X, U, L, _ = solver.solve_batch(x0, xr)
+    X, U, L = X.clone(), U.clone(), L.clone()
+    out = {k: {"t": 0.0, "it": []} for k in ("cold", "shifted", "learned")}
+    xs = x0.clone()
+    for _ in range(2, steps + 1):
+        xs = solver.plant_step_batch(xs, U, P.h)
+        warm = solver.shift_batch(X, U, L)
+        torch.cuda.synchronize()
+        for kind in ("cold", "learned", "shifted"):
+            t = time.perf_counter()
+            if kind == "cold":
+                rc, Xo, Uo, Lo, inf = solver.solve_batch(xs, xr)
+            elif kind == "learned":
+                up = net.predict(xs, xr, out=ubuf)
+                rc, Xo, Uo, Lo, inf = solver.solve_batch(xs, xr, warm=(None, up, None))
+            else:
+                rc, Xo, Uo, Lo, inf = solver.solve_batch(xs, xr, warm=warm)
+            torch.cuda.synchronize()
+            out[kind]["t"] += time.perf_counter() - t
+            out[kind]["it"] += [i["iters"] for i in inf]
+        X, U, L = Xo.clone(), Uo.clone(), Lo.clone()   # the shifted solve's trajectory
+    n = B * (steps - 1)
+    return {k: {"solves_per_s": round(n / v["t"], 1), "iters_mean": round(float(np.mean(v["it"])), 1),
+                "iters_max": int(max(v["it"]))} for k, v in out.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +175,9 @@ def main():
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--closed-loop-steps", type=int, default=10,
+                    help="closed loop per instance of the first timed batch after the timed "
+                         "region: cold vs shifted vs learned starts at steps 2.. (0 disables)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 disables)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -254,6 +291,12 @@ def main():
                                    "frac": round(tf / MFMA_BF16_PEAK_TFLOPS, 4)},
                           "weights": os.path.relpath(args.weights, ROOT),
                           "val_rel_err_median": net.meta.get("val_rel_err_median")}
+
+    if net is not None and args.closed_loop_steps >= 2:
+        cfg["closed_loop"] = dict(
+            closed_loop(solver, net, P, *dev_in[args.warmup], args.closed_loop_steps, ubuf),
+            steps=f"2..{args.closed_loop_steps}", plant="explicit Euler, dt = h",
+            instances=B)
 
     result = {
         "metric": "NMPC solves/s to KKT res 1e-6, 64x64 grid N=40: learned warm start vs plain",

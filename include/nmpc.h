@@ -202,6 +202,23 @@ int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches
 /* Set the calling thread's last-error text (used by the network calls). */
 void nmpc_set_last_error(const char *msg);
 
+/* Shifted start for the next closed-loop step (the paper reuses the previous
+ * step's optimum, Remark rmk_gamma): out_s[b][i] = s[b][i+1] for i < N-1 and
+ * out_s[b][N-1] = s[b][N-1], for x [count][N][n], u [count][N][m] and
+ * lambda [count][N][n] (DEVICE; outputs must not alias inputs). Queued on
+ * `stream`, returns without waiting. */
+int nmpc_shift_batch(nmpc_handle *hd, int32_t count, const double *x, const double *u,
+                     const double *lam, double *out_x, double *out_u, double *out_lam,
+                     void *stream);
+
+/* Plant step of a closed-loop simulation: one explicit-Euler step of the
+ * handle's model, out = x + dt (k(x) .* (L x) + B u), for x [count][n] and the
+ * applied inputs u (instance b's m values at u + b * ldu; ldu = N * m takes
+ * stage 1 of a [count][N][m] trajectory). DEVICE buffers; out must not alias
+ * x. Queued on `stream`, returns without waiting. */
+int nmpc_plant_step_batch(nmpc_handle *hd, int32_t count, const double *x, const double *u,
+                          int32_t ldu, double dt, double *out, void *stream);
+
 /* Tile autotuner: time `iters` upper iterations (1..1000) of this batch from
  * the cold start (DEVICE x0 [count][n], xref [count][n]) with every tile
  * height that the kernel table holds for the problem's grid width in the

@@ -31,6 +31,7 @@ from ._binding import (  # noqa: F401
     nmpc_destroy,
     nmpc_kernel_config,
     nmpc_last_error,
+    nmpc_plant_step_batch,
     nmpc_ragged_autotune,
     nmpc_ragged_config,
     nmpc_ragged_create,
@@ -40,6 +41,7 @@ from ._binding import (  # noqa: F401
     nmpc_ragged_timing_read,
     nmpc_residual_batch,
     nmpc_set_options,
+    nmpc_shift_batch,
     nmpc_solve,
     nmpc_solve_batch,
     nmpc_strerror,

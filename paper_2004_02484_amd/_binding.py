@@ -108,6 +108,11 @@ def _load():
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.nmpc_timing_read.restype = ctypes.c_int
     i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.nmpc_shift_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
+    lib.nmpc_shift_batch.restype = ctypes.c_int
+    lib.nmpc_plant_step_batch.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32,
+                                          ctypes.c_double, vp, vp]
+    lib.nmpc_plant_step_batch.restype = ctypes.c_int
     lib.nmpc_autotune.argtypes = [vp, ctypes.c_int32, vp, vp, ctypes.c_int32, vp, i32p]
     lib.nmpc_autotune.restype = ctypes.c_int
     lib.nmpc_ragged_create.argtypes = [ctypes.POINTER(nmpc_problem), ctypes.c_int32,
@@ -293,6 +298,34 @@ def nmpc_timing_read(hd):
     return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
 
 
+def nmpc_shift_batch(hd, X, U, LAM, out=None, *, n: int, m: int, N: int, **_):
+    """Shifted start (s_i <- s_{i+1}, last stage repeated) of device trajectories."""
+    import torch
+    B = X.shape[0]
+    if out is None:
+        out = (torch.empty_like(X), torch.empty_like(U), torch.empty_like(LAM))
+    rc = _load().nmpc_shift_batch(hd, B, _dev(X, (B, N, n), "x"), _dev(U, (B, N, m), "u"),
+                                  _dev(LAM, (B, N, n), "lam"), _dev(out[0], (B, N, n), "out x"),
+                                  _dev(out[1], (B, N, m), "out u"),
+                                  _dev(out[2], (B, N, n), "out lam"), _stream())
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_shift_batch")
+    return out
+
+
+def nmpc_plant_step_batch(hd, x, U, dt: float, out=None, *, n: int, m: int, N: int, **_):
+    """x+ = x + dt f(u_1, x) for device x [B, n] and trajectories U [B, N, m]."""
+    import torch
+    B = x.shape[0]
+    if out is None:
+        out = torch.empty_like(x)
+    rc = _load().nmpc_plant_step_batch(hd, B, _dev(x, (B, n), "x"), _dev(U, (B, N, m), "u"),
+                                       N * m, float(dt), _dev(out, (B, n), "out"), _stream())
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_plant_step_batch")
+    return out
+
+
 def nmpc_autotune(hd, x0, xref, iters: int = 8, *, n: int, m: int, N: int,
                   xref_stages: bool = False) -> int:
     """Time the tile heights on this batch; returns the chosen tile_rows."""
@@ -416,6 +449,12 @@ class Solver:
 
     def residual_batch(self, x0, xref, X, U, LAM):
         return nmpc_residual_batch(self.hd, x0, xref, X, U, LAM, **self._dims)
+
+    def shift_batch(self, X, U, LAM, out=None):
+        return nmpc_shift_batch(self.hd, X, U, LAM, out, **self._dims)
+
+    def plant_step_batch(self, x, U, dt: float, out=None):
+        return nmpc_plant_step_batch(self.hd, x, U, dt, out, **self._dims)
 
     def autotune(self, x0, xref, iters: int = 8) -> int:
         tr = nmpc_autotune(self.hd, x0, xref, iters, **self._dims)

@@ -107,6 +107,15 @@ struct RgArgs {
     int count;
 };
 
+// Explicit-Euler plant step of a batch (closed-loop simulation).
+struct PlantArgs {
+    long long count;
+    int nsx, nsy, lx, ly, ldu;   // ldu: elements between instances' inputs
+    const double *x, *u, *gx, *gy;
+    double *out;
+    double dt, k0, k1, idx2, idy2;
+};
+
 // Tile configuration of one iteration-kernel instance.
 struct TileCfg {
     int cx, rows, max_waves;
@@ -152,6 +161,9 @@ const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg);
 const void *pad_kernel();
 const void *advance_kernel();
 const void *output_kernel();
+
+const void *shift_kernel();   // (const double *s, double *out, long long count, int N, long long w)
+const void *plant_kernel();   // (PlantArgs)
 
 // Ragged batch kernels (4 x 4 input lattice); waves: 8, 12 or 16.
 const void *ragged_iterate_kernel(int prec, int waves);

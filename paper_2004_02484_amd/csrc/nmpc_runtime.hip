@@ -877,6 +877,52 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
     return NMPC_OK;
 }
 
+int nmpc_shift_batch(nmpc_handle *h, int32_t count, const double *x, const double *u,
+                     const double *lam, double *out_x, double *out_u, double *out_lam,
+                     void *stream)
+{
+    g_err.clear();
+    if (!h || !x || !u || !lam || !out_x || !out_u || !out_lam) return fail(NMPC_E_ARG, "NULL argument");
+    if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    if (out_x == x || out_u == u || out_lam == lam)
+        return fail(NMPC_E_ARG, "shift outputs must not alias the inputs");
+    long long cnt = count;
+    int N = h->N;
+    const double *src[3] = {x, u, lam};
+    double *dst[3] = {out_x, out_u, out_lam};
+    const long long w[3] = {h->n, h->m, h->n};
+    for (int q = 0; q < 3; ++q) {
+        long long ww = w[q];
+        void *args[] = {(void *)&src[q], (void *)&dst[q], (void *)&cnt, (void *)&N, (void *)&ww};
+        HIP_TRY(hipLaunchKernel(nmpc::shift_kernel(), dim3(launch_grid((size_t)cnt * N * ww)),
+                                dim3(256), args, 0, (hipStream_t)stream));
+    }
+    return NMPC_OK;
+}
+
+int nmpc_plant_step_batch(nmpc_handle *h, int32_t count, const double *x, const double *u,
+                          int32_t ldu, double dt, double *out, void *stream)
+{
+    g_err.clear();
+    if (!h || !x || !u || !out) return fail(NMPC_E_ARG, "NULL argument");
+    if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    if (ldu < h->m) return fail(NMPC_E_ARG, "ldu smaller than the number of inputs");
+    if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(NMPC_E_ARG, "dt must be finite and >= 0");
+    if (out == x) return fail(NMPC_E_ARG, "plant output must not alias x");
+    nmpc::PlantArgs a{};
+    const nmpc_problem &p = h->prob;
+    a.count = count; a.nsx = p.nsx; a.nsy = p.nsy; a.lx = p.lx; a.ly = p.ly; a.ldu = ldu;
+    a.x = x; a.u = u; a.gx = h->d_gx; a.gy = h->d_gy; a.out = out;
+    a.dt = dt; a.k0 = p.k0; a.k1 = p.k1;
+    const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
+    a.idx2 = 1.0 / (dx * dx);
+    a.idy2 = p.dim == 2 ? 1.0 / (dy * dy) : 0.0;
+    void *args[] = {(void *)&a};
+    HIP_TRY(hipLaunchKernel(nmpc::plant_kernel(), dim3(launch_grid((size_t)count * h->n)), dim3(256),
+                            args, 0, (hipStream_t)stream));
+    return NMPC_OK;
+}
+
 int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *waves,
                        int32_t *workgroups)
 {

@@ -126,3 +126,9 @@ def test_ragged_null_handle_calls():
     assert lib.nmpc_ragged_solve(None, 1, c, None, None, None, None, None, None, None, None,
                                  None, None) == nm.NMPC_E_ARG
     assert lib.nmpc_autotune(None, 1, None, None, 4, None, None) == nm.NMPC_E_ARG
+
+
+def test_loop_helpers_reject_a_null_handle():
+    lib = _binding._load()
+    assert lib.nmpc_shift_batch(None, 1, None, None, None, None, None, None, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_plant_step_batch(None, 1, None, None, 1, 0.1, None, None) == nm.NMPC_E_ARG
