@@ -64,6 +64,8 @@ enum { NMPC_START_COLD = 0, NMPC_START_WARM = 1 };
 
 enum { NMPC_UPPER_JACOBI = 0, NMPC_UPPER_FGS = 1, NMPC_UPPER_BGS = 2, NMPC_UPPER_SGS = 3 };
 
+enum { NMPC_PATH_AUTO = 0, NMPC_PATH_FUSED = 1, NMPC_PATH_STREAM = 2 };
+
 /* Problem data (Sec. 3 notation). gx/gy are host arrays, copied at create. */
 typedef struct nmpc_problem {
     int32_t dim;          /* 1 or 2 */
@@ -112,6 +114,14 @@ typedef struct nmpc_options {
                              instance runs the whole solve in one launch per
                              precision phase. Every variant has the same
                              solution; iterations count upper iterations */
+    int32_t path;         /* NMPC_PATH_FUSED: one workgroup holds a stage in
+                             registers and runs its whole upper-iteration step
+                             (grids up to 96 columns); NMPC_PATH_STREAM: every
+                             step of the stage algebra is a pass over grid rows
+                             of all stages (any grid size, e.g. 256 x 256;
+                             Jacobi upper layer, cold or given starts, no
+                             fallback); NMPC_PATH_AUTO (default): fused where
+                             it fits, else streaming */
 } nmpc_options;
 
 /* Per-instance result information. */
@@ -128,7 +138,7 @@ typedef struct nmpc_handle nmpc_handle;
 
 /* Fill options with the paper's lower-layer settings (2 sweeps, 2 Schur
  * iterations), tol 1e-6, max_iter 2000, FP64, check_every 16, default
- * tile, Jacobi upper layer. */
+ * tile, Jacobi upper layer, automatic kernel path. */
 void nmpc_default_options(nmpc_options *opt);
 
 /* Create a solver for one problem shape and up to max_batch instances on the

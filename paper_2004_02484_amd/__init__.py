@@ -17,6 +17,9 @@ from ._binding import (  # noqa: F401
     NMPC_FP32_SWEEP,
     NMPC_FP64,
     NMPC_OK,
+    NMPC_PATH_AUTO,
+    NMPC_PATH_FUSED,
+    NMPC_PATH_STREAM,
     NMPC_UPPER_BGS,
     NMPC_UPPER_FGS,
     NMPC_UPPER_JACOBI,

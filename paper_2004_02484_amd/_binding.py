@@ -23,6 +23,9 @@ NMPC_UPPER_JACOBI = 0
 NMPC_UPPER_FGS = 1
 NMPC_UPPER_BGS = 2
 NMPC_UPPER_SGS = 3
+NMPC_PATH_AUTO = 0
+NMPC_PATH_FUSED = 1
+NMPC_PATH_STREAM = 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -41,7 +44,7 @@ class nmpc_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
-                ("upper", ctypes.c_int32)]
+                ("upper", ctypes.c_int32), ("path", ctypes.c_int32)]
 
 
 class nmpc_info(ctypes.Structure):

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmpc.so")
-SOURCES = ["nmpc_kernels.hip", "nmpc_gs.hip", "nmpc_ragged.hip", "nmpc_loop.hip",
+SOURCES = ["nmpc_kernels.hip", "nmpc_gs.hip", "nmpc_ragged.hip", "nmpc_loop.hip", "nmpc_stream.hip",
            "nmpc_runtime.hip", "nmpc_ragged_runtime.hip", "nmpc_net.hip", "nmpc_net_runtime.hip"]
 
 # Packed FP32 ops are disabled: code is written for scalar FP32/FP64 VALU.

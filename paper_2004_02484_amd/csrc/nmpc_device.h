@@ -13,6 +13,7 @@ constexpr int kMaxWaves = 16;   // waves per workgroup (1024 threads)
 constexpr int kMaxM = 64;       // inputs per stage
 constexpr int kMaxLy = 8;       // input lattice rows
 constexpr int kMaxCx = 6;       // columns per lane: nsx <= 16 * 6 = 96
+constexpr int kMaxLx = 8;       // input lattice columns
 
 constexpr int kActive = -1;
 constexpr int kStatusOk = 0;        // == NMPC_OK
@@ -106,6 +107,38 @@ struct RgArgs {
     const int2 *umap;         // per unit: (instance, stage); instance < 0: no work
     int count;
 };
+
+// Streaming (multi-pass) Jacobi iteration for grids beyond one workgroup:
+// dense stage layout, one workgroup per (instance, stage, grid row).
+struct StreamArgs {
+    DevProblem P;                   // P.n unused (dense: nsx * nsy)
+    const double *gx, *gy;          // [lx][nsx], [ly][nsy]
+    const double *x0, *xref;        // dense [B][n], xref as in IterArgs
+    long long xref_inst_stride;
+    int xref_stage_stride;
+    double *X[2], *U[2], *LAM[2];   // [B][N][n] / [B][N][m]
+    // per-point scratch [B][N][n], each in double slots (T values at the front)
+    double *b1, *b2, *invd, *cpk, *g2, *y5, *ytmp, *y4, *y4tmp, *cp;
+    double *sc;                     // [B][N][ly][nsx] column sums of B v
+    double *kun, *v3;               // [B][N][m]
+    unsigned long long *rown;       // [B][N][nsy][2] row maxima of |K^x|, |K^lambda|
+    double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y
+    unsigned long long *rst, *pst;  // [B][N] stage norms (bit patterns)
+    InstState *st;                  // [B]
+    int *work;                      // [B] 1: the instance takes a step in this iteration
+    int *iters;
+    double *rfin;
+    int *ctr;                       // [2] finished, [3] in the FP32 phase
+    long long units;                // count * N * nsy rows
+    int per_xcd, count;
+    double tol;
+    int max_iter, n_sw, n_schur;
+};
+
+struct StreamKernels {
+    const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
+};
+StreamKernels stream_kernels(int prec);
 
 // Explicit-Euler plant step of a batch (closed-loop simulation).
 struct PlantArgs {

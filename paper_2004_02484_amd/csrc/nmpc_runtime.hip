@@ -56,6 +56,9 @@ struct nmpc_handle {
         size_t lds = 0;
     } kern[2];                             // [kModeFp64], [kModeFp32]
     Kern gs[2];                            // Gauss-Seidel kernels (upper != Jacobi)
+    bool streaming = false;                // multi-pass kernels (grids beyond one workgroup)
+    double *d_stream = nullptr;            // streaming scratch (see stream_args)
+    int *d_work = nullptr;                 // [B] streaming: instance steps this iteration
     Kern roll;                             // start built from an input trajectory
     int *d_start = nullptr;                // [B] start used per instance
     int last_start_kind = 0;
@@ -136,8 +139,16 @@ int check_problem(const nmpc_problem *p)
         if (!std::isfinite(p->gx[t])) return fail(NMPC_E_ARG, "gx not finite");
     for (long long t = 0; t < (long long)p->ly * p->nsy; ++t)
         if (!std::isfinite(p->gy[t])) return fail(NMPC_E_ARG, "gy not finite");
-    if (p->nsx > 16 * nmpc::kMaxCx || p->ly > nmpc::kMaxLy || p->lx * p->ly > nmpc::kMaxM)
-        return fail(NMPC_E_UNSUPPORTED, "fused stage kernel needs nsx <= 96, m <= 64");
+    if (p->ly > nmpc::kMaxLy || p->lx > nmpc::kMaxLx || p->lx * p->ly > nmpc::kMaxM)
+        return fail(NMPC_E_UNSUPPORTED, "input lattice larger than 8 x 8");
+    return NMPC_OK;
+}
+
+// Does the fused stage kernel cover this problem?
+int check_fused(const nmpc_problem *p)
+{
+    if (p->nsx > 16 * nmpc::kMaxCx)
+        return fail(NMPC_E_UNSUPPORTED, "fused stage kernel needs nsx <= 96");
     for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
         const int rc = select_kernel(p, prec, 0, nullptr);
         if (rc) return rc;
@@ -162,6 +173,20 @@ int check_options(const nmpc_options *o)
     if (o->fallback != 0 && o->fallback != 1) return fail(NMPC_E_ARG, "fallback must be 0 or 1");
     if (o->upper < NMPC_UPPER_JACOBI || o->upper > NMPC_UPPER_SGS)
         return fail(NMPC_E_ARG, "unknown upper layer");
+    if (o->path < NMPC_PATH_AUTO || o->path > NMPC_PATH_STREAM)
+        return fail(NMPC_E_ARG, "unknown kernel path");
+    return NMPC_OK;
+}
+
+// Kernel path of a problem under options: 1 streaming, 0 fused, or an error.
+int choose_path(const nmpc_problem *p, const nmpc_options *o, bool *streaming)
+{
+    const int fused = o->path == NMPC_PATH_STREAM ? NMPC_E_UNSUPPORTED : check_fused(p);
+    if (o->path == NMPC_PATH_FUSED && fused) return fused;
+    *streaming = fused != NMPC_OK;
+    if (*streaming && o->upper != NMPC_UPPER_JACOBI)
+        return fail(NMPC_E_UNSUPPORTED, "the streaming path runs the Jacobi upper layer only");
+    g_err.clear();
     return NMPC_OK;
 }
 
@@ -206,7 +231,7 @@ void release(nmpc_handle *h)
     for (void *p : {(void *)h->d_gx, (void *)h->d_gy, (void *)h->d_S[0], (void *)h->d_S[1],
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
-                    (void *)h->d_start,
+                    (void *)h->d_start, (void *)h->d_stream, (void *)h->d_work,
                     })
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
@@ -350,6 +375,13 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
                                 dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
                                 0, h->stream));
     }
+    if (h->streaming) {
+        if (kind == kStartInputs)
+            return fail(NMPC_E_UNSUPPORTED, "the streaming path takes cold or (x, u, lambda) starts");
+        h->last_start_kind = kind;
+        h->last_fallback = false;
+        return NMPC_OK;
+    }
     if (kind == kStartInputs) {
         IterArgs a = iter_args(h, count);
         a.units = count;
@@ -397,6 +429,130 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
 
 // Run the upper iteration for `count` instances whose x0/xref already sit in
 // the handle's buffers; S^0 from the warm pointers (device, dense) or cold.
+// Streaming scratch layout in d_stream (doubles): 10 per-point arrays
+// [B][N][n], sc [B][N][ly][nsx], kun and v3 [B][N][m], row maxima (two
+// 64-bit words per row) and row partials [B][N][nsy][kMaxLx].
+size_t stream_doubles(const nmpc_handle *h)
+{
+    const size_t B = h->max_batch, N = h->N, n = h->n, m = h->m;
+    return 10 * B * N * n + B * N * h->prob.ly * h->prob.nsx + 2 * B * N * m +
+           B * N * h->prob.nsy * (2 + nmpc::kMaxLx);
+}
+
+nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
+{
+    nmpc::StreamArgs a{};
+    const nmpc_problem &p = h->prob;
+    a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->n; a.P.N = h->N; a.P.m = h->m;
+    a.P.lx = p.lx; a.P.ly = p.ly;
+    a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
+    const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
+    a.P.idx2 = 1.0 / (dx * dx);
+    a.P.idy2 = p.dim == 2 ? 1.0 / (dy * dy) : 0.0;
+    a.P.c0 = 2.0 * a.P.idx2 + 2.0 * a.P.idy2;
+    a.gx = h->d_gx; a.gy = h->d_gy;
+    a.x0 = h->d_x0; a.xref = h->d_xref;
+    a.xref_inst_stride = (long long)h->xref_len;
+    a.xref_stage_stride = h->opt.xref_per_stage ? h->n : 0;
+    for (int b = 0; b < 2; ++b) { a.X[b] = h->X(b); a.U[b] = h->U(b); a.LAM[b] = h->L(b); }
+    const size_t B = h->max_batch, N = h->N, n = h->n, m = h->m;
+    double *q = h->d_stream;
+    double **arr[10] = {&a.b1, &a.b2, &a.invd, &a.cpk, &a.g2, &a.y5, &a.ytmp, &a.y4, &a.y4tmp, &a.cp};
+    for (double **x : arr) { *x = q; q += B * N * n; }
+    a.sc = q; q += B * N * p.ly * p.nsx;
+    a.kun = q; q += B * N * m;
+    a.v3 = q; q += B * N * m;
+    a.rown = reinterpret_cast<unsigned long long *>(q); q += 2 * B * N * p.nsy;
+    a.rowt = q;
+    a.rst = h->d_rst;
+    a.pst = h->d_rst + B * N;
+    a.st = h->d_st; a.work = h->d_work; a.iters = h->d_iters; a.rfin = h->d_rfin; a.ctr = h->d_ctr;
+    a.count = count;
+    a.units = (long long)count * h->N * p.nsy;
+    a.per_xcd = (int)((a.units + 7) / 8);
+    a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
+    a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
+    return a;
+}
+
+// One streaming upper iteration of precision `prec` (18 launches with the
+// default schedule), queued on s.
+int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a, hipStream_t s)
+{
+    const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
+    const dim3 rows(8 * a.per_xcd), stages(a.count * h->N), inst((a.count + 255) / 256);
+    auto go = [&](const void *fn, dim3 grid, int block, void **args) -> int {
+        HIP_TRY(hipLaunchKernel(fn, grid, dim3(block), args, 0, s));
+        return NMPC_OK;
+    };
+    int rc;
+    const int passes = 1 + std::max(0, h->opt.n_sweep - 2);
+    const int y5_tmp = (passes - 1) & 1;
+    {
+        int which = 0;
+        void *args[] = {(void *)&a, (void *)&which};
+        if ((rc = go(k.bsep, stages, 256, args))) return rc;
+    }
+    {
+        void *args[] = {(void *)&a};
+        if ((rc = go(k.res, rows, 256, args))) return rc;
+        if ((rc = go(k.stage, stages, 64, args))) return rc;
+        if ((rc = go(k.decide, inst, 256, args))) return rc;
+    }
+    for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
+        const bool fin = sch == h->opt.n_schur;   // the final block after the Schur loop
+        int use_v3 = (sch > 0 || fin) ? 1 : 0;
+        if (use_v3) {
+            int which = 1;
+            void *args[] = {(void *)&a, (void *)&which};
+            if ((rc = go(k.bsep, stages, 256, args))) return rc;
+        }
+        int sgn = fin ? 1 : -1;
+        for (int pass = 0; pass < passes; ++pass) {
+            void *args[] = {(void *)&a, (void *)&sgn, (void *)&use_v3, (void *)&pass};
+            if ((rc = go(k.jf, rows, 256, args))) return rc;
+        }
+        int ytmp = y5_tmp;
+        {
+            void *args[] = {(void *)&a, (void *)&sgn, (void *)&ytmp};
+            if ((rc = go(k.axx, rows, 256, args))) return rc;
+        }
+        for (int pass = 0; pass < passes; ++pass) {
+            int last = pass == passes - 1, partials = fin ? 0 : 1, update = fin ? 1 : 0;
+            void *args[] = {(void *)&a, (void *)&pass, (void *)&last, (void *)&partials,
+                            (void *)&update, (void *)&ytmp};
+            if ((rc = go(k.jft, rows, 256, args))) return rc;
+        }
+        if (!fin) {
+            void *args[] = {(void *)&a};
+            if ((rc = go(k.v3, stages, 64, args))) return rc;
+        }
+    }
+    void *args[] = {(void *)&a};
+    return go(k.advance, inst, 256, args);
+}
+
+int ensure_stream_graph(nmpc_handle *h, int prec, int count)
+{
+    const int len = h->opt.check_every;
+    if (h->gexec[prec] && h->graph_count[prec] == count && h->graph_len[prec] == len)
+        return NMPC_OK;
+    if (h->gexec[prec]) { (void)hipGraphExecDestroy(h->gexec[prec]); h->gexec[prec] = nullptr; }
+    if (h->graph[prec]) { (void)hipGraphDestroy(h->graph[prec]); h->graph[prec] = nullptr; }
+    const nmpc::StreamArgs a = stream_args(h, count);
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = NMPC_OK;
+    for (int t = 0; t < len && rc == NMPC_OK; ++t) rc = launch_stream_iteration(h, prec, a, h->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != NMPC_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(NMPC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    h->graph[prec] = g;
+    HIP_TRY(hipGraphInstantiate(&h->gexec[prec], g, nullptr, nullptr, 0));
+    h->graph_count[prec] = count; h->graph_len[prec] = len;
+    return NMPC_OK;
+}
+
 // Each instance's returned iterate (buffer iters[b] & 1) to the outputs.
 int launch_output(nmpc_handle *h, int count, double *ox, double *ou, double *ol)
 {
@@ -459,7 +615,7 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
     const long long cap = 2 * ((long long)h->opt.max_iter + 8 + h->opt.check_every);
     long long launched = 0;
     for (;;) {
-        int rc = ensure_graph(h, prec, count);
+        int rc = h->streaming ? ensure_stream_graph(h, prec, count) : ensure_graph(h, prec, count);
         if (rc != NMPC_OK) return rc;
         if (h->timing) HIP_TRY(hipEventRecord(h->t0, h->stream));
         HIP_TRY(hipGraphLaunch(h->gexec[prec], h->stream));
@@ -536,6 +692,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->warm_sweeps = 0;
     opt->fallback = 0;
     opt->upper = NMPC_UPPER_JACOBI;
+    opt->path = NMPC_PATH_AUTO;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
@@ -557,13 +714,17 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->n = prob->nsx * prob->nsy;
     h->m = prob->lx * prob->ly;
     h->N = prob->horizon;
-    rc = select_all(prob, opt, h->kern, h->gs);
+    rc = choose_path(prob, opt, &h->streaming);
     if (rc) { delete h; return rc; }
+    if (!h->streaming) {
+        rc = select_all(prob, opt, h->kern, h->gs);
+        if (rc) { delete h; return rc; }
+    }
     h->gx.assign(prob->gx, prob->gx + (size_t)prob->lx * prob->nsx);
     h->gy.assign(prob->gy, prob->gy + (size_t)prob->ly * prob->nsy);
     h->prob.gx = h->gx.data();
     h->prob.gy = h->gy.data();
-    {
+    if (!h->streaming) {
         TileCfg cfg{};
         h->roll.fn = nmpc::rollout_kernel(tile_cx(prob->nsx), prob->lx, prob->ly, &cfg);
         if (!h->roll.fn) { delete h; return fail(NMPC_E_UNSUPPORTED, "no rollout kernel instance"); }
@@ -573,7 +734,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
         h->roll.lds = nmpc::lds_layout(h->roll.waves * 4, h->roll.waves, cfg.cx, 8, prob->lx,
                                        prob->ly, cfg.rows).total;
     }
-    h->sx = 16 * h->kern[nmpc::kModeFp64].cfg.cx;
+    h->sx = h->streaming ? prob->nsx : 16 * h->kern[nmpc::kModeFp64].cfg.cx;
     h->np = h->sx * prob->nsy;
     h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
     const size_t B = max_batch, S = B * h->N * (2 * (size_t)h->np + h->m);
@@ -600,6 +761,10 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
     ALLOC(h->d_start, sizeof(int) * B);
+    if (h->streaming) {
+        ALLOC(h->d_stream, sizeof(double) * stream_doubles(h));
+        ALLOC(h->d_work, sizeof(int) * B);
+    }
 
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(int), hipHostMallocDefault);
@@ -608,7 +773,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
             if (e == hipSuccess && k->fn && k->lds > 48 * 1024)
                 e = hipFuncSetAttribute(k->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)k->lds);
-    if (e == hipSuccess && h->roll.lds > 48 * 1024)
+    if (e == hipSuccess && h->roll.fn && h->roll.lds > 48 * 1024)
         e = hipFuncSetAttribute(h->roll.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)h->roll.lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
@@ -636,9 +801,16 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
     int rc = check_options(opt);
     if (rc) return rc;
-    nmpc_handle::Kern kn[2], gn[2];
-    rc = select_all(&h->prob, opt, kn, gn);
+    bool streaming = false;
+    rc = choose_path(&h->prob, opt, &streaming);
     if (rc) return rc;
+    if (streaming != h->streaming)
+        return fail(NMPC_E_UNSUPPORTED, "set_options cannot switch between fused and streaming paths");
+    nmpc_handle::Kern kn[2] = {}, gn[2] = {};
+    if (!streaming) {
+        rc = select_all(&h->prob, opt, kn, gn);
+        if (rc) return rc;
+    }
     for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
         if ((rc = raise_lds(kn[prec]))) return rc;
         if ((rc = raise_lds(gn[prec]))) return rc;
@@ -745,15 +917,31 @@ int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const d
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(), dim3(launch_grid((size_t)count * h->N * h->np)),
                                 dim3(256), args, 0, h->stream));
     }
-    IterArgs a = iter_args(h, count);
-    a.residual_only = 1;
-    rc = launch_iterate(h, nmpc::kModeFp64, a, h->stream);
-    if (rc) return rc;
+    const unsigned long long *rst = nullptr, *pst = nullptr;
+    if (h->streaming) {   // residual passes of the streaming path (stage norms in rst / pst)
+        const nmpc::StreamArgs a = stream_args(h, count);
+        const nmpc::StreamKernels k = nmpc::stream_kernels(nmpc::kModeFp64);
+        int which = 0;
+        void *a1[] = {(void *)&a, (void *)&which};
+        void *a2[] = {(void *)&a};
+        HIP_TRY(hipLaunchKernel(k.bsep, dim3(count * h->N), dim3(256), a1, 0, h->stream));
+        HIP_TRY(hipLaunchKernel(k.res, dim3(8 * a.per_xcd), dim3(256), a2, 0, h->stream));
+        HIP_TRY(hipLaunchKernel(k.stage, dim3(count * h->N), dim3(64), a2, 0, h->stream));
+        rst = a.rst;
+        pst = a.pst;
+    } else {
+        IterArgs a = iter_args(h, count);
+        a.residual_only = 1;
+        rc = launch_iterate(h, nmpc::kModeFp64, a, h->stream);
+        if (rc) return rc;
+        rst = a.rst;
+        pst = a.pst;
+    }
     const size_t per = (size_t)count * h->N;   // slot 0 of both arrays
     std::vector<unsigned long long> bits(2 * per);
-    HIP_TRY(hipMemcpyAsync(bits.data(), a.rst, sizeof(unsigned long long) * per,
+    HIP_TRY(hipMemcpyAsync(bits.data(), rst, sizeof(unsigned long long) * per,
                            hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(bits.data() + per, a.pst, sizeof(unsigned long long) * per,
+    HIP_TRY(hipMemcpyAsync(bits.data() + per, pst, sizeof(unsigned long long) * per,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (int b = 0; b < count; ++b) {
@@ -824,6 +1012,7 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
     if (!h || !x0 || !xref) return fail(NMPC_E_ARG, "NULL argument");
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
     if (iters < 1 || iters > 1000) return fail(NMPC_E_ARG, "iters must be 1..1000");
+    if (h->streaming) return fail(NMPC_E_UNSUPPORTED, "the streaming path has no tile choices");
     const int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
@@ -927,6 +1116,12 @@ int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *wa
                        int32_t *workgroups)
 {
     if (!h) return NMPC_E_ARG;
+    if (h->streaming) {   // one 256-thread workgroup per grid row of every stage
+        if (rows_per_lane) *rows_per_lane = 0;
+        if (waves) *waves = 4;
+        if (workgroups) *workgroups = h->max_batch * h->N * h->prob.nsy;
+        return NMPC_OK;
+    }
     const int prec = main_prec(h->opt);
     const bool gs = h->opt.upper != NMPC_UPPER_JACOBI;
     const nmpc_handle::Kern &k = gs ? h->gs[prec] : h->kern[prec];

@@ -53,20 +53,31 @@ def test_1d_needs_single_row():
 
 
 def test_unsupported_shapes_reported():
+    fused = nm.nmpc_default_options(path=nm.NMPC_PATH_FUSED)
     p = make_problem("grid", ns=100, N=4)   # wider than 16 lanes x 6 columns
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, fused, 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+    p = make_problem("grid", ns=16, N=4, lattice=3)   # no fused kernel for a 3x3 lattice
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(p, fused, 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+    p = make_problem("grid", ns=16, N=4, lattice=9)   # more than 64 inputs: no path
     with pytest.raises(nm.NmpcError) as e:
         nm.nmpc_create(p, nm.nmpc_default_options(), 1)
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
-    p = make_problem("grid", ns=16, N=4, lattice=3)   # no kernel for a 3x3 lattice
+    # the streaming path (any width) runs the Jacobi upper layer only
+    o = nm.nmpc_default_options(path=nm.NMPC_PATH_STREAM, upper=nm.NMPC_UPPER_SGS)
     with pytest.raises(nm.NmpcError) as e:
-        nm.nmpc_create(p, nm.nmpc_default_options(), 1)
+        nm.nmpc_create(make_problem("grid", ns=100, N=4), o, 1)
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("field,value", [("n_sweep", 0), ("n_sweep", 17), ("n_schur", -1),
                                          ("precision", 7), ("check_every", 0),
                                          ("max_iter", -1), ("tol", -1.0), ("tile_rows", -1),
-                                         ("tile_rows", 17), ("upper", 4), ("upper", -1)])
+                                         ("tile_rows", 17), ("upper", 4), ("upper", -1),
+                                         ("path", 3)])
 def test_invalid_options_rejected(field, value):
     o = nm.nmpc_default_options(**{field: value})
     with pytest.raises(nm.NmpcError) as e:

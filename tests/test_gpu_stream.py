@@ -1,0 +1,129 @@
+"""GPU parity of the streaming path (multi-pass kernels for grids beyond one
+workgroup, e.g. the 256 x 256, N = 100 instance) against the CPU oracle.
+
+Equal-k comparisons in FP64 (relative 1e-10) on small grids forced onto the
+streaming path, including a 1D problem and grids wider than the fused
+kernel allows; agreement with the fused path; the full 256 x 256 instance
+at k = 1 against the oracle and converged in FP32 sweeps with the oracle's
+residual of the returned trajectory within the test."""
+import numpy as np
+import pytest
+
+from nmpc_inputs import gaussian_factors, make_batch, make_instance, make_problem
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+
+
+def rel(a, b):
+    b = np.asarray(b)
+    return float(np.abs(np.asarray(a) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def nm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2004_02484_amd as nm
+    return nm
+
+
+def shaped(nsx, nsy, N, lattice):
+    P = make_problem("grid", ns=nsx, N=N, lattice=lattice)
+    sigma = 0.05 if lattice >= 4 else 0.2
+    P = P.with_(nsy=nsy, gx=gaussian_factors(nsx, lattice, sigma),
+                gy=gaussian_factors(nsy, lattice, sigma))
+    P.h = 0.2 / (0.75 * max(nsx + 1, nsy + 1) ** 2)
+    P.gamma = P.h * P.r
+    return P
+
+
+CASES = {"c0": None, "13x37x6 L2": (13, 37, 6, 2), "40x33x4 L4": (40, 33, 4, 4),
+         "130x20x3 L4": (130, 20, 3, 4), "300x7x2 L8": (300, 7, 2, 8), "9x9x1 L2": (9, 9, 1, 2)}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_stream_iterates_match_oracle(nm, case):
+    spec = CASES[case]
+    P = make_problem("c0") if spec is None else shaped(*spec)
+    x0, xref = make_instance(P, 9)
+    for k in (1, 3):
+        for nsw, nsc in ((2, 2), (3, 1), (1, 0)):
+            s = nm.Solver(P, tol=0.0, max_iter=k, path=nm.NMPC_PATH_STREAM, n_sweep=nsw,
+                          n_schur=nsc)
+            rc, X, U, L, info = s.solve(x0, xref)
+            s.close()
+            o = oracle.solve(P, x0, xref, tol=0.0, max_iter=k, n_sw=nsw, n_schur=nsc)
+            assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+            for got, want in ((X, o["X"]), (U, o["U"]), (L, o["LAM"])):
+                assert rel(got, want) <= REL, (k, nsw, nsc, rel(got, want))
+            assert abs(info["r_scaled"] - o["r_scaled"]) <= 1e-9 * o["r_scaled"]
+
+
+def test_stream_equals_fused_path(nm):
+    import torch
+    P = shaped(48, 40, 8, 4)
+    x0, xr = make_batch(P, [3, 4, 5])
+    X0, XR = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
+    outs = []
+    for path in (nm.NMPC_PATH_FUSED, nm.NMPC_PATH_STREAM):
+        s = nm.Solver(P, max_batch=3, tol=0.0, max_iter=6, path=path)
+        rc, X, U, L, info = s.solve_batch(X0, XR)
+        outs.append((X.cpu().numpy(), U.cpu().numpy(), L.cpu().numpy()))
+    for a, b in zip(*outs):
+        assert rel(b, a) <= 1e-11
+    # FP32 sweeps to convergence: same solution, same iteration counts (+-2)
+    res = []
+    for path in (nm.NMPC_PATH_FUSED, nm.NMPC_PATH_STREAM):
+        s = nm.Solver(P, max_batch=3, tol=1e-6, max_iter=5000, path=path,
+                      precision=nm.NMPC_FP32_SWEEP)
+        rc, X, U, L, info = s.solve_batch(X0, XR)
+        assert rc == nm.NMPC_OK
+        res.append((U.cpu().numpy(), [i["iters"] for i in info]))
+    assert rel(res[1][0], res[0][0]) <= 1e-4
+    assert max(abs(a - b) for a, b in zip(res[0][1], res[1][1])) <= 2
+
+
+def test_stream_warm_start_and_residual(nm):
+    import torch
+    P = shaped(130, 20, 3, 4)
+    x0, xr = make_instance(P, 2)
+    ex = oracle.solve(P, x0, xr, tol=1e-11, max_iter=50000)
+    assert ex["status"] == "converged"
+    s = nm.Solver(P, tol=1e-8, path=nm.NMPC_PATH_STREAM)
+    rc, X, U, L, info = s.solve(x0, xr, warm=(ex["X"], ex["U"], ex["LAM"]))
+    assert rc == nm.NMPC_OK and info["iters"] == 0
+    np.testing.assert_array_equal(U, ex["U"])
+    rng = np.random.default_rng(3)
+    Xr, Ur, Lr = (rng.normal(size=a.shape) * 0.1 for a in (ex["X"], ex["U"], ex["LAM"]))
+    rs, rp = s.residual_batch(*(torch.tensor(a[None], device="cuda") for a in (x0, xr)),
+                              *(torch.tensor(a[None], device="cuda") for a in (Xr, Ur, Lr)))
+    os_, op_ = oracle.residual(P, x0, xr, Xr, Ur, Lr)
+    assert abs(rs[0] - os_) <= 1e-12 * os_ and abs(rp[0] - op_) <= 1e-12 * op_
+
+
+def test_c2_full_size(nm):
+    """256 x 256 grid, N = 100, 8 x 8 Gaussian lattice (65,536 nodes and 64
+    inputs per stage): the first iterate equals the oracle's (FP64), and the
+    FP32-sweep solve converges with the oracle's residual of the returned
+    trajectory within the test."""
+    P = make_problem("c2")
+    x0, xref = make_instance(P, 0)
+    s = nm.Solver(P, tol=0.0, max_iter=1)
+    assert s.kernel_config()["rows_per_lane"] == 0   # automatic choice: streaming
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=0.0, max_iter=1)
+    assert rel(X, o["X"]) <= REL and rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
+    s.close()
+    s = nm.Solver(P, tol=1e-6, max_iter=20000, precision=nm.NMPC_FP32_SWEEP)
+    s.timing_enable(True)
+    rc, X, U, L, info = s.solve(x0, xref)
+    t = s.timing_read()
+    print(f"C2: status {rc}, {info['iters']} iterations ({info['fp32_iters']} FP32), "
+          f"r_scaled {info['r_scaled']:.2e}, kernels {t['kernel_ms']:.1f} ms")
+    assert rc == nm.NMPC_OK
+    r_s, _ = oracle.residual(P, x0, xref, X, U, L)
+    assert r_s <= 1e-6
