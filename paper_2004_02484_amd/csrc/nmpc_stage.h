@@ -458,6 +458,16 @@ __device__ __forceinline__ StageLoc jacobi_loc(int cur)
     return v;
 }
 
+// 1 / d for the lower layer's diagonal: the FP32 kernels use the hardware
+// reciprocal (about 1 ulp; the coefficient only shapes the preconditioner,
+// the FP64 residual decides), the FP64 kernels the correctly rounded quotient.
+template <typename T>
+__device__ __forceinline__ T recip(double d);
+template <>
+__device__ __forceinline__ float recip<float>(double d) { return __builtin_amdgcn_rcpf(float(d)); }
+template <>
+__device__ __forceinline__ double recip<double>(double d) { return 1.0 / d; }
+
 // acc (thread 0 only): running bit-pattern max of (r_scaled, r_paper) over
 // the stages processed with res_at == -1.
 template <typename T, int CX, int RY, int LX, int LY>
@@ -570,7 +580,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             for (int q = 0; q < CX; ++q) {
                 const double kk = P.k0 * (1.0 + P.k1 * xc[t][q]);
                 const double d = -1.0 - h * kk * P.c0 + h * kp * Lx[t][q];   // diag of F_x
-                K.invd[t][q] = valid(t, q) ? T(1.0 / d) : T(0);
+                K.invd[t][q] = valid(t, q) ? recip<T>(d) : T(0);
                 K.cpk[t][q] = T(h * kk);
                 K.g2[t][q] = T(kp * lc[t][q]);
             }
