@@ -14,6 +14,7 @@ constexpr int kMaxM = 64;       // inputs per stage
 constexpr int kMaxLy = 8;       // input lattice rows
 constexpr int kMaxCx = 6;       // columns per lane: nsx <= 16 * 6 = 96
 constexpr int kMaxLx = 8;       // input lattice columns
+constexpr size_t kLdsBytes = 160 * 1024;   // LDS of a gfx950 CU (one workgroup's limit)
 
 constexpr int kActive = -1;
 constexpr int kStatusOk = 0;        // == NMPC_OK
@@ -129,11 +130,16 @@ struct StreamArgs {
     int *iters;
     double *rfin;
     int *ctr;                       // [2] finished, [3] in the FP32 phase
-    long long units;                // count * N * nsy rows
+    long long units;                // count * N * ceil(nsy / kStreamRows) row blocks
     int per_xcd, count;
     double tol;
     int max_iter, n_sw, n_schur;
 };
+
+// Grid rows per workgroup of the streaming passes; their LDS holds up to two
+// arrays of (kStreamRows + 2) rows of 8-byte values.
+constexpr int kStreamRows = 8;
+__host__ __device__ inline size_t stream_lds_bytes(int nsx) { return (size_t)2 * (kStreamRows + 2) * nsx * 8; }
 
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;

@@ -143,22 +143,21 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
 #define NMPC_GS_DEFAULTS()                                                          \
     NMPC_GS(kModeFp32, 1, 1, 16) NMPC_GS(kModeFp32, 2, 1, 16)                       \
     NMPC_GS(kModeFp32, 3, 1, 16) NMPC_GS(kModeFp32, 4, 1, 16)                       \
-    NMPC_GS(kModeFp32, 6, 2, 12)                                                    \
+    NMPC_GS(kModeFp32, 6, 3, 8)                                                    \
     NMPC_GS(kModeFp64, 1, 2, 8) NMPC_GS(kModeFp64, 2, 2, 8)                         \
     NMPC_GS(kModeFp64, 3, 2, 8) NMPC_GS(kModeFp64, 4, 2, 8)                         \
-    NMPC_GS(kModeFp64, 6, 2, 12)
+    NMPC_GS(kModeFp64, 6, 3, 8)
 // the 4 x 4 lattice (Gaussian actuators) needs more registers for B and B^T:
 // 16 waves only where the tile still fits 128 VGPRs
 #define NMPC_GS_LATTICE4()                                                          \
     NMPC_GS(kModeFp32, 1, 1, 16) NMPC_GS(kModeFp32, 2, 2, 8)                        \
     NMPC_GS(kModeFp32, 3, 2, 8) NMPC_GS(kModeFp32, 4, 2, 8)                         \
-    NMPC_GS(kModeFp32, 6, 2, 12)                                                    \
+    NMPC_GS(kModeFp32, 6, 3, 8)                                                    \
     NMPC_GS(kModeFp64, 1, 2, 8) NMPC_GS(kModeFp64, 2, 2, 8)                         \
     NMPC_GS(kModeFp64, 3, 2, 8) NMPC_GS(kModeFp64, 4, 2, 8)                         \
-    NMPC_GS(kModeFp64, 6, 2, 12)                                                    \
+    NMPC_GS(kModeFp64, 6, 3, 8)                                                    \
     NMPC_GS(kModeFp32, 2, 1, 16) NMPC_GS(kModeFp32, 3, 1, 16)                       \
     NMPC_GS(kModeFp32, 4, 1, 16) NMPC_GS(kModeFp32, 4, 4, 4)                        \
-    NMPC_GS(kModeFp32, 6, 3, 8)                                                     \
     NMPC_GS(kModeFp64, 4, 1, 16) NMPC_GS(kModeFp64, 4, 4, 4)
 
 const void *gs_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg)

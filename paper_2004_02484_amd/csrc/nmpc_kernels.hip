@@ -343,11 +343,11 @@ __global__ void k_output(const OutArgs a)
     NMPC_TILE(kModeFp32, 2, 4, 4) NMPC_TILE(kModeFp32, 2, 8, 2)                     \
     NMPC_TILE(kModeFp32, 3, 4, 4) NMPC_TILE(kModeFp32, 3, 2, 8)                     \
     NMPC_TILE(kModeFp32, 4, 4, 4) NMPC_TILE(kModeFp32, 4, 2, 8)                     \
-    NMPC_TILE(kModeFp32, 6, 2, 12)                                                  \
+    NMPC_TILE(kModeFp32, 6, 3, 8)                                                  \
     NMPC_TILE(kModeFp64, 1, 4, 4) NMPC_TILE(kModeFp64, 2, 2, 8)                     \
     NMPC_TILE(kModeFp64, 2, 4, 4) NMPC_TILE(kModeFp64, 3, 2, 8)                     \
     NMPC_TILE(kModeFp64, 4, 2, 8)                                                   \
-    NMPC_TILE(kModeFp64, 6, 2, 12)
+    NMPC_TILE(kModeFp64, 6, 3, 8)
 
 const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg)
 {
@@ -384,7 +384,7 @@ const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cf
     }
 #define NMPC_ROLL_LATTICE()                                                         \
     NMPC_ROLL(1, 4, 4) NMPC_ROLL(2, 2, 8) NMPC_ROLL(3, 2, 8) NMPC_ROLL(4, 2, 8)     \
-    NMPC_ROLL(6, 2, 12)
+    NMPC_ROLL(6, 3, 8)
 
 const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg)
 {

@@ -492,9 +492,13 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
     for (int q = 0; q < 3; ++q) {
         bool all = true;
         for (int c = 0; c < nclass; ++c) {
-            r->fits[q][c] = nmpc::ragged_tile(classes[c].nsx, classes[c].nsy, kWaveChoices[q], nullptr,
-                                              nullptr) >= 0;
-            all = all && r->fits[q][c];
+            int cx = 0, ry = 0;
+            const int w = kWaveChoices[q];
+            bool f = nmpc::ragged_tile(classes[c].nsx, classes[c].nsy, w, &cx, &ry) >= 0;
+            for (int ts : {4, 8})   // both precisions' layouts within one CU's LDS
+                f = f && nmpc::lds_layout(4 * w, w, cx, ts, 4, 4, ry).total <= nmpc::kLdsBytes;
+            r->fits[q][c] = f;
+            all = all && f;
         }
         any = any || all;
     }

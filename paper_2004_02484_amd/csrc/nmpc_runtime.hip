@@ -112,12 +112,15 @@ int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k,
     const int waves = (groups + 3) / 4;
     if (waves > cfg.max_waves)
         return fail(NMPC_E_UNSUPPORTED, "grid too tall for the fused stage kernel");
+    const size_t lds = nmpc::lds_layout(waves * 4, waves, cfg.cx, prec == nmpc::kModeFp32 ? 4 : 8,
+                                        p->lx, p->ly, cfg.rows).total;
+    if (lds > nmpc::kLdsBytes)
+        return fail(NMPC_E_UNSUPPORTED, "tile needs more LDS than a CU has");
     if (k) {
         k->fn = fn;
         k->cfg = cfg;
         k->waves = waves;
-        k->lds = nmpc::lds_layout(waves * 4, waves, cfg.cx, prec == nmpc::kModeFp32 ? 4 : 8,
-                                  p->lx, p->ly, cfg.rows).total;
+        k->lds = lds;
     }
     return NMPC_OK;
 }
@@ -186,6 +189,8 @@ int choose_path(const nmpc_problem *p, const nmpc_options *o, bool *streaming)
     *streaming = fused != NMPC_OK;
     if (*streaming && o->upper != NMPC_UPPER_JACOBI)
         return fail(NMPC_E_UNSUPPORTED, "the streaming path runs the Jacobi upper layer only");
+    if (*streaming && nmpc::stream_lds_bytes(p->nsx) > nmpc::kLdsBytes)
+        return fail(NMPC_E_UNSUPPORTED, "grid rows too wide for the streaming path");
     g_err.clear();
     return NMPC_OK;
 }
@@ -468,7 +473,7 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.pst = h->d_rst + B * N;
     a.st = h->d_st; a.work = h->d_work; a.iters = h->d_iters; a.rfin = h->d_rfin; a.ctr = h->d_ctr;
     a.count = count;
-    a.units = (long long)count * h->N * p.nsy;
+    a.units = (long long)count * h->N * ((p.nsy + nmpc::kStreamRows - 1) / nmpc::kStreamRows);
     a.per_xcd = (int)((a.units + 7) / 8);
     a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
     a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
@@ -481,8 +486,9 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
 {
     const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
     const dim3 rows(8 * a.per_xcd), stages(a.count * h->N), inst((a.count + 255) / 256);
-    auto go = [&](const void *fn, dim3 grid, int block, void **args) -> int {
-        HIP_TRY(hipLaunchKernel(fn, grid, dim3(block), args, 0, s));
+    const size_t lds = nmpc::stream_lds_bytes(h->prob.nsx);   // row-block passes only
+    auto go = [&](const void *fn, dim3 grid, int block, void **args, size_t sh = 0) -> int {
+        HIP_TRY(hipLaunchKernel(fn, grid, dim3(block), args, sh, s));
         return NMPC_OK;
     };
     int rc;
@@ -495,8 +501,8 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     }
     {
         void *args[] = {(void *)&a};
-        if ((rc = go(k.res, rows, 256, args))) return rc;
-        if ((rc = go(k.stage, stages, 64, args))) return rc;
+        if ((rc = go(k.res, rows, 256, args, lds))) return rc;
+        if ((rc = go(k.stage, stages, 256, args))) return rc;
         if ((rc = go(k.decide, inst, 256, args))) return rc;
     }
     for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
@@ -510,22 +516,22 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
         int sgn = fin ? 1 : -1;
         for (int pass = 0; pass < passes; ++pass) {
             void *args[] = {(void *)&a, (void *)&sgn, (void *)&use_v3, (void *)&pass};
-            if ((rc = go(k.jf, rows, 256, args))) return rc;
+            if ((rc = go(k.jf, rows, 256, args, lds))) return rc;
         }
         int ytmp = y5_tmp;
         {
             void *args[] = {(void *)&a, (void *)&sgn, (void *)&ytmp};
-            if ((rc = go(k.axx, rows, 256, args))) return rc;
+            if ((rc = go(k.axx, rows, 256, args, lds))) return rc;
         }
         for (int pass = 0; pass < passes; ++pass) {
             int last = pass == passes - 1, partials = fin ? 0 : 1, update = fin ? 1 : 0;
             void *args[] = {(void *)&a, (void *)&pass, (void *)&last, (void *)&partials,
                             (void *)&update, (void *)&ytmp};
-            if ((rc = go(k.jft, rows, 256, args))) return rc;
+            if ((rc = go(k.jft, rows, 256, args, lds))) return rc;
         }
         if (!fin) {
             void *args[] = {(void *)&a};
-            if ((rc = go(k.v3, stages, 64, args))) return rc;
+            if ((rc = go(k.v3, stages, 256, args))) return rc;
         }
     }
     void *args[] = {(void *)&a};
@@ -764,6 +770,16 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     if (h->streaming) {
         ALLOC(h->d_stream, sizeof(double) * stream_doubles(h));
         ALLOC(h->d_work, sizeof(int) * B);
+        const size_t lds = nmpc::stream_lds_bytes(prob->nsx);
+        for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
+            const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
+            for (const void *fn : {k.res, k.jf, k.axx, k.jft})
+                if (lds > 48 * 1024 &&
+                    hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
+                    release(h);
+                    return fail(NMPC_E_DEVICE, "streaming kernels: LDS limit");
+                }
+        }
     }
 
 #undef ALLOC
@@ -925,8 +941,9 @@ int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const d
         void *a1[] = {(void *)&a, (void *)&which};
         void *a2[] = {(void *)&a};
         HIP_TRY(hipLaunchKernel(k.bsep, dim3(count * h->N), dim3(256), a1, 0, h->stream));
-        HIP_TRY(hipLaunchKernel(k.res, dim3(8 * a.per_xcd), dim3(256), a2, 0, h->stream));
-        HIP_TRY(hipLaunchKernel(k.stage, dim3(count * h->N), dim3(64), a2, 0, h->stream));
+        HIP_TRY(hipLaunchKernel(k.res, dim3(8 * a.per_xcd), dim3(256), a2,
+                                nmpc::stream_lds_bytes(h->prob.nsx), h->stream));
+        HIP_TRY(hipLaunchKernel(k.stage, dim3(count * h->N), dim3(256), a2, 0, h->stream));
         rst = a.rst;
         pst = a.pst;
     } else {

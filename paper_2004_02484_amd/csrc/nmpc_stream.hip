@@ -1,9 +1,8 @@
 // nmpc_stream.hip -- streaming kernels of the Jacobi upper iteration for grids
 // whose stage does not fit one workgroup (e.g. 256 x 256): every step of the
-// stage algebra is a pass over all (instance, stage, grid row) units, one
-// workgroup per row, with stencil neighbours read from the adjacent rows
-// (L2-resident: each XCD receives a contiguous run of rows) and per-row
-// partial reductions combined by small per-stage kernels.
+// stage algebra is a pass over all (instance, stage, block of grid rows)
+// units, with stencil inputs staged in LDS per block and per-row partial
+// reductions combined by small per-stage kernels.
 //
 // One upper iteration (eq. 1st_jacobi, alpha = 1), per instance and stage i:
 //   K_res    KKT rows K^x, K^lambda (FP64), stage coefficients, row partials
@@ -15,8 +14,8 @@
 //   final:   y5 = JacF(b1 - h B v3); y4 = JacFT(b2 - A_xx y5);
 //            S^{k+1} = S^k - (y5, v3, y4)
 // A point-Jacobi solve with n_sweep sweeps from zero is one pass for the
-// first two sweeps (the first sweep's value c / d at a neighbour is formed on
-// the fly) and one pass per further sweep.
+// first two sweeps (the first sweep's values are formed in LDS for the block
+// and its halo rows) and one pass per further sweep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -41,20 +40,29 @@ __device__ __forceinline__ unsigned long long sumax(unsigned long long a, unsign
     return a > b ? a : b;
 }
 
-// Row unit of a pass: XCD-aware order (each XCD a contiguous run of rows).
-struct RowUnit {
-    int b, i, iy;
+// Row-block unit of a pass: one workgroup of 4 waves per block of kRows grid
+// rows of one stage, XCD-aware order (each XCD a contiguous run of blocks, so
+// a stage's neighbouring blocks and stages share that XCD's L2). Inputs of a
+// stencil are staged in LDS for the block's rows plus one halo row above and
+// below (zero outside the grid: the Dirichlet values); wave w computes rows
+// w, w + 4, ... of the block, lanes walk the columns, so per-row reductions
+// are wave reductions without barriers.
+constexpr int kRows = kStreamRows;
+
+struct Block {
+    int b, i, iy0;
     bool ok;
 };
 
-__device__ __forceinline__ RowUnit row_unit(const StreamArgs &a)
+__device__ __forceinline__ Block row_block(const StreamArgs &a)
 {
-    RowUnit r{};
+    Block r{};
     const int bid = blockIdx.x;
     const long long unit = (long long)(bid & 7) * a.per_xcd + (bid >> 3);
     if (unit >= a.units) { r.ok = false; return r; }
-    r.iy = (int)(unit % a.P.nsy);
-    const long long bi = unit / a.P.nsy;
+    const int nblk = (a.P.nsy + kRows - 1) / kRows;
+    r.iy0 = (int)(unit % nblk) * kRows;
+    const long long bi = unit / nblk;
     r.i = (int)(bi % a.P.N);
     r.b = (int)(bi / a.P.N);
     r.ok = r.b < a.count;
@@ -70,33 +78,48 @@ __device__ __forceinline__ bool evaluating(const StreamArgs &a, int b)
     return PREC == kModeFp32 ? s.mode == kModeFp32 : s.mode != kModeFp32;
 }
 
-// Block-wide sum / max over 256 threads (4 waves) into thread 0.
-__device__ __forceinline__ double block_sum(double v, double *sh)
+// Stage f(iy, ix) for rows iy0 - 1 .. iy0 + kRows of the block into lds
+// [(kRows + 2)][nsx] (zero outside the grid), then synchronize.
+template <typename V, typename F>
+__device__ __forceinline__ void stage_rows(V *lds, const DevProblem &P, int iy0, F f)
+{
+    const int nsx = P.nsx, tot = (kRows + 2) * nsx;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+        const int rr = e / nsx, ix = e - rr * nsx, iy = iy0 + rr - 1;
+        lds[e] = (iy >= 0 && iy < P.nsy) ? f(iy, ix) : V(0);
+    }
+    __syncthreads();
+}
+
+// Neighbour sum of a staged array at block row rr (0-based), column ix.
+template <typename V>
+__device__ __forceinline__ V lds_nb(const V *lds, int nsx, int rr, int ix, V ax, V ay)
+{
+    const V *row = lds + (rr + 1) * nsx;
+    const V l = ix > 0 ? row[ix - 1] : V(0), r = ix + 1 < nsx ? row[ix + 1] : V(0);
+    return ax * (l + r) + ay * (row[ix - nsx] + row[ix + nsx]);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
-    const int w = threadIdx.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int q = 0; q < (int)(blockDim.x / kWave); ++q) s += sh[q];
-    return s;
+    return v;
 }
-
-__device__ __forceinline__ unsigned long long block_max(unsigned long long v, unsigned long long *sh)
+__device__ __forceinline__ unsigned long long wave_umax(unsigned long long v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = sumax(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+// Own rows of the block for this wave: rows iy0 + w, iy0 + w + 4, ... < nsy;
+// body(rr, iy) for each. Lanes then walk the columns inside body.
+template <typename F>
+__device__ __forceinline__ void own_rows(const DevProblem &P, int iy0, F body)
+{
     const int w = threadIdx.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) sh[w] = v;
-    __syncthreads();
-    unsigned long long s = 0;
-    if (threadIdx.x == 0)
-        for (int q = 0; q < (int)(blockDim.x / kWave); ++q) s = sumax(s, sh[q]);
-    return s;
+    for (int rr = w; rr < kRows && iy0 + rr < P.nsy; rr += (int)(blockDim.x / kWave)) body(rr, iy0 + rr);
 }
 
 }  // namespace
@@ -133,17 +156,17 @@ __device__ __forceinline__ double bsep_at(const StreamArgs &a, size_t bi, int iy
 
 // KKT rows, coefficients and row partials of S^j (FP64 arithmetic; the
 // right-hand sides and coefficients are stored in T for the lower layer).
+// LDS: x and g = k(x) lambda of the block rows and halo rows.
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_res(const StreamArgs a)
 {
-    __shared__ double sh[kMaxWaves];
-    __shared__ unsigned long long shu[kMaxWaves];
-    const RowUnit u = row_unit(a);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Block u = row_block(a);
     if (!u.ok) return;
-    const int PREC = std::is_same<T, float>::value ? kModeFp32 : kModeFp64;
+    constexpr int PREC = std::is_same<T, float>::value ? kModeFp32 : kModeFp64;
     if (!evaluating<PREC>(a, u.b)) return;
     const DevProblem &P = a.P;
-    const int n = P.nsx * P.nsy, nsx = P.nsx, nsy = P.nsy, iy = u.iy;
+    const int n = P.nsx * P.nsy, nsx = P.nsx;
     const size_t bi = (size_t)u.b * P.N + u.i;
     const int cur = a.st[u.b].j & 1;
     const double *x = a.X[cur] + bi * n, *lam = a.LAM[cur] + bi * n;
@@ -156,63 +179,71 @@ __global__ void __launch_bounds__(256) k_st_res(const StreamArgs a)
     T *g2 = reinterpret_cast<T *>(a.g2) + bi * n;
     const double h = P.h, kp = P.k0 * P.k1;
     auto K = [&](double w) { return P.k0 * (1.0 + P.k1 * w); };
-    unsigned long long mx = 0, ml = 0;
-    double tl[kMaxLx];
-    for (int q = 0; q < P.lx; ++q) tl[q] = 0.0;
-    for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-        const int p = iy * nsx + ix;
-        auto at = [&](const double *v, int dx, int dy) {
-            const int jx = ix + dx, jy = iy + dy;
-            return (jx < 0 || jx >= nsx || jy < 0 || jy >= nsy) ? 0.0 : v[jy * nsx + jx];
-        };
-        const double xc = x[p], lc = lam[p];
-        const double Lx = P.idx2 * (at(x, -1, 0) + at(x, 1, 0)) + P.idy2 * (at(x, 0, -1) + at(x, 0, 1))
-                          - P.c0 * xc;
-        auto g = [&](int dx, int dy) {
-            const int jx = ix + dx, jy = iy + dy;
-            if (jx < 0 || jx >= nsx || jy < 0 || jy >= nsy) return 0.0;
-            const int q = jy * nsx + jx;
-            return K(x[q]) * lam[q];
-        };
-        const double gc = K(xc) * lc;
-        const double Lg = P.idx2 * (g(-1, 0) + g(1, 0)) + P.idy2 * (g(0, -1) + g(0, 1)) - P.c0 * gc;
-        const double kl = (last ? 0.0 : ln[p]) - lc + h * (P.q * (xc - xr[p]) + Lg + kp * Lx * lc);
-        const double kx = xp[p] - xc + h * (K(xc) * Lx + bsep_at(a, bi, iy, ix));
-        mx = sumax(mx, sabits(kx));
-        ml = sumax(ml, sabits(kl));
-        b1[p] = T(kx);
-        b2[p] = T(kl);
-        const double d = -1.0 - h * K(xc) * P.c0 + h * kp * Lx;
-        invd[p] = T(1.0 / d);
-        cpk[p] = T(h * K(xc));
-        g2[p] = T(kp * lc);
-        for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * lc;
-    }
-    const size_t ru = bi * nsy + iy;
-    const unsigned long long bx = block_max(mx, shu);
-    if (threadIdx.x == 0) a.rown[2 * ru] = bx;
-    const unsigned long long bl = block_max(ml, shu);
-    if (threadIdx.x == 0) a.rown[2 * ru + 1] = bl;
-    for (int q = 0; q < P.lx; ++q) {
-        const double s = block_sum(tl[q], sh);
-        if (threadIdx.x == 0) a.rowt[ru * kMaxLx + q] = s;
-    }
+    double *xs = reinterpret_cast<double *>(lds_raw);
+    double *gs = xs + (kRows + 2) * nsx;
+    stage_rows(xs, P, u.iy0, [&](int iy, int ix) { return x[iy * nsx + ix]; });
+    stage_rows(gs, P, u.iy0, [&](int iy, int ix) { const int q = iy * nsx + ix; return K(x[q]) * lam[q]; });
+    const int lane = threadIdx.x & (kWave - 1);
+    own_rows(P, u.iy0, [&](int rr, int iy) {
+        unsigned long long mx = 0, ml = 0;
+        double tl[kMaxLx];
+        for (int q = 0; q < P.lx; ++q) tl[q] = 0.0;
+        for (int ix = lane; ix < nsx; ix += kWave) {
+            const int p = iy * nsx + ix, e = (rr + 1) * nsx + ix;
+            const double xc = xs[e], lc = lam[p];
+            const double Lx = lds_nb(xs, nsx, rr, ix, P.idx2, P.idy2) - P.c0 * xc;
+            const double Lg = lds_nb(gs, nsx, rr, ix, P.idx2, P.idy2) - P.c0 * gs[e];
+            const double kl = (last ? 0.0 : ln[p]) - lc + h * (P.q * (xc - xr[p]) + Lg + kp * Lx * lc);
+            const double kx = xp[p] - xc + h * (K(xc) * Lx + bsep_at(a, bi, iy, ix));
+            mx = sumax(mx, sabits(kx));
+            ml = sumax(ml, sabits(kl));
+            b1[p] = T(kx);
+            b2[p] = T(kl);
+            const double d = -1.0 - h * K(xc) * P.c0 + h * kp * Lx;
+            invd[p] = T(1.0 / d);
+            cpk[p] = T(h * K(xc));
+            g2[p] = T(kp * lc);
+            for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * lc;
+        }
+        const size_t ru = bi * P.nsy + iy;
+        mx = wave_umax(mx);
+        ml = wave_umax(ml);
+        for (int q = 0; q < P.lx; ++q) tl[q] = wave_sum(tl[q]);
+        if (lane == 0) {
+            a.rown[2 * ru] = mx;
+            a.rown[2 * ru + 1] = ml;
+            for (int q = 0; q < P.lx; ++q) a.rowt[ru * kMaxLx + q] = tl[q];
+        }
+    });
 }
 
-// (B^T y)_{bb*lx+a} of stage bi from its rows' partials sum_ix gx[a][ix] y.
-__device__ __forceinline__ double bt_from_rows(const StreamArgs &a, size_t bi, int j)
+// (B^T y)_{bb*lx+a} of stage bi from its rows' partials sum_ix gx[a][ix] y,
+// for all j < m: a 256-thread workgroup splits the rows in four quarters
+// (threads j, j + 64, ...) and sums the quarters through LDS; the result is
+// valid in threads t < m.
+__device__ __forceinline__ double bt_from_rows(const StreamArgs &a, size_t bi, double *sh)
 {
-    const int bb = j / a.P.lx, aa = j % a.P.lx;
+    const int t = threadIdx.x, j = t & (kWave - 1), qtr = t / kWave, nq = (int)(blockDim.x / kWave);
     double s = 0.0;
-    for (int iy = 0; iy < a.P.nsy; ++iy)
-        s += a.gy[bb * a.P.nsy + iy] * a.rowt[(bi * a.P.nsy + iy) * kMaxLx + aa];
-    return s;
+    if (j < a.P.m) {
+        const int bb = j / a.P.lx, aa = j % a.P.lx;
+        for (int iy = qtr; iy < a.P.nsy; iy += nq)
+            s += a.gy[bb * a.P.nsy + iy] * a.rowt[(bi * a.P.nsy + iy) * kMaxLx + aa];
+    }
+    sh[t] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (t < kWave)
+        for (int q = 0; q < nq; ++q) tot += sh[q * kWave + t];
+    return tot;
 }
 
-// K^u, the stage's norms and v3 = 0. One workgroup (64 threads) per stage.
+// K^u, the stage's norms and v3 = 0. One workgroup (256 threads) per stage.
 template <int PREC>
-__global__ void k_st_stage(const StreamArgs a)
+__global__ void __launch_bounds__(256) k_st_stage(const StreamArgs a)
 {
+    __shared__ double sh[256];
+    __shared__ unsigned long long shn[2 * kMaxWaves];
     const int bi = blockIdx.x;
     if (bi >= a.count * a.P.N) return;
     const int b = bi / a.P.N;
@@ -221,23 +252,29 @@ __global__ void k_st_stage(const StreamArgs a)
     const int m = P.m;
     const int cur = a.st[b].j & 1;
     unsigned long long mu = 0, mx = 0, ml = 0;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const double ku = P.h * (P.r * a.U[cur][(size_t)bi * m + j] + bt_from_rows(a, bi, j));
+    const double bt = bt_from_rows(a, bi, sh);
+    if (threadIdx.x < m) {
+        const int j = threadIdx.x;
+        const double ku = P.h * (P.r * a.U[cur][(size_t)bi * m + j] + bt);
         a.kun[(size_t)bi * m + j] = ku;
         a.v3[(size_t)bi * m + j] = 0.0;
-        mu = sumax(mu, sabits(ku));
+        mu = sabits(ku);
     }
     for (int iy = threadIdx.x; iy < P.nsy; iy += blockDim.x) {
         mx = sumax(mx, a.rown[2 * ((size_t)bi * P.nsy + iy)]);
         ml = sumax(ml, a.rown[2 * ((size_t)bi * P.nsy + iy) + 1]);
     }
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) {
-        mu = sumax(mu, __shfl_xor(mu, s, kWave));
-        mx = sumax(mx, __shfl_xor(mx, s, kWave));
-        ml = sumax(ml, __shfl_xor(ml, s, kWave));
-    }
+    mx = wave_umax(mx);
+    ml = wave_umax(ml);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) { shn[2 * w] = mx; shn[2 * w + 1] = ml; }
+    mu = wave_umax(mu);   // the inputs live in wave 0
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int q = 1; q < (int)(blockDim.x / kWave); ++q) {
+            mx = sumax(mx, shn[2 * q]);
+            ml = sumax(ml, shn[2 * q + 1]);
+        }
         const double dx = sbits2d(mx), dl = sbits2d(ml), du = sbits2d(mu);
         double rp = dx > du ? dx : du;
         rp = rp > dl ? rp : dl;
@@ -304,189 +341,187 @@ __global__ void k_st_decide(const StreamArgs a)
     a.work[b] = work;
 }
 
-// First pass of a point-Jacobi solve of F_x y = c (transposed: F_x^T y = c)
-// from zero, with the right-hand side c formed per point by rhs():
-//   one sweep:  y = c / d
-//   two sweeps: y = (c - off) / d, off = sum of the neighbours' coupling to
-//               their first-sweep values c_q / d_q
-// F_x couples p to q with h k_p / dx^2 (row scaling by cpk_p); F_x^T with
-// h k_q / dx^2 (the neighbour's cpk_q).
-template <typename T, bool TRANS, typename RHS>
-__device__ __forceinline__ void jacobi_first(const StreamArgs &a, const RowUnit &u, size_t bi,
-                                             int nsw, const T *invd, const T *cpk, T *y, RHS rhs)
-{
-    const DevProblem &P = a.P;
-    const int nsx = P.nsx, nsy = P.nsy, iy = u.iy;
-    const T ax = T(P.idx2), ay = T(P.idy2);
-    for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-        const int p = iy * nsx + ix;
-        const T c = rhs(iy, ix);
-        if (nsw < 2) { y[p] = c * invd[p]; continue; }
-        auto y1 = [&](int dx, int dy) -> T {   // first-sweep value (times cpk for F^T)
-            const int jx = ix + dx, jy = iy + dy;
-            if (jx < 0 || jx >= nsx || jy < 0 || jy >= nsy) return T(0);
-            const int q = jy * nsx + jx;
-            const T v = rhs(jy, jx) * invd[q];
-            return TRANS ? cpk[q] * v : v;
-        };
-        const T nb = ax * (y1(-1, 0) + y1(1, 0)) + ay * (y1(0, -1) + y1(0, 1));
-        y[p] = (c - (TRANS ? nb : cpk[p] * nb)) * invd[p];
-    }
-}
-
-// Further sweeps: y_out = (c - coupling(y_in)) / d with c re-formed by rhs().
-template <typename T, bool TRANS, typename RHS>
-__device__ __forceinline__ void jacobi_more(const StreamArgs &a, const RowUnit &u, const T *invd,
-                                            const T *cpk, const T *yin, T *yout, RHS rhs)
-{
-    const DevProblem &P = a.P;
-    const int nsx = P.nsx, nsy = P.nsy, iy = u.iy;
-    const T ax = T(P.idx2), ay = T(P.idy2);
-    for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-        const int p = iy * nsx + ix;
-        auto yv = [&](int dx, int dy) -> T {
-            const int jx = ix + dx, jy = iy + dy;
-            if (jx < 0 || jx >= nsx || jy < 0 || jy >= nsy) return T(0);
-            const int q = jy * nsx + jx;
-            return TRANS ? cpk[q] * yin[q] : yin[q];
-        };
-        const T nb = ax * (yv(-1, 0) + yv(1, 0)) + ay * (yv(0, -1) + yv(0, 1));
-        yout[p] = (rhs(iy, ix) - (TRANS ? nb : cpk[p] * nb)) * invd[p];
-    }
-}
-
-// F_x solve: c = sgn (b1 - h B v3) (sgn = -1 in the Schur iterations, where
-// c = h B v3 - b1; +1 in the final block). pass 0: first two sweeps into y5;
-// pass s >= 1: sweep s + 2 from y5 / ytmp (ping-pong by parity).
+// F_x solve (point-Jacobi from zero) of c = sgn (b1 - h B v3) (sgn = -1 in
+// the Schur iterations, where c = h B v3 - b1; +1 in the final block).
+// pass 0: c and the first sweep's values y1 = c / d of the block and halo
+// rows are staged in LDS and the second sweep y = (c - cpk N(y1)) / d is
+// written to y5 (one sweep: y1 itself); pass s >= 1: sweep s + 2 from y5 /
+// ytmp (ping-pong by parity) staged in LDS.
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_jf(const StreamArgs a, int sgn, int use_v3, int pass)
 {
-    const RowUnit u = row_unit(a);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Block u = row_block(a);
     if (!u.ok || !a.work[u.b]) return;
-    const int n = a.P.nsx * a.P.nsy;
-    const size_t bi = (size_t)u.b * a.P.N + u.i;
+    const DevProblem &P = a.P;
+    const int nsx = P.nsx, n = nsx * P.nsy;
+    const size_t bi = (size_t)u.b * P.N + u.i;
     const T *b1 = reinterpret_cast<const T *>(a.b1) + bi * n;
     const T *invd = reinterpret_cast<const T *>(a.invd) + bi * n;
     const T *cpk = reinterpret_cast<const T *>(a.cpk) + bi * n;
     T *y5 = reinterpret_cast<T *>(a.y5) + bi * n, *yt = reinterpret_cast<T *>(a.ytmp) + bi * n;
-    const T h = T(a.P.h);
-    auto rhs = [&](int jy, int jx) -> T {
-        const T bv = use_v3 ? T(bsep_at(a, bi, jy, jx)) : T(0);
-        const T v = b1[jy * a.P.nsx + jx] - h * bv;
+    const T h = T(P.h), ax = T(P.idx2), ay = T(P.idy2);
+    auto rhs = [&](int iy, int ix) -> T {
+        const T bv = use_v3 ? T(bsep_at(a, bi, iy, ix)) : T(0);
+        const T v = b1[iy * nsx + ix] - h * bv;
         return sgn > 0 ? v : -v;
     };
+    T *ys = reinterpret_cast<T *>(lds_raw);
+    const int lane = threadIdx.x & (kWave - 1);
     if (pass == 0) {
-        jacobi_first<T, false>(a, u, bi, a.n_sw, invd, cpk, y5, rhs);
+        if (a.n_sw < 2) {
+            own_rows(P, u.iy0, [&](int rr, int iy) {
+                for (int ix = lane; ix < nsx; ix += kWave) y5[iy * nsx + ix] = rhs(iy, ix) * invd[iy * nsx + ix];
+            });
+            return;
+        }
+        T *cs = ys + (kRows + 2) * nsx;   // c of the block and halo rows
+        stage_rows(cs, P, u.iy0, [&](int iy, int ix) { return rhs(iy, ix); });
+        stage_rows(ys, P, u.iy0, [&](int iy, int ix) {
+            return cs[(iy - u.iy0 + 1) * nsx + ix] * invd[iy * nsx + ix];
+        });
+        own_rows(P, u.iy0, [&](int rr, int iy) {
+            for (int ix = lane; ix < nsx; ix += kWave) {
+                const int p = iy * nsx + ix;
+                y5[p] = (cs[(rr + 1) * nsx + ix] - cpk[p] * lds_nb(ys, nsx, rr, ix, ax, ay)) * invd[p];
+            }
+        });
     } else {
-        // sweeps 3, 4, ...: odd passes read y5 and write ytmp, even passes back
         const T *yin = (pass & 1) ? y5 : yt;
         T *yout = (pass & 1) ? yt : y5;
-        jacobi_more<T, false>(a, u, invd, cpk, yin, yout, rhs);
+        stage_rows(ys, P, u.iy0, [&](int iy, int ix) { return yin[iy * nsx + ix]; });
+        own_rows(P, u.iy0, [&](int rr, int iy) {
+            for (int ix = lane; ix < nsx; ix += kWave) {
+                const int p = iy * nsx + ix;
+                yout[p] = (rhs(iy, ix) - cpk[p] * lds_nb(ys, nsx, rr, ix, ax, ay)) * invd[p];
+            }
+        });
     }
 }
 
 // c' = sgn b2 - A_xx y5 (sgn = -1 in the Schur iterations: c' = -b2 - A_xx y5),
-// A_xx y = h ((q - 2 c0 g2) y + g2 N(y) + N(g2 y)). y5 is the F_x solve's
-// result (in ytmp when its last pass was odd).
+// A_xx y = h ((q - 2 c0 g2) y + g2 N(y) + N(g2 y)); y and g2 y of the block
+// and halo rows staged in LDS. y5 is the F_x solve's result (in ytmp when its
+// last pass was odd).
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_axx(const StreamArgs a, int sgn, int y_in_tmp)
 {
-    const RowUnit u = row_unit(a);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Block u = row_block(a);
     if (!u.ok || !a.work[u.b]) return;
     const DevProblem &P = a.P;
-    const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy, iy = u.iy;
+    const int nsx = P.nsx, n = nsx * P.nsy;
     const size_t bi = (size_t)u.b * P.N + u.i;
     const T *y = reinterpret_cast<const T *>(y_in_tmp ? a.ytmp : a.y5) + bi * n;
     const T *g2 = reinterpret_cast<const T *>(a.g2) + bi * n;
     const T *b2 = reinterpret_cast<const T *>(a.b2) + bi * n;
     T *cp = reinterpret_cast<T *>(a.cp) + bi * n;
     const T ax = T(P.idx2), ay = T(P.idy2), h = T(P.h), q = T(P.q), c0 = T(P.c0);
-    for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-        const int p = iy * nsx + ix;
-        auto v = [&](int dx, int dy, bool scaled) -> T {
-            const int jx = ix + dx, jy = iy + dy;
-            if (jx < 0 || jx >= nsx || jy < 0 || jy >= nsy) return T(0);
-            const int qq = jy * nsx + jx;
-            return scaled ? g2[qq] * y[qq] : y[qq];
-        };
-        const T n1 = ax * (v(-1, 0, false) + v(1, 0, false)) + ay * (v(0, -1, false) + v(0, 1, false));
-        const T n2 = ax * (v(-1, 0, true) + v(1, 0, true)) + ay * (v(0, -1, true) + v(0, 1, true));
-        const T Ay = h * ((q - T(2) * c0 * g2[p]) * y[p] + g2[p] * n1 + n2);
-        cp[p] = (sgn > 0 ? b2[p] : -b2[p]) - Ay;
-    }
+    T *ys = reinterpret_cast<T *>(lds_raw);
+    T *zs = ys + (kRows + 2) * nsx;
+    stage_rows(ys, P, u.iy0, [&](int iy, int ix) { return y[iy * nsx + ix]; });
+    stage_rows(zs, P, u.iy0, [&](int iy, int ix) { const int p = iy * nsx + ix; return g2[p] * y[p]; });
+    const int lane = threadIdx.x & (kWave - 1);
+    own_rows(P, u.iy0, [&](int rr, int iy) {
+        for (int ix = lane; ix < nsx; ix += kWave) {
+            const int p = iy * nsx + ix, e = (rr + 1) * nsx + ix;
+            const T n1 = lds_nb(ys, nsx, rr, ix, ax, ay), n2 = lds_nb(zs, nsx, rr, ix, ax, ay);
+            const T Ay = h * ((q - T(2) * c0 * g2[p]) * ys[e] + g2[p] * n1 + n2);
+            cp[p] = (sgn > 0 ? b2[p] : -b2[p]) - Ay;
+        }
+    });
 }
 
-// F_x^T solve of c' into y4 (pass as in k_st_jf, ping-pong with y4tmp); on the
-// last pass optionally the row partials of B^T y4, and in the final block the
-// update of x and lambda into the other iterate buffer.
+// F_x^T solve of c' into y4 (pass as in k_st_jf, ping-pong with y4tmp; the
+// staged values are cpk times the previous sweep's); on the last pass
+// optionally the row partials of B^T y4, and in the final block the update of
+// x, lambda and u into the other iterate buffer.
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_jft(const StreamArgs a, int pass, int last_pass,
                                                 int partials, int update, int y5_in_tmp)
 {
-    __shared__ double sh[kMaxWaves];
-    const RowUnit u = row_unit(a);
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const Block u = row_block(a);
     if (!u.ok || !a.work[u.b]) return;
     const DevProblem &P = a.P;
-    const int nsx = P.nsx, n = nsx * P.nsy, iy = u.iy;
+    const int nsx = P.nsx, n = nsx * P.nsy;
     const size_t bi = (size_t)u.b * P.N + u.i;
     const T *invd = reinterpret_cast<const T *>(a.invd) + bi * n;
     const T *cpk = reinterpret_cast<const T *>(a.cpk) + bi * n;
     const T *cp = reinterpret_cast<const T *>(a.cp) + bi * n;
     T *y4 = reinterpret_cast<T *>(a.y4) + bi * n, *yt = reinterpret_cast<T *>(a.y4tmp) + bi * n;
-    auto rhs = [&](int jy, int jx) -> T { return cp[jy * nsx + jx]; };
+    const T ax = T(P.idx2), ay = T(P.idy2);
+    T *zs = reinterpret_cast<T *>(lds_raw);
+    const int lane = threadIdx.x & (kWave - 1);
     T *res = y4;
-    if (pass == 0) {
-        jacobi_first<T, true>(a, u, bi, a.n_sw, invd, cpk, y4, rhs);
+    if (pass == 0 && a.n_sw < 2) {
+        own_rows(P, u.iy0, [&](int rr, int iy) {
+            for (int ix = lane; ix < nsx; ix += kWave) y4[iy * nsx + ix] = cp[iy * nsx + ix] * invd[iy * nsx + ix];
+        });
     } else {
-        const T *yin = (pass & 1) ? y4 : yt;
-        res = (pass & 1) ? yt : y4;
-        jacobi_more<T, true>(a, u, invd, cpk, yin, res, rhs);
+        const T *yin = pass == 0 ? nullptr : ((pass & 1) ? y4 : yt);
+        res = pass == 0 ? y4 : ((pass & 1) ? yt : y4);
+        stage_rows(zs, P, u.iy0, [&](int iy, int ix) {
+            const int p = iy * nsx + ix;
+            return cpk[p] * (pass == 0 ? cp[p] * invd[p] : yin[p]);
+        });
+        own_rows(P, u.iy0, [&](int rr, int iy) {
+            for (int ix = lane; ix < nsx; ix += kWave) {
+                const int p = iy * nsx + ix;
+                res[p] = (cp[p] - lds_nb(zs, nsx, rr, ix, ax, ay)) * invd[p];
+            }
+        });
     }
     if (!last_pass) return;
-    __syncthreads();   // this thread's own results are read back below
-    if (partials) {
-        double tl[kMaxLx];
-        for (int q = 0; q < P.lx; ++q) tl[q] = 0.0;
-        for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-            const double yv = double(res[iy * nsx + ix]);
-            for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * yv;
+    const int cur = a.st[u.b].j & 1, nxt = cur ^ 1;
+    const T *y5 = reinterpret_cast<const T *>(y5_in_tmp ? a.ytmp : a.y5) + bi * n;
+    own_rows(P, u.iy0, [&](int rr, int iy) {
+        // this wave's own results of row iy are read back (same lanes)
+        if (partials) {
+            double tl[kMaxLx];
+            for (int q = 0; q < P.lx; ++q) tl[q] = 0.0;
+            for (int ix = lane; ix < nsx; ix += kWave) {
+                const double yv = double(res[iy * nsx + ix]);
+                for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * yv;
+            }
+            for (int q = 0; q < P.lx; ++q) tl[q] = wave_sum(tl[q]);
+            if (lane == 0) {
+                const size_t ru = bi * P.nsy + iy;
+                for (int q = 0; q < P.lx; ++q) a.rowt[ru * kMaxLx + q] = tl[q];
+            }
         }
-        const size_t ru = bi * P.nsy + iy;
-        for (int q = 0; q < P.lx; ++q) {
-            const double s = block_sum(tl[q], sh);
-            if (threadIdx.x == 0) a.rowt[ru * kMaxLx + q] = s;
+        if (update) {
+            const double *x = a.X[cur] + bi * n, *lam = a.LAM[cur] + bi * n;
+            double *xn = a.X[nxt] + bi * n, *ln = a.LAM[nxt] + bi * n;
+            for (int ix = lane; ix < nsx; ix += kWave) {
+                const int p = iy * nsx + ix;
+                xn[p] = x[p] - double(y5[p]);
+                ln[p] = lam[p] - double(res[p]);
+            }
         }
-    }
-    if (update) {
-        const int cur = a.st[u.b].j & 1, nxt = cur ^ 1;
-        const T *y5 = reinterpret_cast<const T *>(y5_in_tmp ? a.ytmp : a.y5) + bi * n;
-        const double *x = a.X[cur] + bi * n, *lam = a.LAM[cur] + bi * n;
-        double *xn = a.X[nxt] + bi * n, *ln = a.LAM[nxt] + bi * n;
-        for (int ix = threadIdx.x; ix < nsx; ix += blockDim.x) {
-            const int p = iy * nsx + ix;
-            xn[p] = x[p] - double(y5[p]);
-            ln[p] = lam[p] - double(res[p]);
-        }
-        if (iy == 0) {
-            const double *uc = a.U[cur] + bi * P.m;
-            double *un = a.U[nxt] + bi * P.m;
-            for (int j = threadIdx.x; j < P.m; j += blockDim.x) un[j] = uc[j] - a.v3[bi * P.m + j];
-        }
+    });
+    if (update && u.iy0 == 0) {
+        const double *uc = a.U[cur] + bi * P.m;
+        double *un = a.U[nxt] + bi * P.m;
+        for (int j = threadIdx.x; j < P.m; j += blockDim.x) un[j] = uc[j] - a.v3[bi * P.m + j];
     }
 }
 
 // v3 = (K^u + h B^T y4) / (h r + gamma) per stage (T arithmetic as in the
-// fused kernel). One workgroup (64 threads) per stage.
+// fused kernel). One workgroup (256 threads) per stage.
 template <typename T>
-__global__ void k_st_v3(const StreamArgs a)
+__global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 {
+    __shared__ double sh[256];
     const int bi = blockIdx.x;
     if (bi >= a.count * a.P.N) return;
     const int b = bi / a.P.N;
     if (!a.work[b]) return;
     const T auu = T(a.P.h * a.P.r + a.P.gamma), h = T(a.P.h);
-    for (int j = threadIdx.x; j < a.P.m; j += blockDim.x) {
-        const T bt = T(bt_from_rows(a, bi, j));
+    const double btd = bt_from_rows(a, bi, sh);
+    if (threadIdx.x < a.P.m) {
+        const int j = threadIdx.x;
+        const T bt = T(btd);
         a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * bt) / auu);
     }
 }

@@ -195,3 +195,18 @@ def test_time_varying_reference(nm):
     rc, X, U, L, info = s.solve(x0, xr)
     o = oracle.solve(P, x0, xr, tol=0.0, max_iter=6)
     assert rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
+
+
+@pytest.mark.parametrize("upper", [0, 3])
+def test_widest_fused_grid(nm, upper):
+    """96 x 96 (six columns and three rows per lane, 8 waves) on the fused
+    path, Jacobi and SGS: equal iterate to the oracle at k = 2."""
+    P = make_problem("grid", ns=96, N=3, lattice=4)
+    x0, xref = make_instance(P, 12)
+    s = nm.Solver(P, tol=0.0, max_iter=2, path=nm.NMPC_PATH_FUSED, upper=upper)
+    assert s.kernel_config()["rows_per_lane"] == 3
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=0.0, max_iter=2,
+                     upper="jacobi" if upper == 0 else "sgs")
+    assert rc == nm.NMPC_E_NOCONV and info["iters"] == 2
+    assert rel(X, o["X"]) <= REL and rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
