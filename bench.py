@@ -18,6 +18,12 @@ roofline of the dominant kernel (the persistent Gauss-Seidel kernel, or the
 fused Jacobi iteration kernel, measured with HIP events on the library's
 stream over the timed region), the network's matrix-core rate and the CPU
 oracle timed on a bounded sample of the same workload.
+
+--workload selects other workloads for the same kind of line (the default,
+64x64 N=40 batch 256, is the headline): "c2" solves single 256x256, N=100
+instances (8x8 actuator lattice) on the streaming row-block path, "c3" solves
+batches of 512 instances of mixed grids {32, 48, 64, 96}^2 and horizons
+{20, 40, 60} in the ragged kernel.
 """
 from __future__ import annotations
 
@@ -43,6 +49,10 @@ KERNELS = {
                ("nmpc_kernels.hip", "nmpc_stage.h"), "k_iterate_c1_b256_traffic.json"),
     "gs": ("k_gs (persistent Gauss-Seidel sweeps, one workgroup per instance)",
            ("nmpc_gs.hip", "nmpc_stage.h"), "k_gs_c1_b256_traffic.json"),
+    "stream": ("streaming upper iteration (row-block passes k_st_*, one captured graph)",
+               ("nmpc_stream.hip",), "stream_c2_traffic.json"),
+    "ragged": ("k_iterate_rg (ragged batch, all instances and stages in parallel)",
+               ("nmpc_ragged.hip", "nmpc_stage.h"), "k_iterate_rg_c3_b512_traffic.json"),
 }
 WEIGHTS = os.path.join(ROOT, "paper_2004_02484_amd", "weights", "c1_patchnet.npz")
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -163,9 +173,193 @@ def closed_loop(solver, net, P, x0, xr, steps: int, ubuf):
                 "iters_max": int(max(v["it"]))} for k, v in out.items()}
 
 
+def copy_calibration(dev):
+    """A plain 512 MiB device copy (three times): the known-size reference for
+    scaling the HBM counters of the same run."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def roofline(kind: str, tm, bpu: float):
+    """HBM roofline of the dominant kernel from the library's HIP-event timing
+    (kernel_ms, launches, units) and the algorithmic bytes per unit."""
+    avg_launch_s = tm["kernel_ms"] * 1e-3 / max(tm["launches"], 1)
+    units_per_launch = tm["units"] / max(tm["launches"], 1)
+    achieved = bpu * units_per_launch / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_per_launch(kind, units_per_launch),
+            "kernel": KERNELS[kind][0],
+            "avg_launch_us": round(avg_launch_s * 1e6, 1),
+            "units_per_launch": round(units_per_launch, 1),
+            "bytes_per_unit": round(bpu, 1)}
+
+
+def line(metric, value, args, elapsed, dtype, cfg, roof, cpu=None):
+    out = {"metric": metric, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": dtype, "data": "synthetic", "config": cfg, "roofline": roof}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
+def bench_c2(args):
+    """Single 256x256, N=100 instances (one per step, own seeds) on the
+    streaming path, Jacobi upper layer, FP32 sweeps, tol 1e-6."""
+    import torch
+    import paper_2004_02484_amd as nm
+    from nmpc_inputs import make_instance, make_problem
+    dev = torch.device("cuda:0")
+    P = make_problem("c2")
+    solver = nm.Solver(P, max_batch=1, precision=nm.NMPC_FP32_SWEEP, tol=1e-6, max_iter=5000,
+                       check_every=16, upper=nm.NMPC_UPPER_JACOBI)
+    cfg_path = solver.kernel_config()
+    nb = args.warmup + args.steps
+    host = [make_instance(P, EVAL_SEED0 + s) for s in range(nb)]
+    dev_in = [(torch.tensor(x, device=dev)[None], torch.tensor(r, device=dev)[None])
+              for x, r in host]
+    timed_steps(solver, dev_in[:args.warmup], None)
+    solver.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times, iters, _, worst = timed_steps(solver, dev_in[args.warmup:], None)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = solver.timing_read()
+    solver.timing_enable(False)
+    if args.copy_calibration:
+        copy_calibration(dev)
+    # one streaming "launch" is one upper iteration of all N stages
+    roof = roofline("stream", tm, bytes_per_unit(P.n, P.m, P.N))
+    cfg = {"workload": "2D nonlinear heat 256x256, N=100, 64 Gaussian inputs (8x8 lattice), "
+                       "single instance per step, cold start, Jacobi upper layer, streaming "
+                       "row-block path, tol 1e-6",
+           "global_batch": 1, "grid": "256x256", "horizon": P.N, "path": cfg_path,
+           "iters_min": int(min(iters)), "iters_max": int(max(iters)),
+           "status_worst": worst, "step_ms_median": round(1e3 * float(np.median(times)), 2)}
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle
+        oracle.build(force=False)
+        x0, xr = host[args.warmup]
+        X, U, L = oracle.cold_start(P, x0)
+        t = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t < args.cpu_budget:
+            X, U, L, _, _ = oracle.iterate(P, x0, xr, X, U, L)
+            k += 1
+        per_it = (time.perf_counter() - t) / k
+        it = float(np.mean(iters))
+        cpu = {"value": 1.0 / (per_it * it), "unit": "solves/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"{k} cold-start Jacobi upper iterations of the first timed instance "
+                         f"({per_it:.2f} s each), scaled by the {it:.0f} iterations the "
+                         f"instance takes to tol 1e-6"}
+    line("NMPC solves/s to KKT res 1e-6, 256x256 grid N=100, single instance",
+         len(times) / elapsed, args, elapsed, "f32 sweeps, f64 state/residual", cfg, roof, cpu)
+    solver.close()
+
+
+def bench_c3(args):
+    """Batches of 512 instances of mixed grids and horizons (one batch per
+    step, own seeds) in the ragged kernel, Jacobi upper layer, FP32 sweeps."""
+    import torch
+    import paper_2004_02484_amd as nm
+    from nmpc_inputs import make_instance, make_problem, ragged_specs
+    dev = torch.device("cuda:0")
+    grids, horizons, B = (32, 48, 64, 96), (20, 40, 60), 512
+    keys = [(g, h) for g in grids for h in horizons]
+    classes = [make_problem("grid", ns=g, N=h, lattice=4) for g, h in keys]
+    solver = nm.RaggedSolver(classes, max_instances=B, tol=1e-6, max_iter=5000,
+                             precision=nm.NMPC_FP32_SWEEP)
+    nb = args.warmup + args.steps
+    batches = []
+    for s in range(nb):
+        specs = ragged_specs(B, seed=EVAL_SEED0 + s, grids=grids, horizons=horizons)
+        cls = [keys.index((g, h)) for g, h, _ in specs]
+        inst = [make_instance(classes[c], sd) for c, (_, _, sd) in zip(cls, specs)]
+        x0 = torch.cat([torch.tensor(x, device=dev) for x, _ in inst])
+        xr = torch.cat([torch.tensor(r, device=dev) for _, r in inst])
+        batches.append((cls, x0, xr, inst))
+    waves = solver.autotune(batches[0][0], batches[0][1], batches[0][2], iters=4)
+
+    def run(bs):
+        ts, its, worst = [], [], 0
+        torch.cuda.synchronize()
+        for cls, x0, xr, _ in bs:
+            t = time.perf_counter()
+            rc, _, infos, _ = solver.solve(cls, x0, xr)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            its.append([i["iters"] for i in infos])
+            worst = max(worst, rc)
+        return ts, its, worst
+
+    run(batches[:args.warmup])
+    solver.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times, its, worst = run(batches[args.warmup:])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = solver.timing_read()
+    solver.timing_enable(False)
+    if args.copy_calibration:
+        copy_calibration(dev)
+    # algorithmic bytes per unit, weighted over the instances' stage-iterations
+    wsum = bsum = 0.0
+    for (cls, _, _, _), it in zip(batches[args.warmup:], its):
+        for c, k in zip(cls, it):
+            P = classes[c]
+            w = float(k + 1) * P.N
+            wsum += w
+            bsum += w * bytes_per_unit(P.n, P.m, P.N)
+    roof = roofline("ragged", tm, bsum / wsum)
+    allit = np.concatenate([np.asarray(i) for i in its])
+    cfg = {"workload": "512 independent 2D heat instances per step, grids {32,48,64,96}^2 and "
+                       "horizons {20,40,60} drawn uniformly, 4x4 Gaussian lattice, cold start, "
+                       "Jacobi upper layer, ragged kernel (LPT-balanced over 8 XCDs, hipGraph "
+                       "captured, autotuned waves), tol 1e-6",
+           "global_batch": B, "waves": waves,
+           "iters_min": int(allit.min()), "iters_max": int(allit.max()),
+           "iters_mean": round(float(allit.mean()), 1), "status_worst": worst,
+           "step_ms_median": round(1e3 * float(np.median(times)), 2)}
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle
+        oracle.build(force=False)
+        cls, _, _, inst = batches[args.warmup]
+        t = time.perf_counter()
+        done, sizes = 0, []
+        for c, (x0, xr) in zip(cls, inst):
+            oracle.solve(classes[c], x0, xr, tol=1e-6, max_iter=5000)
+            done += 1
+            sizes.append(f"{classes[c].nsx}/{classes[c].N}")
+            if time.perf_counter() - t >= args.cpu_budget:
+                break
+        dt = time.perf_counter() - t
+        cpu = {"value": done / dt, "unit": "solves/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"the first {done} instances of the first timed batch (grid/horizon "
+                         f"{', '.join(sizes)}), cold start, Jacobi, tol 1e-6, {dt:.1f} s"}
+    line("NMPC solves/s to KKT res 1e-6, 512 ragged instances (mixed grids and horizons)",
+         B * args.steps / elapsed, args, elapsed, "f32 sweeps, f64 state/residual", cfg, roof, cpu)
+    solver.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
+                    help="c1: 64x64 N=40 batch 256 (headline); c2: 256x256 N=100 single "
+                         "instance; c3: 512 ragged instances")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
@@ -194,6 +388,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "c2":
+        return bench_c2(args)
+    if args.workload == "c3":
+        return bench_c3(args)
     P = make_problem("c1")
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
@@ -233,25 +431,11 @@ def main():
     solver.timing_enable(False)
 
     if args.copy_calibration:
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)   # 512 MiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
+        copy_calibration(dev)
 
     solves = B * args.steps
     value = solves / elapsed
-    avg_launch_s = tm["kernel_ms"] * 1e-3 / max(tm["launches"], 1)
-    units_per_launch = tm["units"] / max(tm["launches"], 1)
-    bpu = bytes_per_unit(P.n, P.m, P.N)
-    achieved = bpu * units_per_launch / avg_launch_s / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_per_launch(kind, units_per_launch),
-            "kernel": KERNELS[kind][0],
-            "avg_launch_us": round(avg_launch_s * 1e6, 1),
-            "units_per_launch": round(units_per_launch, 1),
-            "bytes_per_unit": bpu}
+    roof = roofline(kind, tm, bytes_per_unit(P.n, P.m, P.N))
 
     start_desc = "learned warm start (network + rollout + adjoint, cold fallback)" \
         if net is not None else "cold start"

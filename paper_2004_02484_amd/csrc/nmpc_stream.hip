@@ -79,17 +79,43 @@ __device__ __forceinline__ bool evaluating(const StreamArgs &a, int b)
 }
 
 // Stage f(iy, ix) for rows iy0 - 1 .. iy0 + kRows of the block into lds
-// [(kRows + 2)][nsx] (zero outside the grid), then synchronize.
-template <typename V, typename F>
-__device__ __forceinline__ void stage_rows(V *lds, const DevProblem &P, int iy0, F f)
+// [(kRows + 2)][nsx] (zero outside the grid), then synchronize. Threads own
+// columns (ix = thread, thread + 256, ...) and walk the rows, so values a
+// column needs for every row (e.g. the column sums of B v) are loaded once.
+template <typename V, typename COL, typename F>
+__device__ __forceinline__ void stage_cols(V *lds, const DevProblem &P, int iy0, COL col, F f)
 {
-    const int nsx = P.nsx, tot = (kRows + 2) * nsx;
-    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-        const int rr = e / nsx, ix = e - rr * nsx, iy = iy0 + rr - 1;
-        lds[e] = (iy >= 0 && iy < P.nsy) ? f(iy, ix) : V(0);
+    const int nsx = P.nsx;
+    // g thread groups of nsx columns share the rows when the row is narrower
+    // than the workgroup (one division per thread, none per element).
+    const int g = nsx >= (int)blockDim.x ? 1 : (int)blockDim.x / nsx;
+    const int r0 = g == 1 ? 0 : (int)threadIdx.x / nsx;
+    const int c0 = (int)threadIdx.x - r0 * nsx;
+    if (r0 < g) {
+        for (int ix = c0; ix < nsx; ix += g == 1 ? (int)blockDim.x : nsx) {
+            auto cv = col(ix);
+            for (int rr = r0; rr < kRows + 2; rr += g) {
+                const int iy = iy0 + rr - 1;
+                lds[rr * nsx + ix] = (iy >= 0 && iy < P.nsy) ? f(iy, ix, cv) : V(0);
+            }
+        }
     }
     __syncthreads();
 }
+
+struct NoCol {};
+
+template <typename V, typename F>
+__device__ __forceinline__ void stage_rows(V *lds, const DevProblem &P, int iy0, F f)
+{
+    stage_cols(lds, P, iy0, [](int) { return NoCol{}; },
+               [&](int iy, int ix, NoCol) { return f(iy, ix); });
+}
+
+// The ly column sums sc[bb][ix] of B v for one column (registers).
+struct BCol {
+    double s[kMaxLy];
+};
 
 // Neighbour sum of a staged array at block row rr (0-based), column ix.
 template <typename V>
@@ -154,6 +180,29 @@ __device__ __forceinline__ double bsep_at(const StreamArgs &a, size_t bi, int iy
     return s;
 }
 
+__device__ __forceinline__ BCol bsep_col(const StreamArgs &a, size_t bi, int ix)
+{
+    const double *sc = a.sc + bi * a.P.ly * a.P.nsx;
+    BCol c;
+    for (int bb = 0; bb < a.P.ly; ++bb) c.s[bb] = sc[bb * a.P.nsx + ix];
+    return c;
+}
+
+__device__ __forceinline__ double bsep_row(const StreamArgs &a, const BCol &c, int iy)
+{
+    double s = 0.0;
+    for (int bb = 0; bb < a.P.ly; ++bb) s += a.gy[bb * a.P.nsy + iy] * c.s[bb];
+    return s;
+}
+
+// 1 / d for the lower layer (hardware reciprocal in FP32, see the fused kernel).
+template <typename T>
+__device__ __forceinline__ T st_recip(double d);
+template <>
+__device__ __forceinline__ float st_recip<float>(double d) { return __builtin_amdgcn_rcpf(float(d)); }
+template <>
+__device__ __forceinline__ double st_recip<double>(double d) { return 1.0 / d; }
+
 // KKT rows, coefficients and row partials of S^j (FP64 arithmetic; the
 // right-hand sides and coefficients are stored in T for the lower layer).
 // LDS: x and g = k(x) lambda of the block rows and halo rows.
@@ -200,7 +249,7 @@ __global__ void __launch_bounds__(256) k_st_res(const StreamArgs a)
             b1[p] = T(kx);
             b2[p] = T(kl);
             const double d = -1.0 - h * K(xc) * P.c0 + h * kp * Lx;
-            invd[p] = T(1.0 / d);
+            invd[p] = st_recip<T>(d);
             cpk[p] = T(h * K(xc));
             g2[p] = T(kp * lc);
             for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * lc;
@@ -361,10 +410,13 @@ __global__ void __launch_bounds__(256) k_st_jf(const StreamArgs a, int sgn, int 
     const T *cpk = reinterpret_cast<const T *>(a.cpk) + bi * n;
     T *y5 = reinterpret_cast<T *>(a.y5) + bi * n, *yt = reinterpret_cast<T *>(a.ytmp) + bi * n;
     const T h = T(P.h), ax = T(P.idx2), ay = T(P.idy2);
-    auto rhs = [&](int iy, int ix) -> T {
-        const T bv = use_v3 ? T(bsep_at(a, bi, iy, ix)) : T(0);
+    auto crow = [&](int iy, int ix, const BCol &cv) -> T {
+        const T bv = use_v3 ? T(bsep_row(a, cv, iy)) : T(0);
         const T v = b1[iy * nsx + ix] - h * bv;
         return sgn > 0 ? v : -v;
+    };
+    auto rhs = [&](int iy, int ix) -> T {
+        return crow(iy, ix, use_v3 ? bsep_col(a, bi, ix) : BCol{});
     };
     T *ys = reinterpret_cast<T *>(lds_raw);
     const int lane = threadIdx.x & (kWave - 1);
@@ -376,7 +428,8 @@ __global__ void __launch_bounds__(256) k_st_jf(const StreamArgs a, int sgn, int 
             return;
         }
         T *cs = ys + (kRows + 2) * nsx;   // c of the block and halo rows
-        stage_rows(cs, P, u.iy0, [&](int iy, int ix) { return rhs(iy, ix); });
+        stage_cols(cs, P, u.iy0, [&](int ix) { return use_v3 ? bsep_col(a, bi, ix) : BCol{}; },
+                   [&](int iy, int ix, const BCol &cv) { return crow(iy, ix, cv); });
         stage_rows(ys, P, u.iy0, [&](int iy, int ix) {
             return cs[(iy - u.iy0 + 1) * nsx + ix] * invd[iy * nsx + ix];
         });
