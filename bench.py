@@ -51,7 +51,7 @@ KERNELS = {
            ("nmpc_gs.hip", "nmpc_stage.h"), "k_gs_c1_b256_traffic.json"),
     "stream": ("streaming upper iteration (row-block passes k_st_*, one captured graph)",
                ("nmpc_stream.hip",), "stream_c2_traffic.json"),
-    "ragged": ("k_iterate_rg (ragged batch, all instances and stages in parallel)",
+    "ragged": ("k_iterate_rg (ragged batch; one upper iteration = one launch per tile case)",
                ("nmpc_ragged.hip", "nmpc_stage.h"), "k_iterate_rg_c3_b512_traffic.json"),
 }
 WEIGHTS = os.path.join(ROOT, "paper_2004_02484_amd", "weights", "c1_patchnet.npz")

@@ -105,7 +105,8 @@ struct RgArgs {
     const long long *dxoff;   // dense x0 / xref offset
     const long long *dsoff;   // dense X / LAM trajectory offset
     const long long *ustart;  // first stage-residual index (sum of earlier horizons)
-    const int2 *umap;         // per unit: (instance, stage); instance < 0: no work
+    const int2 *umap;         // per unit of the launch's tile case: (instance, stage);
+                              // instance < 0: no work
     int count;
 };
 
@@ -136,10 +137,14 @@ struct StreamArgs {
     int max_iter, n_sw, n_schur;
 };
 
-// Grid rows per workgroup of the streaming passes; their LDS holds up to two
-// arrays of (kStreamRows + 2) rows of 8-byte values.
+// Grid rows per workgroup of the streaming passes; a pass stages `arrays`
+// arrays of (kStreamRows + 2) rows of elem-byte values in LDS (at most two of
+// 8 bytes).
 constexpr int kStreamRows = 8;
-__host__ __device__ inline size_t stream_lds_bytes(int nsx) { return (size_t)2 * (kStreamRows + 2) * nsx * 8; }
+__host__ __device__ inline size_t stream_lds_bytes(int nsx, int elem = 8, int arrays = 2)
+{
+    return (size_t)arrays * (kStreamRows + 2) * nsx * elem;
+}
 
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
@@ -204,8 +209,9 @@ const void *output_kernel();
 const void *shift_kernel();   // (const double *s, double *out, long long count, int N, long long w)
 const void *plant_kernel();   // (PlantArgs)
 
-// Ragged batch kernels (4 x 4 input lattice); waves: 8, 12 or 16.
-const void *ragged_iterate_kernel(int prec, int waves);
+// Ragged batch kernels (4 x 4 input lattice); waves: 8, 12 or 16; tcase: the
+// tile case of ragged_tile (nullptr where the case is not built).
+const void *ragged_iterate_kernel(int prec, int waves, int tcase);
 const void *ragged_pad_kernel();
 const void *ragged_init_kernel();
 const void *ragged_output_kernel();

@@ -1,16 +1,16 @@
-// nmpc_ragged.hip -- one launch per upper iteration over a ragged batch:
+// nmpc_ragged.hip -- the upper iteration over a ragged batch:
 // instances of different grid sizes and horizons (each instance belongs to a
 // problem class with its own grid, horizon, step and input factors).
 //
-// The work list holds one entry per (instance, stage) unit, grouped into
-// eight runs, one per XCD (consecutive workgroup ids go to different XCDs), each
-// run balanced by stage-points and holding whole instances, so that the
-// x_{i-1} / lambda_{i+1} reads of neighbouring stages hit that XCD's L2. All
-// classes share the workgroup size of the launch; each class gets the tile
-// (CX columns x RY rows per lane) that covers its grid with the fewest rows,
-// and the workgroup branches once, uniformly, to that tile's stage code. The
-// per-instance convergence state machine is the one of the batch kernel, with
-// the instance's own horizon.
+// All classes share the workgroup size; each class gets the tile (CX columns
+// x RY rows per lane) that covers its grid with the fewest rows. One upper
+// iteration is one launch per tile case present in the batch, all captured in
+// the same graph. A case's work list holds one entry per (instance, stage)
+// unit of its instances, grouped into eight runs, one per XCD (consecutive
+// workgroup ids go to different XCDs), each run balanced by stage-points and
+// holding whole instances, so that the x_{i-1} / lambda_{i+1} reads of
+// neighbouring stages hit that XCD's L2. The per-instance convergence state
+// machine is the one of the batch kernel, with the instance's own horizon.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,11 +24,34 @@ namespace nmpc {
 constexpr int kRgLx = 4, kRgLy = 4;
 constexpr int kRgCx[5] = {1, 2, 3, 4, 6};
 
+// Rows covered by a tile of RY rows per lane with WB waves: 4 * WB * RY. A
+// case is instantiated only where it is the smallest cover of some grid
+// height <= 96 and has at most 18 (8 waves) or 12 (12, 16 waves) points per
+// lane, so that its registers fit what WB waves leave a lane (512 / (WB / 4)
+// VGPRs, at most 256); the autotuner weighs tile size against occupancy.
+__host__ __device__ constexpr int rg_max_points(int wb) { return wb <= 8 ? 18 : 12; }
+template <int WB, int CX, int RY>
+constexpr bool rg_case() { return 4 * WB * (RY - 1) < 96 && CX * RY <= rg_max_points(WB); }
+
+// One launch per tile case present in the batch: the units of the instances
+// whose class takes this tile (CX x RY per lane), eight XCD runs of per_xcd
+// units each. Every case is its own kernel, so each gets the register
+// allocation of its tile and no call boundary.
 template <int PREC, int WB, int CX, int RY>
-__device__ __noinline__ void rg_unit(const IterArgs &a, const RgArgs &r, const RgClass &cl,
-                                        Ctx &c, int b, int i, int k)
+__global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, const RgArgs r)
 {
     using T = typename std::conditional<PREC == kModeFp32, float, double>::type;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int k = a.residual_only ? 0 : *(volatile const int *)(a.ctr) + a.kofs;
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (unit >= a.units) return;
+    const int2 bi = r.umap[unit];
+    if (bi.x < 0) return;
+    const int b = bi.x, i = bi.y;
+    const RgClass &cl = r.cls[r.icls[b]];
+    Ctx c;
+    c.lds = lds_raw;
     tile_setup<T, CX, RY, kRgLx, kRgLy>(c, cl.P);
     const int N = cl.P.N;
     const long long us = r.ustart[b];
@@ -50,45 +73,6 @@ __device__ __noinline__ void rg_unit(const IterArgs &a, const RgArgs &r, const R
     v.last = i == N - 1;
     unsigned long long acc[2] = {0, 0};
     stage_body<T, CX, RY, kRgLx, kRgLy>(a, cl.P, v, c, acc);
-}
-
-// Rows covered by a tile of RY rows per lane with WB waves: 4 * WB * RY. A
-// case is instantiated only where it is the smallest cover of some grid
-// height <= 96 and has at most 18 (8 waves) or 12 (12, 16 waves) points per
-// lane. Each case is a separate function, so only the large tiles spill when
-// the register file that WB waves leave a lane (512 / (WB / 4) VGPRs, at most
-// 256) is too small for them; the autotuner weighs that against occupancy.
-__host__ __device__ constexpr int rg_max_points(int wb) { return wb <= 8 ? 18 : 12; }
-template <int WB, int CX, int RY>
-constexpr bool rg_case() { return 4 * WB * (RY - 1) < 96 && CX * RY <= rg_max_points(WB); }
-
-template <int PREC, int WB>
-__global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, const RgArgs r)
-{
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    Ctx c;
-    c.lds = lds_raw;
-    const int k = a.residual_only ? 0 : *(volatile const int *)(a.ctr) + a.kofs;
-    const int bid = blockIdx.x;
-    const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
-    if (unit >= a.units) return;
-    const int2 bi = r.umap[unit];
-    if (bi.x < 0) return;
-    const RgClass &cl = r.cls[r.icls[bi.x]];
-#define NMPC_RG_CASE(CI, RY)                                                       \
-    case 3 * CI + RY - 1:                                                           \
-        if constexpr (rg_case<WB, kRgCx[CI], RY>())                                 \
-            rg_unit<PREC, WB, kRgCx[CI], RY>(a, r, cl, c, bi.x, bi.y, k);            \
-        break;
-    switch (cl.tile) {
-        NMPC_RG_CASE(0, 1) NMPC_RG_CASE(0, 2) NMPC_RG_CASE(0, 3)
-        NMPC_RG_CASE(1, 1) NMPC_RG_CASE(1, 2) NMPC_RG_CASE(1, 3)
-        NMPC_RG_CASE(2, 1) NMPC_RG_CASE(2, 2) NMPC_RG_CASE(2, 3)
-        NMPC_RG_CASE(3, 1) NMPC_RG_CASE(3, 2) NMPC_RG_CASE(3, 3)
-        NMPC_RG_CASE(4, 1) NMPC_RG_CASE(4, 2) NMPC_RG_CASE(4, 3)
-    default: break;
-    }
-#undef NMPC_RG_CASE
 }
 
 // Dense inputs [count][n_b] (packed) -> padded rows (stride sx of the
@@ -173,16 +157,35 @@ __global__ void k_rg_output(const IterArgs a, const RgArgs r, double *ox, double
     for (int t = threadIdx.x; t < N * m; t += blockDim.x) ou[r.uoff[b] + t] = U[t];
 }
 
-const void *ragged_iterate_kernel(int prec, int waves)
+template <int PREC, int WB>
+const void *rg_kernel(int tcase)
+{
+#define NMPC_RG_CASE(CI, RY)                                                       \
+    case 3 * CI + RY - 1:                                                           \
+        if constexpr (rg_case<WB, kRgCx[CI], RY>())                                 \
+            return (const void *)&k_iterate_rg<PREC, WB, kRgCx[CI], RY>;             \
+        return nullptr;
+    switch (tcase) {
+        NMPC_RG_CASE(0, 1) NMPC_RG_CASE(0, 2) NMPC_RG_CASE(0, 3)
+        NMPC_RG_CASE(1, 1) NMPC_RG_CASE(1, 2) NMPC_RG_CASE(1, 3)
+        NMPC_RG_CASE(2, 1) NMPC_RG_CASE(2, 2) NMPC_RG_CASE(2, 3)
+        NMPC_RG_CASE(3, 1) NMPC_RG_CASE(3, 2) NMPC_RG_CASE(3, 3)
+        NMPC_RG_CASE(4, 1) NMPC_RG_CASE(4, 2) NMPC_RG_CASE(4, 3)
+    default: return nullptr;
+    }
+#undef NMPC_RG_CASE
+}
+
+const void *ragged_iterate_kernel(int prec, int waves, int tcase)
 {
     if (prec == kModeFp32) {
-        if (waves == 8) return (const void *)&k_iterate_rg<kModeFp32, 8>;
-        if (waves == 12) return (const void *)&k_iterate_rg<kModeFp32, 12>;
-        if (waves == 16) return (const void *)&k_iterate_rg<kModeFp32, 16>;
+        if (waves == 8) return rg_kernel<kModeFp32, 8>(tcase);
+        if (waves == 12) return rg_kernel<kModeFp32, 12>(tcase);
+        if (waves == 16) return rg_kernel<kModeFp32, 16>(tcase);
     } else {
-        if (waves == 8) return (const void *)&k_iterate_rg<kModeFp64, 8>;
-        if (waves == 12) return (const void *)&k_iterate_rg<kModeFp64, 12>;
-        if (waves == 16) return (const void *)&k_iterate_rg<kModeFp64, 16>;
+        if (waves == 8) return rg_kernel<kModeFp64, 8>(tcase);
+        if (waves == 12) return rg_kernel<kModeFp64, 12>(tcase);
+        if (waves == 16) return rg_kernel<kModeFp64, 16>(tcase);
     }
     return nullptr;
 }

@@ -86,8 +86,17 @@ struct nmpc_ragged {
     std::vector<int> h_icls;
     std::vector<long long> h_off;
     std::vector<int2> h_umap;
+    std::vector<double> h_cost;   // stage-points of each instance (balancing)
     size_t S_len = 0, in_len = 0, tot_units = 0, tot_dense_x = 0;
-    int per_xcd = 0, count = 0;
+    int count = 0;
+    // work list of the current batch: one segment (one launch per upper
+    // iteration) per tile case present, eight XCD runs of per_xcd units each
+    struct Seg {
+        int tcase, per_xcd;
+        size_t off;   // first entry in h_umap / d_umap
+    };
+    std::vector<Seg> segs;
+    long long wl_sig = 0;         // identifies the work-list shape (graph key)
     // graphs per precision
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -145,15 +154,15 @@ int pick_waves(const nmpc_ragged *r, unsigned long long mask)
     return -1;
 }
 
-// Host layout of a batch: per-instance offsets and the XCD-balanced work list.
+// Host layout of a batch: per-instance offsets.
 int layout(nmpc_ragged *r, int count, const int32_t *cls, unsigned long long *mask)
 {
     const int nc = (int)r->cls.size();
     r->h_icls.assign(cls, cls + count);
     r->h_off.assign(6 * (size_t)r->max_inst, 0);
+    r->h_cost.assign(count, 0.0);
     long long xo = 0, so = 0, uo = 0, dxo = 0, dso = 0, us = 0;
     *mask = 0;
-    std::vector<double> cost(count);
     for (int b = 0; b < count; ++b) {
         const int c = cls[b];
         if (c < 0 || c >= nc) return rg_fail(NMPC_E_ARG, "class index out of range");
@@ -168,33 +177,55 @@ int layout(nmpc_ragged *r, int count, const int32_t *cls, unsigned long long *ma
         r->h_off[4 * (size_t)r->max_inst + b] = dso;
         r->h_off[5 * (size_t)r->max_inst + b] = us;
         xo += np; so += N * np; uo += N * m; dxo += nd; dso += N * nd; us += N;
-        cost[b] = (double)N * np;
+        r->h_cost[b] = (double)N * np;
     }
     r->in_len = (size_t)xo;
     r->S_len = (size_t)so;
     r->tot_units = (size_t)us;
     r->tot_dense_x = (size_t)dso;
     r->count = count;
-    // longest-first assignment of whole instances to the eight XCD runs
-    std::vector<int> order(count);
-    for (int b = 0; b < count; ++b) order[b] = b;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<std::vector<int>> bins(8);
-    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    size_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int b : order) {
-        const int x = (int)(std::min_element(load, load + 8) - load);
-        bins[x].push_back(b);
-        load[x] += cost[b];
-        len[x] += r->cls[cls[b]].horizon;
+    return NMPC_OK;
+}
+
+// Work list for workgroup size `waves`: the instances grouped by tile case
+// (one segment each, in case order), each group assigned longest-first, as
+// whole instances, to the eight XCD runs.
+int worklist(nmpc_ragged *r, int waves)
+{
+    std::map<int, std::vector<int>> by_case;
+    for (int b = 0; b < r->count; ++b) {
+        const nmpc_problem &p = r->cls[r->h_icls[b]];
+        const int tc = nmpc::ragged_tile(p.nsx, p.nsy, waves, nullptr, nullptr);
+        if (tc < 0) return rg_fail(NMPC_E_UNSUPPORTED, "a class does not fit this workgroup size");
+        by_case[tc].push_back(b);
     }
-    r->per_xcd = (int)*std::max_element(len, len + 8);
-    r->h_umap.assign(8 * (size_t)r->per_xcd, int2{-1, -1});
-    for (int x = 0; x < 8; ++x) {
-        size_t t = (size_t)x * r->per_xcd;
-        for (int b : bins[x])
-            for (int i = 0; i < r->cls[cls[b]].horizon; ++i) r->h_umap[t++] = int2{b, i};
+    r->segs.clear();
+    r->h_umap.clear();
+    long long sig = waves;
+    for (auto &kv : by_case) {
+        std::vector<int> &order = kv.second;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return r->h_cost[a] > r->h_cost[b]; });
+        std::vector<std::vector<int>> bins(8);
+        double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        size_t len[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int b : order) {
+            const int x = (int)(std::min_element(load, load + 8) - load);
+            bins[x].push_back(b);
+            load[x] += r->h_cost[b];
+            len[x] += r->cls[r->h_icls[b]].horizon;
+        }
+        nmpc_ragged::Seg sg{kv.first, (int)*std::max_element(len, len + 8), r->h_umap.size()};
+        r->h_umap.resize(sg.off + 8 * (size_t)sg.per_xcd, int2{-1, -1});
+        for (int x = 0; x < 8; ++x) {
+            size_t t = sg.off + (size_t)x * sg.per_xcd;
+            for (int b : bins[x])
+                for (int i = 0; i < r->cls[r->h_icls[b]].horizon; ++i) r->h_umap[t++] = int2{b, i};
+        }
+        r->segs.push_back(sg);
+        sig = sig * 1000003 + (long long)sg.tcase * 65537 + sg.per_xcd;
     }
+    r->wl_sig = sig;
     return NMPC_OK;
 }
 
@@ -232,8 +263,8 @@ IterArgs rg_iter_args(const nmpc_ragged *r)
     a.st = r->d_st; a.iters = r->d_iters; a.rfin = r->d_rfin;
     a.ctr = r->d_ctr; a.kofs = 0;
     a.B = r->max_inst;
-    a.units = 8 * r->per_xcd;
-    a.per_xcd = r->per_xcd;
+    a.units = 0;       // per launch: 8 * the segment's per_xcd
+    a.per_xcd = 0;
     a.tol = r->opt.tol; a.max_iter = r->opt.max_iter;
     a.n_sw = r->opt.n_sweep; a.n_schur = r->opt.n_schur;
     return a;
@@ -256,29 +287,32 @@ RgArgs rg_args(const nmpc_ragged *r, int wi)
     return g;
 }
 
-size_t lds_bytes(const nmpc_ragged *r, int waves, int prec)
+size_t lds_case(int waves, int tcase, int prec)
 {
-    size_t mx = 0;
-    for (int c = 0; c < (int)r->cls.size(); ++c) {
-        int cx = 0, ry = 0;
-        if (nmpc::ragged_tile(r->cls[c].nsx, r->cls[c].nsy, waves, &cx, &ry) < 0) continue;
-        mx = std::max(mx, nmpc::lds_layout(4 * waves, waves, cx, prec == nmpc::kModeFp32 ? 4 : 8,
-                                           4, 4, ry).total);
-    }
-    return mx;
+    const int cx[5] = {1, 2, 3, 4, 6};
+    return nmpc::lds_layout(4 * waves, waves, cx[tcase / 3], prec == nmpc::kModeFp32 ? 4 : 8, 4, 4,
+                            tcase % 3 + 1).total;
 }
 
+// One upper iteration: one launch per tile case of the work list.
 int launch_rg(nmpc_ragged *r, int prec, int waves, IterArgs a, hipStream_t s)
 {
     const int wi = wave_index(waves);
-    const void *fn = nmpc::ragged_iterate_kernel(prec, waves);
-    if (wi < 0 || !fn) return rg_fail(NMPC_E_UNSUPPORTED, "no ragged kernel for this workgroup size");
+    if (wi < 0) return rg_fail(NMPC_E_UNSUPPORTED, "no ragged kernel for this workgroup size");
     RgArgs g = rg_args(r, wi);
-    void *args[] = {(void *)&a, (void *)&g};
-    const size_t lds = std::max(lds_bytes(r, waves, nmpc::kModeFp64), lds_bytes(r, waves, nmpc::kModeFp32));
-    if (lds > 48 * 1024)
-        RG_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    RG_TRY(hipLaunchKernel(fn, dim3(8 * r->per_xcd), dim3(nmpc::kWave * waves), args, lds, s));
+    for (const nmpc_ragged::Seg &sg : r->segs) {
+        const void *fn = nmpc::ragged_iterate_kernel(prec, waves, sg.tcase);
+        if (!fn) return rg_fail(NMPC_E_UNSUPPORTED, "no ragged kernel for this tile");
+        a.units = 8 * sg.per_xcd;
+        a.per_xcd = sg.per_xcd;
+        g.umap = r->d_umap + sg.off;
+        void *args[] = {(void *)&a, (void *)&g};
+        const size_t lds = lds_case(waves, sg.tcase, prec);
+        if (lds > nmpc::kLdsBytes) return rg_fail(NMPC_E_UNSUPPORTED, "tile exceeds the LDS");
+        if (lds > 48 * 1024)
+            RG_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        RG_TRY(hipLaunchKernel(fn, dim3(8 * sg.per_xcd), dim3(nmpc::kWave * waves), args, lds, s));
+    }
     return NMPC_OK;
 }
 
@@ -286,7 +320,7 @@ int ensure_graph(nmpc_ragged *r, int prec, int waves)
 {
     const int len = r->opt.check_every;
     // the captured launches hold every pointer and length of the layout
-    const long long key[8] = {waves, r->per_xcd, r->count, r->gen, len, (long long)r->in_len,
+    const long long key[8] = {waves, r->wl_sig, r->count, r->gen, len, (long long)r->in_len,
                               (long long)r->S_len, (long long)r->tot_units};
     if (r->gexec[prec] && std::equal(key, key + 8, r->gkey[prec])) return NMPC_OK;
     if (r->gexec[prec]) { (void)hipGraphExecDestroy(r->gexec[prec]); r->gexec[prec] = nullptr; }
@@ -332,6 +366,8 @@ int prepare(nmpc_ragged *r, int count, const int32_t *cls, const double *x0, con
         if (((mask >> c) & 1ull) && !r->fits[wi][c])
             return rg_fail(NMPC_E_UNSUPPORTED, "a class does not fit this workgroup size");
     *waves = w;
+    rc = worklist(r, w);
+    if (rc) return rc;
     rc = ensure_buffers(r);
     if (rc) return rc;
     RG_TRY(hipEventRecord(r->ev, us));

@@ -486,7 +486,12 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
 {
     const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
     const dim3 rows(8 * a.per_xcd), stages(a.count * h->N), inst((a.count + 255) / 256);
-    const size_t lds = nmpc::stream_lds_bytes(h->prob.nsx);   // row-block passes only
+    // LDS of the row-block passes: the residual pass stages two FP64 arrays,
+    // the sweep passes two (one for F_x^T) arrays of T
+    const int tsz = prec == nmpc::kModeFp32 ? 4 : 8;
+    const size_t lds = nmpc::stream_lds_bytes(h->prob.nsx, tsz, 2);
+    const size_t lds_res = nmpc::stream_lds_bytes(h->prob.nsx, 8, 2);
+    const size_t lds_jft = nmpc::stream_lds_bytes(h->prob.nsx, tsz, 1);
     auto go = [&](const void *fn, dim3 grid, int block, void **args, size_t sh = 0) -> int {
         HIP_TRY(hipLaunchKernel(fn, grid, dim3(block), args, sh, s));
         return NMPC_OK;
@@ -501,7 +506,7 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     }
     {
         void *args[] = {(void *)&a};
-        if ((rc = go(k.res, rows, 256, args, lds))) return rc;
+        if ((rc = go(k.res, rows, 256, args, lds_res))) return rc;
         if ((rc = go(k.stage, stages, 256, args))) return rc;
         if ((rc = go(k.decide, inst, 256, args))) return rc;
     }
@@ -527,7 +532,7 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
             int last = pass == passes - 1, partials = fin ? 0 : 1, update = fin ? 1 : 0;
             void *args[] = {(void *)&a, (void *)&pass, (void *)&last, (void *)&partials,
                             (void *)&update, (void *)&ytmp};
-            if ((rc = go(k.jft, rows, 256, args, lds))) return rc;
+            if ((rc = go(k.jft, rows, 256, args, lds_jft))) return rc;
         }
         if (!fin) {
             void *args[] = {(void *)&a};

@@ -71,6 +71,38 @@ struct Ctx {
 template <typename V>
 __device__ __forceinline__ V *lds_ptr(const Ctx &c, size_t o) { return reinterpret_cast<V *>(c.lds + o); }
 
+// Edge slots of the tile-row exchange: two regions (alternating by flip, so a
+// wave that is still reading one exchange's edges is never overwritten by the
+// next exchange), each holding the top and the bottom tile rows of every lane
+// in 8-byte slots. The region offset is in bytes, the same for every value
+// type, so exchanges of double and float values may follow each other.
+template <typename V, int CX>
+__device__ __forceinline__ V *edge_region(const Ctx &c)
+{
+    return reinterpret_cast<V *>(c.lds + c.off.edge + (size_t)c.flip * 2 * c.GT * 16 * CX * 8);
+}
+
+// o = N(v) from the tile and the rows above / below it.
+template <typename V, int CX, int RY>
+__device__ __forceinline__ void stencil(const V (&v)[RY][CX], const V (&above)[CX],
+                                        const V (&below)[CX], V (&o)[RY][CX], const Ctx &c)
+{
+    const V ax = V(c.ax), ay = V(c.ay);
+#pragma unroll
+    for (int t = 0; t < RY; ++t) {
+        const V lin = dpp<kDppRowShr1>(v[t][CX - 1]);
+        const V rin = dpp<kDppRowShl1>(v[t][0]);
+#pragma unroll
+        for (int q = 0; q < CX; ++q) {
+            const V l = q > 0 ? v[t][q - 1] : lin;
+            const V r = q < CX - 1 ? v[t][q + 1] : rin;
+            const V u = t > 0 ? v[t - 1][q] : above[q];
+            const V d = t < RY - 1 ? v[t + 1][q] : below[q];
+            o[t][q] = ax * (l + r) + ay * (u + d);
+        }
+    }
+}
+
 // Neighbour sum N(v)_p = (v_l + v_r)/dx^2 + (v_u + v_d)/dy^2 with zero values
 // off the grid (the Laplacian is L v = N(v) - (2/dx^2 + 2/dy^2) v).
 template <typename V, int CX, int RY>
@@ -79,8 +111,8 @@ __device__ __forceinline__ void nbsum(const V (&v)[RY][CX], V (&o)[RY][CX], Ctx 
     V above[CX], below[CX];
 #pragma unroll
     for (int q = 0; q < CX; ++q) { above[q] = V(0); below[q] = V(0); }
-    if (c.Gv > 1) {   // tile rows shared through LDS (double-buffered by flip)
-        V *top = lds_ptr<V>(c, c.off.edge) + (size_t)c.flip * 2 * c.GT * 16 * CX;
+    if (c.Gv > 1) {   // tile rows shared through LDS
+        V *top = edge_region<V, CX>(c);
         V *bot = top + (size_t)c.GT * 16 * CX;
         const int me = (c.G * 16 + c.cl) * CX;
 #pragma unroll
@@ -96,19 +128,52 @@ __device__ __forceinline__ void nbsum(const V (&v)[RY][CX], V (&o)[RY][CX], Ctx 
         }
         c.flip ^= 1;
     }
-    const V ax = V(c.ax), ay = V(c.ay);
+    stencil<V, CX, RY>(v, above, below, o, c);
+}
+
+// N(v1) and N(v2) with one exchange: for float tiles both arrays' edge values
+// share a slot, so one barrier serves both; double tiles take two exchanges.
+template <typename V, int CX, int RY>
+__device__ __forceinline__ void nbsum2(const V (&v1)[RY][CX], const V (&v2)[RY][CX],
+                                       V (&o1)[RY][CX], V (&o2)[RY][CX], Ctx &c)
+{
+    if constexpr (sizeof(V) != 4) {
+        nbsum<V, CX, RY>(v1, o1, c);
+        nbsum<V, CX, RY>(v2, o2, c);
+    } else {
+        float a1[CX], b1[CX], a2[CX], b2[CX];
 #pragma unroll
-    for (int t = 0; t < RY; ++t) {
-        const V lin = dpp<kDppRowShr1>(v[t][CX - 1]);
-        const V rin = dpp<kDppRowShl1>(v[t][0]);
+        for (int q = 0; q < CX; ++q) { a1[q] = 0.f; b1[q] = 0.f; a2[q] = 0.f; b2[q] = 0.f; }
+        if (c.Gv > 1) {
+            float2 *top = edge_region<float2, CX>(c);
+            float2 *bot = top + (size_t)c.GT * 16 * CX;
+            const int me = (c.G * 16 + c.cl) * CX;
 #pragma unroll
-        for (int q = 0; q < CX; ++q) {
-            const V l = q > 0 ? v[t][q - 1] : lin;
-            const V r = q < CX - 1 ? v[t][q + 1] : rin;
-            const V u = t > 0 ? v[t - 1][q] : above[q];
-            const V d = t < RY - 1 ? v[t + 1][q] : below[q];
-            o[t][q] = ax * (l + r) + ay * (u + d);
+            for (int q = 0; q < CX; ++q) {
+                top[me + q] = make_float2(v1[0][q], v2[0][q]);
+                bot[me + q] = make_float2(v1[RY - 1][q], v2[RY - 1][q]);
+            }
+            __syncthreads();
+            if (c.G > 0) {
+#pragma unroll
+                for (int q = 0; q < CX; ++q) {
+                    const float2 e = bot[me - 16 * CX + q];
+                    a1[q] = e.x;
+                    a2[q] = e.y;
+                }
+            }
+            if (c.G + 1 < c.Gv) {
+#pragma unroll
+                for (int q = 0; q < CX; ++q) {
+                    const float2 e = top[me + 16 * CX + q];
+                    b1[q] = e.x;
+                    b2[q] = e.y;
+                }
+            }
+            c.flip ^= 1;
         }
+        stencil<float, CX, RY>(v1, a1, b1, o1, c);
+        stencil<float, CX, RY>(v2, a2, b2, o2, c);
     }
 }
 
@@ -189,8 +254,9 @@ __device__ __forceinline__ void b_apply(const VS *vs, const Ctx &c, V (&o)[RY][C
     }
 }
 
-// (B^T y)_j for j < M, left in red[j] (double); all threads synchronized on
-// return. Per lane: column partials t_b = sum_t gy[b][iy_t] y_t, then the
+// (B^T y)_j for j < M, left in red[j] (double) by thread j, which is the only
+// thread that reads it before the next barrier (with one tile row, where the
+// stencils take no barrier, all threads are synchronized on return). Per lane: column partials t_b = sum_t gy[b][iy_t] y_t, then the
 // products with gx are formed inside the first halving step of the
 // cross-lane reduction, then the waves' partials are summed.
 template <typename V, int CX, int RY, int LX, int LY>
@@ -248,7 +314,7 @@ __device__ __forceinline__ void bt_reduce(const V (&y)[RY][CX], Ctx &c, int M)
         for (int ww = 0; ww < c.W; ++ww) s += V(red[ww * kMaxM + c.tid]);
         red[c.tid] = double(s);   // only thread tid touches column tid
     }
-    __syncthreads();
+    if (c.Gv == 1) __syncthreads();
 }
 
 // ----------------------------------------------------------- lower layer
@@ -309,14 +375,12 @@ template <typename T, int CX, int RY>
 __device__ __forceinline__ void axx_apply(const T (&y)[RY][CX], T (&o)[RY][CX],
                                           const StageCoef<T, CX, RY> &K, T h, T q, T c0, Ctx &c)
 {
-    T nb1[RY][CX], z[RY][CX];
-    nbsum<T, CX, RY>(y, nb1, c);
+    T nb1[RY][CX], nb2[RY][CX], z[RY][CX];
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll
         for (int p = 0; p < CX; ++p) z[t][p] = K.g2[t][p] * y[t][p];
-    T nb2[RY][CX];
-    nbsum<T, CX, RY>(z, nb2, c);
+    nbsum2<T, CX, RY>(y, z, nb1, nb2, c);
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll

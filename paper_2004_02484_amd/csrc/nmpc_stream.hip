@@ -78,41 +78,47 @@ __device__ __forceinline__ bool evaluating(const StreamArgs &a, int b)
     return PREC == kModeFp32 ? s.mode == kModeFp32 : s.mode != kModeFp32;
 }
 
-// Stage f(iy, ix) for rows iy0 - 1 .. iy0 + kRows of the block into lds
-// [(kRows + 2)][nsx] (zero outside the grid), then synchronize. Threads own
-// columns (ix = thread, thread + 256, ...) and walk the rows, so values a
-// column needs for every row (e.g. the column sums of B v) are loaded once.
-template <typename V, typename COL, typename F>
-__device__ __forceinline__ void stage_cols(V *lds, const DevProblem &P, int iy0, COL col, F f)
+// Visit the staged rows iy0 - 1 .. iy0 + kRows of a block: body(e, iy, ix,
+// inside, cv) for LDS index e = rr * nsx + ix, with inside false outside the
+// grid (the staged value is then the Dirichlet zero). Threads own columns
+// (ix = thread, thread + 256, ...; g thread groups share the rows when the row
+// is narrower than the workgroup) and walk the rows, so the addresses need no
+// division per element and a value a column needs in every row (cv = col(ix),
+// e.g. the column sums of B v) is loaded once. The caller synchronizes.
+template <typename COL, typename F>
+__device__ __forceinline__ void for_staged(const DevProblem &P, int iy0, COL col, F body)
 {
     const int nsx = P.nsx;
-    // g thread groups of nsx columns share the rows when the row is narrower
-    // than the workgroup (one division per thread, none per element).
     const int g = nsx >= (int)blockDim.x ? 1 : (int)blockDim.x / nsx;
     const int r0 = g == 1 ? 0 : (int)threadIdx.x / nsx;
     const int c0 = (int)threadIdx.x - r0 * nsx;
-    if (r0 < g) {
-        for (int ix = c0; ix < nsx; ix += g == 1 ? (int)blockDim.x : nsx) {
-            auto cv = col(ix);
-            for (int rr = r0; rr < kRows + 2; rr += g) {
-                const int iy = iy0 + rr - 1;
-                lds[rr * nsx + ix] = (iy >= 0 && iy < P.nsy) ? f(iy, ix, cv) : V(0);
-            }
+    if (r0 >= g) return;
+    for (int ix = c0; ix < nsx; ix += g == 1 ? (int)blockDim.x : nsx) {
+        auto cv = col(ix);
+#pragma unroll 2
+        for (int rr = r0; rr < kRows + 2; rr += g) {
+            const int iy = iy0 + rr - 1;
+            body(rr * nsx + ix, iy, ix, iy >= 0 && iy < P.nsy, cv);
         }
     }
-    __syncthreads();
 }
 
 struct NoCol {};
+__device__ __forceinline__ NoCol no_col(int) { return NoCol{}; }
 
+// Stage f(iy, ix) for the block's rows and halo rows into lds [(kRows + 2)][nsx]
+// and synchronize.
 template <typename V, typename F>
 __device__ __forceinline__ void stage_rows(V *lds, const DevProblem &P, int iy0, F f)
 {
-    stage_cols(lds, P, iy0, [](int) { return NoCol{}; },
-               [&](int iy, int ix, NoCol) { return f(iy, ix); });
+    for_staged(P, iy0, no_col, [&](int e, int iy, int ix, bool in, NoCol) {
+        lds[e] = in ? f(iy, ix) : V(0);
+    });
+    __syncthreads();
 }
 
-// The ly column sums sc[bb][ix] of B v for one column (registers).
+// The ly column sums sc[bb][ix] of B v for one column (registers; the loops
+// over the lattice rows are unrolled to kMaxLy so the array stays in VGPRs).
 struct BCol {
     double s[kMaxLy];
 };
@@ -184,14 +190,17 @@ __device__ __forceinline__ BCol bsep_col(const StreamArgs &a, size_t bi, int ix)
 {
     const double *sc = a.sc + bi * a.P.ly * a.P.nsx;
     BCol c;
-    for (int bb = 0; bb < a.P.ly; ++bb) c.s[bb] = sc[bb * a.P.nsx + ix];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb) c.s[bb] = bb < a.P.ly ? sc[bb * a.P.nsx + ix] : 0.0;
     return c;
 }
 
 __device__ __forceinline__ double bsep_row(const StreamArgs &a, const BCol &c, int iy)
 {
     double s = 0.0;
-    for (int bb = 0; bb < a.P.ly; ++bb) s += a.gy[bb * a.P.nsy + iy] * c.s[bb];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb)
+        if (bb < a.P.ly) s += a.gy[bb * a.P.nsy + iy] * c.s[bb];
     return s;
 }
 
@@ -230,8 +239,13 @@ __global__ void __launch_bounds__(256) k_st_res(const StreamArgs a)
     auto K = [&](double w) { return P.k0 * (1.0 + P.k1 * w); };
     double *xs = reinterpret_cast<double *>(lds_raw);
     double *gs = xs + (kRows + 2) * nsx;
-    stage_rows(xs, P, u.iy0, [&](int iy, int ix) { return x[iy * nsx + ix]; });
-    stage_rows(gs, P, u.iy0, [&](int iy, int ix) { const int q = iy * nsx + ix; return K(x[q]) * lam[q]; });
+    for_staged(P, u.iy0, no_col, [&](int e, int iy, int ix, bool in, NoCol) {
+        const int q = iy * nsx + ix;
+        const double xv = in ? x[q] : 0.0, lv = in ? lam[q] : 0.0;
+        xs[e] = xv;
+        gs[e] = K(xv) * lv;
+    });
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     own_rows(P, u.iy0, [&](int rr, int iy) {
         unsigned long long mx = 0, ml = 0;
@@ -428,11 +442,13 @@ __global__ void __launch_bounds__(256) k_st_jf(const StreamArgs a, int sgn, int 
             return;
         }
         T *cs = ys + (kRows + 2) * nsx;   // c of the block and halo rows
-        stage_cols(cs, P, u.iy0, [&](int ix) { return use_v3 ? bsep_col(a, bi, ix) : BCol{}; },
-                   [&](int iy, int ix, const BCol &cv) { return crow(iy, ix, cv); });
-        stage_rows(ys, P, u.iy0, [&](int iy, int ix) {
-            return cs[(iy - u.iy0 + 1) * nsx + ix] * invd[iy * nsx + ix];
-        });
+        for_staged(P, u.iy0, [&](int ix) { return use_v3 ? bsep_col(a, bi, ix) : BCol{}; },
+                   [&](int e, int iy, int ix, bool in, const BCol &cv) {
+                       const T cv_ = in ? crow(iy, ix, cv) : T(0);
+                       cs[e] = cv_;
+                       ys[e] = in ? cv_ * invd[iy * nsx + ix] : T(0);
+                   });
+        __syncthreads();
         own_rows(P, u.iy0, [&](int rr, int iy) {
             for (int ix = lane; ix < nsx; ix += kWave) {
                 const int p = iy * nsx + ix;
@@ -472,8 +488,13 @@ __global__ void __launch_bounds__(256) k_st_axx(const StreamArgs a, int sgn, int
     const T ax = T(P.idx2), ay = T(P.idy2), h = T(P.h), q = T(P.q), c0 = T(P.c0);
     T *ys = reinterpret_cast<T *>(lds_raw);
     T *zs = ys + (kRows + 2) * nsx;
-    stage_rows(ys, P, u.iy0, [&](int iy, int ix) { return y[iy * nsx + ix]; });
-    stage_rows(zs, P, u.iy0, [&](int iy, int ix) { const int p = iy * nsx + ix; return g2[p] * y[p]; });
+    for_staged(P, u.iy0, no_col, [&](int e, int iy, int ix, bool in, NoCol) {
+        const int p = iy * nsx + ix;
+        const T yv = in ? y[p] : T(0);
+        ys[e] = yv;
+        zs[e] = in ? g2[p] * yv : T(0);
+    });
+    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1);
     own_rows(P, u.iy0, [&](int rr, int iy) {
         for (int ix = lane; ix < nsx; ix += kWave) {
