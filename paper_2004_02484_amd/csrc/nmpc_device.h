@@ -69,6 +69,7 @@ struct IterArgs {
     double tol;
     int max_iter, n_sw, n_schur;
     int residual_only, res_slot;
+    int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
 };
 
 struct InitArgs {
@@ -169,6 +170,12 @@ struct TileCfg {
 struct LdsOff {
     size_t edge, gx, gy, gxf, gyf, uvec, v3, kun, red, nrm, total;
 };
+
+// Gauss-Seidel stage prefetch: x_i and lambda_i of the next stage (n padded
+// points each) copied into LDS while the current stage runs, in 1 KB chunks
+// (64 lanes x 16 bytes); doubles per array region, after the layout's total.
+__host__ __device__ inline size_t gs_pf_doubles(int n) { return (size_t)((n * 8 + 1023) / 1024) * 128; }
+__host__ __device__ inline size_t gs_pf_bytes(int n) { return 2 * gs_pf_doubles(n) * 8; }
 
 __host__ __device__ inline size_t lds_align16(size_t p) { return (p + 15) & ~(size_t)15; }
 

@@ -48,11 +48,29 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.lnb = dir > 0 ? src : dst;
     v.xrb = src;
     v.lrb = src;
+    v.pf = a.gs_pf != 0;
+    v.pnb = -1;
+    if (v.pf) {   // the sweep's first stage; each stage then prefetches the next
+        // the previous sweep's last stage may have just written this stage,
+        // and a wave's transfer covers other waves' points: their stores
+        // complete before the barrier
+        __syncthreads();
+        const size_t s0 = (size_t)v.so + (size_t)(dir > 0 ? 0 : N - 1) * n;
+        prefetch_xl(c, a.X[src] + s0, a.LAM[src] + s0, n);
+    }
     for (int t = 0; t < N; ++t) {
         const int i = dir > 0 ? t : N - 1 - t;
         v.i = i;
         v.last = i == N - 1;
         v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
+        if (v.pf) {
+            // the stages ahead are not written in this sweep before they are
+            // visited (x_{i+d}, lambda_{i+d} of buffer src)
+            v.pnb = t + 1 < N ? src : -1;
+            v.pni = i + dir;
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's transfers have landed
+            __syncthreads();                 // and every other wave's
+        }
         stage_body<T, CX, RY, LX, LY>(a, a.P, v, c, acc);
     }
 }

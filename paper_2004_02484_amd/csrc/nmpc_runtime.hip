@@ -54,6 +54,7 @@ struct nmpc_handle {
         TileCfg cfg{};
         int waves = 0;
         size_t lds = 0;
+        int pf = 0;                        // Gauss-Seidel: stage prefetch region in LDS
     } kern[2];                             // [kModeFp64], [kModeFp32]
     Kern gs[2];                            // Gauss-Seidel kernels (upper != Jacobi)
     bool streaming = false;                // multi-pass kernels (grids beyond one workgroup)
@@ -116,11 +117,15 @@ int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k,
                                         p->lx, p->ly, cfg.rows).total;
     if (lds > nmpc::kLdsBytes)
         return fail(NMPC_E_UNSUPPORTED, "tile needs more LDS than a CU has");
+    // the Gauss-Seidel kernel prefetches the next stage into LDS where it fits
+    const int np = p->nsy * 16 * cfg.cx;
+    const int pf = gs && lds + nmpc::gs_pf_bytes(np) <= nmpc::kLdsBytes ? 1 : 0;
     if (k) {
         k->fn = fn;
         k->cfg = cfg;
         k->waves = waves;
-        k->lds = lds;
+        k->lds = pf ? lds + nmpc::gs_pf_bytes(np) : lds;
+        k->pf = pf;
     }
     return NMPC_OK;
 }
@@ -591,6 +596,7 @@ int run_gs(nmpc_handle *h, int count)
     for (int prec : {nmpc::kModeFp32, nmpc::kModeFp64}) {
         if (prec == nmpc::kModeFp32 && main_prec(h->opt) != nmpc::kModeFp32) continue;
         const nmpc_handle::Kern &k = h->gs[prec];
+        a.gs_pf = k.pf;
         HIP_TRY(hipLaunchKernel(k.fn, dim3(count), dim3(nmpc::kWave * k.waves), args, k.lds,
                                 h->stream));
         ++launches;
@@ -1062,6 +1068,7 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
                 a.units = count;
                 a.tol = -1.0;
                 a.max_iter = iters;
+                a.gs_pf = k.pf;
                 int upper = h->opt.upper;
                 void *args[] = {(void *)&a, (void *)&upper};
                 HIP_TRY(hipLaunchKernel(k.fn, dim3(count), dim3(nmpc::kWave * k.waves), args,

@@ -511,7 +511,33 @@ struct StageLoc {
     int i, src, dst, xpb, xrb, lnb, lrb, utb;
     bool last;                     // i is the last stage
     bool res_only;                 // stop after the residual (no lower layer, no update)
+    bool pf;                       // x_i, lambda_i are in the LDS prefetch region
+    int pnb, pni;                  // stage pni of buffer pnb is prefetched once this stage
+                                   // has read its own (pnb < 0: none)
 };
+
+// Start the copy of x and lambda (n doubles each, padded layout) into the LDS
+// prefetch region at c.off.total: global -> LDS transfers of 16 bytes per lane,
+// 1 KB per wave instruction, spread over the waves. They complete in the
+// background; the data may be read after s_waitcnt and a barrier. Lanes past
+// the end re-read the last 16 bytes into slots nobody reads (n is even).
+__device__ __forceinline__ void prefetch_xl(const Ctx &c, const double *x, const double *l, int n)
+{
+    typedef const __attribute__((address_space(1))) void *GPtr;
+    typedef __attribute__((address_space(3))) void *LPtr;
+    const int chunks = (n * 8 + 1023) / 1024;
+    const int npf = chunks * 128;
+    double *base = lds_ptr<double>(c, c.off.total);
+    for (int ch = c.w; ch < 2 * chunks; ch += c.W) {
+        const bool isl = ch >= chunks;
+        const int cc = isl ? ch - chunks : ch;
+        int e = cc * 128 + c.lane * 2;
+        e = e < n - 2 ? e : n - 2;
+        const double *src = (isl ? l : x) + e;
+        double *dst = base + (isl ? npf : 0) + cc * 128;
+        __builtin_amdgcn_global_load_lds((GPtr)src, (LPtr)dst, 16, 0, 0);
+    }
+}
 
 __device__ __forceinline__ StageLoc jacobi_loc(int cur)
 {
@@ -519,6 +545,7 @@ __device__ __forceinline__ StageLoc jacobi_loc(int cur)
     v.src = v.xpb = v.xrb = v.lnb = v.lrb = cur;
     v.dst = cur ^ 1;
     v.utb = -1;
+    v.pnb = -1;
     return v;
 }
 
@@ -547,6 +574,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     double *red = lds_ptr<double>(c, c.off.red);
     unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
 
+    const StageLoc &sv = v;
     // stage slices x_i, lam_i, x_{i-1} (x0 at i = 0), lam_{i+1} (none at the
     // last stage), xref_i, all with the padded row stride sx = 16 * CX: a
     // lane's tile lies inside a row or entirely in its zero padding
@@ -581,8 +609,14 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
 #pragma unroll
             for (int q = 0; q < CX; ++q) {
                 const bool v = valid(t, q);
-                xc[t][q] = v ? Xc[pidx(t, q)] : 0.0;
-                lc[t][q] = v ? Lc[pidx(t, q)] : 0.0;
+                if (sv.pf) {
+                    const double *px = lds_ptr<double>(c, c.off.total);
+                    xc[t][q] = v ? px[pidx(t, q)] : 0.0;
+                    lc[t][q] = v ? px[gs_pf_doubles(n) + pidx(t, q)] : 0.0;
+                } else {
+                    xc[t][q] = v ? Xc[pidx(t, q)] : 0.0;
+                    lc[t][q] = v ? Lc[pidx(t, q)] : 0.0;
+                }
             }
         if (c.tid < M) uvec[c.tid] = a.U[v.src][v.uo + (size_t)v.i * M + c.tid];
         nbsum<double, CX, RY>(xc, Lx, c);
@@ -698,6 +732,12 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         }
     } else {
         __syncthreads();   // publish kun / v3 (the norm path's barrier)
+    }
+    // every wave has read its x_i, lambda_i (before the first stencil barrier):
+    // the prefetch region may take the next stage's
+    if (v.pnb >= 0) {
+        const size_t sn = (size_t)v.so + (size_t)v.pni * n;
+        prefetch_xl(c, a.X[v.pnb] + sn, a.LAM[v.pnb] + sn, n);
     }
     if (a.residual_only || v.res_only) return;
 
