@@ -94,17 +94,8 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
     constexpr int M = LX * LY;
     const int b = blockIdx.x;
     if (b >= a.units) return;
-    double *gx = lds_ptr<double>(c, c.off.gx);
-    double *gy = lds_ptr<double>(c, c.off.gy);
     double *uvec = lds_ptr<double>(c, c.off.uvec);
-    for (int t = c.tid; t < LX * 16 * CX; t += blockDim.x) {
-        const int aa = t / (16 * CX), ix = t % (16 * CX);
-        gx[t] = ix < P.nsx ? a.gx[aa * P.nsx + ix] : 0.0;
-    }
-    for (int t = c.tid; t < LY * c.GT * RY; t += blockDim.x) {
-        const int bb = t / (c.GT * RY), iy = t % (c.GT * RY);
-        gy[t] = iy < P.nsy ? a.gy[bb * P.nsy + iy] : 0.0;
-    }
+    load_tables<CX, RY, LX, LY>(c, a.gx, a.gy, P.nsx, P.nsy);
     const int n = P.n, sx = 16 * CX;
     const int ix0 = c.cl * CX, iy0 = c.G * RY;
     auto valid = [&](int t, int q) { return ix0 + q < P.nsx && iy0 + t < P.nsy; };

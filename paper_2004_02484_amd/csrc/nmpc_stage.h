@@ -75,7 +75,10 @@ __device__ __forceinline__ V *lds_ptr(const Ctx &c, size_t o) { return reinterpr
 // wave that is still reading one exchange's edges is never overwritten by the
 // next exchange), each holding the top and the bottom tile rows of every lane
 // in 8-byte slots. The region offset is in bytes, the same for every value
-// type, so exchanges of double and float values may follow each other.
+// type, so exchanges of double and float values may follow each other. Slots
+// are column-major within a tile row set: value q of lane-row G, lane cl sits
+// at q * 16 GT + 16 G + cl, so the 64 lanes of a wave touch consecutive slots
+// (no LDS bank conflicts).
 template <typename V, int CX>
 __device__ __forceinline__ V *edge_region(const Ctx &c)
 {
@@ -114,17 +117,17 @@ __device__ __forceinline__ void nbsum(const V (&v)[RY][CX], V (&o)[RY][CX], Ctx 
     if (c.Gv > 1) {   // tile rows shared through LDS
         V *top = edge_region<V, CX>(c);
         V *bot = top + (size_t)c.GT * 16 * CX;
-        const int me = (c.G * 16 + c.cl) * CX;
+        const int me = c.G * 16 + c.cl, qs = c.GT * 16;
 #pragma unroll
-        for (int q = 0; q < CX; ++q) { top[me + q] = v[0][q]; bot[me + q] = v[RY - 1][q]; }
+        for (int q = 0; q < CX; ++q) { top[q * qs + me] = v[0][q]; bot[q * qs + me] = v[RY - 1][q]; }
         __syncthreads();
         if (c.G > 0) {
 #pragma unroll
-            for (int q = 0; q < CX; ++q) above[q] = bot[me - 16 * CX + q];
+            for (int q = 0; q < CX; ++q) above[q] = bot[q * qs + me - 16];
         }
         if (c.G + 1 < c.Gv) {
 #pragma unroll
-            for (int q = 0; q < CX; ++q) below[q] = top[me + 16 * CX + q];
+            for (int q = 0; q < CX; ++q) below[q] = top[q * qs + me + 16];
         }
         c.flip ^= 1;
     }
@@ -147,17 +150,17 @@ __device__ __forceinline__ void nbsum2(const V (&v1)[RY][CX], const V (&v2)[RY][
         if (c.Gv > 1) {
             float2 *top = edge_region<float2, CX>(c);
             float2 *bot = top + (size_t)c.GT * 16 * CX;
-            const int me = (c.G * 16 + c.cl) * CX;
+            const int me = c.G * 16 + c.cl, qs = c.GT * 16;
 #pragma unroll
             for (int q = 0; q < CX; ++q) {
-                top[me + q] = make_float2(v1[0][q], v2[0][q]);
-                bot[me + q] = make_float2(v1[RY - 1][q], v2[RY - 1][q]);
+                top[q * qs + me] = make_float2(v1[0][q], v2[0][q]);
+                bot[q * qs + me] = make_float2(v1[RY - 1][q], v2[RY - 1][q]);
             }
             __syncthreads();
             if (c.G > 0) {
 #pragma unroll
                 for (int q = 0; q < CX; ++q) {
-                    const float2 e = bot[me - 16 * CX + q];
+                    const float2 e = bot[q * qs + me - 16];
                     a1[q] = e.x;
                     a2[q] = e.y;
                 }
@@ -165,7 +168,7 @@ __device__ __forceinline__ void nbsum2(const V (&v1)[RY][CX], const V (&v2)[RY][
             if (c.G + 1 < c.Gv) {
 #pragma unroll
                 for (int q = 0; q < CX; ++q) {
-                    const float2 e = top[me + 16 * CX + q];
+                    const float2 e = top[q * qs + me + 16];
                     b1[q] = e.x;
                     b2[q] = e.y;
                 }
@@ -177,41 +180,134 @@ __device__ __forceinline__ void nbsum2(const V (&v1)[RY][CX], const V (&v2)[RY][
     }
 }
 
-// Reduce per-lane arrays over the 64 lanes of a wave, starting after FIRST
-// halving steps already done by the caller (a holds MP values). On return,
-// lane l holds the total of element (l >> (6 - log2(MP) - FIRST)): each
-// halving step trades the half a lane does not keep with its partner, so the
-// exchange volume is about the element count instead of 6x it.
-template <int MP, int FIRST, typename V>
-__device__ __forceinline__ V wave_reduce_scatter_from(V (&a)[MP], int lane)
+// Lane exchanges on the VALU, without LDS instructions: xpart<MASK>(v) is the
+// value of lane l ^ MASK. Masks 32 and 16 use the gfx950 half-swaps
+// (v_permlane32_swap: lanes 32..63 of the first operand trade places with
+// lanes 0..31 of the second; v_permlane16_swap: the odd 16-lane rows of the
+// first with the even rows of the second); masks 8, 2, 1 are DPP row / quad
+// permutations, mask 4 a pair of DPP row shifts.
+template <int MASK>
+__device__ __forceinline__ unsigned xpart_u32(unsigned v, int lane)
 {
-    constexpr int LG = Pow2<MP>::lg;
-#pragma unroll
-    for (int s = 0; s < LG; ++s) {
-        const int mask = 32 >> (s + FIRST);
-        const int half = MP >> (s + 1);
-        const bool hi = (lane & mask) != 0;
-#pragma unroll
-        for (int j = 0; j < half; ++j) {
-            V send = hi ? a[j] : a[j + half];
-            V keep = hi ? a[j + half] : a[j];
-            a[j] = keep + __shfl_xor(send, mask, kWave);
-        }
+    if constexpr (MASK == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    } else if constexpr (MASK == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (MASK == 8) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);   // row_ror:8
+    } else if constexpr (MASK == 4) {
+        const int dn = __builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+        const int up = __builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0xF, true);   // row_shl:4
+        return (unsigned)((lane & 4) ? dn : up);
+    } else if constexpr (MASK == 2) {
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad 2,3,0,1
+    } else {
+        static_assert(MASK == 1, "xor masks 32 .. 1");
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad 1,0,3,2
     }
-    V s = a[0];
-#pragma unroll
-    for (int mask = 32 >> (LG + FIRST); mask >= 1; mask >>= 1) s += __shfl_xor(s, mask, kWave);
-    return s;
 }
 
-__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v)
+template <int MASK>
+__device__ __forceinline__ float xpart(float v, int lane)
 {
+    return __uint_as_float(xpart_u32<MASK>(__float_as_uint(v), lane));
+}
+template <int MASK>
+__device__ __forceinline__ unsigned long long xpart(unsigned long long v, int lane)
+{
+    const unsigned lo = xpart_u32<MASK>((unsigned)v, lane);
+    const unsigned hi = xpart_u32<MASK>((unsigned)(v >> 32), lane);
+    return ((unsigned long long)hi << 32) | lo;
+}
+template <int MASK>
+__device__ __forceinline__ double xpart(double v, int lane)
+{
+    return __longlong_as_double((long long)xpart<MASK>((unsigned long long)__double_as_longlong(v), lane));
+}
+
+// One reduce-scatter step of mask MASK: lanes without the mask bit keep x
+// summed with their partner's x, lanes with it keep y summed with their
+// partner's y. For masks 32 and 16 the two outputs of the half-swap of (x, y)
+// are exactly these pairs, so no selection is needed.
+template <int MASK, typename V>
+__device__ __forceinline__ V rs_pair(V x, V y, int lane)
+{
+    if constexpr (MASK == 32 || MASK == 16) {
+        V r0, r1;
+        if constexpr (sizeof(V) == 4) {
+            const unsigned bx = __float_as_uint(x), by = __float_as_uint(y);
+            const auto r = MASK == 32 ? __builtin_amdgcn_permlane32_swap(bx, by, false, false)
+                                      : __builtin_amdgcn_permlane16_swap(bx, by, false, false);
+            r0 = __uint_as_float(r[0]);
+            r1 = __uint_as_float(r[1]);
+        } else {
+            const long long bx = __double_as_longlong(x), by = __double_as_longlong(y);
+            const unsigned xl = (unsigned)bx, xh = (unsigned)(bx >> 32);
+            const unsigned yl = (unsigned)by, yh = (unsigned)(by >> 32);
+            const auto lo = MASK == 32 ? __builtin_amdgcn_permlane32_swap(xl, yl, false, false)
+                                       : __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+            const auto hi = MASK == 32 ? __builtin_amdgcn_permlane32_swap(xh, yh, false, false)
+                                       : __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+            r0 = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+            r1 = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+        }
+        return r0 + r1;
+    } else {
+        const bool up = (lane & MASK) != 0;
+        const V send = up ? x : y, keep = up ? y : x;
+        return keep + xpart<MASK>(send, lane);
+    }
+}
+
+// Sum over the lanes that differ only in the bits MASK, MASK / 2, ..., 1.
+template <int MASK, typename V>
+__device__ __forceinline__ V allreduce_from(V s, int lane)
+{
+    if constexpr (MASK >= 1) {
+        s += xpart<MASK>(s, lane);
+        return allreduce_from<MASK / 2>(s, lane);
+    } else {
+        return s;
+    }
+}
+
+// Reduce-scatter of MP per-lane values over the 64 lanes, the halving steps
+// taking masks MASK, MASK / 2, ... and the rest full butterflies: on return
+// lane l holds the wave total of the element whose index is made of l's bits
+// at the halving masks (l >> (log2(MASK) + 1 - log2(MP)) for the lanes
+// below 2 MASK). Each halving step trades the half a lane does not keep with
+// its partner, so the exchange volume is about the element count instead of
+// 6x it.
+template <int MP, int MASK, typename V>
+__device__ __forceinline__ V reduce_scatter(V (&a)[MP], int lane)
+{
+    if constexpr (MP == 1) {
+        return allreduce_from<MASK>(a[0], lane);
+    } else {
+        constexpr int HALF = MP / 2;
+        V b[HALF];
 #pragma unroll
-    for (int mask = 32; mask >= 1; mask >>= 1) v = umax64(v, __shfl_xor(v, mask, kWave));
-    return v;
+        for (int j = 0; j < HALF; ++j) b[j] = rs_pair<MASK>(a[j], a[j + HALF], lane);
+        return reduce_scatter<HALF, MASK / 2>(b, lane);
+    }
+}
+
+template <int MASK = 32>
+__device__ __forceinline__ unsigned long long wave_max64(unsigned long long v, int lane)
+{
+    if constexpr (MASK >= 1) {
+        v = umax64(v, xpart<MASK>(v, lane));
+        return wave_max64<MASK / 2>(v, lane);
+    } else {
+        return v;
+    }
 }
 
 // (B v)_p = sum_b gy[b][iy] sum_a gx[a][ix] v[b*LX + a]; v in LDS (double).
+// The gx table holds gx[a][cl * CX + q] at (a * CX + q) * 16 + cl, so the 16
+// lanes of a tile row read consecutive values.
 template <typename V>
 __device__ __forceinline__ const V *gx_tab(const Ctx &c)
 {
@@ -236,7 +332,7 @@ __device__ __forceinline__ void b_apply(const VS *vs, const Ctx &c, V (&o)[RY][C
             V acc = V(0);
 #pragma unroll
             for (int a = 0; a < LX; ++a)
-                acc += V(gx[a * 16 * CX + c.cl * CX + q]) * V(vs[b * LX + a]);
+                acc += V(gx[(a * CX + q) * 16 + c.cl]) * V(vs[b * LX + a]);
             s[b][q] = acc;
         }
 #pragma unroll
@@ -284,27 +380,19 @@ __device__ __forceinline__ void bt_reduce(const V (&y)[RY][CX], Ctx &c, int M)
         V acc = V(0);
         if (j < MM) {
 #pragma unroll
-            for (int q = 0; q < CX; ++q) acc += V(gx[(j % LX) * 16 * CX + c.cl * CX + q]) * tb[j / LX][q];
+            for (int q = 0; q < CX; ++q) acc += V(gx[((j % LX) * CX + q) * 16 + c.cl]) * tb[j / LX][q];
         }
         return acc;
     };
     V e;
     if constexpr (MP == 1) {
-        e = prod(0);
-#pragma unroll
-        for (int mask = 32; mask >= 1; mask >>= 1) e += __shfl_xor(e, mask, kWave);
+        e = allreduce_from<32>(prod(0), c.lane);
     } else {
         constexpr int HALF = MP / 2;
         V a[HALF];
-        const bool hi = (c.lane & 32) != 0;
 #pragma unroll
-        for (int j = 0; j < HALF; ++j) {
-            const V pl = prod(j), ph = prod(j + HALF);
-            const V send = hi ? pl : ph;
-            const V keep = hi ? ph : pl;
-            a[j] = keep + __shfl_xor(send, 32, kWave);
-        }
-        e = wave_reduce_scatter_from<HALF, 1>(a, c.lane);
+        for (int j = 0; j < HALF; ++j) a[j] = rs_pair<32>(prod(j), prod(j + HALF), c.lane);
+        e = reduce_scatter<HALF, 16>(a, c.lane);
     }
     constexpr int SH = 6 - Pow2<MP>::lg;
     if ((c.lane & ((1 << SH) - 1)) == 0) red[c.w * kMaxM + (c.lane >> SH)] = double(e);
@@ -430,8 +518,8 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                 ms = umax64(ms, a.rst[base + t]);
                 mp = umax64(mp, a.pst[base + t]);
             }
-            ms = wave_max64(ms);
-            mp = wave_max64(mp);
+            ms = wave_max64(ms, c.lane);
+            mp = wave_max64(mp, c.lane);
             if (c.lane == 0) { nrm[0] = ms; nrm[1] = mp; }
         }
         __syncthreads();
@@ -696,9 +784,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         mu = abits(ku);
     }
     if (want_res) {
-        mx = wave_max64(mx);
-        ml = wave_max64(ml);
-        mu = wave_max64(mu);
+        mx = wave_max64(mx, c.lane);
+        ml = wave_max64(ml, c.lane);
+        mu = wave_max64(mu, c.lane);
         if (c.lane == 0) {
             nrm[c.w * 4 + 0] = mx;
             nrm[c.w * 4 + 1] = ml;
@@ -825,7 +913,7 @@ __device__ __forceinline__ void load_tables(Ctx &c, const double *gxs, const dou
     float *gxf = lds_ptr<float>(c, c.off.gxf);
     float *gyf = lds_ptr<float>(c, c.off.gyf);
     for (int t = c.tid; t < LX * 16 * CX; t += c.W * kWave) {
-        const int aa = t / (16 * CX), ix = t % (16 * CX);
+        const int aq = t >> 4, aa = aq / CX, ix = (t & 15) * CX + aq % CX;
         const double v = ix < nsx ? gxs[aa * nsx + ix] : 0.0;
         gx[t] = v;
         gxf[t] = float(v);
