@@ -59,11 +59,13 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 EVAL_SEED0 = 1_000_000         # disjoint from any training seeds
 
 
-def bytes_per_unit(n: int, m: int, N: int, word: int = 8) -> float:
+def bytes_per_unit(n: int, m: int, N: int, word: int = 8, sweeps: int = 1) -> float:
     """Algorithmic HBM bytes of one (instance, stage) unit of one upper
-    iteration: read s_i^k, write s_i^{k+1} (2n + m values each) and the
-    instance's x0 and xref once per iteration (2n values shared by N stages)."""
-    return word * (2.0 * (2 * n + m) + 2.0 * n / N)
+    iteration: each of the iteration's stage sweeps (one for Jacobi, FGS and
+    BGS, two for SGS) reads s_i and writes its new value (2n + m values each);
+    the instance's x0 and xref are read once per iteration (2n values shared
+    by N stages)."""
+    return word * (sweeps * 2.0 * (2 * n + m) + 2.0 * n / N)
 
 
 def kernel_digest(sources) -> str:
@@ -337,18 +339,19 @@ def bench_c3(args):
         oracle.build(force=False)
         cls, _, _, inst = batches[args.warmup]
         t = time.perf_counter()
-        done, sizes = 0, []
+        done, grids = 0, {}
         for c, (x0, xr) in zip(cls, inst):
             oracle.solve(classes[c], x0, xr, tol=1e-6, max_iter=5000)
             done += 1
-            sizes.append(f"{classes[c].nsx}/{classes[c].N}")
+            grids[classes[c].nsx] = grids.get(classes[c].nsx, 0) + 1
             if time.perf_counter() - t >= args.cpu_budget:
                 break
         dt = time.perf_counter() - t
+        mix = ", ".join(f"{k}x{k}: {v}" for k, v in sorted(grids.items()))
         cpu = {"value": done / dt, "unit": "solves/s", "cores": oracle.threads(),
                "kind": "oracle",
-               "sample": f"the first {done} instances of the first timed batch (grid/horizon "
-                         f"{', '.join(sizes)}), cold start, Jacobi, tol 1e-6, {dt:.1f} s"}
+               "sample": f"the first {done} instances of the first timed batch ({mix}; horizons "
+                         f"as drawn), cold start, Jacobi, tol 1e-6, {dt:.1f} s"}
     line("NMPC solves/s to KKT res 1e-6, 512 ragged instances (mixed grids and horizons)",
          B * args.steps / elapsed, args, elapsed, "f32 sweeps, f64 state/residual", cfg, roof, cpu)
     solver.close()
@@ -435,7 +438,7 @@ def main():
 
     solves = B * args.steps
     value = solves / elapsed
-    roof = roofline(kind, tm, bytes_per_unit(P.n, P.m, P.N))
+    roof = roofline(kind, tm, bytes_per_unit(P.n, P.m, P.N, sweeps=2 if args.upper == "sgs" else 1))
 
     start_desc = "learned warm start (network + rollout + adjoint, cold fallback)" \
         if net is not None else "cold start"
