@@ -127,6 +127,10 @@ struct StreamArgs {
     unsigned long long *rown;       // [B][N][nsy][2] row maxima of |K^x|, |K^lambda|
     double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y
     unsigned long long *rst, *pst;  // [B][N] stage norms (bit patterns)
+    double *part;                   // [B][N][lower units per stage][kMaxM] partial B^T y4
+    int nstrip, nrb;                // lower pass: column strips and row blocks per stage
+    long long lunits;               // lower pass: count * N * nrb * nstrip wave units
+    int lper_xcd;                   // lower pass: workgroups per XCD run
     InstState *st;                  // [B]
     int *work;                      // [B] 1: the instance takes a step in this iteration
     int *iters;
@@ -147,8 +151,17 @@ __host__ __device__ inline size_t stream_lds_bytes(int nsx, int elem = 8, int ar
     return (size_t)arrays * (kStreamRows + 2) * nsx * elem;
 }
 
+// The fused lower-layer pass (two point-Jacobi sweeps per solve): one wave per
+// strip of kLowerCols owned grid columns (64 lanes = the strip and 3 halo
+// columns each side) and kLowerRows grid rows, marching down the rows
+// (kLowerRows + 6 a multiple of the pass's prefetch distance, 6).
+constexpr int kLowerRows = 30;
+constexpr int kLowerHalo = 3;
+constexpr int kLowerCols = kWave - 2 * kLowerHalo;
+
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
+    const void *lower, *lower_fin, *v3f;   // fused Schur step, final block; v3 from partials
 };
 StreamKernels stream_kernels(int prec);
 

@@ -445,8 +445,10 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
 size_t stream_doubles(const nmpc_handle *h)
 {
     const size_t B = h->max_batch, N = h->N, n = h->n, m = h->m;
+    const size_t lunits = (size_t)((h->prob.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols) *
+                          ((h->prob.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows);
     return 10 * B * N * n + B * N * h->prob.ly * h->prob.nsx + 2 * B * N * m +
-           B * N * h->prob.nsy * (2 + nmpc::kMaxLx);
+           B * N * h->prob.nsy * (2 + nmpc::kMaxLx) + B * N * lunits * nmpc::kMaxM;
 }
 
 nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
@@ -473,7 +475,12 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.kun = q; q += B * N * m;
     a.v3 = q; q += B * N * m;
     a.rown = reinterpret_cast<unsigned long long *>(q); q += 2 * B * N * p.nsy;
-    a.rowt = q;
+    a.rowt = q; q += B * N * p.nsy * nmpc::kMaxLx;
+    a.part = q;
+    a.nstrip = (p.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols;
+    a.nrb = (p.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows;
+    a.lunits = (long long)count * h->N * a.nrb * a.nstrip;
+    a.lper_xcd = (int)(((a.lunits + 3) / 4 + 7) / 8);
     a.rst = h->d_rst;
     a.pst = h->d_rst + B * N;
     a.st = h->d_st; a.work = h->d_work; a.iters = h->d_iters; a.rfin = h->d_rfin; a.ctr = h->d_ctr;
@@ -485,8 +492,9 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     return a;
 }
 
-// One streaming upper iteration of precision `prec` (18 launches with the
-// default schedule), queued on s.
+// One streaming upper iteration of precision `prec` (10 launches with the
+// default schedule: two sweeps per solve take the fused lower-layer pass),
+// queued on s.
 int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a, hipStream_t s)
 {
     const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
@@ -502,6 +510,29 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
         return NMPC_OK;
     };
     int rc;
+    if (h->opt.n_sweep == 2) {
+        // fused lower layer: one pass per Schur step and one for the final block
+        {
+            int which = 0;
+            void *args[] = {(void *)&a, (void *)&which};
+            if ((rc = go(k.bsep, stages, 256, args))) return rc;
+        }
+        {
+            void *args[] = {(void *)&a};
+            if ((rc = go(k.res, rows, 256, args, lds_res))) return rc;
+            if ((rc = go(k.stage, stages, 256, args))) return rc;
+            if ((rc = go(k.decide, inst, 256, args))) return rc;
+        }
+        const dim3 lower(8 * a.lper_xcd);
+        for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
+            const bool fin = sch == h->opt.n_schur;
+            void *args[] = {(void *)&a};
+            if ((rc = go(fin ? k.lower_fin : k.lower, lower, 256, args))) return rc;
+            if (!fin && (rc = go(k.v3f, stages, 256, args))) return rc;
+        }
+        void *args[] = {(void *)&a};
+        return go(k.advance, inst, 256, args);
+    }
     const int passes = 1 + std::max(0, h->opt.n_sweep - 2);
     const int y5_tmp = (passes - 1) & 1;
     {

@@ -600,6 +600,263 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
     }
 }
 
+// Fused Schur step (fin = 0, sgn = -1) or final block (fin = 1, sgn = +1) of
+// the lower layer for two point-Jacobi sweeps per solve, in one pass:
+//   c  = sgn (b1 - h B v3),  y1 = c / d,  y5 = (c - cpk N(y1)) / d       (F_x solve)
+//   c' = sgn b2 - A_xx y5,   z1 = cpk c' / d,  y4 = (c' - N(z1)) / d      (F_x^T solve)
+// then the partial sums of B^T y4 (Schur step) or the update
+// S^{k+1} = S^k - (y5, v3, y4) (final block). One wave per unit of
+// kLowerRows rows and a strip of 64 columns whose 58 inner lanes own their
+// column: horizontal neighbours come from the adjacent lanes (DPP wave
+// shifts), vertical ones from the rows the lane has already visited, so the
+// pass needs no LDS and no barrier. Each lane walks its column from three
+// rows above the block to three rows below; every quantity trails the row
+// being loaded by the rows its stencils need (y5 by 1, c' and z1 by 2, y4 by
+// 3). Outside the grid d^-1 = 0 makes every value zero, which is the
+// Dirichlet condition of the stencils. The halo lanes' values are wrong near
+// the strip ends, and only the inner lanes are used.
+template <typename T>
+__device__ __forceinline__ T wshl(T v);   // lane l gets lane l + 1 (0 at the end)
+template <typename T>
+__device__ __forceinline__ T wshr(T v);   // lane l gets lane l - 1 (0 at the start)
+template <>
+__device__ __forceinline__ float wshl<float>(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ float wshr<float>(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ double wshl<double>(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <>
+__device__ __forceinline__ double wshr<double>(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <typename T, bool FIN>
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const StreamArgs a)
+{
+    constexpr bool fin = FIN;
+    const int lane = threadIdx.x & (kWave - 1);
+    const long long g = (long long)(blockIdx.x & 7) * a.lper_xcd + (blockIdx.x >> 3);
+    const long long unit = g * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (unit >= a.lunits) return;
+    const int sp = (int)(unit % a.nstrip);
+    const long long t1 = unit / a.nstrip;
+    const int rb = (int)(t1 % a.nrb);
+    const long long bi = t1 / a.nrb;
+    const int b = (int)(bi / a.P.N);
+    if (!a.work[b]) return;
+    const DevProblem &P = a.P;
+    const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy, m = P.m;
+    const int ix = sp * kLowerCols - kLowerHalo + lane;
+    const bool col_in = ix >= 0 && ix < nsx;
+    const bool own = lane >= kLowerHalo && lane < kWave - kLowerHalo && col_in;
+    const int r0 = rb * kLowerRows;
+    const T sgn = fin ? T(1) : T(-1);
+    const T h = T(P.h), ax = T(P.idx2), ay = T(P.idy2), qw = T(P.q), c0 = T(P.c0);
+    const T *b1 = reinterpret_cast<const T *>(a.b1) + bi * n;
+    const T *b2 = reinterpret_cast<const T *>(a.b2) + bi * n;
+    const T *invd = reinterpret_cast<const T *>(a.invd) + bi * n;
+    const T *cpk = reinterpret_cast<const T *>(a.cpk) + bi * n;
+    const T *g2 = reinterpret_cast<const T *>(a.g2) + bi * n;
+    const int ixc = col_in ? ix : 0;   // in-range column for the factor tables
+    // column factor of B v3: scol[bb] = sum_a gx[a][ix] v3[bb lx + a] (v3 is
+    // exactly zero in the first Schur step, so c = sgn b1 there)
+    // this lane's gx column (zero past lx and outside the grid); every load
+    // below is independent and unrolled, so they are in flight together
+    T gxv[kMaxLx];
+#pragma unroll
+    for (int aa = 0; aa < kMaxLx; ++aa) {
+        const double g = a.gx[(aa < P.lx ? aa : 0) * nsx + ixc];
+        gxv[aa] = aa < P.lx && col_in ? T(g) : T(0);
+    }
+    // v3 (m <= 64 values): lane j loads v3[j], the others read it with readlane
+    T scol[kMaxLy];
+    {
+        const double v3l = lane < m ? a.v3[bi * m + lane] : 0.0;
+        const long long vb = __double_as_longlong(v3l);
+        const int vlo = (int)vb, vhi = (int)(vb >> 32);
+#pragma unroll
+        for (int bb = 0; bb < kMaxLy; ++bb) {
+            double s = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < kMaxLx; ++aa) {
+                const int j = bb < P.ly && aa < P.lx ? bb * P.lx + aa : 0;
+                const long long w = ((long long)__builtin_amdgcn_readlane(vhi, j) << 32) |
+                                    (long long)(unsigned)__builtin_amdgcn_readlane(vlo, j);
+                s += double(gxv[aa]) * __longlong_as_double(w);
+            }
+            scol[bb] = bb < P.ly ? T(s) : T(0);
+        }
+    }
+    // this wave's rows of the gy factors, zero-padded to kMaxLy lattice rows
+    // and outside the grid, in its own LDS slice (read back by the same wave)
+    constexpr int NR = kLowerRows + 2 * kLowerHalo;
+    __shared__ T gys[4][NR][kMaxLy];
+    T (*gyl)[kMaxLy] = gys[threadIdx.x / kWave];
+#pragma unroll
+    for (int it = 0; it < (NR * kMaxLy + kWave - 1) / kWave; ++it) {
+        const int e = lane + it * kWave;
+        const int rr = e / kMaxLy, bb = e - rr * kMaxLy, row = r0 - kLowerHalo + rr;
+        const bool ok = e < NR * kMaxLy && bb < P.ly && row >= 0 && row < nsy;
+        const double g = a.gy[ok ? bb * nsy + row : 0];
+        if (e < NR * kMaxLy) gyl[rr][bb] = ok ? T(g) : T(0);
+    }
+    const int cur = a.st[b].j & 1, nxt = cur ^ 1;
+    const double *xo = a.X[cur] + bi * n, *lo = a.LAM[cur] + bi * n;
+    double *xn = a.X[nxt] + bi * n, *ln = a.LAM[nxt] + bi * n;
+    T colsum[kMaxLy];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb) colsum[bb] = T(0);
+    // row windows (index: rows behind the row k loaded last)
+    T c_1 = 0, c_0 = 0;
+    T y1_2 = 0, y1_1 = 0, y1_0 = 0;
+    T y5_3 = 0, y5_2 = 0, y5_1 = 0;
+    T w_3 = 0, w_2 = 0, w_1 = 0;
+    T cp_3 = 0, cp_2 = 0;
+    T z_4 = 0, z_3 = 0, z_2 = 0;
+    T d_3 = 0, d_2 = 0, d_1 = 0, d_0 = 0;
+    T k_2 = 0, k_1 = 0, k_0 = 0;
+    T g_2 = 0, g_1 = 0, g_0 = 0;
+    T e_2 = 0, e_1 = 0, e_0 = 0;   // b2
+    // the rows' coefficients are loaded PF rows ahead of their use into a
+    // register ring; the loop runs in groups of PF rows with the group
+    // unrolled, so step t of a group reads ring slot t and refills it with
+    // the row PF steps ahead (no register moves of values still in flight)
+    constexpr int PF = 6;
+    static_assert((kLowerRows + 2 * kLowerHalo) % PF == 0, "whole groups of rows");
+    T qd[PF], qk[PF], qg[PF], qe[PF], qb[PF];
+    auto load_row = [&](int k, T &vd, T &vk, T &vg, T &ve, T &vb) {
+        const int kc = k >= 0 && k < nsy ? k : 0;   // in-range address, value masked later
+        const int pc = kc * nsx + ixc;
+        vd = invd[pc]; vk = cpk[pc]; vg = g2[pc]; ve = b2[pc]; vb = b1[pc];
+    };
+#pragma unroll
+    for (int t = 0; t < PF; ++t) load_row(r0 - kLowerHalo + t, qd[t], qk[t], qg[t], qe[t], qb[t]);
+#pragma unroll 1
+    for (int g0 = 0; g0 < kLowerRows + 2 * kLowerHalo; g0 += PF)
+#pragma unroll
+    for (int st = 0; st < PF; ++st) {
+        const int kk = g0 + st;
+        const int k = r0 - kLowerHalo + kk;
+        // shift the windows by one row
+        c_1 = c_0; y1_2 = y1_1; y1_1 = y1_0;
+        d_3 = d_2; d_2 = d_1; d_1 = d_0; k_2 = k_1; k_1 = k_0; g_2 = g_1; g_1 = g_0; e_2 = e_1; e_1 = e_0;
+        // row k from ring slot st; row k + PF refills it
+        const bool rin = k >= 0 && k < nsy, in = col_in && rin;
+        const T vd = qd[st], vk = qk[st], vg = qg[st], ve = qe[st], vb = qb[st];
+        load_row(k + PF, qd[st], qk[st], qg[st], qe[st], qb[st]);
+        T bu = 0;
+#pragma unroll
+        for (int bb = 0; bb < kMaxLy; ++bb) bu += gyl[kk][bb] * scol[bb];
+        d_0 = in ? vd : T(0);
+        k_0 = in ? vk : T(0);
+        g_0 = in ? vg : T(0);
+        e_0 = in ? ve : T(0);
+        c_0 = in ? sgn * (vb - h * bu) : T(0);
+        y1_0 = c_0 * d_0;
+        // y5 and w at row k - 1
+        if (kk >= 2) {
+            y5_3 = y5_2; y5_2 = y5_1; w_3 = w_2; w_2 = w_1;
+            const T nb = ax * (wshr(y1_1) + wshl(y1_1)) + ay * (y1_2 + y1_0);
+            y5_1 = (c_1 - k_1 * nb) * d_1;
+            w_1 = g_1 * y5_1;
+            if constexpr (FIN) {
+                const int r = k - 1;
+                const bool upd = own && r >= r0 && r < r0 + kLowerRows && r < nsy;
+                const int pu = (upd ? r : 0) * nsx + ixc;
+                const double xv = xo[pu];
+                if (upd) xn[pu] = xv - double(y5_1);
+            }
+        }
+        // c' and z1 at row k - 2
+        if (kk >= 4) {
+            cp_3 = cp_2; z_4 = z_3; z_3 = z_2;
+            const T n1 = ax * (wshr(y5_2) + wshl(y5_2)) + ay * (y5_3 + y5_1);
+            const T n2 = ax * (wshr(w_2) + wshl(w_2)) + ay * (w_3 + w_1);
+            const T Ay = h * ((qw - T(2) * c0 * g_2) * y5_2 + g_2 * n1 + n2);
+            cp_2 = sgn * e_2 - Ay;
+            z_2 = k_2 * cp_2 * d_2;
+        }
+        // y4 at row k - 3
+        if (kk >= 6) {
+            const T nb = ax * (wshr(z_3) + wshl(z_3)) + ay * (z_4 + z_2);
+            const T y4 = (cp_3 - nb) * d_3;
+            const int r = k - 3;
+            const bool upd = own && r < nsy;
+            if constexpr (FIN) {
+                const int pu = (upd ? r : 0) * nsx + ixc;
+                const double lv = lo[pu];
+                if (upd) ln[pu] = lv - double(y4);
+            } else {
+                const T y4o = upd ? y4 : T(0);
+#pragma unroll
+                for (int bb = 0; bb < kMaxLy; ++bb) colsum[bb] += gyl[kk - kLowerHalo][bb] * y4o;
+            }
+        }
+    }
+    const long long upart = (bi * a.nrb + rb) * a.nstrip + sp;
+    if constexpr (FIN) {
+        if (rb == 0 && sp == 0) {
+            const double *uc = a.U[cur] + bi * m;
+            double *un = a.U[nxt] + bi * m;
+            for (int j = lane; j < m; j += kWave) un[j] = uc[j] - a.v3[bi * m + j];
+        }
+        return;
+    }
+    // partial (B^T y4)_{bb lx + a} of this unit: sum over the owned columns of
+    // gx[a][ix] colsum[bb], reduced over the wave (m <= 64 values)
+    // lane j < m sums gx[a][column] colsum[bb] over the strip's owned lanes,
+    // read from this wave's LDS slice (rows padded to 65: no bank conflicts)
+    __shared__ T strip[4][2][kMaxLy][kWave + 1];
+    T (*cs)[kWave + 1] = strip[threadIdx.x / kWave][0];
+    T (*gs)[kWave + 1] = strip[threadIdx.x / kWave][1];
+#pragma unroll
+    for (int q = 0; q < kMaxLy; ++q) {
+        cs[q][lane] = own ? colsum[q] : T(0);
+        gs[q][lane] = gxv[q];
+    }
+    if (lane < m) {
+        const int bb = lane / P.lx, aa = lane - bb * P.lx;
+        T v = 0;
+        for (int l = 0; l < kWave; ++l) v += cs[bb][l] * gs[aa][l];
+        a.part[upart * kMaxM + lane] = double(v);
+    }
+}
+
+// v3 = (K^u + h B^T y4) / (h r + gamma) per stage from the fused pass's unit
+// partials. One workgroup (256 threads) per stage; thread j < m.
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
+{
+    const int bi = blockIdx.x;
+    if (bi >= a.count * a.P.N) return;
+    const int b = bi / a.P.N;
+    if (!a.work[b]) return;
+    const int j = threadIdx.x;
+    if (j >= a.P.m) return;
+    const int units = a.nrb * a.nstrip;
+    const double *pp = a.part + (size_t)bi * units * kMaxM + j;
+    double s = 0.0;
+    for (int u = 0; u < units; ++u) s += pp[(size_t)u * kMaxM];
+    const T auu = T(a.P.h * a.P.r + a.P.gamma), h = T(a.P.h);
+    a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * T(s)) / auu);
+}
+
 // j <- j + 1 for the instances that stepped (after every pass has used j).
 __global__ void k_st_advance(const StreamArgs a)
 {
@@ -621,6 +878,9 @@ StreamKernels stream_kernels(int prec)
         k.axx = (const void *)&k_st_axx<float>;
         k.jft = (const void *)&k_st_jft<float>;
         k.v3 = (const void *)&k_st_v3<float>;
+        k.lower = (const void *)&k_st_lower<float, false>;
+        k.lower_fin = (const void *)&k_st_lower<float, true>;
+        k.v3f = (const void *)&k_st_v3f<float>;
     } else {
         k.bsep = (const void *)&k_st_bsep<kModeFp64>;
         k.stage = (const void *)&k_st_stage<kModeFp64>;
@@ -630,6 +890,9 @@ StreamKernels stream_kernels(int prec)
         k.axx = (const void *)&k_st_axx<double>;
         k.jft = (const void *)&k_st_jft<double>;
         k.v3 = (const void *)&k_st_v3<double>;
+        k.lower = (const void *)&k_st_lower<double, false>;
+        k.lower_fin = (const void *)&k_st_lower<double, true>;
+        k.v3f = (const void *)&k_st_v3f<double>;
     }
     return k;
 }
