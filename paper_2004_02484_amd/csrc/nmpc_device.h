@@ -127,7 +127,8 @@ struct StreamArgs {
     unsigned long long *rown;       // [B][N][nsy][2] row maxima of |K^x|, |K^lambda|
     double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y
     unsigned long long *rst, *pst;  // [B][N] stage norms (bit patterns)
-    double *part;                   // [B][N][lower units per stage][kMaxM] partial B^T y4
+    double *part;                   // [B][N][units per stage][kMaxM] partial B^T lambda / y4
+    unsigned long long *unorm;      // [B][N][units per stage][2] partial max |K^x|, |K^lambda|
     int nstrip, nrb;                // lower pass: column strips and row blocks per stage
     long long lunits;               // lower pass: count * N * nrb * nstrip wave units
     int lper_xcd;                   // lower pass: workgroups per XCD run

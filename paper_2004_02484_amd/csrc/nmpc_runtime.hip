@@ -448,7 +448,7 @@ size_t stream_doubles(const nmpc_handle *h)
     const size_t lunits = (size_t)((h->prob.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols) *
                           ((h->prob.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows);
     return 10 * B * N * n + B * N * h->prob.ly * h->prob.nsx + 2 * B * N * m +
-           B * N * h->prob.nsy * (2 + nmpc::kMaxLx) + B * N * lunits * nmpc::kMaxM;
+           B * N * h->prob.nsy * (2 + nmpc::kMaxLx) + B * N * lunits * (nmpc::kMaxM + 2);
 }
 
 nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
@@ -476,9 +476,10 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.v3 = q; q += B * N * m;
     a.rown = reinterpret_cast<unsigned long long *>(q); q += 2 * B * N * p.nsy;
     a.rowt = q; q += B * N * p.nsy * nmpc::kMaxLx;
-    a.part = q;
     a.nstrip = (p.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols;
     a.nrb = (p.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows;
+    a.part = q; q += B * N * a.nrb * a.nstrip * nmpc::kMaxM;
+    a.unorm = reinterpret_cast<unsigned long long *>(q);
     a.lunits = (long long)count * h->N * a.nrb * a.nstrip;
     a.lper_xcd = (int)(((a.lunits + 3) / 4 + 7) / 8);
     a.rst = h->d_rst;
@@ -503,7 +504,7 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     // the sweep passes two (one for F_x^T) arrays of T
     const int tsz = prec == nmpc::kModeFp32 ? 4 : 8;
     const size_t lds = nmpc::stream_lds_bytes(h->prob.nsx, tsz, 2);
-    const size_t lds_res = nmpc::stream_lds_bytes(h->prob.nsx, 8, 2);
+    const dim3 lower(8 * a.lper_xcd);   // strip units (residual and fused lower passes)
     const size_t lds_jft = nmpc::stream_lds_bytes(h->prob.nsx, tsz, 1);
     auto go = [&](const void *fn, dim3 grid, int block, void **args, size_t sh = 0) -> int {
         HIP_TRY(hipLaunchKernel(fn, grid, dim3(block), args, sh, s));
@@ -513,17 +514,11 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     if (h->opt.n_sweep == 2) {
         // fused lower layer: one pass per Schur step and one for the final block
         {
-            int which = 0;
-            void *args[] = {(void *)&a, (void *)&which};
-            if ((rc = go(k.bsep, stages, 256, args))) return rc;
-        }
-        {
             void *args[] = {(void *)&a};
-            if ((rc = go(k.res, rows, 256, args, lds_res))) return rc;
+            if ((rc = go(k.res, lower, 256, args))) return rc;
             if ((rc = go(k.stage, stages, 256, args))) return rc;
             if ((rc = go(k.decide, inst, 256, args))) return rc;
         }
-        const dim3 lower(8 * a.lper_xcd);
         for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
             const bool fin = sch == h->opt.n_schur;
             void *args[] = {(void *)&a};
@@ -536,13 +531,8 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     const int passes = 1 + std::max(0, h->opt.n_sweep - 2);
     const int y5_tmp = (passes - 1) & 1;
     {
-        int which = 0;
-        void *args[] = {(void *)&a, (void *)&which};
-        if ((rc = go(k.bsep, stages, 256, args))) return rc;
-    }
-    {
         void *args[] = {(void *)&a};
-        if ((rc = go(k.res, rows, 256, args, lds_res))) return rc;
+        if ((rc = go(k.res, lower, 256, args))) return rc;
         if ((rc = go(k.stage, stages, 256, args))) return rc;
         if ((rc = go(k.decide, inst, 256, args))) return rc;
     }
@@ -815,7 +805,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
         const size_t lds = nmpc::stream_lds_bytes(prob->nsx);
         for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32}) {
             const nmpc::StreamKernels k = nmpc::stream_kernels(prec);
-            for (const void *fn : {k.res, k.jf, k.axx, k.jft})
+            for (const void *fn : {k.jf, k.axx, k.jft})
                 if (lds > 48 * 1024 &&
                     hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) {
                     release(h);
@@ -979,12 +969,8 @@ int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const d
     if (h->streaming) {   // residual passes of the streaming path (stage norms in rst / pst)
         const nmpc::StreamArgs a = stream_args(h, count);
         const nmpc::StreamKernels k = nmpc::stream_kernels(nmpc::kModeFp64);
-        int which = 0;
-        void *a1[] = {(void *)&a, (void *)&which};
         void *a2[] = {(void *)&a};
-        HIP_TRY(hipLaunchKernel(k.bsep, dim3(count * h->N), dim3(256), a1, 0, h->stream));
-        HIP_TRY(hipLaunchKernel(k.res, dim3(8 * a.per_xcd), dim3(256), a2,
-                                nmpc::stream_lds_bytes(h->prob.nsx), h->stream));
+        HIP_TRY(hipLaunchKernel(k.res, dim3(8 * a.lper_xcd), dim3(256), a2, 0, h->stream));
         HIP_TRY(hipLaunchKernel(k.stage, dim3(count * h->N), dim3(256), a2, 0, h->stream));
         rst = a.rst;
         pst = a.pst;

@@ -145,6 +145,39 @@ __device__ __forceinline__ unsigned long long wave_umax(unsigned long long v)
     return v;
 }
 
+// Wave-wide lane shifts (DPP wave_shl:1 / wave_shr:1): the value of the
+// next / previous lane, zero at the wave's end / start.
+template <typename T>
+__device__ __forceinline__ T wshl(T v);   // lane l gets lane l + 1 (0 at the end)
+template <typename T>
+__device__ __forceinline__ T wshr(T v);   // lane l gets lane l - 1 (0 at the start)
+template <>
+__device__ __forceinline__ float wshl<float>(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ float wshr<float>(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+template <>
+__device__ __forceinline__ double wshl<double>(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <>
+__device__ __forceinline__ double wshr<double>(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // Own rows of the block for this wave: rows iy0 + w, iy0 + w + 4, ... < nsy;
 // body(rr, iy) for each. Lanes then walk the columns inside body.
 template <typename F>
@@ -159,7 +192,8 @@ __device__ __forceinline__ void own_rows(const DevProblem &P, int iy0, F body)
 // sc[b][i][bb][ix] = sum_a gx[a][ix] v[b][i][bb * lx + a]  (which = 0: U of
 // the current iterate, for the instances this graph evaluates; 1: v3, for
 // those it steps); (B v)_p = sum_bb gy[bb][iy] sc[bb][ix]. One workgroup per
-// (instance, stage).
+// (instance, stage). Used by the multi-pass lower layer (more than two sweeps
+// per solve); the residual and fused passes form these sums themselves.
 template <int PREC>
 __global__ void k_st_bsep(const StreamArgs a, int which)
 {
@@ -212,72 +246,164 @@ __device__ __forceinline__ float st_recip<float>(double d) { return __builtin_am
 template <>
 __device__ __forceinline__ double st_recip<double>(double d) { return 1.0 / d; }
 
-// KKT rows, coefficients and row partials of S^j (FP64 arithmetic; the
-// right-hand sides and coefficients are stored in T for the lower layer).
-// LDS: x and g = k(x) lambda of the block rows and halo rows.
+// KKT rows of S^j (FP64), the lower layer's right-hand sides and
+// coefficients (stored in T) and the unit partials of the stage norms and of
+// B^T lambda. Units as in the lower-layer pass: one wave per strip of 58
+// owned columns and kLowerRows rows, each lane marching down its column from
+// one row above the block to one below; x and g = k(x) lambda of the row
+// above, the row and the row below stay in registers, horizontal neighbours
+// come from the adjacent lanes. Rows are loaded PFR rows ahead into a
+// register ring.
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_res(const StreamArgs a)
+__global__ void __launch_bounds__(256, 3) k_st_res(const StreamArgs a)
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const Block u = row_block(a);
-    if (!u.ok) return;
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const long long g = (long long)(blockIdx.x & 7) * a.lper_xcd + (blockIdx.x >> 3);
+    const long long unit = g * (blockDim.x / kWave) + wv;
+    if (unit >= a.lunits) return;
+    const int sp = (int)(unit % a.nstrip);
+    const long long t1 = unit / a.nstrip;
+    const int rb = (int)(t1 % a.nrb);
+    const long long bi = t1 / a.nrb;
+    const int b = (int)(bi / a.P.N), i = (int)(bi % a.P.N);
     constexpr int PREC = std::is_same<T, float>::value ? kModeFp32 : kModeFp64;
-    if (!evaluating<PREC>(a, u.b)) return;
+    if (!evaluating<PREC>(a, b)) return;
     const DevProblem &P = a.P;
-    const int n = P.nsx * P.nsy, nsx = P.nsx;
-    const size_t bi = (size_t)u.b * P.N + u.i;
-    const int cur = a.st[u.b].j & 1;
+    const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy;
+    const int ix = sp * kLowerCols - kLowerHalo + lane;
+    const bool col_in = ix >= 0 && ix < nsx;
+    const int ixc = col_in ? ix : 0;
+    const bool own = lane >= kLowerHalo && lane < kWave - kLowerHalo && col_in;
+    const int r0 = rb * kLowerRows;
+    const int cur = a.st[b].j & 1;
+    const bool last = i == P.N - 1;
     const double *x = a.X[cur] + bi * n, *lam = a.LAM[cur] + bi * n;
-    const double *xp = u.i == 0 ? a.x0 + (size_t)u.b * n : x - n;
-    const double *ln = lam + n;
-    const bool last = u.i == P.N - 1;
-    const double *xr = a.xref + (size_t)u.b * a.xref_inst_stride + (size_t)u.i * a.xref_stage_stride;
+    const double *xp = i == 0 ? a.x0 + (size_t)b * n : x - n;
+    const double *ln = last ? lam : lam + n;   // not read at the last stage (value 0)
+    const double *xr = a.xref + (size_t)b * a.xref_inst_stride + (size_t)i * a.xref_stage_stride;
     T *b1 = reinterpret_cast<T *>(a.b1) + bi * n, *b2 = reinterpret_cast<T *>(a.b2) + bi * n;
     T *invd = reinterpret_cast<T *>(a.invd) + bi * n, *cpk = reinterpret_cast<T *>(a.cpk) + bi * n;
     T *g2 = reinterpret_cast<T *>(a.g2) + bi * n;
-    const double h = P.h, kp = P.k0 * P.k1;
+    const double h = P.h, kp = P.k0 * P.k1, ax = P.idx2, ay = P.idy2;
     auto K = [&](double w) { return P.k0 * (1.0 + P.k1 * w); };
-    double *xs = reinterpret_cast<double *>(lds_raw);
-    double *gs = xs + (kRows + 2) * nsx;
-    for_staged(P, u.iy0, no_col, [&](int e, int iy, int ix, bool in, NoCol) {
-        const int q = iy * nsx + ix;
-        const double xv = in ? x[q] : 0.0, lv = in ? lam[q] : 0.0;
-        xs[e] = xv;
-        gs[e] = K(xv) * lv;
-    });
-    __syncthreads();
-    const int lane = threadIdx.x & (kWave - 1);
-    own_rows(P, u.iy0, [&](int rr, int iy) {
-        unsigned long long mx = 0, ml = 0;
-        double tl[kMaxLx];
-        for (int q = 0; q < P.lx; ++q) tl[q] = 0.0;
-        for (int ix = lane; ix < nsx; ix += kWave) {
-            const int p = iy * nsx + ix, e = (rr + 1) * nsx + ix;
-            const double xc = xs[e], lc = lam[p];
-            const double Lx = lds_nb(xs, nsx, rr, ix, P.idx2, P.idy2) - P.c0 * xc;
-            const double Lg = lds_nb(gs, nsx, rr, ix, P.idx2, P.idy2) - P.c0 * gs[e];
-            const double kl = (last ? 0.0 : ln[p]) - lc + h * (P.q * (xc - xr[p]) + Lg + kp * Lx * lc);
-            const double kx = xp[p] - xc + h * (K(xc) * Lx + bsep_at(a, bi, iy, ix));
-            mx = sumax(mx, sabits(kx));
-            ml = sumax(ml, sabits(kl));
-            b1[p] = T(kx);
-            b2[p] = T(kl);
-            const double d = -1.0 - h * K(xc) * P.c0 + h * kp * Lx;
-            invd[p] = st_recip<T>(d);
-            cpk[p] = T(h * K(xc));
-            g2[p] = T(kp * lc);
-            for (int q = 0; q < P.lx; ++q) tl[q] += a.gx[q * nsx + ix] * lc;
+    // this lane's column sums of B u and gx column; this wave's gy rows in LDS
+    // scb[bb] = sum_a gx[a][ix] u[bb lx + a] (the column factor of B u): lane
+    // j holds u_j, the others read it with readlane
+    double scb[kMaxLy];
+    {
+        const double ul = lane < P.m ? a.U[cur][bi * P.m + lane] : 0.0;
+        const long long ub = __double_as_longlong(ul);
+        const int ulo = (int)ub, uhi = (int)(ub >> 32);
+        double gxv[kMaxLx];
+#pragma unroll
+        for (int aa = 0; aa < kMaxLx; ++aa) {
+            const double gv = a.gx[(aa < P.lx ? aa : 0) * nsx + ixc];
+            gxv[aa] = aa < P.lx && col_in ? gv : 0.0;
         }
-        const size_t ru = bi * P.nsy + iy;
-        mx = wave_umax(mx);
-        ml = wave_umax(ml);
-        for (int q = 0; q < P.lx; ++q) tl[q] = wave_sum(tl[q]);
-        if (lane == 0) {
-            a.rown[2 * ru] = mx;
-            a.rown[2 * ru + 1] = ml;
-            for (int q = 0; q < P.lx; ++q) a.rowt[ru * kMaxLx + q] = tl[q];
+#pragma unroll
+        for (int bb = 0; bb < kMaxLy; ++bb) {
+            double sum = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < kMaxLx; ++aa) {
+                const int j = bb < P.ly && aa < P.lx ? bb * P.lx + aa : 0;
+                const long long w = ((long long)__builtin_amdgcn_readlane(uhi, j) << 32) |
+                                    (long long)(unsigned)__builtin_amdgcn_readlane(ulo, j);
+                sum += gxv[aa] * __longlong_as_double(w);
+            }
+            scb[bb] = bb < P.ly ? sum : 0.0;
         }
-    });
+    }
+    constexpr int NR = kLowerRows + 2;   // rows r0 - 1 .. r0 + kLowerRows
+    constexpr int SLICE = 2 * kMaxLy * (kWave + 1);   // doubles per wave (>= NR kMaxLy)
+    static_assert(NR * kMaxLy <= SLICE, "gy rows fit the wave's slice");
+    __shared__ double slice[4][SLICE];
+    double *gyl = slice[wv];   // [NR][kMaxLy], then [2][kMaxLy][65] for the partials
+#pragma unroll
+    for (int it = 0; it < (NR * kMaxLy + kWave - 1) / kWave; ++it) {
+        const int e = lane + it * kWave;
+        const int rr = e / kMaxLy, bb = e - rr * kMaxLy, row = r0 - 1 + rr;
+        const bool ok = e < NR * kMaxLy && bb < P.ly && row >= 0 && row < nsy;
+        const double v = a.gy[ok ? bb * nsy + row : 0];
+        if (e < NR * kMaxLy) gyl[e] = ok ? v : 0.0;
+    }
+    constexpr int PFR = 2;
+    static_assert(NR % PFR == 0, "whole groups of rows");
+    double qx[PFR], ql[PFR], qp[PFR], qn[PFR], qr[PFR];
+    auto load_row = [&](int k, double &vx, double &vl, double &vp, double &vn, double &vr) {
+        const int pc = (k >= 0 && k < nsy ? k : 0) * nsx + ixc;
+        vx = x[pc]; vl = lam[pc]; vp = xp[pc]; vn = ln[pc]; vr = xr[pc];
+    };
+#pragma unroll
+    for (int t = 0; t < PFR; ++t) load_row(r0 - 1 + t, qx[t], ql[t], qp[t], qn[t], qr[t]);
+    double x_2 = 0, x_1 = 0, x_0 = 0, g_2 = 0, g_1 = 0, g_0 = 0;
+    double l_1 = 0, l_0 = 0, p_1 = 0, p_0 = 0, n_1 = 0, n_0 = 0, r_1 = 0, r_0 = 0;
+    unsigned long long mx = 0, ml = 0;
+    double cl[kMaxLy];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb) cl[bb] = 0.0;
+#pragma unroll 1
+    for (int g0 = 0; g0 < NR; g0 += PFR)
+#pragma unroll
+    for (int st = 0; st < PFR; ++st) {
+        const int kk = g0 + st, k = r0 - 1 + kk;
+        x_2 = x_1; x_1 = x_0; g_2 = g_1; g_1 = g_0;
+        l_1 = l_0; p_1 = p_0; n_1 = n_0; r_1 = r_0;
+        const bool in = col_in && k >= 0 && k < nsy;
+        const double vx = qx[st], vl = ql[st], vp = qp[st], vn = qn[st], vr = qr[st];
+        load_row(k + PFR, qx[st], ql[st], qp[st], qn[st], qr[st]);
+        x_0 = in ? vx : 0.0;
+        l_0 = in ? vl : 0.0;
+        p_0 = vp; n_0 = last ? 0.0 : vn; r_0 = vr;
+        g_0 = K(x_0) * l_0;
+        if (kk >= 2) {   // row r = k - 1 of the block
+            const int r = k - 1;
+            const double Lx = ax * (wshr(x_1) + wshl(x_1)) + ay * (x_2 + x_0) - P.c0 * x_1;
+            const double Lg = ax * (wshr(g_1) + wshl(g_1)) + ay * (g_2 + g_0) - P.c0 * g_1;
+            double bu = 0.0;
+#pragma unroll
+            for (int bb = 0; bb < kMaxLy; ++bb) bu += gyl[(kk - 1) * kMaxLy + bb] * scb[bb];
+            const double kl = n_1 - l_1 + h * (P.q * (x_1 - r_1) + Lg + kp * Lx * l_1);
+            const double kx = p_1 - x_1 + h * (K(x_1) * Lx + bu);
+            const bool ok = own && r < nsy;
+            const unsigned long long ax_ = sabits(kx), al_ = sabits(kl);
+            mx = ok && ax_ > mx ? ax_ : mx;
+            ml = ok && al_ > ml ? al_ : ml;
+            const double lv = ok ? l_1 : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < kMaxLy; ++bb) cl[bb] += gyl[(kk - 1) * kMaxLy + bb] * lv;
+            if (ok) {
+                const int p = r * nsx + ix;
+                b1[p] = T(kx);
+                b2[p] = T(kl);
+                const double d = -1.0 - h * K(x_1) * P.c0 + h * kp * Lx;
+                invd[p] = st_recip<T>(d);
+                cpk[p] = T(h * K(x_1));
+                g2[p] = T(kp * l_1);
+            }
+        }
+    }
+    // unit partials: norms (wave maxima) and B^T lambda over the owned lanes
+    const long long upart = (bi * a.nrb + rb) * a.nstrip + sp;
+    mx = wave_umax(mx);
+    ml = wave_umax(ml);
+    if (lane == 0) {
+        a.unorm[2 * upart] = mx;
+        a.unorm[2 * upart + 1] = ml;
+    }
+    double (*cs)[kWave + 1] = reinterpret_cast<double (*)[kWave + 1]>(gyl);
+    double (*gs)[kWave + 1] = cs + kMaxLy;
+#pragma unroll
+    for (int q = 0; q < kMaxLy; ++q) {
+        cs[q][lane] = own ? cl[q] : 0.0;
+        const double gv = a.gx[(q < P.lx ? q : 0) * nsx + ixc];
+        gs[q][lane] = q < P.lx && col_in ? gv : 0.0;
+    }
+    if (lane < P.m) {
+        const int bb = lane / P.lx, aa = lane - bb * P.lx;
+        double v = 0.0;
+        for (int l = 0; l < kWave; ++l) v += cs[bb][l] * gs[aa][l];
+        a.part[upart * kMaxM + lane] = v;
+    }
 }
 
 // (B^T y)_{bb*lx+a} of stage bi from its rows' partials sum_ix gx[a][ix] y,
@@ -301,31 +427,33 @@ __device__ __forceinline__ double bt_from_rows(const StreamArgs &a, size_t bi, d
     return tot;
 }
 
-// K^u, the stage's norms and v3 = 0. One workgroup (256 threads) per stage.
+// K^u, the stage's norms and v3 = 0 from the residual pass's unit partials.
+// One workgroup (256 threads) per stage.
 template <int PREC>
 __global__ void __launch_bounds__(256) k_st_stage(const StreamArgs a)
 {
-    __shared__ double sh[256];
     __shared__ unsigned long long shn[2 * kMaxWaves];
     const int bi = blockIdx.x;
     if (bi >= a.count * a.P.N) return;
     const int b = bi / a.P.N;
     if (!evaluating<PREC>(a, b)) return;
     const DevProblem &P = a.P;
-    const int m = P.m;
+    const int m = P.m, units = a.nrb * a.nstrip;
     const int cur = a.st[b].j & 1;
     unsigned long long mu = 0, mx = 0, ml = 0;
-    const double bt = bt_from_rows(a, bi, sh);
     if (threadIdx.x < m) {
         const int j = threadIdx.x;
+        const double *pp = a.part + (size_t)bi * units * kMaxM + j;
+        double bt = 0.0;
+        for (int u = 0; u < units; ++u) bt += pp[(size_t)u * kMaxM];
         const double ku = P.h * (P.r * a.U[cur][(size_t)bi * m + j] + bt);
         a.kun[(size_t)bi * m + j] = ku;
         a.v3[(size_t)bi * m + j] = 0.0;
         mu = sabits(ku);
     }
-    for (int iy = threadIdx.x; iy < P.nsy; iy += blockDim.x) {
-        mx = sumax(mx, a.rown[2 * ((size_t)bi * P.nsy + iy)]);
-        ml = sumax(ml, a.rown[2 * ((size_t)bi * P.nsy + iy) + 1]);
+    for (int u = threadIdx.x; u < units; u += blockDim.x) {
+        mx = sumax(mx, a.unorm[2 * ((size_t)bi * units + u)]);
+        ml = sumax(ml, a.unorm[2 * ((size_t)bi * units + u) + 1]);
     }
     mx = wave_umax(mx);
     ml = wave_umax(ml);
@@ -615,37 +743,6 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 // 3). Outside the grid d^-1 = 0 makes every value zero, which is the
 // Dirichlet condition of the stencils. The halo lanes' values are wrong near
 // the strip ends, and only the inner lanes are used.
-template <typename T>
-__device__ __forceinline__ T wshl(T v);   // lane l gets lane l + 1 (0 at the end)
-template <typename T>
-__device__ __forceinline__ T wshr(T v);   // lane l gets lane l - 1 (0 at the start)
-template <>
-__device__ __forceinline__ float wshl<float>(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
-}
-template <>
-__device__ __forceinline__ float wshr<float>(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
-}
-template <>
-__device__ __forceinline__ double wshl<double>(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-template <>
-__device__ __forceinline__ double wshr<double>(double v)
-{
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 template <typename T, bool FIN>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const StreamArgs a)
 {
@@ -839,7 +936,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const 
 }
 
 // v3 = (K^u + h B^T y4) / (h r + gamma) per stage from the fused pass's unit
-// partials. One workgroup (256 threads) per stage; thread j < m.
+// partials (in unit order). One workgroup (256 threads) per stage; thread j < m.
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
 {
