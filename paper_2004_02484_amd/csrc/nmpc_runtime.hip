@@ -517,7 +517,7 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
             void *args[] = {(void *)&a};
             if ((rc = go(k.res, lower, 256, args))) return rc;
             if ((rc = go(k.stage, stages, 256, args))) return rc;
-            if ((rc = go(k.decide, inst, 256, args))) return rc;
+            if ((rc = go(k.decide, dim3(a.count), nmpc::kWave, args))) return rc;
         }
         for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
             const bool fin = sch == h->opt.n_schur;
@@ -534,7 +534,7 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
         void *args[] = {(void *)&a};
         if ((rc = go(k.res, lower, 256, args))) return rc;
         if ((rc = go(k.stage, stages, 256, args))) return rc;
-        if ((rc = go(k.decide, inst, 256, args))) return rc;
+        if ((rc = go(k.decide, dim3(a.count), nmpc::kWave, args))) return rc;
     }
     for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
         const bool fin = sch == h->opt.n_schur;   // the final block after the Schur loop

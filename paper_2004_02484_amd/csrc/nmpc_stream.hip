@@ -445,6 +445,7 @@ __global__ void __launch_bounds__(256) k_st_stage(const StreamArgs a)
         const int j = threadIdx.x;
         const double *pp = a.part + (size_t)bi * units * kMaxM + j;
         double bt = 0.0;
+#pragma unroll 8
         for (int u = 0; u < units; ++u) bt += pp[(size_t)u * kMaxM];
         const double ku = P.h * (P.r * a.U[cur][(size_t)bi * m + j] + bt);
         a.kun[(size_t)bi * m + j] = ku;
@@ -486,16 +487,22 @@ __global__ void __launch_bounds__(256) k_st_stage(const StreamArgs a)
 template <int PREC>
 __global__ void k_st_decide(const StreamArgs a)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per instance: the lanes take the stage maxima, lane 0 decides
+    const int b = blockIdx.x, lane = threadIdx.x;
     if (b >= a.count) return;
-    a.work[b] = 0;
-    if (!evaluating<PREC>(a, b)) return;
-    InstState s = a.st[b];
+    if (!evaluating<PREC>(a, b)) {
+        if (lane == 0) a.work[b] = 0;
+        return;
+    }
     unsigned long long ms = 0, mp = 0;
-    for (int i = 0; i < a.P.N; ++i) {
+    for (int i = lane; i < a.P.N; i += kWave) {
         ms = sumax(ms, a.rst[(size_t)b * a.P.N + i]);
         mp = sumax(mp, a.pst[(size_t)b * a.P.N + i]);
     }
+    ms = wave_umax(ms);
+    mp = wave_umax(mp);
+    if (lane != 0) return;
+    InstState s = a.st[b];
     const double rs = sbits2d(ms), rp = sbits2d(mp);
     const bool was32 = s.mode == kModeFp32;
     int fin = -1, work = 0;
@@ -949,6 +956,7 @@ __global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
     const int units = a.nrb * a.nstrip;
     const double *pp = a.part + (size_t)bi * units * kMaxM + j;
     double s = 0.0;
+#pragma unroll 8
     for (int u = 0; u < units; ++u) s += pp[(size_t)u * kMaxM];
     const T auu = T(a.P.h * a.P.r + a.P.gamma), h = T(a.P.h);
     a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * T(s)) / auu);
