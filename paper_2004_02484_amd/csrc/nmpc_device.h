@@ -124,8 +124,7 @@ struct StreamArgs {
     double *b1, *b2, *invd, *cpk, *g2, *y5, *ytmp, *y4, *y4tmp, *cp;
     double *sc;                     // [B][N][ly][nsx] column sums of B v
     double *kun, *v3;               // [B][N][m]
-    unsigned long long *rown;       // [B][N][nsy][2] row maxima of |K^x|, |K^lambda|
-    double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y
+    double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y4 (multi-pass)
     unsigned long long *rst, *pst;  // [B][N] stage norms (bit patterns)
     double *part;                   // [B][N][units per stage][kMaxM] partial B^T lambda / y4
     unsigned long long *unorm;      // [B][N][units per stage][2] partial max |K^x|, |K^lambda|

@@ -448,7 +448,7 @@ size_t stream_doubles(const nmpc_handle *h)
     const size_t lunits = (size_t)((h->prob.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols) *
                           ((h->prob.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows);
     return 10 * B * N * n + B * N * h->prob.ly * h->prob.nsx + 2 * B * N * m +
-           B * N * h->prob.nsy * (2 + nmpc::kMaxLx) + B * N * lunits * (nmpc::kMaxM + 2);
+           B * N * h->prob.nsy * nmpc::kMaxLx + B * N * lunits * (nmpc::kMaxM + 2);
 }
 
 nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
@@ -474,7 +474,6 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.sc = q; q += B * N * p.ly * p.nsx;
     a.kun = q; q += B * N * m;
     a.v3 = q; q += B * N * m;
-    a.rown = reinterpret_cast<unsigned long long *>(q); q += 2 * B * N * p.nsy;
     a.rowt = q; q += B * N * p.nsy * nmpc::kMaxLx;
     a.nstrip = (p.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols;
     a.nrb = (p.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows;

@@ -1,21 +1,23 @@
 // nmpc_stream.hip -- streaming kernels of the Jacobi upper iteration for grids
-// whose stage does not fit one workgroup (e.g. 256 x 256): every step of the
-// stage algebra is a pass over all (instance, stage, block of grid rows)
-// units, with stencil inputs staged in LDS per block and per-row partial
+// whose stage does not fit one workgroup (e.g. 256 x 256): each step of the
+// stage algebra is a pass over all stages of the batch, with per-unit partial
 // reductions combined by small per-stage kernels.
 //
 // One upper iteration (eq. 1st_jacobi, alpha = 1), per instance and stage i:
-//   K_res    KKT rows K^x, K^lambda (FP64), stage coefficients, row partials
+//   res      KKT rows K^x, K^lambda (FP64), stage coefficients, unit partials
 //            of the norms and of B^T lambda
-//   K_stage  K^u = h (r u + B^T lambda), the stage's norms, v3 = 0
+//   stage    K^u = h (r u + B^T lambda), the stage's norms, v3 = 0
 //   decide   per-instance state machine (test, phases, max_iter)
 //   Schur iterations (Sec. 5.2):  y5 = JacF(h B v3 - b1); c' = -b2 - A_xx y5;
-//            y4 = JacFT(c'), row partials of B^T y4; v3 = (K^u + h B^T y4)/A_uu
+//            y4 = JacFT(c'), partials of B^T y4; v3 = (K^u + h B^T y4)/A_uu
 //   final:   y5 = JacF(b1 - h B v3); y4 = JacFT(b2 - A_xx y5);
 //            S^{k+1} = S^k - (y5, v3, y4)
-// A point-Jacobi solve with n_sweep sweeps from zero is one pass for the
-// first two sweeps (the first sweep's values are formed in LDS for the block
-// and its halo rows) and one pass per further sweep.
+// With two point-Jacobi sweeps per solve (the default) the residual pass and
+// each Schur step / final block are single marching-strip passes (one wave
+// per strip of columns and block of rows, stencils in registers and lane
+// shifts, no LDS stencils or barriers). Other sweep counts use row-block
+// passes with LDS-staged stencils: a solve is one pass for its first two
+// sweeps and one per further sweep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
