@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 // Dirichlet condition of the stencils. The halo lanes' values are wrong near
 // the strip ends, and only the inner lanes are used.
 template <typename T, bool FIN>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const StreamArgs a)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_lower(const StreamArgs a)
 {
     constexpr bool fin = FIN;
     const int lane = threadIdx.x & (kWave - 1);
@@ -846,13 +846,19 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const 
     constexpr int PF = 6;
     static_assert((kLowerRows + 2 * kLowerHalo) % PF == 0, "whole groups of rows");
     T qd[PF], qk[PF], qg[PF], qe[PF], qb[PF];
-    auto load_row = [&](int k, T &vd, T &vk, T &vg, T &ve, T &vb) {
+    double qx[PF], ql[PF];   // final block: x and lambda of the row (for the update)
+    auto load_row = [&](int k, int t) {
         const int kc = k >= 0 && k < nsy ? k : 0;   // in-range address, value masked later
         const int pc = kc * nsx + ixc;
-        vd = invd[pc]; vk = cpk[pc]; vg = g2[pc]; ve = b2[pc]; vb = b1[pc];
+        qd[t] = invd[pc]; qk[t] = cpk[pc]; qg[t] = g2[pc]; qe[t] = b2[pc]; qb[t] = b1[pc];
+        if constexpr (FIN) {
+            qx[t] = xo[pc];
+            ql[t] = lo[pc];
+        }
     };
 #pragma unroll
-    for (int t = 0; t < PF; ++t) load_row(r0 - kLowerHalo + t, qd[t], qk[t], qg[t], qe[t], qb[t]);
+    for (int t = 0; t < PF; ++t) load_row(r0 - kLowerHalo + t, t);
+    double xw_1 = 0, xw_0 = 0, lw_3 = 0, lw_2 = 0, lw_1 = 0, lw_0 = 0;
 #pragma unroll 1
     for (int g0 = 0; g0 < kLowerRows + 2 * kLowerHalo; g0 += PF)
 #pragma unroll
@@ -865,7 +871,12 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const 
         // row k from ring slot st; row k + PF refills it
         const bool rin = k >= 0 && k < nsy, in = col_in && rin;
         const T vd = qd[st], vk = qk[st], vg = qg[st], ve = qe[st], vb = qb[st];
-        load_row(k + PF, qd[st], qk[st], qg[st], qe[st], qb[st]);
+        if constexpr (FIN) {
+            xw_1 = xw_0; lw_3 = lw_2; lw_2 = lw_1; lw_1 = lw_0;
+            xw_0 = qx[st];
+            lw_0 = ql[st];
+        }
+        load_row(k + PF, st);
         T bu = 0;
 #pragma unroll
         for (int bb = 0; bb < kMaxLy; ++bb) bu += gyl[kk][bb] * scol[bb];
@@ -883,10 +894,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const 
             w_1 = g_1 * y5_1;
             if constexpr (FIN) {
                 const int r = k - 1;
-                const bool upd = own && r >= r0 && r < r0 + kLowerRows && r < nsy;
-                const int pu = (upd ? r : 0) * nsx + ixc;
-                const double xv = xo[pu];
-                if (upd) xn[pu] = xv - double(y5_1);
+                if (own && r >= r0 && r < r0 + kLowerRows && r < nsy) xn[r * nsx + ix] = xw_1 - double(y5_1);
             }
         }
         // c' and z1 at row k - 2
@@ -905,9 +913,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 4 : 2) k_st_lower(const 
             const int r = k - 3;
             const bool upd = own && r < nsy;
             if constexpr (FIN) {
-                const int pu = (upd ? r : 0) * nsx + ixc;
-                const double lv = lo[pu];
-                if (upd) ln[pu] = lv - double(y4);
+                if (upd) ln[r * nsx + ix] = lw_3 - double(y4);
             } else {
                 const T y4o = upd ? y4 : T(0);
 #pragma unroll
