@@ -304,18 +304,50 @@ int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32
                    float *C, int32_t ldc, const float *bias, int32_t relu, uint16_t *Cb,
                    int32_t ldcb, void *stream);
 
-/* Network input rows: for each instance and each actuator p = pb*L + pa of an
- * L x L lattice on an ns x ns grid, a win x win window of x0/0.1 - 1 and of
- * xref/0.3 (2 win^2 values, zero outside the grid) starting (win - ns/L)/2
- * nodes before the actuator's cell, then a one-hot of p (L^2 values), then
- * zeros up to ld. x0, xref: [count][ns*ns]; out: [count*L^2][ld] bf16;
- * out_lo (may be NULL): bf16 of (value - out), the low part of a split. */
-int nmpc_net_windows(const double *x0, const double *xref, int32_t count, int32_t ns,
-                     int32_t lattice, int32_t win, uint16_t *out, uint16_t *out_lo, int32_t ld,
-                     void *stream);
+/* C_g = beta C_g + op(A_g) B_g for groups g = 0 .. groups-1, fp32 operands
+ * on the matrix cores with fp32 accumulation (the network's per-actuator
+ * linear map needs more significant bits than bf16 carries). X_g = X + g *
+ * stride_x (elements). A_g(m,k) is A_g[m*lda + k] (trans_a = 0) or
+ * A_g[k*lda + m]; B_g(k,n) = B_g[k*ldb + n]; C_g is M x N with row stride ldc.
+ * The forward map uses trans_a = 0, its weight gradient trans_a = 1. */
+int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A, int32_t lda,
+                  int64_t stride_a, const float *B, int32_t ldb, int64_t stride_b, float beta,
+                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, void *stream);
 
-/* hi = bf16(x), lo = bf16(x - hi) (split operands for higher-precision products). */
-int nmpc_split_bf16(const float *x, uint16_t *hi, uint16_t *lo, int64_t n, void *stream);
+/* The same grouped product with fp64 products and accumulation: C_g =
+ * alpha op(A_g) B_g + beta Cin_g (Cin = C when NULL; Cin_g and C_g share
+ * stride_c and ldc) on fp64 operands (nmpc_gemm_f64), or C_g = op(A_g) B_g +
+ * beta C_g on fp32 operands with an fp64 result (nmpc_gemm_f32_acc64: the
+ * Gram matrices X^T X and X^T T of fp32 feature rows). Used to fit the
+ * network's per-actuator linear map by its normal equations. */
+int nmpc_gemm_f64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const double *A, int32_t lda,
+                  int64_t stride_a, const double *B, int32_t ldb, int64_t stride_b, double alpha,
+                  double beta, const double *Cin, double *C, int32_t ldc, int64_t stride_c,
+                  int32_t groups, void *stream);
+int nmpc_gemm_f32_acc64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A,
+                        int32_t lda, int64_t stride_a, const float *B, int32_t ldb,
+                        int64_t stride_b, double beta, double *C, int32_t ldc, int64_t stride_c,
+                        int32_t groups, void *stream);
+
+/* Start of the Newton-Schulz inverse of ridge-regularized Gram matrices: for
+ * each group g, G_g (n x n, row stride ld, symmetric positive semidefinite)
+ * gets ridge_rel * trace(G_g) / n added to its diagonal, and X_g (n x n, row
+ * stride ld) is set to I / trace(G_g) (after the ridge). Iterating
+ * X <- 2 X - X (G X) with nmpc_gemm_f64 then converges to G^{-1}. */
+int nmpc_ls_prepare(double *G, int32_t n, int32_t ld, int64_t stride_g, double ridge_rel,
+                    double *X, int64_t stride_x, int32_t groups, void *stream);
+
+/* Network input rows: for each instance b and each actuator p = pb*L + pa of
+ * an L x L lattice on an ns x ns grid, row b*L^2 + p holds a win x win window
+ * (starting (win - ns/L)/2 nodes before the actuator's cell, zero outside the
+ * grid) of each feature plane, then a one-hot of p (L^2 values), then zeros
+ * up to ld. With xt = x0/0.1 - 1 and rt = xref/0.3 the planes are xt, rt
+ * (planes = 2) followed by xt^2 - 1/3, xt*rt, rt^2 - 1/3 (planes = 5).
+ * x0, xref: [count][ns*ns]; Xf: fp32 rows and/or Xb: bf16 rows (either may
+ * be NULL), both [count*L^2][ld]. */
+int nmpc_net_features(const double *x0, const double *xref, int32_t count, int32_t ns,
+                      int32_t lattice, int32_t win, int32_t planes, float *Xf, uint16_t *Xb,
+                      int32_t ld, void *stream);
 
 /* dh[i] = h[i] > 0 ? dh[i] : 0 (in place), dhb = bf16(dh). */
 int nmpc_relu_grad(float *dh, const float *h, uint16_t *dhb, int64_t n, void *stream);

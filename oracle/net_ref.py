@@ -1,8 +1,9 @@
 """FP64 numpy reference of the warm-start patch encoder (test infrastructure).
 
 Same layer structure as the library's network, written with numpy slicing and
-matrix products: window rows, three ReLU layers, an output layer plus a
-linear skip, mean squared error, and the hand-derived backward pass. Its
+matrix products: window rows of first- and second-order feature planes, three
+ReLU layers and an output layer, plus a per-actuator linear map of the rows;
+mean squared error and the hand-derived backward pass. Its
 gradients are pinned against central differences of its own forward pass in
 the CPU tests; the GPU kernels are compared against it.
 """
@@ -11,21 +12,27 @@ from __future__ import annotations
 import numpy as np
 
 
-def windows(x0, xref, ns=64, lattice=4, win=24, ld=None):
-    """Rows [count * L^2][ld]: window of x0/0.1 - 1 and xref/0.3 around each
-    actuator (zero outside the grid), one-hot actuator index, zero padding."""
+def features(x0, xref, ns=64, lattice=4, win=32, planes=5, ld=None):
+    """Rows [count * L^2][ld]: for each actuator, a win x win window (starting
+    (win - ns/L)/2 nodes before its cell, zero outside the grid) of each
+    feature plane of xt = x0/0.1 - 1 and rt = xref/0.3 -- xt, rt and, with
+    planes = 5, xt^2 - 1/3, xt rt, rt^2 - 1/3 -- then a one-hot actuator
+    index, then zero padding."""
     x0 = np.asarray(x0, float).reshape(-1, ns, ns)
     xref = np.asarray(xref, float).reshape(-1, ns, ns)
     count, L = x0.shape[0], lattice
     s = ns // L
     off = (win - s) // 2
-    feat = 2 * win * win
+    feat = planes * win * win
     ld = ld or feat + L * L
     out = np.zeros((count * L * L, ld))
+    xt = x0 / 0.1 - 1.0
+    rt = xref / 0.3
+    fields = [xt, rt, xt * xt - 1.0 / 3.0, xt * rt, rt * rt - 1.0 / 3.0][:planes]
     pad = win + s
-    big = np.zeros((count, 2, ns + 2 * pad, ns + 2 * pad))
-    big[:, 0, pad:pad + ns, pad:pad + ns] = x0 / 0.1 - 1.0
-    big[:, 1, pad:pad + ns, pad:pad + ns] = xref / 0.3
+    big = np.zeros((count, planes, ns + 2 * pad, ns + 2 * pad))
+    for c, f in enumerate(fields):
+        big[:, c, pad:pad + ns, pad:pad + ns] = f
     for b in range(count):
         for p in range(L * L):
             y0 = (p // L) * s - off + pad
@@ -35,14 +42,26 @@ def windows(x0, xref, ns=64, lattice=4, win=24, ld=None):
     return out
 
 
-def forward(params, X):
-    """Returns (Y, cache). params: W1 [K][H], b1, W2, b2, W3, b3, W4 [H][N], b4, Ws [K][N]."""
+def skip(Ws, X):
+    """Per-actuator linear map: row r (actuator r mod m) times Ws[r mod m]."""
+    m = Ws.shape[0]
+    Y = np.empty((X.shape[0], Ws.shape[2]))
+    for p in range(m):
+        Y[p::m] = X[p::m] @ Ws[p]
+    return Y
+
+
+def forward(params, X, Xs=None):
+    """Returns (Y, cache). params: W1 [K][H], b1, W2, b2, W3, b3, W4 [H][N],
+    b4, Ws [m][K][N]. The hidden layers read X, the per-actuator linear map
+    reads Xs (default X)."""
     p = params
+    Xs = X if Xs is None else Xs
     z1 = X @ p["W1"] + p["b1"]; h1 = np.maximum(z1, 0.0)
     z2 = h1 @ p["W2"] + p["b2"]; h2 = np.maximum(z2, 0.0)
     z3 = h2 @ p["W3"] + p["b3"]; h3 = np.maximum(z3, 0.0)
-    Y = h3 @ p["W4"] + p["b4"] + X @ p["Ws"]
-    return Y, (X, h1, h2, h3)
+    Y = h3 @ p["W4"] + p["b4"] + skip(p["Ws"], Xs)
+    return Y, (X, h1, h2, h3, Xs)
 
 
 def mse(Y, T):
@@ -51,10 +70,12 @@ def mse(Y, T):
 
 def backward(params, cache, Y, T):
     """Gradients of mse(Y, T) with respect to every parameter."""
-    X, h1, h2, h3 = cache
+    X, h1, h2, h3, Xs = cache
     p = params
+    m = p["Ws"].shape[0]
     dY = 2.0 * (Y - T) / Y.size
-    g = {"W4": h3.T @ dY, "b4": dY.sum(0), "Ws": X.T @ dY}
+    g = {"W4": h3.T @ dY, "b4": dY.sum(0),
+         "Ws": np.stack([Xs[q::m].T @ dY[q::m] for q in range(m)])}
     d3 = (dY @ p["W4"].T) * (h3 > 0)
     g["W3"] = h2.T @ d3; g["b3"] = d3.sum(0)
     d2 = (d3 @ p["W3"].T) * (h2 > 0)

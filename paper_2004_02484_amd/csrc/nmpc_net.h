@@ -21,11 +21,24 @@ struct GemmArgs {
     int ldcb;
 };
 
-struct WinArgs {
+struct GemmMxArgs {
+    int M, N, K;
+    const void *A;             // float or double (kernel's input type)
+    int lda;
+    const void *B;
+    int ldb;
+    double alpha, beta;
+    const void *Cin;           // beta term (null: C itself); accumulator type
+    void *C;                   // accumulator type (float or double)
+    int ldc;
+    long long sa, sb, sc;      // element offsets between groups (blockIdx.z)
+};
+
+struct FeatArgs {
     const double *x0, *xref;   // [count][ns * ns]
-    int count, ns, L, win, ld;
-    unsigned short *out;       // [count * L * L][ld] bf16
-    unsigned short *out_lo;    // bf16 residual (value - out), may be null
+    int count, ns, L, win, planes, ld;
+    float *Xf;                 // [count * L * L][ld] fp32 (may be null)
+    unsigned short *Xb;        // [count * L * L][ld] bf16 (may be null)
 };
 
 struct AdamArgs {
@@ -39,13 +52,14 @@ struct AdamArgs {
 };
 
 const void *gemm_kernel(int ta, int tb);
-const void *windows_kernel();
+const void *gemm_mx_kernel(int ta, int in64, int acc64);
+const void *ls_prepare_kernel();
+const void *features_kernel();
 const void *relu_grad_kernel();
 const void *colsum_kernel();
 const void *mse_kernel();
 const void *adam_kernel();
 const void *to_bf16_kernel();
-const void *split_bf16_kernel();
 const void *pack_u_kernel();
 const void *unpack_u_kernel();
 

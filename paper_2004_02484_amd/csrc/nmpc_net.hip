@@ -1,13 +1,16 @@
 // nmpc_net.hip -- kernels of the learned warm start: a patch encoder mapping
-// (x0, xref) windows around each actuator to that actuator's input trajectory.
+// second-order features of (x0, xref) windows around each actuator to that
+// actuator's input trajectory.
 //
-// Every layer is a GEMM on bf16 operands with fp32 accumulation on the matrix
-// cores (v_mfma_f32_16x16x16_bf16), so forward, data gradient and weight
-// gradient are the three operand layouts of one kernel:
+// The hidden layers are GEMMs on bf16 operands with fp32 accumulation on the
+// matrix cores (v_mfma_f32_16x16x16_bf16), so forward, data gradient and
+// weight gradient are the three operand layouts of one kernel:
 //   forward  C = X W          (A [M][K], B [K][N])
 //   dgrad    C = dY W^T       (B stored [N][K])
 //   wgrad    C = X^T dY       (A stored [K][M])
-// The small elementwise kernels (window gather, ReLU gradient, column sums,
+// The per-actuator linear map of the second-order features runs on fp32
+// operands (v_mfma_f32_16x16x4_f32). The small elementwise kernels (feature
+// gather, ReLU gradient, column sums,
 // squared-error gradient, Adam, layout packing) complete the training step.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -117,49 +120,182 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
             }
 }
 
+// Grouped GEMM on the matrix cores with fp32 or fp64 products: the
+// per-actuator linear map of the network's second-order features (fp32
+// operands, v_mfma_f32_16x16x4_f32: more significant bits than bf16 carries)
+// and the fit of that map by its normal equations (fp64 products and
+// accumulation, v_mfma_f64_16x16x4_f64, on fp32 or fp64 operands). Group z
+// works on A + z sa, B + z sb, Cin + z sc, C + z sc.
+// A(m, k) = TA ? A[k lda + m] : A[m lda + k]; B(k, n) = B[k ldb + n];
+// C = alpha A B + beta Cin (Cin = C when not given). Tails are zero-filled.
+constexpr int kFK = 16;
+
+template <typename T> struct MfmaTile;
+// Result layout of one 16 x 16 block: lane l holds column l % 16 and rows
+// row(l, r), r = 0..3 (fp32: 4 consecutive rows per lane quarter; fp64: rows
+// interleaved with stride 4).
+template <> struct MfmaTile<float> {
+    using acc_t = f32x4;
+    static constexpr int pad = 4;
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static acc_t mma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct MfmaTile<double> {
+    using acc_t = __attribute__((ext_vector_type(4))) double;
+    static constexpr int pad = 1;
+    __device__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+    __device__ static acc_t mma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <bool TA, typename InT, typename AccT>
+__global__ void __launch_bounds__(256) k_gemm_mx(const GemmMxArgs g)
+{
+    using MT = MfmaTile<AccT>;
+    __shared__ AccT As[kBM][kFK + MT::pad];   // [m][k]
+    __shared__ AccT Bs[kBN][kFK + MT::pad];   // [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const InT *A = (const InT *)g.A + (size_t)blockIdx.z * g.sa;
+    const InT *B = (const InT *)g.B + (size_t)blockIdx.z * g.sb;
+    AccT *C = (AccT *)g.C + (size_t)blockIdx.z * g.sc;
+    const AccT *Cin = (g.Cin ? (const AccT *)g.Cin : (const AccT *)g.C) + (size_t)blockIdx.z * g.sc;
+    typename MT::acc_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename MT::acc_t{0, 0, 0, 0};
+
+    for (int k0 = 0; k0 < g.K; k0 += kFK) {
+        // a 64 x 16 tile of A and of B^T: four elements per thread each
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid * 4 + e;
+            int r, kk;
+            if (TA) { kk = idx / kBM; r = idx % kBM; }   // consecutive threads walk m
+            else    { r = idx / kFK; kk = idx % kFK; }   // consecutive threads walk k
+            const int gm = m0 + r, gk = k0 + kk;
+            AccT v = 0;
+            if (gm < g.M && gk < g.K) v = (AccT)(TA ? A[(size_t)gk * g.lda + gm] : A[(size_t)gm * g.lda + gk]);
+            As[r][kk] = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int idx = tid * 4 + e;
+            const int kk = idx / kBN, c = idx % kBN;         // consecutive threads walk n
+            const int gn = n0 + c, gk = k0 + kk;
+            Bs[c][kk] = (gn < g.N && gk < g.K) ? (AccT)B[(size_t)gk * g.ldb + gn] : (AccT)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kFK; ks += 4) {
+            // lane l holds row / column l % 16 at k = ks + l / 16
+            const int kq = ks + (lane >> 4);
+            AccT af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) af[i] = As[wm + i * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) bfr[j] = Bs[wn + j * 16 + (lane & 15)][kq];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = MT::mma(af[i], bfr[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    const AccT alpha = (AccT)g.alpha, beta = (AccT)g.beta;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gm = m0 + wm + i * 16 + MT::row(lane, r);
+                const int gn = n0 + wn + j * 16 + (lane & 15);
+                if (gm >= g.M || gn >= g.N) continue;
+                AccT v = alpha * acc[i][j][r];
+                if (beta != (AccT)0) v += beta * Cin[(size_t)gm * g.ldc + gn];
+                C[(size_t)gm * g.ldc + gn] = v;
+            }
+}
+
+// Normal equations of group z: G_z (n x n, row stride ld) gets the ridge
+// rel * trace(G_z) / n added to its diagonal, and X_z = I / trace(G_z + ridge)
+// starts the Newton-Schulz inverse iteration X <- 2 X - X G X (the trace bounds
+// the largest eigenvalue of a positive semidefinite matrix, so the iteration
+// contracts). One workgroup per group; X rows have stride ld.
+__global__ void __launch_bounds__(1024) k_ls_prepare(double *G, int n, int ld, long long sg,
+                                                     double rel, double *X, long long sx)
+{
+    __shared__ double part[1024];
+    double *Gz = G + (size_t)blockIdx.x * sg;
+    double *Xz = X + (size_t)blockIdx.x * sx;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += Gz[(size_t)i * ld + i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double tr = part[0];
+    const double ridge = rel * tr / n;
+    const double a = 1.0 / (tr + n * ridge);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) Gz[(size_t)i * ld + i] += ridge;
+    for (size_t t = threadIdx.x; t < (size_t)n * n; t += blockDim.x) {
+        const int i = (int)(t / n), j = (int)(t % n);
+        Xz[(size_t)i * ld + j] = i == j ? a : 0.0;
+    }
+}
+
 // ------------------------------------------------------------ elementwise
 
-// Windows of (x0 / 0.1 - 1, xref / 0.3) around each actuator of an L x L
-// lattice on an ns x ns grid (spacing s = ns / L, window win = 1.5 s, so a
-// window starts s/4 before the actuator's cell), followed by a one-hot
-// actuator index; zero outside the grid and in the padding up to ld.
-// Row (b, p) with p = pb * L + pa (the input index) of out [count * L^2][ld].
-__global__ void k_windows(const WinArgs a)
+// Input rows of the network. For instance b and actuator p = pb * L + pa of
+// an L x L lattice on an ns x ns grid, a win x win window starting
+// (win - s) / 2 nodes before the actuator's cell (s = ns / L), in `planes`
+// feature planes of the scaled fields xt = x0 / 0.1 - 1 and rt = xref / 0.3:
+// xt, rt, xt^2 - 1/3, xt rt, rt^2 - 1/3 (the first two, or all five); zero
+// outside the grid. Then a one-hot actuator index and zeros up to the row
+// length ld. Row b * L^2 + p; fp32 (Xf) and/or bf16 (Xb) copies.
+__global__ void k_features(const FeatArgs a)
 {
     const int rows = a.count * a.L * a.L;
-    const int feat = 2 * a.win * a.win;
-    const size_t tot = (size_t)rows * a.ld, stride = (size_t)gridDim.x * blockDim.x;
+    const int ww = a.win * a.win, feat = a.planes * ww;
+    const int ld = a.ld;
+    const size_t tot = (size_t)rows * ld, stride = (size_t)gridDim.x * blockDim.x;
     const int s = a.ns / a.L, off = (a.win - s) / 2;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-        const int row = (int)(t / a.ld), col = (int)(t % a.ld);
+        const int row = (int)(t / ld), col = (int)(t % ld);
         const int b = row / (a.L * a.L), p = row % (a.L * a.L);
         float v = 0.f;
         if (col < feat) {
-            const int ch = col / (a.win * a.win), r = col % (a.win * a.win);
+            const int ch = col / ww, r = col % ww;
             const int wy = r / a.win, wx = r % a.win;
             const int iy = (p / a.L) * s - off + wy, ix = (p % a.L) * s - off + wx;
             if (iy >= 0 && iy < a.ns && ix >= 0 && ix < a.ns) {
-                const size_t g = (size_t)b * a.ns * a.ns + (size_t)iy * a.ns + ix;
-                v = ch == 0 ? float(a.x0[g] / 0.1 - 1.0) : float(a.xref[g] / 0.3);
+                const size_t gi = (size_t)b * a.ns * a.ns + (size_t)iy * a.ns + ix;
+                const double xt = a.x0[gi] / 0.1 - 1.0, rt = a.xref[gi] / 0.3;
+                double f;
+                switch (ch) {
+                case 0: f = xt; break;
+                case 1: f = rt; break;
+                case 2: f = __dmul_rn(xt, xt) - 1.0 / 3.0; break;
+                case 3: f = __dmul_rn(xt, rt); break;
+                default: f = __dmul_rn(rt, rt) - 1.0 / 3.0; break;
+                }
+                v = (float)f;
             }
         } else if (col < feat + a.L * a.L) {
             v = (col - feat) == p ? 1.f : 0.f;
         }
-        const unsigned short hi = f2bf(v);
-        a.out[t] = hi;
-        if (a.out_lo) a.out_lo[t] = f2bf(v - bf2f(hi));
-    }
-}
-
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): products of split
-// operands (hi*hi + hi*lo + lo*hi) carry about 16 significant bits.
-__global__ void k_split_bf16(const float *x, unsigned short *hi, unsigned short *lo, long long n)
-{
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)n; t += stride) {
-        const unsigned short h = f2bf(x[t]);
-        hi[t] = h;
-        lo[t] = f2bf(x[t] - bf2f(h));
+        if (a.Xf) a.Xf[t] = v;
+        if (a.Xb) a.Xb[t] = f2bf(v);
     }
 }
 
@@ -253,13 +389,22 @@ const void *gemm_kernel(int ta, int tb)
     if (ta && !tb) return (const void *)&k_gemm<true, false>;
     return (const void *)&k_gemm<true, true>;
 }
-const void *windows_kernel() { return (const void *)&k_windows; }
+const void *features_kernel() { return (const void *)&k_features; }
+const void *gemm_mx_kernel(int ta, int in64, int acc64)
+{
+    if (!acc64) return ta ? (const void *)&k_gemm_mx<true, float, float>
+                          : (const void *)&k_gemm_mx<false, float, float>;
+    if (in64) return ta ? (const void *)&k_gemm_mx<true, double, double>
+                        : (const void *)&k_gemm_mx<false, double, double>;
+    return ta ? (const void *)&k_gemm_mx<true, float, double>
+              : (const void *)&k_gemm_mx<false, float, double>;
+}
+const void *ls_prepare_kernel() { return (const void *)&k_ls_prepare; }
 const void *relu_grad_kernel() { return (const void *)&k_relu_grad; }
 const void *colsum_kernel() { return (const void *)&k_colsum; }
 const void *mse_kernel() { return (const void *)&k_mse; }
 const void *adam_kernel() { return (const void *)&k_adam; }
 const void *to_bf16_kernel() { return (const void *)&k_to_bf16; }
-const void *split_bf16_kernel() { return (const void *)&k_split_bf16; }
 const void *pack_u_kernel() { return (const void *)&k_pack_u; }
 const void *unpack_u_kernel() { return (const void *)&k_unpack_u; }
 

@@ -24,6 +24,24 @@ int net_fail(int code, const char *msg)
 
 unsigned grid_for(size_t tot) { return (unsigned)std::min<size_t>((tot + 255) / 256 + 1, 16384); }
 
+int launch_mx(int ta, int in64, int acc64, int32_t M, int32_t N, int32_t K, const void *A,
+              int32_t lda, int64_t sa, const void *B, int32_t ldb, int64_t sb, double alpha,
+              double beta, const void *Cin, void *C, int32_t ldc, int64_t sc, int32_t groups,
+              void *stream, const char *what)
+{
+    if (M < 1 || N < 1 || K < 1 || groups < 1 || groups > 65535 || !A || !B || !C)
+        return net_fail(NMPC_E_ARG, what);
+    if (lda < (ta ? M : K) || ldb < N || ldc < N) return net_fail(NMPC_E_ARG, what);
+    if (groups > 1 && (sa < 0 || sb < 0 || sc < 0)) return net_fail(NMPC_E_ARG, what);
+    nmpc::GemmMxArgs g{M, N, K, A, lda, B, ldb, alpha, beta, Cin, C, ldc, (long long)sa,
+                       (long long)sb, (long long)sc};
+    void *args[] = {(void *)&g};
+    NET_TRY(hipLaunchKernel(nmpc::gemm_mx_kernel(ta != 0, in64, acc64),
+                            dim3((N + 63) / 64, (M + 63) / 64, groups), dim3(256), args, 0,
+                            (hipStream_t)stream));
+    return NMPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -46,16 +64,58 @@ int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32
     return NMPC_OK;
 }
 
-int nmpc_net_windows(const double *x0, const double *xref, int32_t count, int32_t ns,
-                     int32_t lattice, int32_t win, uint16_t *out, uint16_t *out_lo, int32_t ld,
-                     void *stream)
+int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A, int32_t lda,
+                  int64_t stride_a, const float *B, int32_t ldb, int64_t stride_b, float beta,
+                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, void *stream)
 {
-    if (!x0 || !xref || !out || count < 1 || ns < 1 || lattice < 1 || ns % lattice || win < 1)
-        return net_fail(NMPC_E_ARG, "windows: bad arguments");
-    if (ld < 2 * win * win + lattice * lattice) return net_fail(NMPC_E_ARG, "windows: ld too small");
-    nmpc::WinArgs a{x0, xref, count, ns, lattice, win, ld, out, out_lo};
+    return launch_mx(trans_a, 0, 0, M, N, K, A, lda, stride_a, B, ldb, stride_b, 1.0, beta,
+                     nullptr, C, ldc, stride_c, groups, stream, "gemm_f32: bad arguments");
+}
+
+int nmpc_gemm_f64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const double *A, int32_t lda,
+                  int64_t stride_a, const double *B, int32_t ldb, int64_t stride_b, double alpha,
+                  double beta, const double *Cin, double *C, int32_t ldc, int64_t stride_c,
+                  int32_t groups, void *stream)
+{
+    return launch_mx(trans_a, 1, 1, M, N, K, A, lda, stride_a, B, ldb, stride_b, alpha, beta,
+                     Cin, C, ldc, stride_c, groups, stream, "gemm_f64: bad arguments");
+}
+
+int nmpc_gemm_f32_acc64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A,
+                        int32_t lda, int64_t stride_a, const float *B, int32_t ldb,
+                        int64_t stride_b, double beta, double *C, int32_t ldc, int64_t stride_c,
+                        int32_t groups, void *stream)
+{
+    return launch_mx(trans_a, 0, 1, M, N, K, A, lda, stride_a, B, ldb, stride_b, 1.0, beta,
+                     nullptr, C, ldc, stride_c, groups, stream, "gemm_f32_acc64: bad arguments");
+}
+
+int nmpc_ls_prepare(double *G, int32_t n, int32_t ld, int64_t stride_g, double ridge_rel,
+                    double *X, int64_t stride_x, int32_t groups, void *stream)
+{
+    if (!G || !X || n < 1 || ld < n || groups < 1 || groups > 65535 || ridge_rel < 0 ||
+        (groups > 1 && (stride_g < (int64_t)n * ld || stride_x < (int64_t)n * ld)))
+        return net_fail(NMPC_E_ARG, "ls_prepare: bad arguments");
+    long long sg = stride_g, sx = stride_x;
+    void *args[] = {(void *)&G, (void *)&n, (void *)&ld, (void *)&sg, (void *)&ridge_rel,
+                    (void *)&X, (void *)&sx};
+    NET_TRY(hipLaunchKernel(nmpc::ls_prepare_kernel(), dim3(groups), dim3(1024), args, 0,
+                            (hipStream_t)stream));
+    return NMPC_OK;
+}
+
+int nmpc_net_features(const double *x0, const double *xref, int32_t count, int32_t ns,
+                      int32_t lattice, int32_t win, int32_t planes, float *Xf, uint16_t *Xb,
+                      int32_t ld, void *stream)
+{
+    if (!x0 || !xref || (!Xf && !Xb) || count < 1 || ns < 1 || lattice < 1 || ns % lattice ||
+        win < ns / lattice || (win - ns / lattice) % 2 || (planes != 2 && planes != 5))
+        return net_fail(NMPC_E_ARG, "features: bad arguments");
+    if (ld < planes * win * win + lattice * lattice)
+        return net_fail(NMPC_E_ARG, "features: ld too small");
+    nmpc::FeatArgs a{x0, xref, count, ns, lattice, win, planes, ld, Xf, Xb};
     void *args[] = {(void *)&a};
-    NET_TRY(hipLaunchKernel(nmpc::windows_kernel(),
+    NET_TRY(hipLaunchKernel(nmpc::features_kernel(),
                             dim3(grid_for((size_t)count * lattice * lattice * ld)), dim3(256),
                             args, 0, (hipStream_t)stream));
     return NMPC_OK;
@@ -110,16 +170,6 @@ int nmpc_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream)
     void *args[] = {(void *)&x, (void *)&y, (void *)&nn};
     NET_TRY(hipLaunchKernel(nmpc::to_bf16_kernel(), dim3(grid_for((size_t)n)), dim3(256), args, 0,
                             (hipStream_t)stream));
-    return NMPC_OK;
-}
-
-int nmpc_split_bf16(const float *x, uint16_t *hi, uint16_t *lo, int64_t n, void *stream)
-{
-    if (!x || !hi || !lo || n < 0) return net_fail(NMPC_E_ARG, "split_bf16: bad arguments");
-    long long nn = n;
-    void *args[] = {(void *)&x, (void *)&hi, (void *)&lo, (void *)&nn};
-    NET_TRY(hipLaunchKernel(nmpc::split_bf16_kernel(), dim3(grid_for((size_t)n)), dim3(256), args,
-                            0, (hipStream_t)stream));
     return NMPC_OK;
 }
 
