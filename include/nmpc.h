@@ -309,10 +309,15 @@ int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32
  * linear map needs more significant bits than bf16 carries). X_g = X + g *
  * stride_x (elements). A_g(m,k) is A_g[m*lda + k] (trans_a = 0) or
  * A_g[k*lda + m]; B_g(k,n) = B_g[k*ldb + n]; C_g is M x N with row stride ldc.
- * The forward map uses trans_a = 0, its weight gradient trans_a = 1. */
+ * The forward map uses trans_a = 0, its weight gradient trans_a = 1. With
+ * ksplit > 1 the K range is cut in ksplit parts computed in parallel into
+ * `work` (caller-owned device memory of groups * ksplit * M * N floats) and
+ * added in a fixed order (a result that does not depend on scheduling);
+ * ksplit = 1 takes work = NULL. groups * ksplit <= 65535. */
 int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A, int32_t lda,
                   int64_t stride_a, const float *B, int32_t ldb, int64_t stride_b, float beta,
-                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, void *stream);
+                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, int32_t ksplit,
+                  float *work, void *stream);
 
 /* The same grouped product with fp64 products and accumulation: C_g =
  * alpha op(A_g) B_g + beta Cin_g (Cin = C when NULL; Cin_g and C_g share

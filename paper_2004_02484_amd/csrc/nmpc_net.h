@@ -31,7 +31,9 @@ struct GemmMxArgs {
     const void *Cin;           // beta term (null: C itself); accumulator type
     void *C;                   // accumulator type (float or double)
     int ldc;
-    long long sa, sb, sc;      // element offsets between groups (blockIdx.z)
+    long long sa, sb, sc;      // element offsets between groups
+    int ksplit, kc;            // K split in ksplit parts of kc (blockIdx.z = group * ksplit + part)
+    void *work;                // ksplit > 1: partial sums [groups][ksplit][M][N]
 };
 
 struct FeatArgs {
@@ -54,6 +56,7 @@ struct AdamArgs {
 const void *gemm_kernel(int ta, int tb);
 const void *gemm_mx_kernel(int ta, int in64, int acc64);
 const void *ls_prepare_kernel();
+const void *splitk_reduce_kernel();
 const void *features_kernel();
 const void *relu_grad_kernel();
 const void *colsum_kernel();

@@ -162,17 +162,20 @@ __global__ void __launch_bounds__(256) k_gemm_mx(const GemmMxArgs g)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
-    const InT *A = (const InT *)g.A + (size_t)blockIdx.z * g.sa;
-    const InT *B = (const InT *)g.B + (size_t)blockIdx.z * g.sb;
-    AccT *C = (AccT *)g.C + (size_t)blockIdx.z * g.sc;
-    const AccT *Cin = (g.Cin ? (const AccT *)g.Cin : (const AccT *)g.C) + (size_t)blockIdx.z * g.sc;
+    // blockIdx.z = group * ksplit + part: part covers K range [kb, ke)
+    const int grp = blockIdx.z / g.ksplit, part = blockIdx.z % g.ksplit;
+    const int kb = part * g.kc, ke = min(g.K, kb + g.kc);
+    const InT *A = (const InT *)g.A + (size_t)grp * g.sa;
+    const InT *B = (const InT *)g.B + (size_t)grp * g.sb;
+    AccT *C = (AccT *)g.C + (size_t)grp * g.sc;
+    const AccT *Cin = (g.Cin ? (const AccT *)g.Cin : (const AccT *)g.C) + (size_t)grp * g.sc;
     typename MT::acc_t acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = typename MT::acc_t{0, 0, 0, 0};
 
-    for (int k0 = 0; k0 < g.K; k0 += kFK) {
+    for (int k0 = kb; k0 < ke; k0 += kFK) {
         // a 64 x 16 tile of A and of B^T: four elements per thread each
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(256) k_gemm_mx(const GemmMxArgs g)
             else    { r = idx / kFK; kk = idx % kFK; }   // consecutive threads walk k
             const int gm = m0 + r, gk = k0 + kk;
             AccT v = 0;
-            if (gm < g.M && gk < g.K) v = (AccT)(TA ? A[(size_t)gk * g.lda + gm] : A[(size_t)gm * g.lda + gk]);
+            if (gm < g.M && gk < ke) v = (AccT)(TA ? A[(size_t)gk * g.lda + gm] : A[(size_t)gm * g.lda + gk]);
             As[r][kk] = v;
         }
 #pragma unroll
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(256) k_gemm_mx(const GemmMxArgs g)
             const int idx = tid * 4 + e;
             const int kk = idx / kBN, c = idx % kBN;         // consecutive threads walk n
             const int gn = n0 + c, gk = k0 + kk;
-            Bs[c][kk] = (gn < g.N && gk < g.K) ? (AccT)B[(size_t)gk * g.ldb + gn] : (AccT)0;
+            Bs[c][kk] = (gn < g.N && gk < ke) ? (AccT)B[(size_t)gk * g.ldb + gn] : (AccT)0;
         }
         __syncthreads();
 #pragma unroll
@@ -219,10 +222,35 @@ __global__ void __launch_bounds__(256) k_gemm_mx(const GemmMxArgs g)
                 const int gm = m0 + wm + i * 16 + MT::row(lane, r);
                 const int gn = n0 + wn + j * 16 + (lane & 15);
                 if (gm >= g.M || gn >= g.N) continue;
+                if (g.ksplit > 1) {   // partial sum of this K range: [group][part][M][N]
+                    ((AccT *)g.work)[((size_t)blockIdx.z * g.M + gm) * g.N + gn] = acc[i][j][r];
+                    continue;
+                }
                 AccT v = alpha * acc[i][j][r];
                 if (beta != (AccT)0) v += beta * Cin[(size_t)gm * g.ldc + gn];
                 C[(size_t)gm * g.ldc + gn] = v;
             }
+}
+
+// Split-K epilogue: C_g = alpha sum_part work[g][part] + beta Cin_g, the parts
+// added in a fixed order. One thread per (group, m, n).
+template <typename AccT>
+__global__ void k_splitk_reduce(const GemmMxArgs g)
+{
+    const size_t mn = (size_t)g.M * g.N, tot = mn * (size_t)gridDim.y;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= mn) return;
+    const int grp = blockIdx.y;
+    const int m = (int)(t / g.N), n = (int)(t % g.N);
+    const AccT *wk = (const AccT *)g.work + (size_t)grp * g.ksplit * mn + t;
+    AccT v = 0;
+    for (int p = 0; p < g.ksplit; ++p) v += wk[(size_t)p * mn];
+    AccT *C = (AccT *)g.C + (size_t)grp * g.sc;
+    const AccT *Cin = (g.Cin ? (const AccT *)g.Cin : (const AccT *)g.C) + (size_t)grp * g.sc;
+    v *= (AccT)g.alpha;
+    if (g.beta != 0.0) v += (AccT)g.beta * Cin[(size_t)m * g.ldc + n];
+    C[(size_t)m * g.ldc + n] = v;
+    (void)tot;
 }
 
 // Normal equations of group z: G_z (n x n, row stride ld) gets the ridge
@@ -400,6 +428,7 @@ const void *gemm_mx_kernel(int ta, int in64, int acc64)
               : (const void *)&k_gemm_mx<false, float, double>;
 }
 const void *ls_prepare_kernel() { return (const void *)&k_ls_prepare; }
+const void *splitk_reduce_kernel() { return (const void *)&k_splitk_reduce<float>; }
 const void *relu_grad_kernel() { return (const void *)&k_relu_grad; }
 const void *colsum_kernel() { return (const void *)&k_colsum; }
 const void *mse_kernel() { return (const void *)&k_mse; }

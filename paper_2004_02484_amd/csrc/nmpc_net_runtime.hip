@@ -27,18 +27,26 @@ unsigned grid_for(size_t tot) { return (unsigned)std::min<size_t>((tot + 255) / 
 int launch_mx(int ta, int in64, int acc64, int32_t M, int32_t N, int32_t K, const void *A,
               int32_t lda, int64_t sa, const void *B, int32_t ldb, int64_t sb, double alpha,
               double beta, const void *Cin, void *C, int32_t ldc, int64_t sc, int32_t groups,
-              void *stream, const char *what)
+              void *stream, const char *what, int32_t ksplit = 1, void *work = nullptr)
 {
-    if (M < 1 || N < 1 || K < 1 || groups < 1 || groups > 65535 || !A || !B || !C)
+    if (M < 1 || N < 1 || K < 1 || groups < 1 || !A || !B || !C || ksplit < 1 ||
+        (long long)groups * ksplit > 65535 || (ksplit > 1 && !work))
         return net_fail(NMPC_E_ARG, what);
     if (lda < (ta ? M : K) || ldb < N || ldc < N) return net_fail(NMPC_E_ARG, what);
     if (groups > 1 && (sa < 0 || sb < 0 || sc < 0)) return net_fail(NMPC_E_ARG, what);
+    // K parts: multiples of the 16-deep K step
+    const int kc = ksplit > 1 ? ((K + ksplit - 1) / ksplit + 15) / 16 * 16 : K;
     nmpc::GemmMxArgs g{M, N, K, A, lda, B, ldb, alpha, beta, Cin, C, ldc, (long long)sa,
-                       (long long)sb, (long long)sc};
+                       (long long)sb, (long long)sc, ksplit, kc, work};
     void *args[] = {(void *)&g};
     NET_TRY(hipLaunchKernel(nmpc::gemm_mx_kernel(ta != 0, in64, acc64),
-                            dim3((N + 63) / 64, (M + 63) / 64, groups), dim3(256), args, 0,
-                            (hipStream_t)stream));
+                            dim3((N + 63) / 64, (M + 63) / 64, groups * ksplit), dim3(256), args,
+                            0, (hipStream_t)stream));
+    if (ksplit > 1) {
+        const size_t mn = (size_t)M * N;
+        NET_TRY(hipLaunchKernel(nmpc::splitk_reduce_kernel(), dim3((unsigned)((mn + 255) / 256), groups),
+                                dim3(256), args, 0, (hipStream_t)stream));
+    }
     return NMPC_OK;
 }
 
@@ -66,10 +74,12 @@ int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32
 
 int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A, int32_t lda,
                   int64_t stride_a, const float *B, int32_t ldb, int64_t stride_b, float beta,
-                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, void *stream)
+                  float *C, int32_t ldc, int64_t stride_c, int32_t groups, int32_t ksplit,
+                  float *work, void *stream)
 {
     return launch_mx(trans_a, 0, 0, M, N, K, A, lda, stride_a, B, ldb, stride_b, 1.0, beta,
-                     nullptr, C, ldc, stride_c, groups, stream, "gemm_f32: bad arguments");
+                     nullptr, C, ldc, stride_c, groups, stream, "gemm_f32: bad arguments", ksplit,
+                     work);
 }
 
 int nmpc_gemm_f64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const double *A, int32_t lda,

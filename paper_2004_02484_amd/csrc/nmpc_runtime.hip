@@ -291,9 +291,15 @@ int launch_iterate(nmpc_handle *h, int prec, const IterArgs &a, hipStream_t s)
 }
 
 // Captured sequence of check_every launches of the precision-`prec` kernel.
+// After FP32 sweeps the FP64 phase is the final correction, which takes three
+// launches per instance (the FP64 re-evaluation of the accepted iterate, the
+// correction step, the final test): its graph is four launches long, and the
+// host relaunches it if an instance needs more.
 int ensure_graph(nmpc_handle *h, int prec, int count)
 {
-    const int len = h->opt.check_every;
+    const int len = (prec == nmpc::kModeFp64 && main_prec(h->opt) == nmpc::kModeFp32)
+                        ? std::min(4, h->opt.check_every)
+                        : h->opt.check_every;
     if (h->gexec[prec] && h->graph_count[prec] == count && h->graph_len[prec] == len)
         return NMPC_OK;
     if (h->gexec[prec]) { (void)hipGraphExecDestroy(h->gexec[prec]); h->gexec[prec] = nullptr; }

@@ -50,7 +50,7 @@ def rel_errors(net, x0, xr, u, batch=256):
     return np.concatenate(errs)
 
 
-def train(samples=81920, val=1024, epochs=40, batch=256, lr=3e-4, wd=1e-5, hidden=512, seed=0,
+def train(samples=81920, val=1024, epochs=40, batch=256, lr=3e-4, wd=1e-5, hidden=128, seed=0,
           ridge=1e-6, log=print):
     import torch
     from nmpc_inputs import make_problem
@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--samples", type=int, default=81920)
     ap.add_argument("--val", type=int, default=1024)
     ap.add_argument("--epochs", type=int, default=40)
-    ap.add_argument("--hidden", type=int, default=512)
+    ap.add_argument("--hidden", type=int, default=128)
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--ridge", type=float, default=1e-6)
     ap.add_argument("--out", required=True)

@@ -50,7 +50,7 @@ def _lib():
         lib.nmpc_gemm_bf16.argtypes = [i32, i32, i32, i32, i32, _vp, i32, _vp, i32, f32, _vp, i32,
                                        _vp, i32, _vp, i32, _vp]
         lib.nmpc_gemm_f32.argtypes = [i32, i32, i32, i32, _vp, i32, i64, _vp, i32, i64, f32, _vp,
-                                      i32, i64, i32, _vp]
+                                      i32, i64, i32, i32, _vp, _vp]
         lib.nmpc_gemm_f64.argtypes = [i32, i32, i32, i32, _vp, i32, i64, _vp, i32, i64,
                                       ctypes.c_double, ctypes.c_double, _vp, _vp, i32, i64, i32, _vp]
         lib.nmpc_gemm_f32_acc64.argtypes = [i32, i32, i32, i32, _vp, i32, i64, _vp, i32, i64,
@@ -99,10 +99,12 @@ def gemm(A, B_, M, N, K, *, ta=0, tb=0, lda=None, ldb=None, C=None, ldc=None, be
         "nmpc_gemm_bf16")
 
 
-def gemm_f32(A, B_, M, N, K, C, *, ta=0, lda, ldb, ldc, sa=0, sb=0, sc=0, groups=1, beta=0.0):
-    """C_g = beta C_g + op(A_g) B_g on fp32 operands for groups g (X_g = X + g sx)."""
+def gemm_f32(A, B_, M, N, K, C, *, ta=0, lda, ldb, ldc, sa=0, sb=0, sc=0, groups=1, beta=0.0,
+             ksplit=1, work=None):
+    """C_g = beta C_g + op(A_g) B_g on fp32 operands for groups g (X_g = X + g sx);
+    ksplit > 1 cuts K in parts summed in a fixed order (work: groups*ksplit*M*N floats)."""
     _ck(_lib().nmpc_gemm_f32(ta, M, N, K, _p(A), lda, sa, _p(B_), ldb, sb, beta, _p(C), ldc, sc,
-                             groups, _stream()), "nmpc_gemm_f32")
+                             groups, ksplit, _p(work), _stream()), "nmpc_gemm_f32")
 
 
 def gemm_f64(A, B_, M, N, K, C, *, ta=0, lda, ldb, ldc, sa=0, sb=0, sc=0, groups=1, alpha=1.0,
@@ -142,6 +144,7 @@ class PatchNet:
     """Patch encoder for an ns x ns grid with an L x L actuator lattice and N stages."""
 
     PLANES = 5
+    KSPLIT = 8      # K parts of the per-actuator map (few output tiles, long K)
 
     def __init__(self, N: int = 40, ns: int = 64, lattice: int = 4, win: int = 32,
                  hidden: int = 512, seed: int = 0, device: str = "cuda"):
@@ -187,7 +190,7 @@ class PatchNet:
             "H1": f(rows, H), "H1b": h(rows, H), "H2": f(rows, H), "H2b": h(rows, H),
             "H3": f(rows, H), "H3b": h(rows, H), "Y": f(rows, N),
             "dY": f(rows, N), "dYb": h(rows, N), "T": f(rows, N), "sse": f(rows),
-            "dH": f(rows, H), "dHb": h(rows, H),
+            "dH": f(rows, H), "dHb": h(rows, H), "work": f(self.KSPLIT * rows * N),
         }
         self._buf_rows = key
         return self._buf
@@ -210,7 +213,7 @@ class PatchNet:
         gemm(b["H3b"], W["W4"], rows, N, H, C=b["Y"], bias=P["b4"])
         # per-actuator map: group p takes rows p, p + m, ... (row stride m K0)
         gemm_f32(b["Xf"], P["Ws"], count, N, K0, b["Y"], lda=m * K0, ldb=N, ldc=m * N,
-                 sa=K0, sb=K0 * N, sc=N, groups=m, beta=1.0)
+                 sa=K0, sb=K0 * N, sc=N, groups=m, beta=1.0, ksplit=self.KSPLIT, work=b["work"])
         return b["Y"]
 
     def predict(self, x0, xref, out=None):

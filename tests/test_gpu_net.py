@@ -46,8 +46,9 @@ def test_gemm_layouts(ws, ta, tb, M, N, K):
 
 
 @pytest.mark.parametrize("ta", [0, 1])
-@pytest.mark.parametrize("M,N,K,G", [(77, 45, 83, 1), (130, 40, 200, 3), (5, 70, 33, 2)])
-def test_gemm_f32_groups(ws, ta, M, N, K, G):
+@pytest.mark.parametrize("M,N,K,G,S", [(77, 45, 83, 1, 1), (130, 40, 200, 3, 1), (5, 70, 33, 2, 1),
+                                       (130, 40, 200, 3, 4), (77, 45, 83, 2, 7)])
+def test_gemm_f32_groups(ws, ta, M, N, K, G, S):
     """Grouped fp32 products against float64 products of the same float32 operands,
     with the operands of each group interleaved the way the network stores rows."""
     import torch
@@ -60,8 +61,9 @@ def test_gemm_f32_groups(ws, ta, M, N, K, G):
     C0 = rng.normal(size=(M * G, N)).astype(np.float32)
     dA = torch.tensor(A, device="cuda"); dB = torch.tensor(Bm, device="cuda")
     C = torch.tensor(C0, device="cuda")
+    work = torch.empty(G * S * M * N, dtype=torch.float32, device="cuda") if S > 1 else None
     ws.gemm_f32(dA, dB, M, N, K, C, ta=ta, lda=G * wA, ldb=N, ldc=G * N, sa=wA, sb=K * N, sc=N,
-                groups=G, beta=0.5)
+                groups=G, beta=0.5, ksplit=S, work=work)
     torch.cuda.synchronize()
     got = C.cpu().numpy().astype(np.float64)
     for g in range(G):
