@@ -46,7 +46,8 @@ struct InstState {
     int j;        // index of the last evaluated iterate S^j
     int pending;  // 1: an FP64 correction step is still owed
     int f32;      // evaluations run with FP32 sweeps
-    int pad[2];
+    int eonly;    // 1: the last evaluation stopped after the residual (no S^{j+1})
+    int pad;
 };
 
 struct IterArgs {

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
         const int b = unit / N, i = unit % N;
         Decision d;
         if (a.residual_only) {
-            d.work = true; d.j = 0; d.slot = a.res_slot;
+            d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false;
         } else {
             d = decide<PREC>(a, c, b, i, k, N, (long long)b * N);
         }
@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             v.xo = (long long)b * n;
             v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
             v.res_at = (long long)d.slot * a.rslot + (long long)b * N + i;
+            v.res_only = d.eval_only;
             v.i = i;
             v.last = i == N - 1;
             unsigned long long acc[2] = {0, 0};
@@ -270,7 +271,7 @@ __global__ void k_init(const InitArgs a)
          t += stride) {
         InstState s;
         s.status = kActive; s.mode = a.mode; s.e = 0; s.j = 0; s.pending = 0; s.f32 = 0;
-        s.pad[0] = s.pad[1] = 0;
+        s.eonly = s.pad = 0;
         a.st[t] = s;
         a.st[a.B + t] = s;
         a.iters[t] = 0;

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
     const long long us = r.ustart[b];
     Decision d;
     if (a.residual_only) {
-        d.work = true; d.j = 0; d.slot = a.res_slot;
+        d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false;
     } else {
         d = decide<PREC>(a, c, b, i, k, N, us);
     }
@@ -69,6 +69,7 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
     v.xo = r.xoff[b];
     v.xro = r.xoff[b];
     v.res_at = (long long)d.slot * a.rslot + us + i;
+    v.res_only = d.eval_only;
     v.i = i;
     v.last = i == N - 1;
     unsigned long long acc[2] = {0, 0};
@@ -122,7 +123,7 @@ __global__ void k_rg_init(const IterArgs a, const RgArgs r, int mode, const doub
     if (threadIdx.x == 0) {
         InstState s;
         s.status = kActive; s.mode = mode; s.e = 0; s.j = 0; s.pending = 0; s.f32 = 0;
-        s.pad[0] = s.pad[1] = 0;
+        s.eonly = s.pad = 0;
         a.st[b] = s;
         a.st[a.B + b] = s;
         a.iters[b] = 0;

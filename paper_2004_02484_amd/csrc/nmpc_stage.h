@@ -480,9 +480,10 @@ __device__ __forceinline__ void axx_apply(const T (&y)[RY][CX], T (&o)[RY][CX],
 // ------------------------------------------------------------- the kernel
 
 struct Decision {
-    bool work;     // evaluate and update in this kernel
-    int j;         // index of the iterate evaluated (S^j)
-    int slot;      // residual slot this evaluation accumulates into
+    bool work;       // evaluate (and update) in this kernel
+    int j;           // index of the iterate evaluated (S^j)
+    int slot;        // residual slot this evaluation accumulates into
+    bool eval_only;  // evaluate S^j only: its test is the last one owed
 };
 
 // Per-instance state machine. All workgroups of an instance compute the same
@@ -494,7 +495,9 @@ struct Decision {
 //   FP32 mode, test passed at S^j  -> REDO (FP32-active count decremented)
 //   REDO (FP64 kernel)             -> re-evaluate S^j in FP64: its update is the
 //                                     FP64 step S^{j+1}; owe the evaluation of S^{j+1}
-//   FP64 mode, test passed, owed   -> evaluate S^{j+1} (its own test decides)
+//   FP64 mode, test passed, owed   -> evaluate S^{j+1} without an update (its
+//                                     own test decides; a failed test makes
+//                                     the next step re-evaluate S^{j+1})
 //   FP64 mode, test passed         -> finished, S^j returned
 // Nb: the instance's stages; rbase: offset of its stage residuals within a
 // residual slot (slot stride a.rslot).
@@ -504,7 +507,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
 {
     const InstState s = a.st[(k & 1) * a.B + b];
     InstState ns = s;
-    Decision d{false, 0, 0};
+    Decision d{false, 0, 0, false};
     int fin = -1;
     double rs = 0.0, rp = 0.0;
     if (s.status == kActive && s.e > 0) {
@@ -548,6 +551,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                         ns.pending = 0;
                         d.work = true;
                         d.j = s.j + 1;
+                        d.eval_only = true;
                     }
                 } else {
                     fin = kStatusOk;
@@ -556,13 +560,14 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                 fin = kStatusNoconv;
             } else if (s.mode == PREC) {
                 d.work = true;
-                d.j = s.j + 1;
+                d.j = s.eonly ? s.j : s.j + 1;   // no S^{j+1} after an evaluation-only kernel
             }
         }
         if (d.work) {
             d.slot = s.e % 3;
             ns.e = s.e + 1;
             ns.j = d.j;
+            ns.eonly = d.eval_only ? 1 : 0;
             if (PREC == kModeFp32) ns.f32 = s.f32 + 1;
         }
         if (fin >= 0) ns.status = fin;
