@@ -67,6 +67,10 @@ struct nmpc_handle {
     std::vector<double> gx, gy;
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
+    // second stream of the fallback check: the cold start is built and
+    // evaluated there while the input-built start's rollout runs
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double *d_gx = nullptr, *d_gy = nullptr;
     double *d_S[2] = {nullptr, nullptr};
     double *d_x0 = nullptr, *d_xref = nullptr, *d_out = nullptr;
@@ -246,6 +250,9 @@ void release(nmpc_handle *h)
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
     if (h->ev) (void)hipEventDestroy(h->ev);
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->t0) (void)hipEventDestroy(h->t0);
     if (h->t1) (void)hipEventDestroy(h->t1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -360,13 +367,13 @@ int start_kind(const double *wx, const double *wu, const double *wl)
     return -1;
 }
 
-int launch_residual(nmpc_handle *h, int count, int buf, int slot)
+int launch_residual(nmpc_handle *h, int count, int buf, int slot, hipStream_t s = nullptr)
 {
     IterArgs a = iter_args(h, count);
     a.residual_only = 1;
     a.res_slot = slot;
     a.X[0] = h->X(buf); a.U[0] = h->U(buf); a.LAM[0] = h->L(buf);
-    return launch_iterate(h, nmpc::kModeFp64, a, h->stream);
+    return launch_iterate(h, nmpc::kModeFp64, a, s ? s : h->stream);
 }
 
 // S^0 for `count` instances in buffer 0 (and the iteration state reset):
@@ -385,12 +392,14 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
     ia.st = h->d_st;
     ia.iters = h->d_iters; ia.ctr = h->d_ctr;
+    const bool check = kind != kStartCold && h->opt.fallback && !h->streaming;
     {
         void *args[] = {(void *)&ia};
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
                                 dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
                                 0, h->stream));
     }
+    if (check) HIP_TRY(hipEventRecord(h->ev_fork, h->stream));
     if (h->streaming) {
         if (kind == kStartInputs)
             return fail(NMPC_E_UNSUPPORTED, "the streaming path takes cold or (x, u, lambda) starts");
@@ -406,23 +415,30 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         HIP_TRY(hipLaunchKernel(h->roll.fn, dim3(count), dim3(nmpc::kWave * h->roll.waves), args,
                                 h->roll.lds, h->stream));
     }
-    h->last_start_kind = kind;
-    h->last_fallback = false;
-    if (kind != kStartCold && h->opt.fallback) {
-        int rc = launch_residual(h, count, 0, 0);
-        if (rc) return rc;
-        InitArgs ic = ia;   // cold start into buffer 1, iteration state untouched
+    if (check) {
+        // fork (queued after the rollout, so the rollout's workgroups are
+        // placed first): the cold start into buffer 1 (iteration state
+        // untouched) and its residual into slot 1 on the side stream, while
+        // the main stream builds and evaluates the supplied start
+        HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+        InitArgs ic = ia;
         ic.wx = ic.wu = ic.wl = nullptr;
         ic.X = h->X(1); ic.U = h->U(1); ic.LAM = h->L(1);
         ic.trajectory_only = 1;
-        {
-            void *args[] = {(void *)&ic};
-            HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
-                                    dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256),
-                                    args, 0, h->stream));
-        }
-        rc = launch_residual(h, count, 1, 1);
+        void *args[] = {(void *)&ic};
+        HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
+                                dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
+                                0, h->side));
+        const int rc = launch_residual(h, count, 1, 1, h->side);
         if (rc) return rc;
+        HIP_TRY(hipEventRecord(h->ev_join, h->side));
+    }
+    h->last_start_kind = kind;
+    h->last_fallback = false;
+    if (check) {
+        int rc = launch_residual(h, count, 0, 0);
+        if (rc) return rc;
+        HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_join, 0));   // join
         IterArgs a = iter_args(h, count);
         a.units = count;
         int *st = h->d_start;
@@ -831,6 +847,9 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
                                 (int)h->roll.lds);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreate(&h->t0);
     if (e == hipSuccess) e = hipEventCreate(&h->t1);
 
