@@ -42,8 +42,8 @@ constexpr int kBM = 64, kBN = 64, kBK = 32, kPad = 8;
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 {
-    __shared__ unsigned short As[kBM][kBK + kPad];   // [m][k]
-    __shared__ unsigned short Bs[kBN][kBK + kPad];   // [n][k]
+    __shared__ __align__(16) unsigned short As[kBM][kBK + kPad];   // [m][k]
+    __shared__ __align__(16) unsigned short Bs[kBN][kBK + kPad];   // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
@@ -53,29 +53,52 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // each thread stages 8 consecutive elements of A and of B per K step; when
+    // they are contiguous in memory, inside the matrix and 16-byte aligned,
+    // as one 16-byte load
+    const bool vecA = !TA && (g.lda & 7) == 0 && (((uintptr_t)g.A) & 15) == 0;
+    const bool vecB = !TB && (g.ldb & 7) == 0 && (((uintptr_t)g.B) & 15) == 0;
     for (int k0 = 0; k0 < g.K; k0 += kBK) {
         // stage a 64 x 32 tile of A and of B^T (8 elements per thread each)
+        {
+            const int r0 = (tid * 8) / kBK, kk0 = (tid * 8) % kBK;   // !TA: 8 consecutive k
+            if (vecA && m0 + r0 < g.M && k0 + kk0 + 8 <= g.K) {
+                const uint4 q = *(const uint4 *)&g.A[(size_t)(m0 + r0) * g.lda + k0 + kk0];
+                *(uint4 *)&As[r0][kk0] = q;
+            } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid * 8 + e;
-            int r, kk;
-            if (TA) { kk = idx / kBM; r = idx % kBM; }   // consecutive threads walk m
-            else    { r = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
-            const int gm = m0 + r, gk = k0 + kk;
-            unsigned short v = 0;
-            if (gm < g.M && gk < g.K) v = TA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
-            As[r][kk] = v;
+                for (int e = 0; e < 8; ++e) {
+                    const int idx = tid * 8 + e;
+                    int r, kk;
+                    if (TA) { kk = idx / kBM; r = idx % kBM; }   // consecutive threads walk m
+                    else    { r = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
+                    const int gm = m0 + r, gk = k0 + kk;
+                    unsigned short v = 0;
+                    if (gm < g.M && gk < g.K) v = TA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
+                    As[r][kk] = v;
+                }
+            }
         }
+        {
+            const int kk0 = (tid * 8) / kBN, c0 = (tid * 8) % kBN;   // !TB: 8 consecutive n
+            if (vecB && k0 + kk0 < g.K && n0 + c0 + 8 <= g.N) {
+                const uint4 q = *(const uint4 *)&g.B[(size_t)(k0 + kk0) * g.ldb + n0 + c0];
+                const unsigned short *qs = (const unsigned short *)&q;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int idx = tid * 8 + e;
-            int c, kk;
-            if (TB) { c = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
-            else    { kk = idx / kBN; c = idx % kBN; }   // consecutive threads walk n
-            const int gn = n0 + c, gk = k0 + kk;
-            unsigned short v = 0;
-            if (gn < g.N && gk < g.K) v = TB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
-            Bs[c][kk] = v;
+                for (int e = 0; e < 8; ++e) Bs[c0 + e][kk0] = qs[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int idx = tid * 8 + e;
+                    int c, kk;
+                    if (TB) { c = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
+                    else    { kk = idx / kBN; c = idx % kBN; }   // consecutive threads walk n
+                    const int gn = n0 + c, gk = k0 + kk;
+                    unsigned short v = 0;
+                    if (gn < g.N && gk < g.K) v = TB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
+                    Bs[c][kk] = v;
+                }
+            }
         }
         __syncthreads();
 #pragma unroll
