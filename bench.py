@@ -371,6 +371,10 @@ def main():
     ap.add_argument("--upper", choices=list(UPPER), default="jacobi",
                     help="upper-layer splitting: Jacobi (default: every stage in parallel), or "
                          "the Gauss-Seidel sweeps SGS, FGS, BGS")
+    ap.add_argument("--n-sweep", type=int, default=2,
+                    help="point-Jacobi sweeps per lower-layer solve (the paper's 2)")
+    ap.add_argument("--n-schur", type=int, default=2,
+                    help="Schur input iterations of the lower layer (the paper's 2)")
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -404,8 +408,10 @@ def main():
     # and costates from the predicted inputs (20 keep the rollout's error far
     # below the tolerance on this grid and step; 12 leave an error the upper
     # iteration takes about four times longer to remove)
+    inner = dict(n_sweep=args.n_sweep, n_schur=args.n_schur)
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
-                       check_every=16, fallback=1, upper=UPPER[args.upper], warm_sweeps=20)
+                       check_every=16, fallback=1, upper=UPPER[args.upper], warm_sweeps=20,
+                       **inner)
     kind = "jacobi" if args.upper == "jacobi" else "gs"
     net = None
     if args.start == "learned":
@@ -451,7 +457,7 @@ def main():
     cfg = {"workload": "2D nonlinear heat 64x64, N=40, 16 Gaussian inputs, batch 256, "
                        f"{start_desc}, {args.upper.upper()} upper layer, tol 1e-6",
            "global_batch": B, "grid": "64x64", "horizon": P.N, "start": args.start,
-           "upper": args.upper,
+           "upper": args.upper, "n_sweep": args.n_sweep, "n_schur": args.n_schur,
            "iters_min": int(min(iters)), "iters_max": int(max(iters)),
            "iters_mean": round(float(np.mean(iters)), 1), "status_worst": worst,
            "step_ms_median": round(1e3 * float(np.median(times)), 2),
@@ -475,7 +481,7 @@ def main():
             if up == args.upper or up in ("fgs", "bgs"):
                 continue
             s2 = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
-                           check_every=16, fallback=1, upper=UPPER[up])
+                           check_every=16, fallback=1, upper=UPPER[up], **inner)
             timed_steps(s2, dev_in[:1], out)
             t2, it2, _, w2 = timed_steps(s2, dev_in[args.warmup:], out)
             r2 = solves / sum(t2)
