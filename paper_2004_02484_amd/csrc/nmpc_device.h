@@ -70,6 +70,7 @@ struct IterArgs {
     double tol;
     int max_iter, n_sw, n_schur;
     int residual_only, res_slot;
+    int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
 };
 

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
     const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
     if (unit < a.units) {
         const int N = a.P.N, n = a.P.n, M = LX * LY;
-        const int b = unit / N, i = unit % N;
+        const int b = a.res_first_stage ? unit : unit / N, i = a.res_first_stage ? 0 : unit % N;
         Decision d;
         if (a.residual_only) {
             d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false;
@@ -200,7 +200,10 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
 
 // Fallback between two starts, per instance: keep buffer 0's start unless its
 // residual (slot 0) is non-finite or larger than that of the start in buffer
-// 1 (slot 1). start_used[b] = used_if_kept, or 0 (the buffer-1 start).
+// 1 (slot 1). start_used[b] = used_if_kept, or 0 (the buffer-1 start). With
+// res_first_stage, slot 1 holds the buffer-1 start's stage-0 residual only
+// (a cold start with one reference for all stages has the same residual at
+// every stage).
 __global__ void k_choose_flags(const IterArgs a, int *start_used, int used_if_kept)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +212,7 @@ __global__ void k_choose_flags(const IterArgs a, int *start_used, int used_if_ke
     unsigned long long mw = 0, mc = 0;
     for (size_t i = 0; i < N; ++i) {
         mw = umax64(mw, a.rst[(size_t)b * N + i]);
-        mc = umax64(mc, a.rst[((size_t)a.B + b) * N + i]);
+        if (!a.res_first_stage || i == 0) mc = umax64(mc, a.rst[((size_t)a.B + b) * N + i]);
     }
     start_used[b] = (bits2d(mw) <= bits2d(mc)) ? used_if_kept : 0;
 }

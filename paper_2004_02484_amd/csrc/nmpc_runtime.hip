@@ -367,11 +367,17 @@ int start_kind(const double *wx, const double *wu, const double *wl)
     return -1;
 }
 
-int launch_residual(nmpc_handle *h, int count, int buf, int slot, hipStream_t s = nullptr)
+int launch_residual(nmpc_handle *h, int count, int buf, int slot, hipStream_t s = nullptr,
+                    bool first_stage = false)
 {
     IterArgs a = iter_args(h, count);
     a.residual_only = 1;
     a.res_slot = slot;
+    if (first_stage) {   // one unit per instance: stage 0
+        a.res_first_stage = 1;
+        a.units = count;
+        a.per_xcd = (count + 7) / 8;
+    }
     a.X[0] = h->X(buf); a.U[0] = h->U(buf); a.LAM[0] = h->L(buf);
     return launch_iterate(h, nmpc::kModeFp64, a, s ? s : h->stream);
 }
@@ -429,7 +435,9 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
                                 dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
                                 0, h->side));
-        const int rc = launch_residual(h, count, 1, 1, h->side);
+        // with one reference for all stages the cold start's stage residuals
+        // are all equal (x_i = x0, u = 0, lambda = 0): stage 0 stands for all
+        const int rc = launch_residual(h, count, 1, 1, h->side, !h->opt.xref_per_stage);
         if (rc) return rc;
         HIP_TRY(hipEventRecord(h->ev_join, h->side));
     }
@@ -441,6 +449,7 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_join, 0));   // join
         IterArgs a = iter_args(h, count);
         a.units = count;
+        a.res_first_stage = !h->opt.xref_per_stage;
         int *st = h->d_start;
         int used = kind;
         {
