@@ -469,3 +469,38 @@ def test_gauss_seidel_fixed_point_is_jacobis(upper):
     assert oj["status"] == og["status"] == "converged"
     np.testing.assert_allclose(og["U"], oj["U"], atol=1e-9 * np.abs(oj["U"]).max())
     assert og["iters"] < oj["iters"]
+
+
+# ----------------------------------------- cold start: every stage the same
+
+@pytest.mark.parametrize("which", ["tiny", "c1"])
+def test_cold_start_rows_equal_at_every_stage(which):
+    """The cold start (x_i = x0, u_i = 0, lambda_i = 0) with one reference for
+    all stages has the same KKT rows at every stage: K^x_i = -h f(x0, 0) (the
+    backward-Euler step from x_{i-1} = x0 at every stage, the initial state
+    included), K^u_i = 0, and the costate row reduces to the stage-cost
+    gradient (no costate terms). So one stage's residual is the whole start's,
+    which the library's fallback check relies on. Checked against the dense
+    reference's rows; a per-stage reference breaks the equality."""
+    if which == "tiny":
+        P = tiny2d(N=5)
+        x0, xref, *_ = tiny_data(P, seed=3)
+    else:
+        P = make_problem("c1").with_(N=6)
+        x0, xref = make_instance(P, 11)
+    X, U, LAM = oracle.cold_start(P, x0)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM)
+    dX, dU, dL = dense.kkt(P, x0, xref, X, U, LAM)
+    np.testing.assert_allclose(KX, dX, rtol=0, atol=1e-13 * max(1.0, np.abs(dX).max()))
+    np.testing.assert_allclose(KL, dL, rtol=0, atol=1e-13 * max(1.0, np.abs(dL).max()))
+    assert np.abs(KU).max() == 0.0
+    for i in range(1, P.N):
+        np.testing.assert_array_equal(KX[i], KX[0])
+        np.testing.assert_array_equal(KL[i], KL[0])
+    assert np.abs(KX[0]).max() > 0 and np.abs(KL[0]).max() > 0
+    rs_all, rp_all = oracle.norms(P, KX, KU, KL)
+    rs_0, rp_0 = oracle.norms(P, KX[:1].repeat(P.N, 0), KU, KL[:1].repeat(P.N, 0))
+    assert rs_all == rs_0 and rp_all == rp_0
+    xr2 = np.stack([np.asarray(xref) * (1 + 0.1 * i) for i in range(P.N)])
+    _, _, KL2 = oracle.kkt(P, x0, xr2, X, U, LAM)
+    assert np.abs(KL2[1] - KL2[0]).max() > 0
