@@ -73,11 +73,11 @@ def _load():
                                   ctypes.POINTER(ctypes.c_int), dp, dp, dp]
         lib.ref_solve.restype = ctypes.c_int
         lib.ref_gs_sweep.argtypes = [pp, dp, dp, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int,
-                                     ctypes.c_int, ctypes.c_int]
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_double]
         lib.ref_gs_sweep.restype = None
         lib.ref_solve_gs.argtypes = [pp, dp, dp, ctypes.c_int, dp, dp, dp, ctypes.c_int,
                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp]
+                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, ctypes.c_double]
         lib.ref_solve_gs.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -173,25 +173,28 @@ STATUS = {0: "converged", 1: "max_iter", 2: "nonfinite"}
 UPPER = {"jacobi": 0, "fgs": 1, "bgs": 2, "sgs": 3}
 
 
-def gs_sweep(P: Problem, x0, xref, X, U, LAM, direction: int, n_sw=2, n_schur=2, UT=None):
+def gs_sweep(P: Problem, x0, xref, X, U, LAM, direction: int, n_sw=2, n_schur=2, UT=None,
+             omega=1.0):
     """One Gauss-Seidel sweep (direction +1 forward, -1 backward) on copies;
     returns the new (X, U, LAM). UT: regularization reference (default: each
-    stage's input at its visit)."""
+    stage's input at its visit). omega: over-relaxation of each stage's step
+    (SOR, Sec. 4.4)."""
     lib = _load()
     C = _Ctx(P)
     xr, st = _xref(P, xref)
     X, U, LAM = _c(X).copy(), _c(U).copy(), _c(LAM).copy()
     ut = None if UT is None else _d(_c(UT))
     lib.ref_gs_sweep(C.ptr, _d(_c(x0)), _d(xr), st, _d(X), _d(U), _d(LAM), ut, int(direction),
-                     n_sw, n_schur)
+                     n_sw, n_schur, float(omega))
     return X, U, LAM
 
 
 def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_schur=2,
-          trace=False, upper="jacobi"):
+          trace=False, upper="jacobi", omega=1.0):
     """Run the upper iteration from ``start`` (default cold) to r_scaled <= tol.
 
-    upper: "jacobi" (eq. 1st_jacobi), "fgs" (eq. fgs), "bgs" or "sgs" (eq. sgs).
+    upper: "jacobi" (eq. 1st_jacobi), "fgs" (eq. fgs), "bgs" or "sgs" (eq. sgs);
+    omega: over-relaxation of the Gauss-Seidel sweeps (SOR / SSOR, Sec. 4.4).
     Returns a dict with X, U, LAM (the last evaluated iterate S^k), iters = k,
     r_scaled, r_paper, status and, if ``trace``, rhist[0..k].
     """
@@ -202,6 +205,8 @@ def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_s
     X, U, LAM = _c(X).copy(), _c(U).copy(), _c(LAM).copy()
     it = ctypes.c_int(); rs = ctypes.c_double(); rp = ctypes.c_double()
     hist = np.zeros(max_iter + 1) if trace else None
+    if UPPER[upper] == 0 and omega != 1.0:
+        raise ValueError("over-relaxation applies to the Gauss-Seidel sweeps")
     if UPPER[upper] == 0:
         status = lib.ref_solve(C.ptr, _d(_c(x0)), _d(xr), st, _d(X), _d(U), _d(LAM), tol,
                                max_iter, n_sw, n_schur, ctypes.byref(it), ctypes.byref(rs),
@@ -210,7 +215,7 @@ def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_s
         status = lib.ref_solve_gs(C.ptr, _d(_c(x0)), _d(xr), st, _d(X), _d(U), _d(LAM),
                                   UPPER[upper], tol, max_iter, n_sw, n_schur, ctypes.byref(it),
                                   ctypes.byref(rs), ctypes.byref(rp),
-                                  _d(hist) if trace else None)
+                                  _d(hist) if trace else None, float(omega))
     out = dict(X=X, U=U, LAM=LAM, iters=it.value, r_scaled=rs.value, r_paper=rp.value,
                status=STATUS[status])
     if trace:

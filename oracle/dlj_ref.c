@@ -409,10 +409,13 @@ int ref_solve(const ref_problem *P, const double *x0, const double *xref, int xr
  * (BGS), with L / U the blocks coupling a stage to the previous / next one.
  * UT (may be NULL) is the regularization reference u~ of every stage: NULL
  * means the stage's input at its visit, which is u^k in a single sweep.
+ * omega scales every stage's step (successive over-relaxation, Sec. 4.4): a
+ * forward sweep is then S - omega (D^k + omega L)^{-1} K^k, and omega = 1 is
+ * the plain sweep.
  */
 void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
                   double *X, double *U, double *LAM, const double *UT, int dir, int n_sw,
-                  int n_schur)
+                  int n_schur, double omega)
 {
     int n = ref_n(P), m = P->m, N = P->N;
     double *w = (double *)malloc(sizeof(double) * (size_t)(4 * n + 2 * m));
@@ -424,10 +427,10 @@ void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, in
         ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n, kx, kl, ku, n_sw, n_schur,
                         dx, du, dl);
         for (int p = 0; p < n; ++p) {
-            X[(size_t)i * n + p] -= dx[p];
-            LAM[(size_t)i * n + p] -= dl[p];
+            X[(size_t)i * n + p] -= omega * dx[p];
+            LAM[(size_t)i * n + p] -= omega * dl[p];
         }
-        for (int j = 0; j < m; ++j) U[(size_t)i * m + j] -= du[j];
+        for (int j = 0; j < m; ++j) U[(size_t)i * m + j] -= omega * du[j];
     }
     free(w);
 }
@@ -438,12 +441,13 @@ void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, in
  * with the regularization reference u~ = u^k of the iteration; in the linear
  * case this is eq. sgs exactly). Every iteration first evaluates K(S^k) and
  * its norms for the stopping test, exactly as ref_solve does; the returned
- * trajectory is the last evaluated iterate S^k.
+ * trajectory is the last evaluated iterate S^k. omega: the over-relaxation of
+ * every sweep (SOR forward, backward; SSOR for SGS).
  */
 int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
                  double *X, double *U, double *LAM, int upper, double tol, int max_iter,
                  int n_sw, int n_schur, int *iters, double *r_scaled, double *r_paper,
-                 double *rhist)
+                 double *rhist, double omega)
 {
     int n = ref_n(P), m = P->m, N = P->N, k = 0, status = 1;
     double *KX = (double *)malloc(sizeof(double) * (size_t)N * n);
@@ -459,13 +463,13 @@ int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int
         if (rs <= tol) { status = 0; break; }
         if (k >= max_iter) { status = 1; break; }
         if (upper == 1) {
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, +1, n_sw, n_schur);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, +1, n_sw, n_schur, omega);
         } else if (upper == 2) {
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega);
         } else {
             memcpy(UK, U, sizeof(double) * (size_t)N * m);
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur);
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UK, +1, n_sw, n_schur);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega);
+            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UK, +1, n_sw, n_schur, omega);
         }
         ++k;
     }

@@ -504,3 +504,44 @@ def test_cold_start_rows_equal_at_every_stage(which):
     xr2 = np.stack([np.asarray(xref) * (1 + 0.1 * i) for i in range(P.N)])
     _, _, KL2 = oracle.kkt(P, x0, xr2, X, U, LAM)
     assert np.abs(KL2[1] - KL2[0]).max() > 0
+
+
+# -------------------------------------------- SOR: over-relaxed sweeps (Sec. 4.4)
+
+@pytest.mark.parametrize("direction", [1, -1])
+@pytest.mark.parametrize("omega", [0.7, 1.3])
+def test_sor_sweep_is_the_papers_relaxed_step(direction, omega):
+    """A forward sweep with over-relaxation omega equals
+    S - omega (D^k + omega L)^{-1} K^k (the paper's SOR step with alpha = 1),
+    a backward one S - omega (D^k + omega U)^{-1} K^k, on a nonlinear instance
+    (same reason as the plain sweep: K_i is affine in the neighbour stages with
+    the coupling blocks as coefficients, D_i depends on s_i only)."""
+    P = tiny2d(N=4)
+    x0, xref, X, U, LAM, _ = tiny_data(P, seed=22)
+    Xn, Un, Ln = oracle.gs_sweep(P, x0, xref, X, U, LAM, direction, n_sw=400, n_schur=60,
+                                 omega=omega)
+    J = dense.jacobian(P, X, U, LAM)
+    D, L, Up = _tri_parts(J, P)
+    K = dense.pack(*dense.kkt(P, x0, xref, X, U, LAM))
+    C = L if direction > 0 else Up
+    Sn = dense.pack(X, U, LAM) - omega * np.linalg.solve(D + omega * C, K)
+    got = dense.pack(Xn, Un, Ln)
+    assert np.abs(got - Sn).max() <= 1e-9 * np.abs(Sn).max()
+    # omega = 1 is the plain sweep, bit for bit
+    a = oracle.gs_sweep(P, x0, xref, X, U, LAM, direction, omega=1.0)
+    b = oracle.gs_sweep(P, x0, xref, X, U, LAM, direction)
+    for p, q in zip(a, b):
+        np.testing.assert_array_equal(p, q)
+
+
+@pytest.mark.parametrize("upper", ["fgs", "sgs"])
+def test_sor_fixed_point_is_jacobis(upper):
+    """Over-relaxation changes the rate, not the KKT point."""
+    P = make_problem("c0")
+    x0, xref = make_instance(P, 3)
+    oj = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    og = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000, upper=upper, omega=1.2)
+    assert oj["status"] == og["status"] == "converged"
+    np.testing.assert_allclose(og["U"], oj["U"], atol=1e-9 * np.abs(oj["U"]).max())
+    with pytest.raises(ValueError):
+        oracle.solve(P, x0, xref, omega=1.2)
