@@ -122,6 +122,12 @@ typedef struct nmpc_options {
                              Jacobi upper layer, cold or given starts, no
                              fallback); NMPC_PATH_AUTO (default): fused where
                              it fits, else streaming */
+    double omega;         /* over-relaxation of the Gauss-Seidel sweeps
+                             (Sec. 4.4): each stage's step is scaled by omega,
+                             so FGS becomes SOR, S - omega (D + omega L)^{-1} K,
+                             BGS its backward form and SGS the symmetric SSOR;
+                             0 < omega < 2, default 1. The Jacobi upper layer
+                             takes omega = 1 only (NMPC_E_ARG otherwise) */
 } nmpc_options;
 
 /* Per-instance result information. */

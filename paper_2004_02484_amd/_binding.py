@@ -44,7 +44,8 @@ class nmpc_options(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
-                ("upper", ctypes.c_int32), ("path", ctypes.c_int32)]
+                ("upper", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("omega", ctypes.c_double)]
 
 
 class nmpc_info(ctypes.Structure):

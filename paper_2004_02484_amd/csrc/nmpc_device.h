@@ -72,6 +72,7 @@ struct IterArgs {
     int residual_only, res_slot;
     int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
+    double omega;                   // Gauss-Seidel kernel: over-relaxation of each stage's step
 };
 
 struct InitArgs {

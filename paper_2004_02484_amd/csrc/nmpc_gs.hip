@@ -42,6 +42,7 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.utb = utb;
     v.res_at = res ? -1 : -2;
     v.res_only = res_only;
+    v.omega = a.omega;
     // forward: x_{i-1} updated (dst), lambda_{i+1} not yet (src); backward:
     // the reverse. The residual of S^j takes both from src.
     v.xpb = dir > 0 ? dst : src;

@@ -187,6 +187,10 @@ int check_options(const nmpc_options *o)
         return fail(NMPC_E_ARG, "unknown upper layer");
     if (o->path < NMPC_PATH_AUTO || o->path > NMPC_PATH_STREAM)
         return fail(NMPC_E_ARG, "unknown kernel path");
+    if (!(o->omega > 0.0 && o->omega < 2.0))
+        return fail(NMPC_E_ARG, "omega must lie in (0, 2)");
+    if (o->upper == NMPC_UPPER_JACOBI && o->omega != 1.0)
+        return fail(NMPC_E_ARG, "over-relaxation (omega != 1) needs a Gauss-Seidel upper layer");
     return NMPC_OK;
 }
 
@@ -285,6 +289,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.rslot = (long long)h->max_batch * h->N;
     a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
     a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
+    a.omega = h->opt.omega;
     a.residual_only = 0;
     return a;
 }
@@ -761,6 +766,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->fallback = 0;
     opt->upper = NMPC_UPPER_JACOBI;
     opt->path = NMPC_PATH_AUTO;
+    opt->omega = 1.0;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,

@@ -604,6 +604,7 @@ struct StageLoc {
     int i, src, dst, xpb, xrb, lnb, lrb, utb;
     bool last;                     // i is the last stage
     bool res_only;                 // stop after the residual (no lower layer, no update)
+    double omega;                  // the update is S^j - omega ds (1: the plain step)
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
     int pnb, pni;                  // stage pni of buffer pnb is prefetched once this stage
                                    // has read its own (pnb < 0: none)
@@ -637,6 +638,7 @@ __device__ __forceinline__ StageLoc jacobi_loc(int cur)
     StageLoc v{};
     v.src = v.xpb = v.xrb = v.lnb = v.lrb = cur;
     v.dst = cur ^ 1;
+    v.omega = 1.0;
     v.utb = -1;
     v.pnb = -1;
     return v;
@@ -892,19 +894,20 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         jac_ft<T, CX, RY>(cc, y4, K, a.n_sw, c);         // v1 = dlam
     }
 
-    // ---- update S^{j+1} = S^j - ds (FP64); x_i, lam_i re-read (L2-resident)
+    // ---- update S^{j+1} = S^j - omega ds (FP64); x_i, lam_i re-read (L2-resident)
     double *Xn = a.X[v.dst] + si;
     double *Lw = a.LAM[v.dst] + si;
+    const double om = v.omega;
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll
         for (int q = 0; q < CX; ++q)
             if (valid(t, q)) {
                 const int p = pidx(t, q);
-                Xn[p] = Xc[p] - double(y5[t][q]);
-                Lw[p] = Lc[p] - double(y4[t][q]);
+                Xn[p] = Xc[p] - om * double(y5[t][q]);
+                Lw[p] = Lc[p] - om * double(y4[t][q]);
             }
-    if (c.tid < M) a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - v3[c.tid];
+    if (c.tid < M) a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - om * v3[c.tid];
 }
 
 // The separable input factors gx [LX][nsx], gy [LY][nsy] into LDS (double and

@@ -155,3 +155,27 @@ def test_sgs_autotune_keeps_the_results(nm):
     print(f"SGS tile rows {tr}, waves {cfg['waves']}")
     _, _, U1, _, _ = s.solve_batch(X0, XR)
     assert rel(U1.cpu().numpy(), U0) <= 1e-5
+
+
+@pytest.mark.parametrize("upper", ["fgs", "bgs", "sgs"])
+@pytest.mark.parametrize("omega", [0.8, 1.3])
+def test_sor_iterates_match_oracle(nm, upper, omega):
+    """Over-relaxed sweeps (SOR, backward SOR, SSOR): the first iterates match
+    the oracle's relaxed sweeps, and the solve converges to the Jacobi fixed
+    point with the oracle's iteration count."""
+    P = shaped(13, 37, 6, 2)
+    x0, xref = make_instance(P, 5)
+    for k in (1, 3):
+        s = nm.Solver(P, tol=0.0, max_iter=k, upper=UPPERS[upper], omega=omega)
+        rc, X, U, L, info = s.solve(x0, xref)
+        s.close()
+        o = oracle.solve(P, x0, xref, tol=0.0, max_iter=k, upper=upper, omega=omega)
+        assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+        assert rel(X, o["X"]) <= REL and rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
+    s = nm.Solver(P, tol=1e-8, max_iter=5000, upper=UPPERS[upper], omega=omega)
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-8, max_iter=5000, upper=upper, omega=omega)
+    assert rc == nm.NMPC_OK and o["status"] == "converged"
+    assert abs(info["iters"] - o["iters"]) <= 1
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=50000)
+    assert rel(U, ex["U"]) <= 1e-6
