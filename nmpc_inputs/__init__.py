@@ -56,6 +56,9 @@ class Problem:
     q: float = 1.0      # state weight (Q = q I)
     r: float = 0.01     # input weight (R = r I)
     gamma: float = 0.0  # regularization weight
+    tau: float = 0.0    # barrier weight of the input box u_lo <= u <= u_hi (0: no box)
+    u_lo: float = 0.0
+    u_hi: float = 0.0
     name: str = ""
 
     @property

@@ -44,7 +44,8 @@ class _RefProblem(ctypes.Structure):
                 ("N", ctypes.c_int), ("m", ctypes.c_int),
                 ("B", ctypes.POINTER(ctypes.c_double)),
                 ("h", ctypes.c_double), ("k0", ctypes.c_double), ("k1", ctypes.c_double),
-                ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double)]
+                ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("tau", ctypes.c_double), ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double)]
 
 
 _lib = None
@@ -62,7 +63,9 @@ def _load():
         lib.ref_kkt.restype = None
         lib.ref_norms.argtypes = [pp, dp, dp, dp, dp, dp]
         lib.ref_norms.restype = None
-        lib.ref_stage_solve.argtypes = [pp, dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
+        lib.ref_alpha_max.argtypes = [pp, dp, dp]
+        lib.ref_alpha_max.restype = ctypes.c_double
+        lib.ref_stage_solve.argtypes = [pp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ctypes.c_int,
                                         dp, dp, dp]
         lib.ref_stage_solve.restype = None
         lib.ref_iterate.argtypes = [pp, dp, dp, ctypes.c_int, dp, dp, dp, dp, dp, dp,
@@ -93,7 +96,7 @@ class _Ctx:
     def __init__(self, P: Problem):
         self.B = np.ascontiguousarray(P.dense_B(), dtype=np.float64)
         self.s = _RefProblem(P.dim, P.nsx, P.nsy, P.N, P.m, _d(self.B),
-                             P.h, P.k0, P.k1, P.q, P.r, P.gamma)
+                             P.h, P.k0, P.k1, P.q, P.r, P.gamma, P.tau, P.u_lo, P.u_hi)
         self.P = P
 
     @property
@@ -145,13 +148,22 @@ def residual(P: Problem, x0, xref, X, U, LAM):
     return norms(P, *kkt(P, x0, xref, X, U, LAM))
 
 
-def stage_solve(P: Problem, x, lam, b1, b2, b3, n_sw=2, n_schur=2):
+def stage_solve(P: Problem, x, lam, b1, b2, b3, n_sw=2, n_schur=2, u=None):
+    """Lower layer of one stage; u: the stage's inputs (needed with an input box)."""
     lib = _load()
     C = _Ctx(P)
     dx = np.zeros(P.n); du = np.zeros(P.m); dl = np.zeros(P.n)
-    lib.ref_stage_solve(C.ptr, _d(_c(x)), _d(_c(lam)), _d(_c(b1)), _d(_c(b2)), _d(_c(b3)),
-                        n_sw, n_schur, _d(dx), _d(du), _d(dl))
+    lib.ref_stage_solve(C.ptr, _d(_c(x)), _d(_c(lam)), None if u is None else _d(_c(u)),
+                        _d(_c(b1)), _d(_c(b2)), _d(_c(b3)), n_sw, n_schur, _d(dx), _d(du),
+                        _d(dl))
     return dx, du, dl
+
+
+def alpha_max(P: Problem, U, DU):
+    """Fraction-to-the-boundary step (eq. eq_alphamax) for inputs U and steps DU [N][m]."""
+    lib = _load()
+    C = _Ctx(P)
+    return lib.ref_alpha_max(C.ptr, _d(_c(U)), _d(_c(DU)))
 
 
 def iterate(P: Problem, x0, xref, X, U, LAM, n_sw=2, n_schur=2):
@@ -207,6 +219,8 @@ def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_s
     hist = np.zeros(max_iter + 1) if trace else None
     if UPPER[upper] == 0 and omega != 1.0:
         raise ValueError("over-relaxation applies to the Gauss-Seidel sweeps")
+    if UPPER[upper] != 0 and P.tau > 0.0:
+        raise ValueError("the input box (tau > 0) is provided with the Jacobi upper layer")
     if UPPER[upper] == 0:
         status = lib.ref_solve(C.ptr, _d(_c(x0)), _d(xr), st, _d(X), _d(U), _d(LAM), tol,
                                max_iter, n_sw, n_schur, ctypes.byref(it), ctypes.byref(rs),

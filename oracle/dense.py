@@ -62,6 +62,47 @@ def hxx_mat(P: Problem, L, lam):
     return P.q * np.eye(L.shape[0]) + kp * (lam[:, None] * L + L * lam[None, :])
 
 
+def barrier(P: Problem, u):
+    """Phi(u) = -tau sum_j (ln(u_j - u_lo) + ln(u_hi - u_j)) (eq. nlp_relaxed with
+    the input box as G); 0 without a box (tau = 0)."""
+    if P.tau <= 0.0:
+        return 0.0
+    return -P.tau * float(np.sum(np.log(u - P.u_lo) + np.log(P.u_hi - u)))
+
+
+def barrier_grad(P: Problem, u):
+    if P.tau <= 0.0:
+        return np.zeros_like(u)
+    return -P.tau / (u - P.u_lo) + P.tau / (P.u_hi - u)
+
+
+def barrier_hess(P: Problem, u):
+    """Diagonal of the barrier's Hessian."""
+    if P.tau <= 0.0:
+        return np.zeros_like(u)
+    return P.tau / (u - P.u_lo) ** 2 + P.tau / (P.u_hi - u) ** 2
+
+
+def alpha_max(P: Problem, U, DU):
+    """Largest alpha in (0, 1] with G(u - alpha du) >= 0.005 G(u) for every input
+    (eq. eq_alphamax), by bisection on the rule itself (no closed form used)."""
+    if P.tau <= 0.0:
+        return 1.0
+    U = np.asarray(U); DU = np.asarray(DU)
+
+    def ok(a):
+        un = U - a * DU
+        return (np.all(un - P.u_lo >= 0.005 * (U - P.u_lo))
+                and np.all(P.u_hi - un >= 0.005 * (P.u_hi - U)))
+    if ok(1.0):
+        return 1.0
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if ok(mid) else (lo, mid)
+    return lo
+
+
 def kkt(P: Problem, x0, xref, X, U, LAM, UT=None):
     """(KX [N,n], KU [N,m], KL [N,n]); UT None means ut = u (gamma term zero)."""
     L = lap_matrix(P)
@@ -73,7 +114,7 @@ def kkt(P: Problem, x0, xref, X, U, LAM, UT=None):
         x, u, lam = X[i], U[i], LAM[i]
         KX[i] = xp - x + P.h * f_dyn(P, L, B, x, u)
         reg = 0.0 if UT is None else P.gamma * (u - UT[i])
-        KU[i] = P.h * (P.r * u + B.T @ lam) + reg
+        KU[i] = P.h * (P.r * u + barrier_grad(P, u) + B.T @ lam) + reg
         lnext = LAM[i + 1] if i + 1 < N else np.zeros(P.n)
         KL[i] = lnext - lam + P.h * (P.q * (x - _ref(P, xref, i)) + fx_mat(P, L, x).T @ lam)
     return KX, KU, KL
@@ -88,14 +129,15 @@ def norms(P: Problem, KX, KU, KL):
 
 
 def lagrangian(P: Problem, x0, xref, X, U, LAM, UT=None):
-    """sum_i h l_i + gamma/2 |u_i - ut_i|^2 + lam_i^T (x_{i-1} - x_i + h f(u_i, x_i))."""
+    """sum_i h (l_i + Phi(u_i)) + gamma/2 |u_i - ut_i|^2
+    + lam_i^T (x_{i-1} - x_i + h f(u_i, x_i))."""
     L = lap_matrix(P)
     B = P.dense_B()
     tot = 0.0
     for i in range(P.N):
         xp = x0 if i == 0 else X[i - 1]
         d = X[i] - _ref(P, xref, i)
-        tot += P.h * 0.5 * (P.q * d @ d + P.r * U[i] @ U[i])
+        tot += P.h * 0.5 * (P.q * d @ d + P.r * U[i] @ U[i]) + P.h * barrier(P, U[i])
         if UT is not None:
             e = U[i] - UT[i]
             tot += 0.5 * P.gamma * e @ e
@@ -117,14 +159,16 @@ def pack_K(KX, KU, KL):
     return pack(KX, KU, KL)
 
 
-def stage_block(P: Problem, L, B, x, lam, gamma):
-    """D_i = grad_{s_i} K_i (rows: state, input, costate; cols: x, u, lam)."""
+def stage_block(P: Problem, L, B, x, lam, gamma, u=None):
+    """D_i = grad_{s_i} K_i (rows: state, input, costate; cols: x, u, lam); u: the
+    stage's inputs (the barrier's Hessian; needed with an input box)."""
     n, m, h = P.n, P.m, P.h
     Fx = fx_mat(P, L, x)
     D = np.zeros((2 * n + m, 2 * n + m))
     D[:n, :n] = h * Fx - np.eye(n)
     D[:n, n:n + m] = h * B
-    D[n:n + m, n:n + m] = (h * P.r + gamma) * np.eye(m)
+    bh = np.zeros(m) if u is None else barrier_hess(P, np.asarray(u))
+    D[n:n + m, n:n + m] = np.diag(h * (P.r + bh) + gamma)
     D[n:n + m, n + m:] = h * B.T
     D[n + m:, :n] = h * hxx_mat(P, L, lam)
     D[n + m:, n + m:] = h * Fx.T - np.eye(n)
@@ -140,7 +184,7 @@ def jacobian(P: Problem, X, U, LAM, gamma=None):
     w = 2 * n + m
     J = np.zeros((N * w, N * w))
     for i in range(N):
-        J[i * w:(i + 1) * w, i * w:(i + 1) * w] = stage_block(P, L, B, X[i], LAM[i], gamma)
+        J[i * w:(i + 1) * w, i * w:(i + 1) * w] = stage_block(P, L, B, X[i], LAM[i], gamma, U[i])
         if i > 0:      # M_L: state row of stage i on x_{i-1}
             J[i * w:i * w + n, (i - 1) * w:(i - 1) * w + n] = np.eye(n)
         if i + 1 < N:  # M_U: costate row of stage i on lam_{i+1}

@@ -9,8 +9,12 @@
  * Everything is written as plain loops over explicit matrix rows so that it can
  * be checked against the paper by eye:
  *   - problem:   N-stage backward-Euler NMPC (Sec. 3, eq. nlp), stage cost
- *                l = 0.5 q |x - xref|^2 + 0.5 r |u|^2, no inequality constraints
- *                (barrier term and fraction-to-boundary rule inactive: alpha = 1);
+ *                l = 0.5 q |x - xref|^2 + 0.5 r |u|^2; with tau > 0 the input
+ *                box u_lo <= u <= u_hi enters as the log barrier
+ *                Phi = -tau sum_j (ln(u_j - u_lo) + ln(u_hi - u_j)) of the
+ *                relaxed problem (eq. nlp_relaxed) and the Jacobi step is cut
+ *                by the fraction-to-the-boundary rule (eq. eq_alphamax);
+ *                tau = 0: no inequality constraints, alpha = 1;
  *   - dynamics:  f(u, x) = k(x) .* (L x) + B u, k(w) = k0 (1 + k1 w), L the
  *                central-difference Laplacian with zero Dirichlet values
  *                (class of eq. pde, discretization of Sec. 2.1);
@@ -35,9 +39,25 @@ typedef struct {
     int dim, nsx, nsy, N, m;
     const double *B;                 /* [n][m] */
     double h, k0, k1, q, r, gamma;
+    double tau, u_lo, u_hi;          /* input box by log barrier; tau = 0: none */
 } ref_problem;
 
 static int ref_n(const ref_problem *P) { return P->nsx * P->nsy; }
+
+/* Barrier Phi(u) = -tau sum_j (ln(u_j - u_lo) + ln(u_hi - u_j)) of the
+ * input box (eq. nlp_relaxed with G = (u - u_lo, u_hi - u)): its gradient and
+ * the diagonal of its Hessian for one input; 0 without a box. */
+static double bar_grad(const ref_problem *P, double u)
+{
+    if (P->tau <= 0.0) return 0.0;
+    return -P->tau / (u - P->u_lo) + P->tau / (P->u_hi - u);
+}
+static double bar_hess(const ref_problem *P, double u)
+{
+    if (P->tau <= 0.0) return 0.0;
+    double a = u - P->u_lo, b = P->u_hi - u;
+    return P->tau / (a * a) + P->tau / (b * b);
+}
 
 /* Conductivity k(w) = k0 (1 + k1 w) and its derivative k' = k0 k1. */
 static double cond(const ref_problem *P, double w) { return P->k0 * (1.0 + P->k1 * w); }
@@ -109,7 +129,7 @@ static void dfx_T_apply(const ref_problem *P, const double *x, const double *lam
  * KKT function K_i of Sec. 3.2 for all stages, with x_0 = x0 and
  * lambda_{N+1} = 0:
  *   KX_i = x_{i-1} - x_i + h f(u_i, x_i)
- *   KU_i = h (r u_i + B^T lam_i) + gamma (u_i - ut_i)
+ *   KU_i = h (r u_i + grad Phi(u_i) + B^T lam_i) + gamma (u_i - ut_i)
  *   KL_i = lam_{i+1} - lam_i + h (q (x_i - xref_i) + (grad_x f_i)^T lam_i)
  * xref has xref_stride = 0 (one reference for all stages) or n (per stage).
  * ut (the regularization reference) may be NULL, meaning ut = u.
@@ -130,7 +150,7 @@ static void stage_kkt(const ref_problem *P, int i, const double *x0, const doubl
         double btl = 0.0;
         for (int p = 0; p < n; ++p) btl += P->B[(size_t)p * m + j] * lam[p];
         double reg = UT ? P->gamma * (u[j] - UT[(size_t)i * m + j]) : 0.0;
-        ku[j] = P->h * (P->r * u[j] + btl) + reg;
+        ku[j] = P->h * (P->r * u[j] + bar_grad(P, u[j]) + btl) + reg;
     }
     dfx_T_apply(P, x, lam, g);
     for (int p = 0; p < n; ++p) {
@@ -277,7 +297,8 @@ static void BT_apply(const ref_problem *P, const double *y, double *out)
  * Reordered unknowns v1 = d lambda, v2 = d x, v3 = d u and right-hand sides
  * b1 = KX_i, b2 = KL_i, b3 = KU_i. Blocks: F_x = h grad_x f - I, F_u = h B,
  * A_xx = h grad_xx^2 H, A_xu = A_ux = 0 (f is affine in u, l separable),
- * A_uu = (h r + gamma) I.
+ * A_uu = h (r + Phi''(u)) + gamma, diagonal (u: the stage's inputs; may be
+ * NULL without a box).
  *  Schur iteration (n_schur times from v3 = 0):
  *     v5 = F_x^{-1} (F_u v3 - b1)
  *     v4 = F_x^{-T} (-b2 - A_xx v5)
@@ -285,7 +306,7 @@ static void BT_apply(const ref_problem *P, const double *y, double *out)
  *  then eq. step2:  v2 = F_x^{-1} (b1 - F_u v3),  v1 = F_x^{-T} (b2 - A_xx v2),
  *  with every F_x^{-1} / F_x^{-T} replaced by n_sw point-Jacobi sweeps.
  */
-void ref_stage_solve(const ref_problem *P, const double *x, const double *lam,
+void ref_stage_solve(const ref_problem *P, const double *x, const double *lam, const double *u,
                      const double *b1, const double *b2, const double *b3,
                      int n_sw, int n_schur, double *dx, double *du, double *dlam)
 {
@@ -307,7 +328,8 @@ void ref_stage_solve(const ref_problem *P, const double *x, const double *lam,
         for (int p = 0; p < n; ++p) c[p] = -b2[p] - Ay[p];
         jacobi_FT(&S, n_sw, c, v4, tmp);
         BT_apply(P, v4, btv);
-        for (int j = 0; j < m; ++j) v3[j] = (b3[j] + P->h * btv[j]) / Auu;
+        for (int j = 0; j < m; ++j)
+            v3[j] = (b3[j] + P->h * btv[j]) / (Auu + (u ? P->h * bar_hess(P, u[j]) : 0.0));
     }
     B_apply(P, v3, Bv);
     for (int p = 0; p < n; ++p) c[p] = b1[p] - P->h * Bv[p];
@@ -323,9 +345,30 @@ void ref_stage_solve(const ref_problem *P, const double *x, const double *lam,
 /* ---------------------------------------------------------------- upper layer */
 
 /*
- * One upper-layer Jacobi iteration (eq. 1st_jacobi with alpha = 1 and the
- * regularization reference ut = u^k): evaluates K^k, its norms, and writes
- * S^{k+1} = S^k - (D^k)^{-1} K^k into (Xn, Un, LAMn). All stage blocks are
+ * Fraction-to-the-boundary rule (eq. eq_alphamax) for the input box: the
+ * largest alpha in (0, 1] with G(u - alpha du) >= 0.005 G(u) for every input
+ * of every stage, i.e. alpha <= 0.995 (u - u_lo) / du where du > 0 and
+ * alpha <= 0.995 (u_hi - u) / (-du) where du < 0. 1 without a box.
+ */
+double ref_alpha_max(const ref_problem *P, const double *U, const double *DU)
+{
+    if (P->tau <= 0.0) return 1.0;
+    double a = 1.0;
+    size_t mN = (size_t)P->N * P->m;
+    for (size_t t = 0; t < mN; ++t) {
+        double u = U[t], d = DU[t], lim = 1.0;
+        if (d > 0.0) lim = 0.995 * (u - P->u_lo) / d;
+        else if (d < 0.0) lim = 0.995 * (P->u_hi - u) / (-d);
+        if (lim < a) a = lim;
+    }
+    return a;
+}
+
+/*
+ * One upper-layer Jacobi iteration (eq. 1st_jacobi with the regularization
+ * reference ut = u^k): evaluates K^k, its norms, and writes
+ * S^{k+1} = S^k - alpha (D^k)^{-1} K^k into (Xn, Un, LAMn), alpha from the
+ * fraction-to-the-boundary rule (1 without a box). All stage blocks are
  * solved independently from S^k.
  */
 void ref_iterate(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
@@ -340,20 +383,21 @@ void ref_iterate(const ref_problem *P, const double *x0, const double *xref, int
     ref_kkt(P, x0, xref, xref_stride, X, U, LAM, U, KX, KU, KL);
     ref_norms(P, KX, KU, KL, r_scaled, r_paper);
     if (Xn) {
+        /* the steps of all stages first (into the outputs), then alpha */
+        double *DU = (double *)malloc(sizeof(double) * (size_t)N * m);
         #pragma omp parallel for schedule(static)
-        for (int i = 0; i < N; ++i) {
-            double *dx = (double *)malloc(sizeof(double) * (size_t)(2 * n + m));
-            double *dl = dx + n, *du = dx + 2 * n;
-            ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n,
+        for (int i = 0; i < N; ++i)
+            ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n, U + (size_t)i * m,
                             KX + (size_t)i * n, KL + (size_t)i * n, KU + (size_t)i * m,
-                            n_sw, n_schur, dx, du, dl);
-            for (int p = 0; p < n; ++p) {
-                Xn[(size_t)i * n + p] = X[(size_t)i * n + p] - dx[p];
-                LAMn[(size_t)i * n + p] = LAM[(size_t)i * n + p] - dl[p];
-            }
-            for (int j = 0; j < m; ++j) Un[(size_t)i * m + j] = U[(size_t)i * m + j] - du[j];
-            free(dx);
+                            n_sw, n_schur, Xn + (size_t)i * n, DU + (size_t)i * m,
+                            LAMn + (size_t)i * n);
+        const double alpha = ref_alpha_max(P, U, DU);
+        for (size_t t = 0; t < (size_t)N * n; ++t) {
+            Xn[t] = X[t] - alpha * Xn[t];
+            LAMn[t] = LAM[t] - alpha * LAMn[t];
         }
+        for (size_t t = 0; t < (size_t)N * m; ++t) Un[t] = U[t] - alpha * DU[t];
+        free(DU);
     }
     free(KX); free(KL); free(KU);
 }
@@ -424,8 +468,8 @@ void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, in
     for (int t = 0; t < N; ++t) {
         int i = dir > 0 ? t : N - 1 - t;
         stage_kkt(P, i, x0, xref, xref_stride, X, U, LAM, UT, kx, ku, kl);
-        ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n, kx, kl, ku, n_sw, n_schur,
-                        dx, du, dl);
+        ref_stage_solve(P, X + (size_t)i * n, LAM + (size_t)i * n, U + (size_t)i * m, kx, kl, ku,
+                        n_sw, n_schur, dx, du, dl);
         for (int p = 0; p < n; ++p) {
             X[(size_t)i * n + p] -= omega * dx[p];
             LAM[(size_t)i * n + p] -= omega * dl[p];

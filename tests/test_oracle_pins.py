@@ -545,3 +545,116 @@ def test_sor_fixed_point_is_jacobis(upper):
     np.testing.assert_allclose(og["U"], oj["U"], atol=1e-9 * np.abs(oj["U"]).max())
     with pytest.raises(ValueError):
         oracle.solve(P, x0, xref, omega=1.2)
+
+
+# ----------------------------- input box: log barrier and the step rule (NEXT-2)
+
+def boxed(P, tau=0.02, lo=-2.0, hi=3.0):
+    return P.with_(tau=tau, u_lo=lo, u_hi=hi)
+
+
+def box_data(P, seed=0):
+    x0, xref, X, U, LAM, UT = tiny_data(P, seed)
+    rng = np.random.default_rng(seed + 100)
+    U = rng.uniform(P.u_lo + 0.1, P.u_hi - 0.1, U.shape)     # strictly inside the box
+    UT = rng.uniform(P.u_lo + 0.1, P.u_hi - 0.1, U.shape)
+    return x0, xref, X, U, LAM, UT
+
+
+@pytest.mark.parametrize("which", ["2d", "1d"])
+def test_box_kkt_is_lagrangian_gradient(which):
+    """With the input box the KKT rows are still the gradient of the Lagrangian
+    of the relaxed problem (eq. nlp_relaxed: stage cost h (l + Phi), Phi the
+    log barrier of G = (u - u_lo, u_hi - u)); checked by central differences,
+    and the C rows against the dense ones."""
+    P = boxed(tiny2d() if which == "2d" else make_problem("c0", N=3))
+    x0, xref, X, U, LAM, UT = box_data(P)
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM, UT)
+    dX, dU, dL = dense.kkt(P, x0, xref, X, U, LAM, UT)
+    for a, b in ((KX, dX), (KU, dU), (KL, dL)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-12 * max(1.0, np.abs(b).max()))
+    S = dense.pack(X, U, LAM)
+    g = fd_grad(lambda s: dense.lagrangian(P, x0, xref, *dense.unpack(P, s), UT), S)
+    gX, gU, gL = dense.unpack(P, g)
+    scale = max(np.abs(KX).max(), np.abs(KU).max(), np.abs(KL).max())
+    assert np.abs(gU - KU).max() <= 1e-8 * scale
+    assert np.abs(gX - KL).max() <= 1e-8 * scale
+    assert np.abs(gL - KX).max() <= 1e-8 * scale
+    # the barrier really enters: without it the input rows differ
+    KU0 = oracle.kkt(P.with_(tau=0.0), x0, xref, X, U, LAM, UT)[1]
+    assert np.abs(KU0 - KU).max() > 1e-6 * scale
+
+
+def test_box_newton_matrix_and_stage_solve():
+    """The dense Newton matrix with the barrier's Hessian in A_uu is the
+    Jacobian of K (finite differences), and the lower layer with many sweeps
+    solves the stage block with that A_uu."""
+    P = boxed(tiny2d())
+    x0, xref, X, U, LAM, _ = box_data(P, seed=4)
+    J = dense.jacobian(P, X, U, LAM)
+    S = dense.pack(X, U, LAM)
+    UT = U.copy()
+
+    def Kvec(s):
+        return dense.pack(*oracle.kkt(P, x0, xref, *dense.unpack(P, s), UT))
+
+    Jfd = np.zeros_like(J)
+    for t in range(S.size):
+        Sp = S.copy(); Sp[t] += 1e-6
+        Sm = S.copy(); Sm[t] -= 1e-6
+        Jfd[:, t] = (Kvec(Sp) - Kvec(Sm)) / 2e-6
+    assert np.abs(Jfd - J).max() <= 1e-7 * np.abs(J).max()
+    KX, KU, KL = oracle.kkt(P, x0, xref, X, U, LAM)
+    i = 1
+    dx, du, dl = oracle.stage_solve(P, X[i], LAM[i], KX[i], KL[i], KU[i], n_sw=400, n_schur=60,
+                                    u=U[i])
+    w = 2 * P.n + P.m
+    Di = J[i * w:(i + 1) * w, i * w:(i + 1) * w]
+    ref = np.linalg.solve(Di, np.concatenate([KX[i], KU[i], KL[i]]))
+    got = np.concatenate([dx, du, dl])
+    assert np.abs(got - ref).max() <= 1e-7 * np.abs(ref).max()
+
+
+def test_fraction_to_boundary_rule():
+    """eq. eq_alphamax: the C closed form against bisection on the rule itself;
+    the binding input lands exactly on G^{k+1} = 0.005 G^k."""
+    P = boxed(tiny2d(N=2))
+    U = np.array([[0.0, 1.0, 2.9, -1.9], [0.5, 0.5, 0.5, 0.5]])[:, :P.m]
+    DU = np.array([[0.1, -3.0, 0.0, 0.0], [0.0, 0.0, 0.0, 0.0]])[:, :P.m]
+    a = oracle.alpha_max(P, U, DU)
+    assert a == pytest.approx(dense.alpha_max(P, U, DU), rel=1e-12)
+    un = U - a * DU
+    assert P.u_hi - un[0, 1] == pytest.approx(0.005 * (P.u_hi - U[0, 1]), rel=1e-12)
+    assert oracle.alpha_max(P, U, DU * 1e-3) == 1.0
+    assert oracle.alpha_max(P.with_(tau=0.0), U, DU) == 1.0
+
+
+def test_box_solution_is_the_relaxed_optimum():
+    """1D heat with a box that binds (the unconstrained inputs leave it): the
+    Jacobi iteration with the barrier and the step rule converges, keeps every
+    iterate strictly inside the box, and reaches the point where the dense
+    Newton iteration with the same rule converges (K = 0 of the relaxed
+    problem); the constrained inputs differ from the unconstrained ones."""
+    P0 = make_problem("c0")
+    x0, xref = make_instance(P0, 3)
+    free = oracle.solve(P0, x0, xref, tol=1e-10, max_iter=20000)
+    umax = np.abs(free["U"]).max()
+    P = P0.with_(tau=1e-3 * P0.r * umax, u_lo=-0.5 * umax, u_hi=0.5 * umax)
+    o = oracle.solve(P, x0, xref, tol=1e-9, max_iter=50000, trace=True)
+    assert o["status"] == "converged"
+    assert np.all(o["U"] > P.u_lo) and np.all(o["U"] < P.u_hi)
+    assert np.abs(o["U"] - free["U"]).max() > 0.1 * umax
+    # dense Newton with the fraction-to-boundary rule from the cold start
+    Xc, Uc, Lc = oracle.cold_start(P, x0)
+    S = dense.pack(Xc, Uc, Lc)
+    for _ in range(200):
+        Xk, Uk, Lk = dense.unpack(P, S)
+        K = dense.pack_K(*dense.kkt(P, x0, xref, Xk, Uk, Lk))
+        if np.abs(K).max() <= 1e-12:
+            break
+        d = np.linalg.solve(dense.jacobian(P, Xk, Uk, Lk, gamma=0.0), K)
+        _, dU, _ = dense.unpack(P, d)
+        S = S - dense.alpha_max(P, Uk, dU) * d
+    Xn, Un, Ln = dense.unpack(P, S)
+    assert np.abs(dense.pack_K(*dense.kkt(P, x0, xref, Xn, Un, Ln))).max() <= 1e-10
+    np.testing.assert_allclose(o["U"], Un, rtol=0, atol=1e-6 * umax)
