@@ -165,6 +165,9 @@ class _Problem:
     """nmpc_problem plus the host arrays it points at (kept alive here)."""
 
     def __init__(self, p):
+        if float(getattr(p, "tau", 0.0)) > 0.0:
+            raise NmpcError(NMPC_E_UNSUPPORTED, "nmpc_problem: the input box (tau > 0) is not "
+                            "in the library yet")
         self.gx = np.ascontiguousarray(p.gx, dtype=np.float64)
         self.gy = np.ascontiguousarray(p.gy, dtype=np.float64)
         self.s = nmpc_problem(int(p.dim), int(p.nsx), int(p.nsy), int(p.N), int(p.lx), int(p.ly),

@@ -144,3 +144,12 @@ def test_loop_helpers_reject_a_null_handle():
     lib = _binding._load()
     assert lib.nmpc_shift_batch(None, 1, None, None, None, None, None, None, None) == nm.NMPC_E_ARG
     assert lib.nmpc_plant_step_batch(None, 1, None, None, 1, 0.1, None, None) == nm.NMPC_E_ARG
+
+
+def test_input_box_rejected_until_the_library_has_it():
+    """The oracle carries the input box (barrier + step rule); the library does
+    not yet, so a problem with tau > 0 is refused instead of solved without it."""
+    P = make_problem("c0").with_(tau=0.1, u_lo=-1.0, u_hi=1.0)
+    with pytest.raises(nm.NmpcError) as e:
+        nm.Solver(P)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
