@@ -78,6 +78,16 @@ typedef struct nmpc_problem {
     double k0, k1;        /* conductivity k(w) = k0 (1 + k1 w) */
     double q, r;          /* cost weights Q = q I, R = r I; r > 0 */
     double gamma;         /* regularization weight >= 0 */
+    double tau;           /* input box u_lo <= u <= u_hi by the log barrier
+                             -tau sum_j (ln(u_j - u_lo) + ln(u_hi - u_j)) of
+                             the relaxed problem (eq. nlp_relaxed), each Jacobi
+                             step cut by the fraction-to-the-boundary rule
+                             (eq. eq_alphamax, alpha global over the stages);
+                             tau = 0: no box. tau > 0 needs u_lo < 0 < u_hi
+                             (the cold start u = 0 inside), the Jacobi upper
+                             layer and the fused path (NMPC_E_UNSUPPORTED for
+                             the others and for ragged batches) */
+    double u_lo, u_hi;
 } nmpc_problem;
 
 /* Solver options. */

@@ -35,7 +35,8 @@ class nmpc_problem(ctypes.Structure):
                 ("horizon", ctypes.c_int32), ("lx", ctypes.c_int32), ("ly", ctypes.c_int32),
                 ("gx", _dp), ("gy", _dp),
                 ("h", ctypes.c_double), ("k0", ctypes.c_double), ("k1", ctypes.c_double),
-                ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double)]
+                ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("tau", ctypes.c_double), ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double)]
 
 
 class nmpc_options(ctypes.Structure):
@@ -165,15 +166,13 @@ class _Problem:
     """nmpc_problem plus the host arrays it points at (kept alive here)."""
 
     def __init__(self, p):
-        if float(getattr(p, "tau", 0.0)) > 0.0:
-            raise NmpcError(NMPC_E_UNSUPPORTED, "nmpc_problem: the input box (tau > 0) is not "
-                            "in the library yet")
         self.gx = np.ascontiguousarray(p.gx, dtype=np.float64)
         self.gy = np.ascontiguousarray(p.gy, dtype=np.float64)
         self.s = nmpc_problem(int(p.dim), int(p.nsx), int(p.nsy), int(p.N), int(p.lx), int(p.ly),
                               self.gx.ctypes.data_as(_dp), self.gy.ctypes.data_as(_dp),
                               float(p.h), float(p.k0), float(p.k1), float(p.q), float(p.r),
-                              float(p.gamma))
+                              float(p.gamma), float(getattr(p, "tau", 0.0)),
+                              float(getattr(p, "u_lo", 0.0)), float(getattr(p, "u_hi", 0.0)))
 
 
 def nmpc_create(problem, options: nmpc_options, max_batch: int = 1) -> ctypes.c_void_p:

@@ -35,6 +35,7 @@ constexpr int kUpperSgs = 3;
 struct DevProblem {
     int nsx, nsy, n, N, m, lx, ly;   // n: padded points per stage, nsy * 16 * CX
     double h, k0, k1, q, r, gamma;
+    double tau, ulo, uhi;            // input box by log barrier (tau = 0: none)
     double idx2, idy2, c0;   // 1/dx^2, 1/dy^2 (0 in 1D), 2/dx^2 + 2/dy^2
 };
 
@@ -73,6 +74,8 @@ struct IterArgs {
     int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
     double omega;                   // Gauss-Seidel kernel: over-relaxation of each stage's step
+    double *apart;                  // input box: [B][N] step limit of each stage's update
+    int *aupd;                      // input box: [B] 1 + launch index of the instance's last update
 };
 
 struct InitArgs {
@@ -222,6 +225,7 @@ const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cf
 // Gauss-Seidel kernel (one workgroup per instance); arguments (IterArgs, int upper).
 const void *gs_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);
 const void *init_kernel();
+const void *box_apply_kernel();   // (IterArgs): input-box step rule after an iteration launch
 const void *choose_flags_kernel();
 const void *choose_copy_kernel();
 const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg);

@@ -43,6 +43,7 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.res_at = res ? -1 : -2;
     v.res_only = res_only;
     v.omega = a.omega;
+    v.box_at = -1;   // the input box runs with the Jacobi upper layer only
     // forward: x_{i-1} updated (dst), lambda_{i+1} not yet (src); backward:
     // the reverse. The residual of S^j takes both from src.
     v.xpb = dir > 0 ? dst : src;

@@ -57,11 +57,55 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
             v.res_at = (long long)d.slot * a.rslot + (long long)b * N + i;
             v.res_only = d.eval_only;
+            if (a.P.tau > 0.0 && !a.residual_only && !d.eval_only) {
+                v.box_at = (long long)b * N + i;
+                if (i == 0 && c.tid == 0) a.aupd[b] = k + 1;   // this launch updates b
+            }
             v.i = i;
             v.last = i == N - 1;
             unsigned long long acc[2] = {0, 0};
             stage_body<T, CX, RY, LX, LY>(a, a.P, v, c, acc);
         }
+    }
+}
+
+// Input box: after an iteration launch, the fraction-to-the-boundary rule
+// (eq. eq_alphamax) with alpha global over an instance's stages. The launch
+// wrote the alpha = 1 step S^{j+1} = S^j - ds and each stage's limit; where
+// their minimum alpha is below 1 the step is scaled in place,
+// S^{j+1} = S^j + alpha (S^{j+1} - S^j). One workgroup per (instance, stage),
+// in the iteration kernel's unit order; instances that did not update in this
+// launch, or whose alpha is 1, return at once.
+__global__ void __launch_bounds__(256) k_box_apply(const IterArgs a)
+{
+    __shared__ double red[256];
+    const int k = *(volatile const int *)(a.ctr) + a.kofs;
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (unit >= a.units) return;
+    const int N = a.P.N, n = a.P.n, M = a.P.m;
+    const int b = unit / N, i = unit % N;
+    if (a.aupd[b] != k + 1) return;
+    double l = 1.0;
+    for (int t = threadIdx.x; t < N; t += blockDim.x) l = fmin(l, a.apart[(size_t)b * N + t]);
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double alpha = red[0];
+    if (!(alpha < 1.0)) return;
+    const int src = a.st[((k + 1) & 1) * a.B + b].j & 1, dst = src ^ 1;
+    const size_t so = ((size_t)b * N + i) * n, uo = ((size_t)b * N + i) * M;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const double xs = a.X[src][so + p], ls = a.LAM[src][so + p];
+        a.X[dst][so + p] = xs + alpha * (a.X[dst][so + p] - xs);
+        a.LAM[dst][so + p] = ls + alpha * (a.LAM[dst][so + p] - ls);
+    }
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double us = a.U[src][uo + j];
+        a.U[dst][uo + j] = us + alpha * (a.U[dst][uo + j] - us);
     }
 }
 
@@ -409,6 +453,7 @@ const void *rollout_kernel(int cx, int lx, int ly, TileCfg *cfg)
 #undef NMPC_ROLL
 
 const void *init_kernel() { return (const void *)&k_init; }
+const void *box_apply_kernel() { return (const void *)&k_box_apply; }
 const void *choose_flags_kernel() { return (const void *)&k_choose_flags; }
 const void *choose_copy_kernel() { return (const void *)&k_choose_copy; }
 const void *pad_kernel() { return (const void *)&k_pad; }

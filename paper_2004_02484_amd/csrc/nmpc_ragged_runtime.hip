@@ -508,6 +508,8 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
     if (rc) return rc;
     for (int c = 0; c < nclass; ++c)
         if ((rc = check_class(&classes[c]))) return rc;
+    for (int c = 0; c < nclass; ++c)
+        if (classes[c].tau != 0.0) return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches take no input box");
     nmpc_ragged *r = new (std::nothrow) nmpc_ragged();
     if (!r) return rg_fail(NMPC_E_OOM, "host allocation failed");
     r->opt = *opt;
@@ -571,6 +573,7 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
         k.P.nsx = p.nsx; k.P.nsy = p.nsy; k.P.n = p.nsy * 16 * cx; k.P.N = p.horizon;
         k.P.m = 16; k.P.lx = 4; k.P.ly = 4;
         k.P.h = p.h; k.P.k0 = p.k0; k.P.k1 = p.k1; k.P.q = p.q; k.P.r = p.r; k.P.gamma = p.gamma;
+        k.P.tau = 0.0; k.P.ulo = k.P.uhi = 0.0;
         const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
         k.P.idx2 = 1.0 / (dx * dx);
         k.P.idy2 = 1.0 / (dy * dy);

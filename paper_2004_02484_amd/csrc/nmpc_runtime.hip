@@ -62,6 +62,8 @@ struct nmpc_handle {
     int *d_work = nullptr;                 // [B] streaming: instance steps this iteration
     Kern roll;                             // start built from an input trajectory
     int *d_start = nullptr;                // [B] start used per instance
+    double *d_apart = nullptr;             // input box: [B][N] step limits
+    int *d_aupd = nullptr;                 // input box: [B] last updating launch + 1
     int last_start_kind = 0;
     bool last_fallback = false;
     std::vector<double> gx, gy;
@@ -147,6 +149,11 @@ int check_problem(const nmpc_problem *p)
         !std::isfinite(p->k1) || !std::isfinite(p->q) || p->q < 0.0 ||
         !std::isfinite(p->gamma) || p->gamma < 0.0)
         return fail(NMPC_E_ARG, "need h > 0, r > 0, q >= 0, gamma >= 0, finite k0, k1");
+    if (!std::isfinite(p->tau) || p->tau < 0.0)
+        return fail(NMPC_E_ARG, "tau must be finite and >= 0");
+    if (p->tau > 0.0 && !(std::isfinite(p->u_lo) && std::isfinite(p->u_hi) && p->u_lo < 0.0 &&
+                          p->u_hi > 0.0))
+        return fail(NMPC_E_ARG, "an input box needs finite u_lo < 0 < u_hi (cold start inside)");
     for (long long t = 0; t < (long long)p->lx * p->nsx; ++t)
         if (!std::isfinite(p->gx[t])) return fail(NMPC_E_ARG, "gx not finite");
     for (long long t = 0; t < (long long)p->ly * p->nsy; ++t)
@@ -250,7 +257,7 @@ void release(nmpc_handle *h)
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
                     (void *)h->d_start, (void *)h->d_stream, (void *)h->d_work,
-                    })
+                    (void *)h->d_apart, (void *)h->d_aupd})
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -270,6 +277,9 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->np; a.P.N = h->N; a.P.m = h->m;
     a.P.lx = p.lx; a.P.ly = p.ly;
     a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
+    a.P.tau = 0.0; a.P.ulo = a.P.uhi = 0.0;   // the streaming path takes no input box
+    a.P.tau = p.tau; a.P.ulo = p.u_lo; a.P.uhi = p.u_hi;
+    a.apart = h->d_apart; a.aupd = h->d_aupd;
     const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
     a.P.idx2 = 1.0 / (dx * dx);
     a.P.idy2 = p.dim == 2 ? 1.0 / (dy * dy) : 0.0;
@@ -299,6 +309,9 @@ int launch_iterate(nmpc_handle *h, int prec, const IterArgs &a, hipStream_t s)
     const nmpc_handle::Kern &k = h->kern[prec];
     void *args[] = {(void *)&a};
     HIP_TRY(hipLaunchKernel(k.fn, dim3(8 * a.per_xcd), dim3(nmpc::kWave * k.waves), args, k.lds, s));
+    if (h->prob.tau > 0.0 && !a.residual_only)   // input box: step rule of this launch
+        HIP_TRY(hipLaunchKernel(nmpc::box_apply_kernel(), dim3(8 * a.per_xcd), dim3(256), args, 0,
+                                s));
     return NMPC_OK;
 }
 
@@ -403,6 +416,8 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
     ia.st = h->d_st;
     ia.iters = h->d_iters; ia.ctr = h->d_ctr;
+    if (h->d_aupd)   // input box: no update recorded for this solve yet (not captured)
+        HIP_TRY(hipMemsetAsync(h->d_aupd, 0, sizeof(int) * h->max_batch, h->stream));
     const bool check = kind != kStartCold && h->opt.fallback && !h->streaming;
     {
         void *args[] = {(void *)&ia};
@@ -790,6 +805,10 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->N = prob->horizon;
     rc = choose_path(prob, opt, &h->streaming);
     if (rc) { delete h; return rc; }
+    if (prob->tau > 0.0 && (h->streaming || opt->upper != NMPC_UPPER_JACOBI)) {
+        delete h;
+        return fail(NMPC_E_UNSUPPORTED, "the input box runs with the Jacobi upper layer on the fused path");
+    }
     if (!h->streaming) {
         rc = select_all(prob, opt, h->kern, h->gs);
         if (rc) { delete h; return rc; }
@@ -835,6 +854,10 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
     ALLOC(h->d_start, sizeof(int) * B);
+    if (prob->tau > 0.0) {
+        ALLOC(h->d_apart, sizeof(double) * B * h->N);
+        ALLOC(h->d_aupd, sizeof(int) * B);
+    }
     if (h->streaming) {
         ALLOC(h->d_stream, sizeof(double) * stream_doubles(h));
         ALLOC(h->d_work, sizeof(int) * B);
@@ -893,6 +916,8 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (rc) return rc;
     if (streaming != h->streaming)
         return fail(NMPC_E_UNSUPPORTED, "set_options cannot switch between fused and streaming paths");
+    if (h->prob.tau > 0.0 && opt->upper != NMPC_UPPER_JACOBI)
+        return fail(NMPC_E_UNSUPPORTED, "the input box runs with the Jacobi upper layer");
     nmpc_handle::Kern kn[2] = {}, gn[2] = {};
     if (!streaming) {
         rc = select_all(&h->prob, opt, kn, gn);

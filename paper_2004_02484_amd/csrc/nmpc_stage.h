@@ -605,6 +605,7 @@ struct StageLoc {
     bool last;                     // i is the last stage
     bool res_only;                 // stop after the residual (no lower layer, no update)
     double omega;                  // the update is S^j - omega ds (1: the plain step)
+    long long box_at;              // >= 0: index into a.apart for this stage's step limit
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
     int pnb, pni;                  // stage pni of buffer pnb is prefetched once this stage
                                    // has read its own (pnb < 0: none)
@@ -639,6 +640,7 @@ __device__ __forceinline__ StageLoc jacobi_loc(int cur)
     v.src = v.xpb = v.xrb = v.lnb = v.lrb = cur;
     v.dst = cur ^ 1;
     v.omega = 1.0;
+    v.box_at = -1;
     v.utb = -1;
     v.pnb = -1;
     return v;
@@ -783,7 +785,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     if (c.tid < M) {
         // with u~ = u^k the gamma term vanishes at evaluation; a stage whose
         // reference is another buffer's input (second sweep of SGS) keeps it
-        const double ku = h * (P.r * uvec[c.tid] + red[c.tid]);
+        double bg = 0.0;   // gradient of the input-box barrier
+        if (P.tau > 0.0) bg = -P.tau / (uvec[c.tid] - P.ulo) + P.tau / (P.uhi - uvec[c.tid]);
+        const double ku = h * (P.r * uvec[c.tid] + bg + red[c.tid]);
         const double reg = v.utb >= 0
             ? P.gamma * (uvec[c.tid] - a.U[v.utb][v.uo + (size_t)v.i * M + c.tid]) : 0.0;
         kun[c.tid] = ku + reg;
@@ -868,7 +872,12 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         bt_reduce<T, CX, RY, LX, LY>(y4, c, M);
         if (c.tid < M) {
             const T bt = T(red[c.tid]);
-            v3[c.tid] = double((T(kun[c.tid]) + hT * bt) / T(auu));
+            double au = auu;   // plus the barrier's Hessian with an input box
+            if (P.tau > 0.0) {
+                const double lo = uvec[c.tid] - P.ulo, hi = P.uhi - uvec[c.tid];
+                au += h * (P.tau / (lo * lo) + P.tau / (hi * hi));
+            }
+            v3[c.tid] = double((T(kun[c.tid]) + hT * bt) / T(au));
         }
         __syncthreads();
     }
@@ -908,6 +917,25 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 Lw[p] = Lc[p] - om * double(y4[t][q]);
             }
     if (c.tid < M) a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - om * v3[c.tid];
+    if (P.tau > 0.0 && v.box_at >= 0) {
+        // fraction-to-the-boundary limit of this stage's input step (eq.
+        // eq_alphamax); the launch's box kernel takes the minimum over the
+        // instance's stages and scales the steps when it is below 1
+        double *lim = lds_ptr<double>(c, c.off.red);
+        if (c.tid < M) {
+            const double u = uvec[c.tid], d = v3[c.tid];
+            double l = 1.0;
+            if (d > 0.0) l = 0.995 * (u - P.ulo) / d;
+            else if (d < 0.0) l = 0.995 * (P.uhi - u) / (-d);
+            lim[c.tid] = l;
+        }
+        __syncthreads();
+        if (c.tid == 0) {
+            double l = 1.0;
+            for (int j = 0; j < M; ++j) l = fmin(l, lim[j]);
+            a.apart[v.box_at] = l;
+        }
+    }
 }
 
 // The separable input factors gx [LX][nsx], gy [LY][nsy] into LDS (double and

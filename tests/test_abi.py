@@ -146,10 +146,12 @@ def test_loop_helpers_reject_a_null_handle():
     assert lib.nmpc_plant_step_batch(None, 1, None, None, 1, 0.1, None, None) == nm.NMPC_E_ARG
 
 
-def test_input_box_rejected_until_the_library_has_it():
-    """The oracle carries the input box (barrier + step rule); the library does
-    not yet, so a problem with tau > 0 is refused instead of solved without it."""
-    P = make_problem("c0").with_(tau=0.1, u_lo=-1.0, u_hi=1.0)
-    with pytest.raises(nm.NmpcError) as e:
-        nm.Solver(P)
-    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+def test_input_box_arguments_checked():
+    """An input box needs finite u_lo < 0 < u_hi (the cold start inside) and tau >= 0;
+    the checks run before any device work."""
+    base = make_problem("c0")
+    for bad in (base.with_(tau=0.1, u_lo=0.1, u_hi=1.0), base.with_(tau=0.1, u_lo=-1.0, u_hi=-0.1),
+                base.with_(tau=-1.0)):
+        with pytest.raises(nm.NmpcError) as e:
+            nm.Solver(bad)
+        assert e.value.code == nm.NMPC_E_ARG
