@@ -117,6 +117,10 @@ __global__ void __launch_bounds__(256) k_box_apply(const IterArgs a)
 // sweeps in FP64 (for the state: on the implicit equation with k(x) taken at
 // the current sweep). The costate sweeps start from the lambda already in
 // buffer 0 (a supplied guess, or 0). One workgroup per instance.
+// The start's KKT residual comes out of the same pass: after each stage's
+// sweeps the kernel evaluates that stage's rows (K^x from the built state,
+// K^lam and K^u from the built costate) and writes the stage norms into
+// residual slot 0, as the residual kernel would.
 template <int CX, int RY, int WB, int LX, int LY>
 __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
 {
@@ -147,6 +151,7 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
     auto pidx = [&](int t, int q) { return (iy0 + t) * sx + ix0 + q; };
     const double h = P.h, kp = P.k0 * P.k1;
     const int nsw = a.n_sw;
+    unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
 
     // ---- states, forward in the horizon
     double xp[RY][CX];
@@ -177,6 +182,29 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
                                      (1.0 + h * kk * P.c0);
                     x[t][q] = valid(t, q) ? v : 0.0;
                 }
+        }
+        {   // state rows of the built start: K^x_i = x_{i-1} - x_i + h f(u_i, x_i)
+            double nb[RY][CX];
+            nbsum<double, CX, RY>(x, nb, c);
+            unsigned long long mx = 0;
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q)
+                    if (valid(t, q)) {
+                        const double kk = P.k0 * (1.0 + P.k1 * x[t][q]);
+                        const double kx = xp[t][q] - x[t][q] +
+                                          h * (kk * (nb[t][q] - P.c0 * x[t][q]) + Bu[t][q]);
+                        mx = umax64(mx, abits(kx));
+                    }
+            mx = wave_max64(mx, c.lane);
+            if (c.lane == 0) nrm[c.w * 4] = mx;
+            __syncthreads();
+            if (c.tid == 0) {   // provisional: the state rows' norm, completed below
+                unsigned long long ax = 0;
+                for (int ww = 0; ww < c.W; ++ww) ax = umax64(ax, nrm[ww * 4]);
+                a.rst[unit] = ax;
+            }
         }
         double *Xo = a.X[0] + unit * n;
 #pragma unroll
@@ -231,6 +259,53 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
             for (int t = 0; t < RY; ++t)
 #pragma unroll
                 for (int q = 0; q < CX; ++q) lam[t][q] = (cc[t][q] - nb[t][q]) * invd[t][q];
+        }
+        {   // costate and input rows of the built start, then the stage norms
+            double z[RY][CX], nb[RY][CX];
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q) z[t][q] = cpk[t][q] * lam[t][q];
+            nbsum<double, CX, RY>(z, nb, c);
+            unsigned long long ml = 0, mu = 0;
+#pragma unroll
+            for (int t = 0; t < RY; ++t)
+#pragma unroll
+                for (int q = 0; q < CX; ++q)
+                    if (valid(t, q)) {
+                        // K^lam_i = -(cc - diag(F_x^T) lam - offdiag(F_x^T) lam)
+                        const double kk = P.k0 * (1.0 + P.k1 * x[t][q]);
+                        const double d = -1.0 - h * kk * P.c0 + h * kp * Lx[t][q];
+                        ml = umax64(ml, abits(cc[t][q] - d * lam[t][q] - nb[t][q]));
+                    }
+            bt_reduce<double, CX, RY, LX, LY>(lam, c, M);
+            if (c.tid < M) {   // K^u_i = h (r u_i + grad Phi(u_i) + B^T lam_i)
+                const double u = a.U[0][unit * M + c.tid];
+                double bg = 0.0;
+                if (P.tau > 0.0) bg = -P.tau / (u - P.ulo) + P.tau / (P.uhi - u);
+                const double bt = lds_ptr<double>(c, c.off.red)[c.tid];
+                mu = abits(h * (P.r * u + bg + bt));
+            }
+            ml = wave_max64(ml, c.lane);
+            mu = wave_max64(mu, c.lane);
+            if (c.lane == 0) { nrm[c.w * 4 + 1] = ml; nrm[c.w * 4 + 2] = mu; }
+            __syncthreads();
+            if (c.tid == 0) {
+                unsigned long long al = 0, au = 0;
+                for (int ww = 0; ww < c.W; ++ww) {
+                    al = umax64(al, nrm[ww * 4 + 1]);
+                    au = umax64(au, nrm[ww * 4 + 2]);
+                }
+                const unsigned long long ax = a.rst[unit];
+                const double dx_ = bits2d(ax), dl_ = bits2d(al), du_ = bits2d(au);
+                double rp = fmax(fmax(dx_, du_), dl_);
+                double rs = fmax(fmax(dx_, du_ / (h * P.r)), dl_ / h);
+                if (ax >= 0x7FF0000000000000ull || al >= 0x7FF0000000000000ull ||
+                    au >= 0x7FF0000000000000ull)
+                    rs = rp = __longlong_as_double(0x7FF8000000000000ll);
+                a.rst[unit] = abits(rs);
+                a.pst[unit] = abits(rp);
+            }
         }
 #pragma unroll
         for (int t = 0; t < RY; ++t)

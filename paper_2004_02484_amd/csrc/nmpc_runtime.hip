@@ -464,8 +464,11 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     h->last_start_kind = kind;
     h->last_fallback = false;
     if (check) {
-        int rc = launch_residual(h, count, 0, 0);
-        if (rc) return rc;
+        // an input-built start has its residual from the rollout pass
+        if (kind != kStartInputs) {
+            int rc = launch_residual(h, count, 0, 0);
+            if (rc) return rc;
+        }
         HIP_TRY(hipStreamWaitEvent(h->stream, h->ev_join, 0));   // join
         IterArgs a = iter_args(h, count);
         a.units = count;

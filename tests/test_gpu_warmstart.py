@@ -11,6 +11,7 @@ import pytest
 from nmpc_inputs import make_instance, make_problem
 
 import oracle
+from oracle.start import input_start
 
 pytestmark = pytest.mark.gpu
 
@@ -100,3 +101,30 @@ def test_batch_input_start_with_fallback(nm, c1_case):
     for b in range(B):
         err = np.abs(Uo[b].cpu().numpy() - ex["U"]).max() / np.abs(ex["U"]).max()
         assert err <= 1e-4
+
+
+@pytest.mark.parametrize("per_stage", [False, True])
+def test_fallback_decision_follows_the_start_residuals(nm, c1_case, per_stage):
+    """The fallback compares the built start's residual (evaluated by the
+    library while it builds the start) with the cold start's (stage 0 only
+    when one reference serves all stages). Over a range of input scalings the
+    choice must be the one the oracle's residuals of the two starts give;
+    scalings whose two residuals lie within 25 % of each other are skipped."""
+    P, x0, xref, ex = c1_case
+    xr = np.stack([xref * (1.0 + 0.05 * i / P.N) for i in range(P.N)]) if per_stage else xref
+    rs_cold, _ = oracle.residual(P, x0, xr, *oracle.cold_start(P, x0))
+    s = nm.Solver(P, fallback=1, tol=0.0, max_iter=0, xref_per_stage=int(per_stage))
+    seen = set()
+    for c in (0.5, 0.95, 1.0, 1.05, 2.0, 10.0):
+        U = c * ex["U"]
+        rs_in, _ = oracle.residual(P, x0, xr, *input_start(P, x0, xr, U))
+        ratio = rs_in / rs_cold
+        if 0.8 < ratio < 1.25:
+            continue
+        rc, X, Uo, L, info = s.solve(x0, xr, warm=(None, U, None))
+        want = 2 if ratio < 1.0 else 0
+        print(f"scale {c:g}: oracle residuals built {rs_in:.3e} cold {rs_cold:.3e}, "
+              f"start used {info['start_used']}")
+        assert rc == nm.NMPC_E_NOCONV and info["start_used"] == want, (c, ratio)
+        seen.add(want)
+    assert seen == {0, 2}
