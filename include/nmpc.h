@@ -138,6 +138,13 @@ typedef struct nmpc_options {
                              BGS its backward form and SGS the symmetric SSOR;
                              0 < omega < 2, default 1. The Jacobi upper layer
                              takes omega = 1 only (NMPC_E_ARG otherwise) */
+    int32_t fp32_finish;  /* with NMPC_FP32_SWEEP: 0 (default) takes the final
+                             FP64 correction described under precision; 1
+                             returns S^j as soon as its FP64-evaluated test
+                             passes in the FP32 phase (S^j is FP64 data; only
+                             the step that produced it was solved in FP32).
+                             Fused path only (NMPC_E_UNSUPPORTED on the
+                             streaming path and for ragged batches); 0 or 1 */
 } nmpc_options;
 
 /* Per-instance result information. */

@@ -46,7 +46,7 @@ class nmpc_options(ctypes.Structure):
                 ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("upper", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("omega", ctypes.c_double)]
+                ("omega", ctypes.c_double), ("fp32_finish", ctypes.c_int32)]
 
 
 class nmpc_info(ctypes.Structure):

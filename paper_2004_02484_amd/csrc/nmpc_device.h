@@ -74,6 +74,7 @@ struct IterArgs {
     int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
     double omega;                   // Gauss-Seidel kernel: over-relaxation of each stage's step
+    int fp32_finish;                // FP32 phase: a passed test finishes (no FP64 correction)
     double *apart;                  // input box: [B][N] step limit of each stage's update
     int *aupd;                      // input box: [B] 1 + launch index of the instance's last update
 };

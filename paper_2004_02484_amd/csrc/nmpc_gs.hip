@@ -82,7 +82,7 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
 // the FP64 kernel then takes one FP64 correction sweep from S^j (the first
 // sweep of the variant's iteration), checks the result with a residual-only
 // pass and returns it if the test passes, else continues with FP64
-// iterations.
+// iterations. With a.fp32_finish the FP32 kernel returns S^j itself.
 template <int PREC, int CX, int RY, int WB, int LX, int LY>
 __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const int upper)
 {
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
         __syncthreads();   // bc is reused by the next stage's norms
         if (!(rs <= 1.7976931348623157e308)) { fin = kStatusNonfinite; break; }
         if (rs <= a.tol) {
-            if (PREC == kModeFp32) { s.mode = kModeFp64Redo; break; }
+            if (PREC == kModeFp32 && !a.fp32_finish) { s.mode = kModeFp64Redo; break; }
             fin = kStatusOk;
             break;
         }

@@ -483,6 +483,8 @@ int check_opts(const nmpc_options *o)
     if (o->upper < 0 || o->upper > 3) return rg_fail(NMPC_E_ARG, "unknown upper layer");
     if (o->upper != NMPC_UPPER_JACOBI)
         return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches use the Jacobi upper layer");
+    if (o->fp32_finish != 0)
+        return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches take the final FP64 correction (fp32_finish 0)");
     return NMPC_OK;
 }
 

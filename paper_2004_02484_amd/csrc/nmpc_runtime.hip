@@ -198,6 +198,7 @@ int check_options(const nmpc_options *o)
         return fail(NMPC_E_ARG, "omega must lie in (0, 2)");
     if (o->upper == NMPC_UPPER_JACOBI && o->omega != 1.0)
         return fail(NMPC_E_ARG, "over-relaxation (omega != 1) needs a Gauss-Seidel upper layer");
+    if (o->fp32_finish != 0 && o->fp32_finish != 1) return fail(NMPC_E_ARG, "fp32_finish must be 0 or 1");
     return NMPC_OK;
 }
 
@@ -209,6 +210,8 @@ int choose_path(const nmpc_problem *p, const nmpc_options *o, bool *streaming)
     *streaming = fused != NMPC_OK;
     if (*streaming && o->upper != NMPC_UPPER_JACOBI)
         return fail(NMPC_E_UNSUPPORTED, "the streaming path runs the Jacobi upper layer only");
+    if (*streaming && o->fp32_finish)
+        return fail(NMPC_E_UNSUPPORTED, "fp32_finish runs on the fused path");
     if (*streaming && nmpc::stream_lds_bytes(p->nsx) > nmpc::kLdsBytes)
         return fail(NMPC_E_UNSUPPORTED, "grid rows too wide for the streaming path");
     g_err.clear();
@@ -300,6 +303,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.tol = h->opt.tol; a.max_iter = h->opt.max_iter;
     a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
     a.omega = h->opt.omega;
+    a.fp32_finish = h->opt.fp32_finish;
     a.residual_only = 0;
     return a;
 }
@@ -669,6 +673,9 @@ int run_gs(nmpc_handle *h, int count)
     int launches = 0;
     for (int prec : {nmpc::kModeFp32, nmpc::kModeFp64}) {
         if (prec == nmpc::kModeFp32 && main_prec(h->opt) != nmpc::kModeFp32) continue;
+        // every instance leaves the FP32 kernel finished when it returns S^j
+        if (prec == nmpc::kModeFp64 && main_prec(h->opt) == nmpc::kModeFp32 && h->opt.fp32_finish)
+            continue;
         const nmpc_handle::Kern &k = h->gs[prec];
         a.gs_pf = k.pf;
         HIP_TRY(hipLaunchKernel(k.fn, dim3(count), dim3(nmpc::kWave * k.waves), args, k.lds,
@@ -785,6 +792,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->upper = NMPC_UPPER_JACOBI;
     opt->path = NMPC_PATH_AUTO;
     opt->omega = 1.0;
+    opt->fp32_finish = 0;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,

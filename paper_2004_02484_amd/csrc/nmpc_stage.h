@@ -492,7 +492,8 @@ struct Decision {
 // evaluation, max-reduced here); the stage-0 workgroup publishes the next
 // state into the other parity slot. PREC is this kernel's precision (kModeFp32 or kModeFp64); an
 // instance in another mode waits for the kernel of its precision.
-//   FP32 mode, test passed at S^j  -> REDO (FP32-active count decremented)
+//   FP32 mode, test passed at S^j  -> REDO (FP32-active count decremented),
+//                                     or finished with S^j when a.fp32_finish
 //   REDO (FP64 kernel)             -> re-evaluate S^j in FP64: its update is the
 //                                     FP64 step S^{j+1}; owe the evaluation of S^{j+1}
 //   FP64 mode, test passed, owed   -> evaluate S^{j+1} without an update (its
@@ -545,7 +546,8 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                 }
             } else if (rs <= a.tol) {
                 if (s.mode == kModeFp32) {
-                    ns.mode = kModeFp64Redo;
+                    if (a.fp32_finish) fin = kStatusOk;
+                    else ns.mode = kModeFp64Redo;
                 } else if (s.pending) {
                     if (PREC == kModeFp64) {
                         ns.pending = 0;

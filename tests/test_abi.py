@@ -78,7 +78,7 @@ def test_unsupported_shapes_reported():
                                          ("max_iter", -1), ("tol", -1.0), ("tile_rows", -1),
                                          ("tile_rows", 17), ("upper", 4), ("upper", -1),
                                          ("path", 3), ("omega", 0.0), ("omega", 2.0),
-                                         ("omega", 1.2)])
+                                         ("omega", 1.2), ("fp32_finish", 2)])
 def test_invalid_options_rejected(field, value):
     o = nm.nmpc_default_options(**{field: value})
     with pytest.raises(nm.NmpcError) as e:
@@ -92,6 +92,13 @@ def test_null_handle_calls():
     assert lib.nmpc_kernel_config(None, None, None, None) == nm.NMPC_E_ARG
     lib.nmpc_strerror.restype = ctypes.c_char_p
     assert b"argument" in lib.nmpc_strerror(1)
+
+
+def test_fp32_finish_needs_the_fused_path():
+    o = nm.nmpc_default_options(fp32_finish=1, path=nm.NMPC_PATH_STREAM)
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_create(make_problem("c1"), o, 1)
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
 
 
 def test_unknown_tile_height_is_unsupported():
@@ -114,6 +121,7 @@ def _grid(ns, N, lattice=4):
     ([("grid", 32, 4, 4)], {"n_sweep": 0}, nm.NMPC_E_ARG),
     ([("grid", 32, 0, 4)], {}, nm.NMPC_E_ARG),                           # horizon 0
     ([("grid", 32, 4, 4)], {"upper": 3}, nm.NMPC_E_UNSUPPORTED),         # SGS not ragged
+    ([("grid", 32, 4, 4)], {"fp32_finish": 1}, nm.NMPC_E_UNSUPPORTED),   # FP64 correction kept
 ])
 def test_ragged_create_validates_before_any_device_call(classes, opts, code):
     cl = [make_problem("c0") if c[0] == "c0" else _grid(c[1], c[2], c[3]) for c in classes]

@@ -107,6 +107,34 @@ def test_sgs_fp32_sweeps_c1_batch(nm):
         assert r_s <= 1e-6
 
 
+def test_sgs_fp32_finish(nm):
+    """fp32_finish = 1 with SGS: the solve returns the iterate whose test passed
+    in the FP32 phase, one iteration before the default's FP64-corrected one;
+    it passes the oracle's residual test and meets the FP32-sweep bar."""
+    import torch
+    P = make_problem("c1")
+    x0, xr = make_batch(P, [35, 36])
+    X0, XR = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
+    runs = {}
+    for fin in (0, 1):
+        s = nm.Solver(P, max_batch=2, tol=1e-6, max_iter=3000, precision=nm.NMPC_FP32_SWEEP,
+                      upper=nm.NMPC_UPPER_SGS, fp32_finish=fin)
+        rc, X, U, L, infos = s.solve_batch(X0, XR)
+        assert rc == nm.NMPC_OK
+        runs[fin] = (X.cpu().numpy(), U.cpu().numpy(), L.cpu().numpy(), infos)
+        s.close()
+    X, U, L, infos = runs[1]
+    for b in range(2):
+        assert infos[b]["iters"] <= runs[0][3][b]["iters"] - 1
+        r_s, _ = oracle.residual(P, x0[b], xr[b], X[b], U[b], L[b])
+        assert r_s <= 1e-6
+        ex = oracle.solve(P, x0[b], xr[b], tol=1e-11, max_iter=20000)
+        err = rel(U[b], ex["U"])
+        print(f"instance {b}: {infos[b]['iters']} iterations "
+              f"(default {runs[0][3][b]['iters']}), control error vs exact {err:.2e}")
+        assert err <= 1e-4
+
+
 def test_sgs_batch_equals_single_solves(nm):
     import torch
     P = shaped(40, 33, 6, 4)

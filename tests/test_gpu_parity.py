@@ -170,6 +170,35 @@ def test_fp32_sweeps_reach_fp64_fixed_point(nm):
     assert err <= 1e-4
 
 
+def test_fp32_finish_returns_the_fp32_phase_iterate(nm):
+    """fp32_finish = 1: the solve ends where the FP32 phase's test passes, one
+    upper iteration before the default (which then takes the FP64 correction
+    step and tests its result). The returned iterate passes the oracle's FP64
+    residual test and meets the FP32-sweep bar against the exact solution."""
+    import torch
+    P = make_problem("c1")
+    x0s, xrefs = make_batch(P, [6, 9])
+    X0, XR = torch.tensor(x0s, device="cuda"), torch.tensor(xrefs, device="cuda")
+    runs = {}
+    for fin in (0, 1):
+        s = nm.Solver(P, max_batch=2, precision=nm.NMPC_FP32_SWEEP, fp32_finish=fin)
+        rc, X, U, L, infos = s.solve_batch(X0, XR)
+        assert rc == nm.NMPC_OK
+        runs[fin] = (X.cpu().numpy(), U.cpu().numpy(), L.cpu().numpy(), infos)
+        s.close()
+    for b in range(2):
+        X, U, L, infos = runs[1]
+        i0, i1 = runs[0][3][b], infos[b]
+        assert i1["iters"] <= i0["iters"] - 1 and i1["r_scaled"] <= 1e-6
+        rs, _ = oracle.residual(P, x0s[b], xrefs[b], X[b], U[b], L[b])
+        assert rs <= 1e-6 and abs(rs - i1["r_scaled"]) <= 1e-9 * rs
+        ex = oracle.solve(P, x0s[b], xrefs[b], tol=1e-12, max_iter=20000)
+        err = rel(U[b], ex["U"])
+        print(f"instance {b}: fp32_finish {i1['iters']} iterations (default {i0['iters']}), "
+              f"control rel. error vs exact {err:.2e} (default {rel(runs[0][1][b], ex['U']):.2e})")
+        assert err <= 1e-4
+
+
 def test_warm_start_and_failure_statuses(nm):
     P = make_problem("c0")
     x0, xref = make_instance(P, 7)
