@@ -379,6 +379,9 @@ def main():
                     help="FP32 sweeps: 1 returns the iterate whose FP64-evaluated test passed "
                          "in the FP32 phase (same test, same tolerance), 0 takes the library "
                          "default's final FP64 correction step first")
+    ap.add_argument("--warm-sweeps", type=int, default=20,
+                    help="point-Jacobi sweeps per stage when the library builds the learned "
+                         "start's states and costates")
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -415,7 +418,8 @@ def main():
     inner = dict(n_sweep=args.n_sweep, n_schur=args.n_schur)
     fin = args.fp32_finish if prec == nm.NMPC_FP32_SWEEP else 0
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
-                       check_every=16, fallback=1, upper=UPPER[args.upper], warm_sweeps=20,
+                       check_every=16, fallback=1, upper=UPPER[args.upper],
+                       warm_sweeps=args.warm_sweeps,
                        fp32_finish=fin, **inner)
     kind = "jacobi" if args.upper == "jacobi" else "gs"
     net = None
