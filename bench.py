@@ -375,10 +375,10 @@ def main():
                     help="point-Jacobi sweeps per lower-layer solve (the paper's 2)")
     ap.add_argument("--n-schur", type=int, default=2,
                     help="Schur input iterations of the lower layer (the paper's 2)")
-    ap.add_argument("--fp32-finish", type=int, choices=[0, 1], default=1,
-                    help="FP32 sweeps: 1 returns the iterate whose FP64-evaluated test passed "
-                         "in the FP32 phase (same test, same tolerance), 0 takes the library "
-                         "default's final FP64 correction step first")
+    ap.add_argument("--fp32-finish", type=int, choices=[0, 1], default=0,
+                    help="FP32 sweeps: 0 (default) ends with the final FP64 correction step; "
+                         "1 returns the iterate whose FP64-evaluated test passed in the FP32 "
+                         "phase (same test, same tolerance, no FP64 step)")
     ap.add_argument("--warm-sweeps", type=int, default=20,
                     help="point-Jacobi sweeps per stage when the library builds the learned "
                          "start's states and costates")
