@@ -103,14 +103,23 @@ def test_batch_input_start_with_fallback(nm, c1_case):
         assert err <= 1e-4
 
 
-@pytest.mark.parametrize("per_stage", [False, True])
-def test_fallback_decision_follows_the_start_residuals(nm, c1_case, per_stage):
+@pytest.mark.parametrize("name,per_stage", [("c1", False), ("c1", True), ("c0", False),
+                                             ("grid40", True)])
+def test_fallback_decision_follows_the_start_residuals(nm, c1_case, name, per_stage):
     """The fallback compares the built start's residual (evaluated by the
     library while it builds the start) with the cold start's (stage 0 only
     when one reference serves all stages). Over a range of input scalings the
     choice must be the one the oracle's residuals of the two starts give;
-    scalings whose two residuals lie within 25 % of each other are skipped."""
-    P, x0, xref, ex = c1_case
+    scalings whose two residuals lie within 25 % of each other are skipped.
+    Cases: the 64 x 64 batch grid, 1D, and a 40 x 40 grid whose tiles end in
+    a partial one."""
+    if name == "c1":
+        P, x0, xref, ex = c1_case
+    else:
+        P = make_problem("c0") if name == "c0" else make_problem("grid", ns=40, N=6, lattice=2)
+        x0, xref = make_instance(P, 21)
+        ex = oracle.solve(P, x0, xref, tol=1e-11, max_iter=50000)
+        assert ex["status"] == "converged"
     xr = np.stack([xref * (1.0 + 0.05 * i / P.N) for i in range(P.N)]) if per_stage else xref
     rs_cold, _ = oracle.residual(P, x0, xr, *oracle.cold_start(P, x0))
     s = nm.Solver(P, fallback=1, tol=0.0, max_iter=0, xref_per_stage=int(per_stage))
