@@ -379,9 +379,9 @@ def main():
                     help="FP32 sweeps: 0 (default) ends with the final FP64 correction step; "
                          "1 returns the iterate whose FP64-evaluated test passed in the FP32 "
                          "phase (same test, same tolerance, no FP64 step)")
-    ap.add_argument("--warm-sweeps", type=int, default=20,
-                    help="point-Jacobi sweeps per stage when the library builds the learned "
-                         "start's states and costates")
+    ap.add_argument("--warm-sweeps", type=int, default=14,
+                    help="sweeps per stage (point-Jacobi, Chebyshev weights) when the library "
+                         "builds the learned start's states and costates")
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -411,10 +411,10 @@ def main():
     P = make_problem("c1")
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
-    # warm_sweeps: point-Jacobi sweeps per stage when the library builds states
-    # and costates from the predicted inputs (20 keep the rollout's error far
-    # below the tolerance on this grid and step; 12 leave an error the upper
-    # iteration takes about four times longer to remove)
+    # warm_sweeps: Chebyshev-weighted point-Jacobi sweeps per stage when the
+    # library builds states and costates from the predicted inputs (12 already
+    # give the iteration counts of many more on this grid and step, 10 leave an
+    # error the upper iteration takes longer to remove; 14 keep a margin)
     inner = dict(n_sweep=args.n_sweep, n_schur=args.n_schur)
     fin = args.fp32_finish if prec == nm.NMPC_FP32_SWEEP else 0
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,

@@ -110,8 +110,10 @@ typedef struct nmpc_options {
                              values select alternative kernel instances (as
                              chosen by the tile autotuner); unsupported values
                              give NMPC_E_UNSUPPORTED */
-    int32_t warm_sweeps;  /* point-Jacobi sweeps per stage when a start is
-                             built from an input trajectory (0 = 24) */
+    int32_t warm_sweeps;  /* sweeps per stage (point-Jacobi with Chebyshev
+                             weights) for the states and for the costates
+                             when a start is built from an input trajectory
+                             (0 = 24) */
     int32_t fallback;     /* 1: for a warm start, compare its residual with the
                              cold start's per instance and keep the smaller
                              (non-finite counts as larger) */
