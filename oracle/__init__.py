@@ -123,6 +123,20 @@ def cold_start(P: Problem, x0):
             np.zeros((P.N, P.n)))
 
 
+def feasible_inputs(P: Problem, U):
+    """With an input box (tau > 0) the method starts from a strictly feasible
+    S^0 (Sec. 4.2); the paper gives no rule for a start outside the box. The
+    reading taken: clip the start's inputs to [u_lo + d, u_hi - d] with d half
+    a percent of the box width (NaN stays NaN). Without a box U is returned
+    unchanged."""
+    U = np.array(U, dtype=np.float64)
+    if P.tau > 0.0:
+        d = 0.005 * (P.u_hi - P.u_lo)
+        lo, hi = P.u_lo + d, P.u_hi - d
+        U = np.where(U < lo, lo, np.where(U > hi, hi, U))
+    return U
+
+
 def kkt(P: Problem, x0, xref, X, U, LAM, UT=None):
     lib = _load()
     C = _Ctx(P)
@@ -214,7 +228,7 @@ def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_s
     C = _Ctx(P)
     xr, st = _xref(P, xref)
     X, U, LAM = cold_start(P, x0) if start is None else start
-    X, U, LAM = _c(X).copy(), _c(U).copy(), _c(LAM).copy()
+    X, U, LAM = _c(X).copy(), _c(feasible_inputs(P, U)), _c(LAM).copy()
     it = ctypes.c_int(); rs = ctypes.c_double(); rp = ctypes.c_double()
     hist = np.zeros(max_iter + 1) if trace else None
     if UPPER[upper] == 0 and omega != 1.0:

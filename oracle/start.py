@@ -48,7 +48,10 @@ def input_start(P: Problem, x0, xref, U):
     L = lap_sparse(P)
     B = P.dense_B()
     I = sp.identity(P.n, format="csr")
-    U = np.asarray(U, dtype=float).reshape(P.N, P.m)
+    U = np.array(U, dtype=float).reshape(P.N, P.m)
+    if P.tau > 0.0:   # strictly feasible start inside an input box (Sec. 4.2)
+        d = 0.005 * (P.u_hi - P.u_lo)
+        U = np.where(U < P.u_lo + d, P.u_lo + d, np.where(U > P.u_hi - d, P.u_hi - d, U))
     xref = np.asarray(xref, dtype=float)
     X = np.zeros((P.N, P.n))
     LAM = np.zeros((P.N, P.n))

@@ -82,6 +82,8 @@ struct IterArgs {
 struct InitArgs {
     int count, B, N, nsx, nsy, sx, m, mode;
     int trajectory_only;            // 1: write S^0 only, keep the iteration state
+    int project;                    // 1: move given inputs strictly inside [ulo, uhi]
+    double ulo, uhi;                // input box (with project)
     const double *x0, *wx, *wu, *wl;
     double *X, *U, *LAM;
     InstState *st;

@@ -444,8 +444,18 @@ __global__ void k_init(const InitArgs a)
         a.X[t] = x;
         a.LAM[t] = l;
     }
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < mN; t += stride)
-        a.U[t] = a.wu ? a.wu[t] : 0.0;
+    // with an input box the method starts from a strictly feasible S^0
+    // (Sec. 4.2): given inputs are clipped to the box shrunk by 0.5 % of its
+    // width at each end (NaN stays NaN, so the residual test still rejects it)
+    const double marg = 0.005 * (a.uhi - a.ulo);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < mN; t += stride) {
+        double u = a.wu ? a.wu[t] : 0.0;
+        if (a.project && a.wu) {
+            if (u < a.ulo + marg) u = a.ulo + marg;
+            if (u > a.uhi - marg) u = a.uhi - marg;
+        }
+        a.U[t] = u;
+    }
     if (a.trajectory_only) return;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.count;
          t += stride) {

@@ -420,6 +420,8 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     ia.X = h->X(0); ia.U = h->U(0); ia.LAM = h->L(0);
     ia.st = h->d_st;
     ia.iters = h->d_iters; ia.ctr = h->d_ctr;
+    ia.project = h->prob.tau > 0.0 ? 1 : 0;
+    ia.ulo = h->prob.u_lo; ia.uhi = h->prob.u_hi;
     if (h->d_aupd)   // input box: no update recorded for this solve yet (not captured)
         HIP_TRY(hipMemsetAsync(h->d_aupd, 0, sizeof(int) * h->max_batch, h->stream));
     const bool check = kind != kStartCold && h->opt.fallback && !h->streaming;

@@ -929,7 +929,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             double l = 1.0;
             if (d > 0.0) l = 0.995 * (u - P.ulo) / d;
             else if (d < 0.0) l = 0.995 * (P.uhi - u) / (-d);
-            lim[c.tid] = l;
+            lim[c.tid] = fmax(l, 0.0);   // S^j is strictly feasible: l > 0
         }
         __syncthreads();
         if (c.tid == 0) {

@@ -85,6 +85,44 @@ def test_box_solve_matches_oracle(nm, prec):
     assert r_s <= 1e-8 * (1 if prec == "fp64" else 10)
 
 
+def test_start_outside_the_box_is_moved_inside(nm):
+    """A warm start whose inputs leave the box is clipped into it (strictly
+    feasible S^0, Sec. 4.2; 0.5 % of the box width from each bound) before
+    anything else runs: given starts and starts built from inputs, with the
+    fallback check. Iterates equal the oracle's, which applies the same rule."""
+    from oracle.start import input_start
+    P, x0, xref, free = boxed_c0(seed=4, tau_rel=1e-4)
+    U0 = free["U"] * 1.3                      # about a third of the entries outside
+    assert np.mean((U0 <= P.u_lo) | (U0 >= P.u_hi)) > 0.2
+    d = 0.005 * (P.u_hi - P.u_lo)
+    np.testing.assert_array_equal(oracle.feasible_inputs(P, U0),
+                                  np.clip(U0, P.u_lo + d, P.u_hi - d))
+    start = (free["X"].copy(), U0, free["LAM"].copy())
+    for k in (0, 1, 3):
+        s = nm.Solver(P, tol=0.0, max_iter=k)
+        rc, X, U, L, info = s.solve(x0, xref, warm=start)
+        s.close()
+        o = oracle.solve(P, x0, xref, start=tuple(a.copy() for a in start), tol=0.0, max_iter=k)
+        assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+        assert rel(U, o["U"]) <= 1e-10 and rel(X, o["X"]) <= 1e-10
+        assert rel(L, o["LAM"]) <= 1e-10
+        assert np.all(U > P.u_lo) and np.all(U < P.u_hi)
+        assert np.isfinite(info["r_scaled"])
+    # start built from the inputs alone (rollout), fallback on
+    s = nm.Solver(P, tol=0.0, max_iter=0, fallback=1)
+    rc, X, U, L, info = s.solve(x0, xref, warm=(None, U0, None))
+    s.close()
+    Xs, Us, Ls = input_start(P, x0, xref, U0)
+    np.testing.assert_array_equal(U, Us)
+    assert rel(X, Xs) <= 1e-8 and rel(L, Ls) <= 1e-8
+    assert info["start_used"] == 2 and np.isfinite(info["r_scaled"])
+    # and the solve from it reaches the oracle's solution inside the box
+    s = nm.Solver(P, tol=1e-8, max_iter=20000)
+    rc, X, U, L, info = s.solve(x0, xref, warm=start)
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=50000)
+    assert rc == nm.NMPC_OK and rel(U, ex["U"]) <= 1e-6
+
+
 def test_box_2d_batch_fp32(nm):
     """Small 2D batch with FP32 sweeps: every instance converges inside the box,
     matching the oracle's solution of each instance."""

@@ -97,6 +97,15 @@ def test_degenerate_single_node_single_stage(nm):
     assert rel(U, o["U"]) <= REL
 
 
+def oracle_at(P, x0, xref, o, k, **kw):
+    """The oracle's iterate S^k: ``o`` itself when it stopped at k, else the
+    oracle rerun without a tolerance for exactly k upper iterations (the two
+    stopping tests may fall on either side of a threshold tie)."""
+    if o["iters"] == k:
+        return o
+    return oracle.solve(P, x0, xref, tol=0.0, max_iter=k, **kw)
+
+
 @pytest.mark.parametrize("name,seed", [("c0", 3), ("c1", 4)])
 def test_converged_solution_matches_oracle(nm, name, seed):
     P = make_problem(name)
@@ -106,16 +115,37 @@ def test_converged_solution_matches_oracle(nm, name, seed):
     o = oracle.solve(P, x0, xref, tol=1e-6)
     assert rc == nm.NMPC_OK and o["status"] == "converged"
     assert abs(info["iters"] - o["iters"]) <= 1
-    if info["iters"] == o["iters"]:
-        assert rel(U, o["U"]) <= 1e-9 and rel(L, o["LAM"]) <= 1e-9
+    # element by element against the oracle's iterate of the same index, always
+    ok = oracle_at(P, x0, xref, o, info["iters"])
+    assert rel(X, ok["X"]) <= 1e-9 and rel(U, ok["U"]) <= 1e-9 and rel(L, ok["LAM"]) <= 1e-9
+    err_oracle = rel(U, ok["U"])
+    assert err_oracle <= 1e-6          # the FP64 bar against the oracle
     assert info["r_scaled"] <= 1e-6
     # the returned trajectory satisfies the KKT conditions (oracle re-check)
     rs, _ = oracle.residual(P, x0, xref, X, U, L)
     assert rs <= 1e-6 and abs(rs - info["r_scaled"]) <= 1e-9 * rs
     ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
     err = rel(U, ex["U"])
-    print(f"{name}: iters {info['iters']}, control rel. error vs exact {err:.2e}")
+    print(f"{name}: iters {info['iters']} (oracle {o['iters']}), control rel. error vs the "
+          f"oracle's S^k {err_oracle:.2e}, vs exact {err:.2e}")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name,seed", [("c0", 3), ("c1", 4)])
+def test_fp64_solution_meets_the_fp64_bar_against_the_exact_solution(nm, name, seed):
+    """At tol 1e-9 the FP64 solve is within 1e-6 (relative, controls) of the
+    oracle's exact solution (r_scaled <= 1e-12); at tol 1e-6 the distance to
+    the exact solution is set by the tolerance (C0: about 2e-6), not by the
+    GPU arithmetic, which the same-k comparison above bounds."""
+    P = make_problem(name)
+    x0, xref = make_instance(P, seed)
+    s = nm.Solver(P, tol=1e-9, max_iter=20000)
+    rc, X, U, L, info = s.solve(x0, xref)
+    assert rc == nm.NMPC_OK
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    err = rel(U, ex["U"])
+    print(f"{name}: tol 1e-9, {info['iters']} iterations, control rel. error vs exact {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_batch_matches_single_solves(nm):
@@ -130,8 +160,10 @@ def test_batch_matches_single_solves(nm):
     for b, sd in enumerate(seeds):
         o = oracle.solve(P, x0[b], xref[b], tol=1e-6)
         assert abs(infos[b]["iters"] - o["iters"]) <= 1
-        if infos[b]["iters"] == o["iters"]:
-            assert rel(U[b].cpu().numpy(), o["U"]) <= 1e-9
+        ok = oracle_at(P, x0[b], xref[b], o, infos[b]["iters"])
+        assert rel(U[b].cpu().numpy(), ok["U"]) <= 1e-9
+        assert rel(X[b].cpu().numpy(), ok["X"]) <= 1e-9
+        assert rel(L[b].cpu().numpy(), ok["LAM"]) <= 1e-9
     # graph replay length does not change the result
     s.set_options(check_every=1)
     rc2, X2, U2, L2, infos2 = s.solve_batch(torch.tensor(x0, device="cuda"),
