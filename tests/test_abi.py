@@ -16,7 +16,7 @@ def declared_functions():
     src = open(_binding.library_path().replace("paper_2004_02484_amd/libnmpc.so",
                                                "include/nmpc.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(nmpc_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(nmpc_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
