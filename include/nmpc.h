@@ -344,6 +344,22 @@ int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float 
                   float *C, int32_t ldc, int64_t stride_c, int32_t groups, int32_t ksplit,
                   float *work, void *stream);
 
+/* nmpc_gemm_f32 without a caller workspace, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid allocation): the split-K partials live in a static device array
+ * of 2^21 floats (8 MiB) that each GPU holds from the first call on it until
+ * the process ends; this call allocates nothing. ksplit > 1 needs groups *
+ * ksplit * M * N <= 2^21 (NMPC_E_ARG otherwise, before anything is queued).
+ * Every call on a GPU shares that GPU's array: calls whose execution may
+ * overlap on one GPU (several streams or host threads) race and must be
+ * serialized by the caller. Results equal nmpc_gemm_f32 with the same
+ * arguments (the partials are fully written before they are summed, in the
+ * same fixed order). */
+int nmpc_gemm_f32_noalloc(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A,
+                          int32_t lda, int64_t stride_a, const float *B, int32_t ldb,
+                          int64_t stride_b, float beta, float *C, int32_t ldc, int64_t stride_c,
+                          int32_t groups, int32_t ksplit, void *stream);
+
 /* The same grouped product with fp64 products and accumulation: C_g =
  * alpha op(A_g) B_g + beta Cin_g (Cin = C when NULL; Cin_g and C_g share
  * stride_c and ldc) on fp64 operands (nmpc_gemm_f64), or C_g = op(A_g) B_g +

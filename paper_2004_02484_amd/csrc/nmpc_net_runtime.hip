@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "nmpc.h"
@@ -50,6 +51,33 @@ int launch_mx(int ta, int in64, int acc64, int32_t M, int32_t N, int32_t K, cons
     return NMPC_OK;
 }
 
+// Split-K partials of nmpc_gemm_f32_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends. Host code must not pass the
+// array's name to a kernel (on the host it is only a stand-in): the device
+// address of each GPU's copy is looked up once per device and kept here.
+constexpr size_t kNoAllocFloats = (size_t)2 << 20;   // 8 MiB
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+constexpr int kMaxDevices = 64;
+float *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_for_current_device(float **out)
+{
+    int dev = -1;
+    NET_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return net_fail(NMPC_E_DEVICE, "gemm_f32_noalloc: device index");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return net_fail(NMPC_E_DEVICE, "gemm_f32_noalloc: hipGetSymbolAddress of the scratch array failed");
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NMPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -80,6 +108,28 @@ int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float 
     return launch_mx(trans_a, 0, 0, M, N, K, A, lda, stride_a, B, ldb, stride_b, 1.0, beta,
                      nullptr, C, ldc, stride_c, groups, stream, "gemm_f32: bad arguments", ksplit,
                      work);
+}
+
+int nmpc_gemm_f32_noalloc(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A,
+                          int32_t lda, int64_t stride_a, const float *B, int32_t ldb,
+                          int64_t stride_b, float beta, float *C, int32_t ldc, int64_t stride_c,
+                          int32_t groups, int32_t ksplit, void *stream)
+{
+    if (M < 1 || N < 1 || groups < 1 || ksplit < 1)
+        return net_fail(NMPC_E_ARG, "gemm_f32_noalloc: bad arguments");
+    float *work = nullptr;
+    if (ksplit > 1) {
+        const unsigned long long need =
+            (unsigned long long)groups * (unsigned long long)ksplit * (unsigned long long)M * N;
+        if (need > kNoAllocFloats)
+            return net_fail(NMPC_E_ARG, "gemm_f32_noalloc: groups * ksplit * M * N exceeds the "
+                                        "static scratch of 2^21 floats (8 MiB)");
+        const int rc = scratch_for_current_device(&work);
+        if (rc) return rc;
+    }
+    return launch_mx(trans_a, 0, 0, M, N, K, A, lda, stride_a, B, ldb, stride_b, 1.0, beta,
+                     nullptr, C, ldc, stride_c, groups, stream, "gemm_f32_noalloc: bad arguments",
+                     ksplit, work);
 }
 
 int nmpc_gemm_f64(int32_t trans_a, int32_t M, int32_t N, int32_t K, const double *A, int32_t lda,
