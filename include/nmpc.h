@@ -157,6 +157,13 @@ typedef struct nmpc_info {
     int32_t status;       /* NMPC_OK, NMPC_E_NOCONV or NMPC_E_NONFINITE */
     int32_t fp32_iters;   /* iterations run with FP32 sweeps */
     int32_t start_used;   /* 0 cold, 1 given (x, u, lambda), 2 built from u */
+    double err_vs_fp64;   /* error of the FP32-sweep phase against FP64: the
+                             size of the final FP64 correction step taken from
+                             the iterate accepted in the FP32 phase, max |du| /
+                             max |u| over the horizon (relative control change);
+                             0 for NMPC_FP64 solves; -1 where no FP64 step was
+                             taken (fp32_finish = 1, or the solve ended in the
+                             FP32 phase) */
 } nmpc_info;
 
 typedef struct nmpc_handle nmpc_handle;

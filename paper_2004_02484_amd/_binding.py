@@ -52,12 +52,13 @@ class nmpc_options(ctypes.Structure):
 class nmpc_info(ctypes.Structure):
     _fields_ = [("r_scaled", ctypes.c_double), ("r_paper", ctypes.c_double),
                 ("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("fp32_iters", ctypes.c_int32), ("start_used", ctypes.c_int32)]
+                ("fp32_iters", ctypes.c_int32), ("start_used", ctypes.c_int32),
+                ("err_vs_fp64", ctypes.c_double)]
 
     def as_dict(self):
         return {"r_scaled": self.r_scaled, "r_paper": self.r_paper, "iters": self.iters,
                 "status": self.status, "fp32_iters": self.fp32_iters,
-                "start_used": self.start_used}
+                "start_used": self.start_used, "err_vs_fp64": self.err_vs_fp64}
 
 
 class NmpcError(RuntimeError):

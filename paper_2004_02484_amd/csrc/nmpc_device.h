@@ -77,6 +77,8 @@ struct IterArgs {
     int fp32_finish;                // FP32 phase: a passed test finishes (no FP64 correction)
     double *apart;                  // input box: [B][N] step limit of each stage's update
     int *aupd;                      // input box: [B] 1 + launch index of the instance's last update
+    unsigned long long *du;         // [B][2] FP64 correction step of an FP32-sweep solve: max |du|,
+                                    // max |u^{j+1}| (bit patterns of non-negative doubles)
 };
 
 struct InitArgs {
@@ -88,6 +90,7 @@ struct InitArgs {
     double *X, *U, *LAM;
     InstState *st;
     int *iters, *ctr;
+    unsigned long long *du;         // [B][2] zeroed with the iteration state
 };
 
 struct OutArgs {
@@ -141,7 +144,9 @@ struct StreamArgs {
     long long lunits;               // lower pass: count * N * nrb * nstrip wave units
     int lper_xcd;                   // lower pass: workgroups per XCD run
     InstState *st;                  // [B]
-    int *work;                      // [B] 1: the instance takes a step in this iteration
+    int *work;                      // [B] 1: the instance takes a step in this iteration,
+                                    // 2: that step is the FP64 correction of an FP32-sweep solve
+    unsigned long long *du;         // [B][2] as IterArgs::du
     int *iters;
     double *rfin;
     int *ctr;                       // [2] finished, [3] in the FP32 phase
@@ -222,6 +227,10 @@ __host__ __device__ inline LdsOff lds_layout(int GT, int W, int CX, int tsize, i
     o.total = p;
     return o;
 }
+
+// nmpc_info.err_vs_fp64 of one result from its final state and the recorded
+// FP64 correction step (host code, nmpc_runtime.hip).
+double fp32_step_error(bool fp32, bool finish, const InstState &s, const unsigned long long *du);
 
 // ry = 0 selects the default tile height for (prec, cx).
 const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);

@@ -30,7 +30,7 @@ namespace nmpc {
 template <typename T, int CX, int RY, int LX, int LY>
 __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int dir, int src,
                                          int dst, int utb, bool res, bool res_only,
-                                         unsigned long long (&acc)[2])
+                                         unsigned long long (&acc)[2], bool redo = false)
 {
     const int N = a.P.N, n = a.P.n, M = LX * LY;
     StageLoc v{};
@@ -44,6 +44,7 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.res_only = res_only;
     v.omega = a.omega;
     v.box_at = -1;   // the input box runs with the Jacobi upper layer only
+    v.du_at = redo && a.du ? b : -1;
     // forward: x_{i-1} updated (dst), lambda_{i+1} not yet (src); backward:
     // the reverse. The residual of S^j takes both from src.
     v.xpb = dir > 0 ? dst : src;
@@ -104,7 +105,8 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
     double rs = 0.0, rp = 0.0;
     if (PREC == kModeFp64 && s.mode == kModeFp64Redo) {
         unsigned long long none[2] = {0, 0};
-        gs_sweep<T, CX, RY, LX, LY>(a, c, b, dir1, j & 1, (j & 1) ^ 1, -1, false, false, none);
+        gs_sweep<T, CX, RY, LX, LY>(a, c, b, dir1, j & 1, (j & 1) ^ 1, -1, false, false, none,
+                                    true);
         ++s.e;
         ++j;
         check_only = true;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
         const int b = a.res_first_stage ? unit : unit / N, i = a.res_first_stage ? 0 : unit % N;
         Decision d;
         if (a.residual_only) {
-            d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false;
+            d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false; d.redo = false;
         } else {
             d = decide<PREC>(a, c, b, i, k, N, (long long)b * N);
         }
@@ -57,6 +57,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
             v.res_at = (long long)d.slot * a.rslot + (long long)b * N + i;
             v.res_only = d.eval_only;
+            if (d.redo && a.du) v.du_at = b;
             if (a.P.tau > 0.0 && !a.residual_only && !d.eval_only) {
                 v.box_at = (long long)b * N + i;
                 if (i == 0 && c.tid == 0) a.aupd[b] = k + 1;   // this launch updates b
@@ -465,6 +466,7 @@ __global__ void k_init(const InitArgs a)
         a.st[t] = s;
         a.st[a.B + t] = s;
         a.iters[t] = 0;
+        if (a.du) { a.du[2 * t] = 0; a.du[2 * t + 1] = 0; }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         a.ctr[0] = 0;

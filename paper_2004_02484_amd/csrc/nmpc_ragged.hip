@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
     const long long us = r.ustart[b];
     Decision d;
     if (a.residual_only) {
-        d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false;
+        d.work = true; d.j = 0; d.slot = a.res_slot; d.eval_only = false; d.redo = false;
     } else {
         d = decide<PREC>(a, c, b, i, k, N, us);
     }
@@ -70,6 +70,7 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
     v.xro = r.xoff[b];
     v.res_at = (long long)d.slot * a.rslot + us + i;
     v.res_only = d.eval_only;
+    if (d.redo && a.du) v.du_at = b;
     v.i = i;
     v.last = i == N - 1;
     unsigned long long acc[2] = {0, 0};
@@ -127,6 +128,7 @@ __global__ void k_rg_init(const IterArgs a, const RgArgs r, int mode, const doub
         a.st[b] = s;
         a.st[a.B + b] = s;
         a.iters[b] = 0;
+        if (a.du) { a.du[2 * b] = 0; a.du[2 * b + 1] = 0; }
     }
     if (b == 0 && threadIdx.x == 0) {
         a.ctr[0] = 0;

@@ -79,6 +79,7 @@ struct nmpc_ragged {
     InstState *d_st = nullptr;
     int *d_iters = nullptr;
     double *d_rfin = nullptr;
+    unsigned long long *d_du = nullptr;   // [B][2] FP64 correction step (max |du|, max |u|)
     int *d_ctr = nullptr;
     int *h_poll = nullptr;
     int gen = 0;                  // bumped when a buffer moves (graphs hold pointers)
@@ -123,7 +124,7 @@ void rg_release(nmpc_ragged *r)
     for (void *p : {(void *)r->d_cls[0], (void *)r->d_cls[1], (void *)r->d_cls[2], (void *)r->d_g,
                     (void *)r->d_icls, (void *)r->d_off, (void *)r->d_umap, (void *)r->d_S[0],
                     (void *)r->d_S[1], (void *)r->d_in, (void *)r->d_rst, (void *)r->d_st,
-                    (void *)r->d_iters, (void *)r->d_rfin, (void *)r->d_ctr})
+                    (void *)r->d_iters, (void *)r->d_rfin, (void *)r->d_ctr, (void *)r->d_du})
         if (p) (void)hipFree(p);
     if (r->h_poll) (void)hipHostFree(r->h_poll);
     for (hipEvent_t e : {r->ev, r->t0, r->t1})
@@ -260,7 +261,7 @@ IterArgs rg_iter_args(const nmpc_ragged *r)
     a.rst = r->d_rst;
     a.pst = r->d_rst + 3 * r->tot_units;
     a.rslot = (long long)r->tot_units;
-    a.st = r->d_st; a.iters = r->d_iters; a.rfin = r->d_rfin;
+    a.st = r->d_st; a.iters = r->d_iters; a.rfin = r->d_rfin; a.du = r->d_du;
     a.ctr = r->d_ctr; a.kofs = 0;
     a.B = r->max_inst;
     a.units = 0;       // per launch: 8 * the segment's per_xcd
@@ -429,6 +430,9 @@ int collect(nmpc_ragged *r, nmpc_info *info)
     std::vector<InstState> st(count), st2(count);
     RG_TRY(hipMemcpyAsync(iters.data(), r->d_iters, sizeof(int) * count, hipMemcpyDeviceToHost, r->stream));
     RG_TRY(hipMemcpyAsync(rf.data(), r->d_rfin, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, r->stream));
+    std::vector<unsigned long long> du(2 * (size_t)count);
+    RG_TRY(hipMemcpyAsync(du.data(), r->d_du, sizeof(unsigned long long) * 2 * count,
+                          hipMemcpyDeviceToHost, r->stream));
     RG_TRY(hipMemcpyAsync(st.data(), r->d_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, r->stream));
     RG_TRY(hipMemcpyAsync(st2.data(), r->d_st + r->max_inst, sizeof(InstState) * count,
                           hipMemcpyDeviceToHost, r->stream));
@@ -445,6 +449,8 @@ int collect(nmpc_ragged *r, nmpc_info *info)
             info[b].status = status;
             info[b].fp32_iters = s.f32;
             info[b].start_used = 0;
+            info[b].err_vs_fp64 = nmpc::fp32_step_error(r->opt.precision == NMPC_FP32_SWEEP, false, s,
+                                                  &du[2 * b]);
         }
         if (status != NMPC_OK && worst == NMPC_OK) worst = status;
     }
@@ -557,6 +563,7 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
     A((void **)&r->d_st, sizeof(InstState) * 2 * max_instances);
     A((void **)&r->d_iters, sizeof(int) * max_instances);
     A((void **)&r->d_rfin, sizeof(double) * 2 * max_instances);
+    A((void **)&r->d_du, sizeof(unsigned long long) * 2 * max_instances);
     A((void **)&r->d_ctr, sizeof(int) * 4);
     if (e == hipSuccess) e = hipHostMalloc((void **)&r->h_poll, 2 * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking);

@@ -80,6 +80,7 @@ struct nmpc_handle {
     InstState *d_st = nullptr;             // [2][B]
     int *d_iters = nullptr;                // [B]
     double *d_rfin = nullptr;              // [B][2]
+    unsigned long long *d_du = nullptr;    // [B][2] FP64 correction step (max |du|, max |u|)
     int *d_ctr = nullptr;                  // [4]
     int *h_poll = nullptr;                 // pinned
     bool timing = false;
@@ -260,7 +261,7 @@ void release(nmpc_handle *h)
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
                     (void *)h->d_start, (void *)h->d_stream, (void *)h->d_work,
-                    (void *)h->d_apart, (void *)h->d_aupd})
+                    (void *)h->d_apart, (void *)h->d_aupd, (void *)h->d_du})
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
     if (h->ev) (void)hipEventDestroy(h->ev);
@@ -294,7 +295,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     for (int b = 0; b < 2; ++b) { a.X[b] = h->X(b); a.U[b] = h->U(b); a.LAM[b] = h->L(b); }
     a.rst = h->d_rst;
     a.pst = h->d_rst + 3 * (size_t)h->max_batch * h->N;
-    a.st = h->d_st; a.iters = h->d_iters; a.rfin = h->d_rfin;
+    a.st = h->d_st; a.iters = h->d_iters; a.rfin = h->d_rfin; a.du = h->d_du;
     a.ctr = h->d_ctr; a.kofs = 0;
     a.B = h->max_batch;
     a.units = count * h->N;
@@ -421,6 +422,7 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     ia.st = h->d_st;
     ia.iters = h->d_iters; ia.ctr = h->d_ctr;
     ia.project = h->prob.tau > 0.0 ? 1 : 0;
+    ia.du = h->d_du;
     ia.ulo = h->prob.u_lo; ia.uhi = h->prob.u_hi;
     if (h->d_aupd)   // input box: no update recorded for this solve yet (not captured)
         HIP_TRY(hipMemsetAsync(h->d_aupd, 0, sizeof(int) * h->max_batch, h->stream));
@@ -544,6 +546,7 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.rst = h->d_rst;
     a.pst = h->d_rst + B * N;
     a.st = h->d_st; a.work = h->d_work; a.iters = h->d_iters; a.rfin = h->d_rfin; a.ctr = h->d_ctr;
+    a.du = h->d_du;
     a.count = count;
     a.units = (long long)count * h->N * ((p.nsy + nmpc::kStreamRows - 1) / nmpc::kStreamRows);
     a.per_xcd = (int)((a.units + 7) / 8);
@@ -738,6 +741,28 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
     return launch_output(h, count, ox, ou, ol);
 }
 
+}  // namespace
+
+namespace nmpc {
+
+// err_vs_fp64 of one result: 0 for FP64 solves; for FP32-sweep solves the
+// size of the FP64 correction step taken from the iterate accepted in the FP32
+// phase, max |du| / max |u^{j+1}| over the horizon; -1 where no such step was
+// taken (fp32_finish, or the solve ended in the FP32 phase).
+double fp32_step_error(bool fp32, bool finish, const InstState &s, const unsigned long long *du)
+{
+    if (!fp32) return 0.0;
+    if (finish || s.mode != nmpc::kModeFp64) return -1.0;
+    double d, u;
+    std::memcpy(&d, &du[0], sizeof d);
+    std::memcpy(&u, &du[1], sizeof u);
+    return u > 0.0 ? d / u : d;
+}
+
+}  // namespace nmpc
+
+namespace {
+
 int collect_info(nmpc_handle *h, int count, nmpc_info *info)
 {
     std::vector<int> iters(count);
@@ -752,6 +777,9 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
                                h->stream));
     HIP_TRY(hipMemcpyAsync(iters.data(), h->d_iters, sizeof(int) * count, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(rf.data(), h->d_rfin, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, h->stream));
+    std::vector<unsigned long long> du(2 * (size_t)count);
+    HIP_TRY(hipMemcpyAsync(du.data(), h->d_du, sizeof(unsigned long long) * 2 * count,
+                           hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(st.data(), h->d_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipMemcpyAsync(st2.data(), h->d_st + h->max_batch, sizeof(InstState) * count,
                            hipMemcpyDeviceToHost, h->stream));
@@ -768,6 +796,8 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
             info[b].status = status;
             info[b].fp32_iters = s.f32;
             info[b].start_used = used[b];
+            info[b].err_vs_fp64 = nmpc::fp32_step_error(main_prec(h->opt) == nmpc::kModeFp32,
+                                                  h->opt.fp32_finish != 0, s, &du[2 * b]);
         }
         if (status != NMPC_OK && worst == NMPC_OK) worst = status;
     }
@@ -865,6 +895,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_st, sizeof(InstState) * 2 * B);
     ALLOC(h->d_iters, sizeof(int) * B);
     ALLOC(h->d_rfin, sizeof(double) * 2 * B);
+    ALLOC(h->d_du, sizeof(unsigned long long) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
     ALLOC(h->d_start, sizeof(int) * B);
     if (prob->tau > 0.0) {

@@ -484,6 +484,7 @@ struct Decision {
     int j;           // index of the iterate evaluated (S^j)
     int slot;        // residual slot this evaluation accumulates into
     bool eval_only;  // evaluate S^j only: its test is the last one owed
+    bool redo;       // the FP64 correction step from the FP32-sweep iterate S^j
 };
 
 // Per-instance state machine. All workgroups of an instance compute the same
@@ -508,7 +509,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
 {
     const InstState s = a.st[(k & 1) * a.B + b];
     InstState ns = s;
-    Decision d{false, 0, 0, false};
+    Decision d{false, 0, 0, false, false};
     int fin = -1;
     double rs = 0.0, rp = 0.0;
     if (s.status == kActive && s.e > 0) {
@@ -543,6 +544,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                     ns.pending = 1;
                     d.work = true;
                     d.j = s.j;
+                    d.redo = true;
                 }
             } else if (rs <= a.tol) {
                 if (s.mode == kModeFp32) {
@@ -608,6 +610,8 @@ struct StageLoc {
     bool res_only;                 // stop after the residual (no lower layer, no update)
     double omega;                  // the update is S^j - omega ds (1: the plain step)
     long long box_at;              // >= 0: index into a.apart for this stage's step limit
+    long long du_at;               // >= 0: instance whose FP64 correction step this is
+                                   // (max |du|, max |u_new| into a.du)
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
     int pnb, pni;                  // stage pni of buffer pnb is prefetched once this stage
                                    // has read its own (pnb < 0: none)
@@ -643,6 +647,7 @@ __device__ __forceinline__ StageLoc jacobi_loc(int cur)
     v.dst = cur ^ 1;
     v.omega = 1.0;
     v.box_at = -1;
+    v.du_at = -1;
     v.utb = -1;
     v.pnb = -1;
     return v;
@@ -918,7 +923,14 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 Xn[p] = Xc[p] - om * double(y5[t][q]);
                 Lw[p] = Lc[p] - om * double(y4[t][q]);
             }
-    if (c.tid < M) a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = uvec[c.tid] - om * v3[c.tid];
+    if (c.tid < M) {
+        const double un = uvec[c.tid] - om * v3[c.tid];
+        a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = un;
+        if (v.du_at >= 0) {   // size of the FP64 correction step (reported per result)
+            atomicMax(a.du + 2 * v.du_at, abits(om * v3[c.tid]));
+            atomicMax(a.du + 2 * v.du_at + 1, abits(un));
+        }
+    }
     if (P.tau > 0.0 && v.box_at >= 0) {
         // fraction-to-the-boundary limit of this stage's input step (eq.
         // eq_alphamax); the launch's box kernel takes the minimum over the

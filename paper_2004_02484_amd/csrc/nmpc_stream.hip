@@ -515,15 +515,15 @@ __global__ void k_st_decide(const StreamArgs a)
             s.mode = kModeFp64Redo;
         } else if (s.mode == kModeFp64Redo) {
             s.mode = kModeFp64;
-            work = 1;
+            work = 2;   // the FP64 correction step from the FP32-sweep iterate
         } else {
             fin = kStatusOk;
         }
     } else if (s.j >= a.max_iter) {
         fin = kStatusNoconv;
     } else {
+        work = s.mode == kModeFp64Redo ? 2 : 1;
         if (s.mode == kModeFp64Redo) s.mode = kModeFp64;
-        work = 1;
     }
     if (was32 && (s.mode != kModeFp32 || fin >= 0)) atomicSub(a.ctr + 3, 1);
     if (work) {
@@ -714,7 +714,14 @@ __global__ void __launch_bounds__(256) k_st_jft(const StreamArgs a, int pass, in
     if (update && u.iy0 == 0) {
         const double *uc = a.U[cur] + bi * P.m;
         double *un = a.U[nxt] + bi * P.m;
-        for (int j = threadIdx.x; j < P.m; j += blockDim.x) un[j] = uc[j] - a.v3[bi * P.m + j];
+        const int b = (int)(bi / P.N);
+        for (int j = threadIdx.x; j < P.m; j += blockDim.x) {
+            un[j] = uc[j] - a.v3[bi * P.m + j];
+            if (a.work[b] == 2 && a.du) {   // size of the FP64 correction step
+                atomicMax(a.du + 2 * b, sabits(a.v3[bi * P.m + j]));
+                atomicMax(a.du + 2 * b + 1, sabits(un[j]));
+            }
+        }
     }
 }
 
@@ -926,7 +933,14 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
         if (rb == 0 && sp == 0) {
             const double *uc = a.U[cur] + bi * m;
             double *un = a.U[nxt] + bi * m;
-            for (int j = lane; j < m; j += kWave) un[j] = uc[j] - a.v3[bi * m + j];
+            const int b = (int)(bi / a.P.N);
+            for (int j = lane; j < m; j += kWave) {
+                un[j] = uc[j] - a.v3[bi * m + j];
+                if (a.work[b] == 2 && a.du) {   // size of the FP64 correction step
+                    atomicMax(a.du + 2 * b, sabits(a.v3[bi * m + j]));
+                    atomicMax(a.du + 2 * b + 1, sabits(un[j]));
+                }
+            }
         }
         return;
     }

@@ -100,8 +100,10 @@ def test_sgs_fp32_sweeps_c1_batch(nm):
     for b in (0, 3):
         ex = oracle.solve(P, x0[b], xr[b], tol=1e-11, max_iter=20000)
         err = rel(U[b].cpu().numpy(), ex["U"])
-        print(f"instance {b}: control error vs exact {err:.2e}")
+        print(f"instance {b}: control error vs exact {err:.2e}, "
+              f"err_vs_fp64 {infos[b]['err_vs_fp64']:.2e}")
         assert err <= 1e-4
+        assert 0.0 < infos[b]["err_vs_fp64"] <= 1e-4
         r_s, _ = oracle.residual(P, x0[b], xr[b], X[b].cpu().numpy(), U[b].cpu().numpy(),
                                  L[b].cpu().numpy())
         assert r_s <= 1e-6
@@ -133,6 +135,12 @@ def test_sgs_fp32_finish(nm):
         print(f"instance {b}: {infos[b]['iters']} iterations "
               f"(default {runs[0][3][b]['iters']}), control error vs exact {err:.2e}")
         assert err <= 1e-4
+        assert infos[b]["err_vs_fp64"] == -1.0
+        d = runs[0][3][b]
+        assert 0.0 < d["err_vs_fp64"] <= 1e-4
+        if d["iters"] == infos[b]["iters"] + 1:   # one FP64 sweep from the FP32 iterate
+            step = np.abs(runs[0][1][b] - U[b]).max() / np.abs(runs[0][1][b]).max()
+            assert abs(d["err_vs_fp64"] - step) <= 1e-6 * step
 
 
 def test_sgs_batch_equals_single_solves(nm):

@@ -115,6 +115,7 @@ def test_converged_solution_matches_oracle(nm, name, seed):
     o = oracle.solve(P, x0, xref, tol=1e-6)
     assert rc == nm.NMPC_OK and o["status"] == "converged"
     assert abs(info["iters"] - o["iters"]) <= 1
+    assert info["err_vs_fp64"] == 0.0     # an FP64 solve has no FP32 phase
     # element by element against the oracle's iterate of the same index, always
     ok = oracle_at(P, x0, xref, o, info["iters"])
     assert rel(X, ok["X"]) <= 1e-9 and rel(U, ok["U"]) <= 1e-9 and rel(L, ok["LAM"]) <= 1e-9
@@ -198,8 +199,9 @@ def test_fp32_sweeps_reach_fp64_fixed_point(nm):
     ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
     err = rel(U, ex["U"])
     print(f"fp32 sweeps: iters {info['iters']} (fp32 {info['fp32_iters']}), "
-          f"control rel. error vs exact {err:.2e}")
+          f"control rel. error vs exact {err:.2e}, err_vs_fp64 {info['err_vs_fp64']:.2e}")
     assert err <= 1e-4
+    assert 0.0 < info["err_vs_fp64"] <= 1e-4
 
 
 def test_fp32_finish_returns_the_fp32_phase_iterate(nm):
@@ -228,8 +230,16 @@ def test_fp32_finish_returns_the_fp32_phase_iterate(nm):
         ex = oracle.solve(P, x0s[b], xrefs[b], tol=1e-12, max_iter=20000)
         err = rel(U[b], ex["U"])
         print(f"instance {b}: fp32_finish {i1['iters']} iterations (default {i0['iters']}), "
-              f"control rel. error vs exact {err:.2e} (default {rel(runs[0][1][b], ex['U']):.2e})")
+              f"control rel. error vs exact {err:.2e} (default {rel(runs[0][1][b], ex['U']):.2e}),"
+              f" err_vs_fp64 {i0['err_vs_fp64']:.2e}")
         assert err <= 1e-4
+        # err_vs_fp64: the default's FP64 correction step from the FP32-phase
+        # iterate, which is what fp32_finish returns (same arithmetic up to it)
+        assert i1["err_vs_fp64"] == -1.0
+        if i0["iters"] == i1["iters"] + 1:
+            step = np.abs(runs[0][1][b] - U[b]).max() / np.abs(runs[0][1][b]).max()
+            assert abs(i0["err_vs_fp64"] - step) <= 1e-6 * step, (i0["err_vs_fp64"], step)
+        assert 0.0 < i0["err_vs_fp64"] <= 1e-4
 
 
 def test_warm_start_and_failure_statuses(nm):

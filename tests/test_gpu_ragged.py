@@ -108,6 +108,7 @@ def test_ragged_fp32_converges_to_the_exact_solution(nm):
         r_s, _ = oracle.residual(classes[c], x0, xr, X.cpu().numpy(), U.cpu().numpy(),
                                  L.cpu().numpy())
         assert r_s <= 1e-6 and info["r_scaled"] <= 1e-6
+        assert 0.0 < info["err_vs_fp64"] <= 1e-4
 
 
 def test_ragged_warm_start_given(nm):

@@ -127,3 +127,17 @@ def test_c2_full_size(nm):
     assert rc == nm.NMPC_OK
     r_s, _ = oracle.residual(P, x0, xref, X, U, L)
     assert r_s <= 1e-6
+    assert 0.0 < info["err_vs_fp64"] <= 1e-4
+    # control error against a reference solution: the FP64 streaming solve
+    # (its first iterate equals the oracle's above) run to tol 1e-10, whose
+    # KKT point the oracle's residual confirms
+    s.close()
+    s = nm.Solver(P, tol=1e-10, max_iter=20000)
+    rc, Xe, Ue, Le, ie = s.solve(x0, xref)
+    assert rc == nm.NMPC_OK and ie["err_vs_fp64"] == 0.0
+    r_e, _ = oracle.residual(P, x0, xref, Xe, Ue, Le)
+    assert r_e <= 1e-10
+    err = rel(U, Ue)
+    print(f"C2: FP64 reference {ie['iters']} iterations; FP32-sweep control error {err:.2e}, "
+          f"err_vs_fp64 {info['err_vs_fp64']:.2e}")
+    assert err <= 1e-4
