@@ -27,16 +27,42 @@ from nmpc_inputs import Problem
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dlj_ref.c")
 _LIB = os.path.join(_HERE, "libdlj_ref.so")
+_LIB_NATIVE = os.path.join(_HERE, "libdlj_ref_native.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile dlj_ref.c into libdlj_ref.so (gcc, FP64, OpenMP over stages)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile dlj_ref.c into libdlj_ref.so (gcc, FP64, OpenMP over stages).
+    native: a copy tuned for the CPU it is built on (-march=native), for timing
+    the oracle on the machine that runs it (built there, never shipped)."""
+    lib = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        flags = ["-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99"]
+        if native:
+            flags.append("-march=native")
+        subprocess.check_call(["gcc", *flags, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
+
+
+_use_native = False
+
+
+def use_native() -> None:
+    """Build the host-tuned copy here and load it for every later call (must be
+    called before the first call into the oracle)."""
+    global _use_native
+    if _use_native:
+        return
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    build(force=True, native=True)
+    _use_native = True
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops."""
+    _load().ref_set_threads(int(n))
 
 
 class _RefProblem(ctypes.Structure):
@@ -54,9 +80,12 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        path = _LIB_NATIVE if _use_native else _LIB
+        if not os.path.exists(path):
+            build(force=False, native=_use_native)
+        lib = ctypes.CDLL(path)
+        lib.ref_set_threads.argtypes = [ctypes.c_int]
+        lib.ref_set_threads.restype = None
         dp = ctypes.POINTER(ctypes.c_double)
         pp = ctypes.POINTER(_RefProblem)
         lib.ref_kkt.argtypes = [pp, dp, dp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp]
