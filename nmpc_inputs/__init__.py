@@ -35,6 +35,11 @@ __all__ = [
     "make_batch",
     "ragged_specs",
     "CONFIG_NAMES",
+    "ModelProblem",
+    "make_plate_problem",
+    "make_plate_instance",
+    "make_wave_problem",
+    "make_wave_instance",
 ]
 
 
@@ -60,6 +65,7 @@ class Problem:
     u_lo: float = 0.0
     u_hi: float = 0.0
     name: str = ""
+    B: Optional[np.ndarray] = None   # explicit dense input matrix [n, m] (overrides gx, gy)
 
     @property
     def n(self) -> int:
@@ -78,7 +84,10 @@ class Problem:
         return 1.0 / (self.nsy + 1) if self.dim == 2 else 1.0
 
     def dense_B(self) -> np.ndarray:
-        """Input matrix B [n, m] with B[iy*nsx+ix, b*lx+a] = gy[b,iy] gx[a,ix]."""
+        """Input matrix B [n, m] with B[iy*nsx+ix, b*lx+a] = gy[b,iy] gx[a,ix],
+        or the explicit matrix when one is given."""
+        if self.B is not None:
+            return np.asarray(self.B, dtype=np.float64)
         return np.kron(self.gy.T, self.gx.T)
 
     def with_(self, **kw) -> "Problem":
@@ -199,3 +208,167 @@ CONFIG_NAMES: Dict[str, str] = {
     "c1": "2D heat 64x64, N=40, 4x4 Gaussian lattice",
     "c2": "2D heat 256x256, N=100, 8x8 Gaussian lattice",
 }
+
+
+# ----------------------------------------------------------------------------
+# Further workloads of the paper's PDE class (Sec. 2): problem data only.
+
+@dataclasses.dataclass
+class ModelProblem:
+    """One discretized NMPC problem of the model engine (data only).
+
+    Grid: ``nsy x nsx`` nodes, node ``p = iy * nsx + ix``. ``boundary``:
+    ``"neumann"`` -- the nodes include the boundary of the unit square
+    (``dx = 1/(nsx-1)``) and the normal derivative is zero there (Sec. 2.1,
+    fictitious points); ``"dirichlet"`` -- interior nodes (``dx = 1/(nsx+1)``),
+    zero values outside.
+
+    Models (``model``):
+      ``"plate"`` -- thin plate, ``w_t = alpha Lap w - beta (w - t_amb) -
+      rad (w^4 - t_amb^4)`` (Sec. 5); the inputs are the temperatures of the
+      actuator nodes ``act`` (those nodes are not states);
+      ``"wave"`` -- second order in time (Sec. 2, a = 1):
+      ``W_tt + damp W_t = k0 (1 + k1 W) Lap W + B u``, state ``(W, W_t)``;
+      ``"heat"`` -- ``w_t = k0 (1 + k1 w) Lap w + B u`` with a dense B.
+    Stage cost ``0.5 q |w - wref|^2 + 0.5 qv |W_t|^2 + 0.5 r |u - uref|^2``
+    (qv: wave only), regularization ``gamma``, optional input box ``[u_lo,
+    u_hi]`` by the log barrier ``tau`` (eq. nlp_relaxed).
+    """
+
+    model: str
+    nsx: int
+    nsy: int
+    N: int
+    h: float
+    boundary: str = "dirichlet"
+    act: Optional[List[int]] = None      # plate: actuator node indices
+    B: Optional[np.ndarray] = None       # wave / heat: [nsx*nsy, m]
+    q: float = 1.0
+    qv: float = 0.0
+    r: float = 0.01
+    gamma: float = 0.0
+    tau: float = 0.0
+    u_lo: float = 0.0
+    u_hi: float = 0.0
+    u_cold: float = 0.0                  # inputs of the cold start
+    alpha: float = 0.0                   # plate physics
+    beta: float = 0.0
+    rad: float = 0.0
+    t_amb: float = 0.0
+    k0: float = 0.0                      # wave / heat physics
+    k1: float = 0.0
+    damp: float = 0.0
+    name: str = ""
+
+    @property
+    def nodes(self) -> int:
+        return self.nsx * self.nsy
+
+    @property
+    def m(self) -> int:
+        return len(self.act) if self.model == "plate" else int(self.B.shape[1])
+
+    @property
+    def dx(self) -> float:
+        return 1.0 / (self.nsx - 1) if self.boundary == "neumann" else 1.0 / (self.nsx + 1)
+
+    @property
+    def dy(self) -> float:
+        if self.nsy == 1:
+            return 1.0
+        return 1.0 / (self.nsy - 1) if self.boundary == "neumann" else 1.0 / (self.nsy + 1)
+
+    def with_(self, **kw) -> "ModelProblem":
+        return dataclasses.replace(self, **kw)
+
+
+# Copper plate of Sec. 5 (Table of process parameters)
+PLATE_RHO, PLATE_CP, PLATE_TZ, PLATE_K = 8960.0, 386.0, 0.01, 400.0
+PLATE_HC, PLATE_TA, PLATE_EPS, PLATE_SB = 1.0, 300.0, 0.5, 5.67e-8
+PLATE_ACT_AXIS = (2, 5, 7, 10)   # actuator rows/columns on the 13 x 13 grid (reading)
+
+
+def make_plate_problem(N: int = 20, T: float = 100.0, ns: int = 13,
+                       tau: float = 100.0, gamma: float = 0.5, r: float = 0.1) -> ModelProblem:
+    """The paper's copper-plate NMPC problem: 13 x 13 nodes, zero Neumann
+    boundary, 16 actuator nodes (a 4 x 4 lattice at rows/columns 2, 5, 7, 10:
+    the figure with their positions is not available), inputs boxed to
+    [T_a, T_a + 400] with tau = 100, gamma = 0.5, Q = I, R = 0.1 I, T = 100 s,
+    N = 20. The PDE rho C_p t_z w_t = k t_z Lap w - 2 Q_c - 2 Q_r divided by
+    rho C_p t_z."""
+    if ns != 13:
+        axis = tuple(int(round(v * (ns - 1) / 12.0)) for v in PLATE_ACT_AXIS)
+    else:
+        axis = PLATE_ACT_AXIS
+    act = [iy * ns + ix for iy in axis for ix in axis]
+    c = PLATE_RHO * PLATE_CP * PLATE_TZ
+    return ModelProblem(model="plate", nsx=ns, nsy=ns, N=N, h=T / N, boundary="neumann",
+                        act=act, q=1.0, r=r, gamma=gamma, tau=tau, u_lo=PLATE_TA,
+                        u_hi=PLATE_TA + 400.0, u_cold=PLATE_TA + 200.0,
+                        alpha=PLATE_K / (PLATE_RHO * PLATE_CP), beta=2.0 * PLATE_HC / c,
+                        rad=2.0 * PLATE_EPS * PLATE_SB / c, t_amb=PLATE_TA, name="plate")
+
+
+def plate_reference(P: ModelProblem, kind: str, rng: np.random.Generator) -> np.ndarray:
+    """Temperature reference over all nodes [nsy*nsx]: a slope or a V shape
+    (the paper's two reference shapes, drawn from the seed: direction, level
+    and amplitude), inside [T_a + 50, T_a + 350]."""
+    xs = np.linspace(0.0, 1.0, P.nsx)
+    ys = np.linspace(0.0, 1.0, P.nsy)
+    X, Y = np.meshgrid(xs, ys)
+    th = rng.uniform(0.0, 2.0 * np.pi)
+    s = np.cos(th) * (X - 0.5) + np.sin(th) * (Y - 0.5)
+    if kind == "v":
+        s = np.abs(s - rng.uniform(-0.2, 0.2))
+    s = (s - s.min()) / max(s.max() - s.min(), 1e-12)
+    lo = rng.uniform(50.0, 120.0)
+    amp = rng.uniform(120.0, 230.0)
+    return (P.t_amb + lo + amp * s).reshape(-1)
+
+
+def make_plate_instance(P: ModelProblem, seed: int, kind: Optional[str] = None):
+    """(x0 [nodes], xref [nodes]) for one seed. x0: the ambient temperature
+    plus a seeded disturbance U[0, 20] K (seed 0 with kind given: exactly the
+    ambient temperature, the paper's start); the actuator nodes' entries are
+    not states and are ignored by the solvers (the reference's values there
+    are the input references u_ref)."""
+    rng = np.random.default_rng(seed)
+    k = kind if kind is not None else ("slope" if rng.uniform() < 0.5 else "v")
+    dist = rng.uniform(0.0, 20.0, size=P.nodes)
+    x0 = np.full(P.nodes, P.t_amb) + (0.0 if (kind is not None and seed == 0) else dist)
+    return x0, plate_reference(P, k, rng)
+
+
+def make_wave_problem(ns: int = 24, N: int = 30, lattice: int = 4, sigma: float = 0.1,
+                      k0: float = 1.0, k1: float = 0.5, damp: float = 2.0, rho: float = 0.3,
+                      q: float = 1.0, qv: float = 0.1, r: float = 0.01,
+                      gamma_rel: float = 1.0) -> ModelProblem:
+    """Nonlinear damped membrane, second order in time, on ns x ns interior
+    nodes (zero Dirichlet values), Gaussian actuator lattice as a dense B.
+    The stage length is chosen from the sweep contraction of the reduced
+    system (eq. jaco2_sys): 4 h^2 kmax / dx^2 = rho with kmax = k0 (1 + k1)."""
+    dx = 1.0 / (ns + 1)
+    g = gaussian_factors(ns, lattice, sigma)
+    B = np.kron(g.T, g.T)
+    kmax = k0 * (1.0 + k1)
+    h = dx * np.sqrt(rho / (4.0 * kmax))
+    return ModelProblem(model="wave", nsx=ns, nsy=ns, N=N, h=float(h), boundary="dirichlet",
+                        B=B, q=q, qv=qv, r=r, gamma=gamma_rel * h * r, k0=k0, k1=k1,
+                        damp=damp, name=f"wave{ns}n{N}")
+
+
+def make_wave_instance(P: ModelProblem, seed: int):
+    """(x0 [2 nodes]: W0 ~ U[0, 0.2] then W_t = 0; xref [nodes]: W reference,
+    the smooth field of the heat workloads)."""
+    rng = np.random.default_rng(seed)
+    W0 = rng.uniform(0.0, 0.2, size=P.nodes)
+    a = rng.integers(1, 5, size=8)
+    b = rng.integers(1, 5, size=8)
+    c = rng.uniform(-1.0, 1.0, size=8)
+    xs = (np.arange(P.nsx) + 1.0) * P.dx
+    ys = (np.arange(P.nsy) + 1.0) * P.dy
+    s = np.zeros((P.nsy, P.nsx))
+    for k in range(8):
+        s += c[k] * np.sin(np.pi * b[k] * ys)[:, None] * np.sin(np.pi * a[k] * xs)[None, :]
+    wref = (0.3 * s / np.max(np.abs(s))).reshape(-1)
+    return np.concatenate([W0, np.zeros(P.nodes)]), wref
