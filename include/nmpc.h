@@ -66,6 +66,10 @@ enum { NMPC_UPPER_JACOBI = 0, NMPC_UPPER_FGS = 1, NMPC_UPPER_BGS = 2, NMPC_UPPER
 
 enum { NMPC_PATH_AUTO = 0, NMPC_PATH_FUSED = 1, NMPC_PATH_STREAM = 2 };
 
+/* Norm of the stopping test: NMPC_RES_SCALED, r_scaled (see above), or
+ * NMPC_RES_PAPER, the paper's |K|_inf (Table tab_NMPC_para). */
+enum { NMPC_RES_SCALED = 0, NMPC_RES_PAPER = 1 };
+
 /* Problem data (Sec. 3 notation). gx/gy are host arrays, copied at create. */
 typedef struct nmpc_problem {
     int32_t dim;          /* 1 or 2 */
@@ -147,6 +151,9 @@ typedef struct nmpc_options {
                              the step that produced it was solved in FP32).
                              Fused path only (NMPC_E_UNSUPPORTED on the
                              streaming path and for ragged batches); 0 or 1 */
+    int32_t residual;     /* NMPC_RES_SCALED (default): stop when r_scaled <= tol;
+                             NMPC_RES_PAPER: stop when r_paper = |K|_inf <= tol,
+                             the paper's rule (Table tab_NMPC_para) */
 } nmpc_options;
 
 /* Per-instance result information. */
@@ -427,6 +434,94 @@ int nmpc_pack_inputs(const double *u, int32_t count, int32_t N, int32_t m, float
                      int32_t ldr, void *stream);
 int nmpc_unpack_inputs(const float *rows, int32_t ldr, int32_t count, int32_t N, int32_t m,
                        float scale, double *u, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Model engine: the double-layer method for further members of the paper's
+ * PDE class (Sec. 2, eq. pde) on grids of up to 4096 nodes, one workgroup per
+ * instance running the whole solve (FP64; every upper layer of
+ * nmpc_options.upper; input box by the log barrier of eq. nlp_relaxed with
+ * the fraction-to-the-boundary rule eq. alphamax applied to every pass of the
+ * upper layer: S <- S + alpha (S_pass - S), alpha global over the stages).
+ *
+ * Grid: nsy x nsx nodes, node p = iy * nsx + ix. NMPC_BC_DIRICHLET: interior
+ * nodes of the unit interval / square (dx = 1 / (nsx + 1)), zero values
+ * outside. NMPC_BC_NEUMANN: the nodes include the boundary (dx = 1 / (nsx -
+ * 1)) and the normal derivative is zero, by fictitious points mirrored onto
+ * the inner neighbours (eq. neumann, eq. dis_neumann with e = 0).
+ *
+ * Models (stage cost h (q/2 |w - wref|^2 + qv/2 |W_t|^2 + r/2 |u - uref|^2)):
+ *   NMPC_MODEL_HEAT   w_t = k0 (1 + k1 w) Lap w + B u, dense B [nodes][m];
+ *   NMPC_MODEL_PLATE  the copper plate of Sec. 5: w_t = alpha Lap w - beta (w -
+ *                     t_amb) - rad (w^4 - t_amb^4); the temperatures of the
+ *                     actuator nodes act[0..m-1] are the inputs (those nodes
+ *                     are not states); uref = wref at the actuator nodes;
+ *   NMPC_MODEL_WAVE   second order in time (eq. ode): W_tt + damp W_t = k0 (1 +
+ *                     k1 W) Lap W + B u, state (W, W_t); the F_x and F_x^T
+ *                     solves eliminate v6 = h v7 - b6 and sweep the reduced
+ *                     system of eq. jaco2_sys. uref = 0, qv weighs W_t.
+ * Layouts (DEVICE, caller-owned, leading instance index): x0 [count][nx],
+ * nx = nodes (wave: 2 nodes, W then W_t); xref [count][nodes] (wref over the
+ * grid); trajectories x, lambda [count][N][nx], u [count][N][m]. The plate's
+ * returned x holds the inputs at the actuator nodes (the node temperatures),
+ * its lambda zero there; those entries of a given start are ignored.
+ * ------------------------------------------------------------------------ */
+enum { NMPC_MODEL_HEAT = 0, NMPC_MODEL_PLATE = 1, NMPC_MODEL_WAVE = 2 };
+enum { NMPC_BC_DIRICHLET = 0, NMPC_BC_NEUMANN = 1 };
+
+typedef struct nmpc_model_problem {
+    int32_t model;        /* NMPC_MODEL_* */
+    int32_t boundary;     /* NMPC_BC_* */
+    int32_t nsx, nsy;     /* grid nodes per axis (nsy = 1: 1D); nsx * nsy <= 4096 */
+    int32_t horizon;      /* N, 1..256 */
+    int32_t n_inputs;     /* m, 1..64 */
+    const int32_t *act;   /* plate: [m] actuator node of each input (host, copied) */
+    const double *B;      /* heat, wave: [nsx * nsy][m] row-major (host, copied) */
+    double h;             /* stage length > 0 */
+    double q, qv, r;      /* cost weights, r > 0 */
+    double gamma;         /* regularization weight >= 0 (u~ = u^k) */
+    double tau, u_lo, u_hi;   /* input box by the log barrier (tau = 0: none) */
+    double u_cold;        /* inputs of the cold start (strictly inside a box) */
+    double alpha, beta, rad, t_amb;   /* plate constants */
+    double k0, k1, damp;  /* heat / wave constants */
+} nmpc_model_problem;
+
+typedef struct nmpc_model nmpc_model;
+
+/* Create for up to max_batch instances on the current device (allocates the
+ * device workspace). opt: tol, max_iter, n_sweep, n_schur, upper, residual
+ * are used; precision must be NMPC_FP64 and omega 1 (NMPC_E_UNSUPPORTED
+ * otherwise); NULL takes nmpc_default_options. Errors: NMPC_E_ARG for invalid
+ * data, NMPC_E_UNSUPPORTED beyond the engine's sizes, NMPC_E_OOM/DEVICE. */
+int nmpc_model_create(const nmpc_model_problem *prob, const nmpc_options *opt, int32_t max_batch,
+                      nmpc_model **out);
+int nmpc_model_set_options(nmpc_model *hd, const nmpc_options *opt);
+
+/* Solve count <= max_batch instances (DEVICE buffers as above). warm_*: all
+ * NULL (cold start x_i = x0, u_i = u_cold, lambda_i = 0) or all given; given
+ * inputs are clipped strictly inside a box (0.5 % of its width). Work is
+ * queued on `stream` (hipStream_t) and the call returns when done; info: HOST
+ * [count] or NULL (err_vs_fp64 = 0: FP64 sweeps). Returns NMPC_OK if every
+ * instance converged, else the first failing instance's status. */
+int nmpc_model_solve_batch(nmpc_model *hd, int32_t count, const double *x0, const double *xref,
+                           const double *warm_x, const double *warm_u, const double *warm_lam,
+                           double *out_x, double *out_u, double *out_lam, nmpc_info *info,
+                           void *stream);
+
+/* KKT residual norms of given trajectories (DEVICE, layouts as above; the
+ * trajectory is evaluated as given). r_scaled, r_paper: HOST [count]. */
+int nmpc_model_residual_batch(nmpc_model *hd, int32_t count, const double *x0, const double *xref,
+                              const double *x, const double *u, const double *lam,
+                              double *r_scaled, double *r_paper, void *stream);
+
+/* Kernel timing (HIP events around each solve's launch): GPU milliseconds,
+ * launches, and stage visits run (each reads a stage's s_i, writes its new
+ * value). */
+int nmpc_model_timing_enable(nmpc_model *hd, int32_t enable);
+int nmpc_model_timing_read(const nmpc_model *hd, double *kernel_ms, int64_t *launches,
+                           int64_t *units);
+
+/* Release the handle. NULL is ignored. */
+void nmpc_model_destroy(nmpc_model *hd);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ from ._binding import (  # noqa: F401
     NMPC_UPPER_FGS,
     NMPC_UPPER_JACOBI,
     NMPC_UPPER_SGS,
+    NMPC_RES_PAPER,
+    NMPC_RES_SCALED,
+    ModelSolver,
     NmpcError,
     RaggedSolver,
     Solver,
@@ -34,6 +37,7 @@ from ._binding import (  # noqa: F401
     nmpc_destroy,
     nmpc_kernel_config,
     nmpc_last_error,
+    nmpc_model_create,
     nmpc_plant_step_batch,
     nmpc_ragged_autotune,
     nmpc_ragged_config,

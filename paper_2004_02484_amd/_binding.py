@@ -26,6 +26,13 @@ NMPC_UPPER_SGS = 3
 NMPC_PATH_AUTO = 0
 NMPC_PATH_FUSED = 1
 NMPC_PATH_STREAM = 2
+NMPC_RES_SCALED = 0
+NMPC_RES_PAPER = 1
+NMPC_MODEL_HEAT = 0
+NMPC_MODEL_PLATE = 1
+NMPC_MODEL_WAVE = 2
+NMPC_BC_DIRICHLET = 0
+NMPC_BC_NEUMANN = 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -46,7 +53,20 @@ class nmpc_options(ctypes.Structure):
                 ("xref_per_stage", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("upper", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("omega", ctypes.c_double), ("fp32_finish", ctypes.c_int32)]
+                ("omega", ctypes.c_double), ("fp32_finish", ctypes.c_int32),
+                ("residual", ctypes.c_int32)]
+
+
+class nmpc_model_problem(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("boundary", ctypes.c_int32),
+                ("nsx", ctypes.c_int32), ("nsy", ctypes.c_int32), ("horizon", ctypes.c_int32),
+                ("n_inputs", ctypes.c_int32), ("act", ctypes.POINTER(ctypes.c_int32)),
+                ("B", _dp), ("h", ctypes.c_double), ("q", ctypes.c_double),
+                ("qv", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("tau", ctypes.c_double), ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double),
+                ("u_cold", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("rad", ctypes.c_double), ("t_amb", ctypes.c_double),
+                ("k0", ctypes.c_double), ("k1", ctypes.c_double), ("damp", ctypes.c_double)]
 
 
 class nmpc_info(ctypes.Structure):
@@ -141,6 +161,26 @@ def _load():
     lib.nmpc_ragged_timing_read.restype = ctypes.c_int
     lib.nmpc_ragged_destroy.argtypes = [vp]
     lib.nmpc_ragged_destroy.restype = None
+    lib.nmpc_model_create.argtypes = [ctypes.POINTER(nmpc_model_problem),
+                                      ctypes.POINTER(nmpc_options), ctypes.c_int32,
+                                      ctypes.POINTER(vp)]
+    lib.nmpc_model_create.restype = ctypes.c_int
+    lib.nmpc_model_set_options.argtypes = [vp, ctypes.POINTER(nmpc_options)]
+    lib.nmpc_model_set_options.restype = ctypes.c_int
+    lib.nmpc_model_solve_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                           ctypes.POINTER(nmpc_info), vp]
+    lib.nmpc_model_solve_batch.restype = ctypes.c_int
+    lib.nmpc_model_residual_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp,
+                                              vp]
+    lib.nmpc_model_residual_batch.restype = ctypes.c_int
+    lib.nmpc_model_timing_enable.argtypes = [vp, ctypes.c_int32]
+    lib.nmpc_model_timing_enable.restype = ctypes.c_int
+    lib.nmpc_model_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]
+    lib.nmpc_model_timing_read.restype = ctypes.c_int
+    lib.nmpc_model_destroy.argtypes = [vp]
+    lib.nmpc_model_destroy.restype = None
     _lib = lib
     return lib
 
@@ -561,6 +601,119 @@ class RaggedSolver:
     def close(self):
         if getattr(self, "hd", None):
             nmpc_ragged_destroy(self.hd)
+            self.hd = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- model engine
+
+_MODELS = {"heat": NMPC_MODEL_HEAT, "plate": NMPC_MODEL_PLATE, "wave": NMPC_MODEL_WAVE}
+_BCS = {"dirichlet": NMPC_BC_DIRICHLET, "neumann": NMPC_BC_NEUMANN}
+
+
+class _ModelProblem:
+    """nmpc_model_problem plus the host arrays it points at (kept alive here)."""
+
+    def __init__(self, p):
+        self.act = None if p.act is None else np.ascontiguousarray(p.act, dtype=np.int32)
+        self.B = None if p.B is None else np.ascontiguousarray(p.B, dtype=np.float64)
+        m = len(self.act) if self.act is not None else self.B.shape[1]
+        self.s = nmpc_model_problem(
+            _MODELS[p.model], _BCS[p.boundary], int(p.nsx), int(p.nsy), int(p.N), int(m),
+            None if self.act is None else self.act.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            None if self.B is None else self.B.ctypes.data_as(_dp),
+            float(p.h), float(p.q), float(p.qv), float(p.r), float(p.gamma), float(p.tau),
+            float(p.u_lo), float(p.u_hi), float(p.u_cold), float(p.alpha), float(p.beta),
+            float(p.rad), float(p.t_amb), float(p.k0), float(p.k1), float(p.damp))
+        self.m = m
+
+
+def nmpc_model_create(problem, options: nmpc_options, max_batch: int = 1):
+    pr = _ModelProblem(problem)
+    hd = ctypes.c_void_p()
+    rc = _load().nmpc_model_create(ctypes.byref(pr.s), ctypes.byref(options), int(max_batch),
+                                   ctypes.byref(hd))
+    if rc != NMPC_OK:
+        raise NmpcError(rc, "nmpc_model_create")
+    return hd, pr.m
+
+
+class ModelSolver:
+    """Model engine handle (plate, wave, dense-B heat); device tensors in and
+    out on torch's current stream. x0 [B][nx], xref [B][nodes]; returns
+    (status, X [B][N][nx], U [B][N][m], LAM [B][N][nx], [info dicts])."""
+
+    def __init__(self, problem, *, max_batch: int = 1, **options):
+        _load()
+        self.problem = problem
+        self.nodes = int(problem.nsx) * int(problem.nsy)
+        self.nx = 2 * self.nodes if problem.model == "wave" else self.nodes
+        self.N = int(problem.N)
+        self.options = nmpc_default_options(**options)
+        self.max_batch = max_batch
+        self.hd, self.m = nmpc_model_create(problem, self.options, max_batch)
+
+    def set_options(self, **kw):
+        for k, v in kw.items():
+            setattr(self.options, k, v)
+        rc = _load().nmpc_model_set_options(self.hd, ctypes.byref(self.options))
+        if rc != NMPC_OK:
+            raise NmpcError(rc, "nmpc_model_set_options")
+
+    def solve_batch(self, x0, xref, warm=None, out=None):
+        import torch
+        B, N, nx, m = x0.shape[0], self.N, self.nx, self.m
+        px0 = _dev(x0, (B, nx), "x0")
+        pxr = _dev(xref, (B, self.nodes), "xref")
+        if out is None:
+            out = (torch.empty((B, N, nx), dtype=torch.float64, device=x0.device),
+                   torch.empty((B, N, m), dtype=torch.float64, device=x0.device),
+                   torch.empty((B, N, nx), dtype=torch.float64, device=x0.device))
+        po = [_dev(out[0], (B, N, nx), "out x"), _dev(out[1], (B, N, m), "out u"),
+              _dev(out[2], (B, N, nx), "out lam")]
+        pw = [None, None, None]
+        if warm is not None:
+            pw = [_dev(warm[0], (B, N, nx), "warm x"), _dev(warm[1], (B, N, m), "warm u"),
+                  _dev(warm[2], (B, N, nx), "warm lam")]
+        infos = (nmpc_info * B)()
+        rc = _load().nmpc_model_solve_batch(self.hd, B, px0, pxr, pw[0], pw[1], pw[2], po[0],
+                                            po[1], po[2], infos, _stream())
+        if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
+            raise NmpcError(rc, "nmpc_model_solve_batch")
+        return rc, out[0], out[1], out[2], [i.as_dict() for i in infos]
+
+    def residual_batch(self, x0, xref, X, U, LAM):
+        B, N, nx, m = x0.shape[0], self.N, self.nx, self.m
+        rs = np.zeros(B); rp = np.zeros(B)
+        rc = _load().nmpc_model_residual_batch(
+            self.hd, B, _dev(x0, (B, nx), "x0"), _dev(xref, (B, self.nodes), "xref"),
+            _dev(X, (B, N, nx), "x"), _dev(U, (B, N, m), "u"), _dev(LAM, (B, N, nx), "lam"),
+            rs.ctypes.data, rp.ctypes.data, _stream())
+        if rc != NMPC_OK:
+            raise NmpcError(rc, "nmpc_model_residual_batch")
+        return rs, rp
+
+    def timing_enable(self, enable: bool = True):
+        rc = _load().nmpc_model_timing_enable(self.hd, 1 if enable else 0)
+        if rc != NMPC_OK:
+            raise NmpcError(rc, "nmpc_model_timing_enable")
+
+    def timing_read(self):
+        ms = ctypes.c_double(); la = ctypes.c_int64(); un = ctypes.c_int64()
+        rc = _load().nmpc_model_timing_read(self.hd, ctypes.byref(ms), ctypes.byref(la),
+                                            ctypes.byref(un))
+        if rc != NMPC_OK:
+            raise NmpcError(rc, "nmpc_model_timing_read")
+        return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
+
+    def close(self):
+        if getattr(self, "hd", None):
+            _load().nmpc_model_destroy(self.hd)
             self.hd = None
 
     def __del__(self):

@@ -77,6 +77,7 @@ struct IterArgs {
     int fp32_finish;                // FP32 phase: a passed test finishes (no FP64 correction)
     double *apart;                  // input box: [B][N] step limit of each stage's update
     int *aupd;                      // input box: [B] 1 + launch index of the instance's last update
+    int res_paper;                  // the test is on r_paper (|K|_inf) instead of r_scaled
     unsigned long long *du;         // [B][2] FP64 correction step of an FP32-sweep solve: max |du|,
                                     // max |u^{j+1}| (bit patterns of non-negative doubles)
 };
@@ -147,6 +148,7 @@ struct StreamArgs {
     int *work;                      // [B] 1: the instance takes a step in this iteration,
                                     // 2: that step is the FP64 correction of an FP32-sweep solve
     unsigned long long *du;         // [B][2] as IterArgs::du
+    int res_paper;                  // the test is on r_paper instead of r_scaled
     int *iters;
     double *rfin;
     int *ctr;                       // [2] finished, [3] in the FP32 phase

@@ -122,8 +122,9 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
         rs = bits2d(bc[0]);
         rp = bits2d(bc[1]);
         __syncthreads();   // bc is reused by the next stage's norms
-        if (!(rs <= 1.7976931348623157e308)) { fin = kStatusNonfinite; break; }
-        if (rs <= a.tol) {
+        const double rt = a.res_paper ? rp : rs;
+        if (!(rt <= 1.7976931348623157e308)) { fin = kStatusNonfinite; break; }
+        if (rt <= a.tol) {
             if (PREC == kModeFp32 && !a.fp32_finish) { s.mode = kModeFp64Redo; break; }
             fin = kStatusOk;
             break;

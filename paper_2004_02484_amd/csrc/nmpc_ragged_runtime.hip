@@ -268,6 +268,7 @@ IterArgs rg_iter_args(const nmpc_ragged *r)
     a.per_xcd = 0;
     a.tol = r->opt.tol; a.max_iter = r->opt.max_iter;
     a.n_sw = r->opt.n_sweep; a.n_schur = r->opt.n_schur;
+    a.res_paper = r->opt.residual == NMPC_RES_PAPER;
     return a;
 }
 

@@ -200,6 +200,8 @@ int check_options(const nmpc_options *o)
     if (o->upper == NMPC_UPPER_JACOBI && o->omega != 1.0)
         return fail(NMPC_E_ARG, "over-relaxation (omega != 1) needs a Gauss-Seidel upper layer");
     if (o->fp32_finish != 0 && o->fp32_finish != 1) return fail(NMPC_E_ARG, "fp32_finish must be 0 or 1");
+    if (o->residual != NMPC_RES_SCALED && o->residual != NMPC_RES_PAPER)
+        return fail(NMPC_E_ARG, "residual must be NMPC_RES_SCALED or NMPC_RES_PAPER");
     return NMPC_OK;
 }
 
@@ -305,6 +307,7 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.n_sw = h->opt.n_sweep; a.n_schur = h->opt.n_schur;
     a.omega = h->opt.omega;
     a.fp32_finish = h->opt.fp32_finish;
+    a.res_paper = h->opt.residual == NMPC_RES_PAPER;
     a.residual_only = 0;
     return a;
 }
@@ -547,6 +550,7 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.pst = h->d_rst + B * N;
     a.st = h->d_st; a.work = h->d_work; a.iters = h->d_iters; a.rfin = h->d_rfin; a.ctr = h->d_ctr;
     a.du = h->d_du;
+    a.res_paper = h->opt.residual == NMPC_RES_PAPER;
     a.count = count;
     a.units = (long long)count * h->N * ((p.nsy + nmpc::kStreamRows - 1) / nmpc::kStreamRows);
     a.per_xcd = (int)((a.units + 7) / 8);
@@ -825,6 +829,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->path = NMPC_PATH_AUTO;
     opt->omega = 1.0;
     opt->fp32_finish = 0;
+    opt->residual = NMPC_RES_SCALED;
 }
 
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,

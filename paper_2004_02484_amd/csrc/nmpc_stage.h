@@ -532,11 +532,12 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
         rp = bits2d(nrm[1]);
         __syncthreads();
     }
+    const double rt = a.res_paper ? rp : rs;   // the norm the test is on
     if (s.status == kActive) {
         if (s.e == 0) {
             if (s.mode == PREC) { d.work = true; d.j = 0; }
         } else {
-            if (!(rs <= 1.7976931348623157e308)) {            // NaN or Inf
+            if (!(rt <= 1.7976931348623157e308)) {            // NaN or Inf
                 fin = kStatusNonfinite;
             } else if (s.mode == kModeFp64Redo) {
                 if (PREC == kModeFp64) {
@@ -546,7 +547,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                     d.j = s.j;
                     d.redo = true;
                 }
-            } else if (rs <= a.tol) {
+            } else if (rt <= a.tol) {
                 if (s.mode == kModeFp32) {
                     if (a.fp32_finish) fin = kStatusOk;
                     else ns.mode = kModeFp64Redo;

@@ -506,11 +506,12 @@ __global__ void k_st_decide(const StreamArgs a)
     if (lane != 0) return;
     InstState s = a.st[b];
     const double rs = sbits2d(ms), rp = sbits2d(mp);
+    const double rt = a.res_paper ? rp : rs;   // the norm the test is on
     const bool was32 = s.mode == kModeFp32;
     int fin = -1, work = 0;
-    if (!(rs <= 1.7976931348623157e308)) {
+    if (!(rt <= 1.7976931348623157e308)) {
         fin = kStatusNonfinite;
-    } else if (rs <= a.tol) {
+    } else if (rt <= a.tol) {
         if (s.mode == kModeFp32) {
             s.mode = kModeFp64Redo;
         } else if (s.mode == kModeFp64Redo) {
