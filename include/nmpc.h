@@ -66,11 +66,15 @@ enum { NMPC_UPPER_JACOBI = 0, NMPC_UPPER_FGS = 1, NMPC_UPPER_BGS = 2, NMPC_UPPER
 
 enum { NMPC_PATH_AUTO = 0, NMPC_PATH_FUSED = 1, NMPC_PATH_STREAM = 2 };
 
+/* Form of the input operator B in nmpc_problem. */
+enum { NMPC_B_DENSE = 0, NMPC_B_KRON = 1 };
+
 /* Norm of the stopping test: NMPC_RES_SCALED, r_scaled (see above), or
  * NMPC_RES_PAPER, the paper's |K|_inf (Table tab_NMPC_para). */
 enum { NMPC_RES_SCALED = 0, NMPC_RES_PAPER = 1 };
 
-/* Problem data (Sec. 3 notation). gx/gy are host arrays, copied at create. */
+/* Problem data (Sec. 3 notation). gx/gy (or B) are host arrays, copied at
+ * create. */
 typedef struct nmpc_problem {
     int32_t dim;          /* 1 or 2 */
     int32_t nsx, nsy;     /* interior nodes per axis; nsy = 1 when dim == 1 */
@@ -92,6 +96,18 @@ typedef struct nmpc_problem {
                              layer and the fused path (NMPC_E_UNSUPPORTED for
                              the others and for ragged batches) */
     double u_lo, u_hi;
+    int32_t b_kind;       /* NMPC_B_KRON: B from the factors gx, gy (above);
+                             NMPC_B_DENSE: B is the dense matrix below, m =
+                             lx * ly inputs (gx, gy unused). A dense-B problem
+                             (up to 4096 nodes, 64 inputs, 256 stages) runs on
+                             the model engine (NMPC_MODEL_HEAT): FP64 sweeps,
+                             every upper layer (the input box included), cold
+                             or (x, u, lambda) starts, one reference per
+                             instance; nmpc_solve, nmpc_solve_batch,
+                             nmpc_residual_batch, nmpc_set_options and the
+                             timing calls apply, the others give
+                             NMPC_E_UNSUPPORTED */
+    const double *B;      /* NMPC_B_DENSE: [nsx * nsy][m] row-major */
 } nmpc_problem;
 
 /* Solver options. */

@@ -43,7 +43,12 @@ class nmpc_problem(ctypes.Structure):
                 ("gx", _dp), ("gy", _dp),
                 ("h", ctypes.c_double), ("k0", ctypes.c_double), ("k1", ctypes.c_double),
                 ("q", ctypes.c_double), ("r", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("tau", ctypes.c_double), ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double)]
+                ("tau", ctypes.c_double), ("u_lo", ctypes.c_double), ("u_hi", ctypes.c_double),
+                ("b_kind", ctypes.c_int32), ("B", _dp)]
+
+
+NMPC_B_DENSE = 0
+NMPC_B_KRON = 1
 
 
 class nmpc_options(ctypes.Structure):
@@ -209,11 +214,15 @@ class _Problem:
     def __init__(self, p):
         self.gx = np.ascontiguousarray(p.gx, dtype=np.float64)
         self.gy = np.ascontiguousarray(p.gy, dtype=np.float64)
+        dense = getattr(p, "B", None)
+        self.B = None if dense is None else np.ascontiguousarray(dense, dtype=np.float64)
         self.s = nmpc_problem(int(p.dim), int(p.nsx), int(p.nsy), int(p.N), int(p.lx), int(p.ly),
                               self.gx.ctypes.data_as(_dp), self.gy.ctypes.data_as(_dp),
                               float(p.h), float(p.k0), float(p.k1), float(p.q), float(p.r),
                               float(p.gamma), float(getattr(p, "tau", 0.0)),
-                              float(getattr(p, "u_lo", 0.0)), float(getattr(p, "u_hi", 0.0)))
+                              float(getattr(p, "u_lo", 0.0)), float(getattr(p, "u_hi", 0.0)),
+                              NMPC_B_KRON if self.B is None else NMPC_B_DENSE,
+                              None if self.B is None else self.B.ctypes.data_as(_dp))
 
 
 def nmpc_create(problem, options: nmpc_options, max_batch: int = 1) -> ctypes.c_void_p:

@@ -461,6 +461,8 @@ int collect(nmpc_ragged *r, nmpc_info *info)
 int check_class(const nmpc_problem *p)
 {
     if (p->dim != 2) return rg_fail(NMPC_E_UNSUPPORTED, "ragged classes are 2D problems");
+    if (p->b_kind != NMPC_B_KRON)
+        return rg_fail(NMPC_E_UNSUPPORTED, "ragged classes take the Kronecker input form");
     if (p->nsx < 1 || p->nsy < 1 || p->horizon < 1) return rg_fail(NMPC_E_ARG, "sizes must be positive");
     if (p->lx != 4 || p->ly != 4) return rg_fail(NMPC_E_UNSUPPORTED, "ragged classes use the 4 x 4 input lattice");
     if (!p->gx || !p->gy) return rg_fail(NMPC_E_ARG, "gx/gy are NULL");

@@ -83,6 +83,7 @@ struct nmpc_handle {
     unsigned long long *d_du = nullptr;    // [B][2] FP64 correction step (max |du|, max |u|)
     int *d_ctr = nullptr;                  // [4]
     int *h_poll = nullptr;                 // pinned
+    nmpc_model *dense = nullptr;           // dense-B problems: the model engine's handle
     bool timing = false;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double kernel_ms = 0.0;
@@ -145,7 +146,15 @@ int check_problem(const nmpc_problem *p)
         return fail(NMPC_E_ARG, "sizes must be positive");
     if (p->dim == 1 && (p->nsy != 1 || p->ly != 1))
         return fail(NMPC_E_ARG, "1D problems need nsy == 1 and ly == 1");
-    if (!p->gx || !p->gy) return fail(NMPC_E_ARG, "gx/gy are NULL");
+    if (p->b_kind != NMPC_B_KRON && p->b_kind != NMPC_B_DENSE)
+        return fail(NMPC_E_ARG, "b_kind must be NMPC_B_KRON or NMPC_B_DENSE");
+    if (p->b_kind == NMPC_B_DENSE) {
+        if (!p->B) return fail(NMPC_E_ARG, "a dense B is NULL");
+        for (long long t = 0; t < (long long)p->nsx * p->nsy * p->lx * p->ly; ++t)
+            if (!std::isfinite(p->B[t])) return fail(NMPC_E_ARG, "B not finite");
+    } else if (!p->gx || !p->gy) {
+        return fail(NMPC_E_ARG, "gx/gy are NULL");
+    }
     if (!finite_pos(p->h) || !finite_pos(p->r) || !std::isfinite(p->k0) ||
         !std::isfinite(p->k1) || !std::isfinite(p->q) || p->q < 0.0 ||
         !std::isfinite(p->gamma) || p->gamma < 0.0)
@@ -155,6 +164,7 @@ int check_problem(const nmpc_problem *p)
     if (p->tau > 0.0 && !(std::isfinite(p->u_lo) && std::isfinite(p->u_hi) && p->u_lo < 0.0 &&
                           p->u_hi > 0.0))
         return fail(NMPC_E_ARG, "an input box needs finite u_lo < 0 < u_hi (cold start inside)");
+    if (p->b_kind == NMPC_B_DENSE) return NMPC_OK;   // sizes checked by the model engine
     for (long long t = 0; t < (long long)p->lx * p->nsx; ++t)
         if (!std::isfinite(p->gx[t])) return fail(NMPC_E_ARG, "gx not finite");
     for (long long t = 0; t < (long long)p->ly * p->nsy; ++t)
@@ -273,6 +283,7 @@ void release(nmpc_handle *h)
     if (h->t0) (void)hipEventDestroy(h->t0);
     if (h->t1) (void)hipEventDestroy(h->t1);
     if (h->stream) (void)hipStreamDestroy(h->stream);
+    if (h->dense) nmpc_model_destroy(h->dense);
     delete h;
 }
 
@@ -832,6 +843,46 @@ void nmpc_default_options(nmpc_options *opt)
     opt->residual = NMPC_RES_SCALED;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A dense-B problem: the heat model of the model engine, plus a staging area
+// and a stream for host-buffer solves.
+int create_dense(nmpc_handle *h, nmpc_handle **out)
+{
+    const nmpc_problem &p = h->prob;
+    nmpc_model_problem mp{};
+    mp.model = NMPC_MODEL_HEAT;
+    mp.boundary = NMPC_BC_DIRICHLET;
+    mp.nsx = p.nsx;
+    mp.nsy = p.dim == 1 ? 1 : p.nsy;
+    mp.horizon = p.horizon;
+    mp.n_inputs = h->m;
+    mp.B = p.B;
+    mp.h = p.h; mp.q = p.q; mp.qv = 0.0; mp.r = p.r; mp.gamma = p.gamma;
+    mp.tau = p.tau; mp.u_lo = p.u_lo; mp.u_hi = p.u_hi; mp.u_cold = 0.0;
+    mp.k0 = p.k0; mp.k1 = p.k1; mp.damp = 0.0;
+    int rc = nmpc_model_create(&mp, &h->opt, h->max_batch, &h->dense);
+    if (rc) { delete h; return rc; }
+    h->prob.B = nullptr;
+    h->prob.gx = h->prob.gy = nullptr;
+    hipError_t e = hipMalloc((void **)&h->d_out,
+                             sizeof(double) * ((size_t)h->N * (2 * (size_t)h->n + h->m) + 2 * h->n));
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        release(h);
+        return fail(e == hipErrorOutOfMemory ? NMPC_E_OOM : NMPC_E_DEVICE,
+                    std::string("create: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return NMPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_batch,
                 nmpc_handle **out)
 {
@@ -851,6 +902,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     h->n = prob->nsx * prob->nsy;
     h->m = prob->lx * prob->ly;
     h->N = prob->horizon;
+    if (prob->b_kind == NMPC_B_DENSE) return create_dense(h, out);
     rc = choose_path(prob, opt, &h->streaming);
     if (rc) { delete h; return rc; }
     if (prob->tau > 0.0 && (h->streaming || opt->upper != NMPC_UPPER_JACOBI)) {
@@ -960,6 +1012,11 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
     int rc = check_options(opt);
     if (rc) return rc;
+    if (h->dense) {
+        rc = nmpc_model_set_options(h->dense, opt);
+        if (rc == NMPC_OK) h->opt = *opt;
+        return rc;
+    }
     bool streaming = false;
     rc = choose_path(&h->prob, opt, &streaming);
     if (rc) return rc;
@@ -997,6 +1054,32 @@ int nmpc_solve(nmpc_handle *h, const double *x0, const double *xref, const doubl
     if (start_kind(warm_x, warm_u, warm_lam) < 0)
         return fail(NMPC_E_ARG, "warm start needs (x, u, lambda), u alone, or (u, lambda)");
     const size_t n = h->n, m = h->m, N = h->N;
+    if (h->dense) {   // model engine: stage x0, xref, the start and the outputs in d_out
+        double *dx0 = h->d_out + N * (2 * n + m), *dxr = dx0 + n;
+        double *ox = h->d_out, *ol = h->d_out + N * n, *ou = h->d_out + 2 * N * n;
+        HIP_TRY(hipMemcpyAsync(dx0, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipMemcpyAsync(dxr, xref, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        if (warm_x) {
+            if (!warm_u || !warm_lam)
+                return fail(NMPC_E_UNSUPPORTED, "dense-B problems take cold or (x, u, lambda) starts");
+            HIP_TRY(hipMemcpyAsync(ox, warm_x, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipMemcpyAsync(ol, warm_lam, sizeof(double) * N * n, hipMemcpyHostToDevice, h->stream));
+            HIP_TRY(hipMemcpyAsync(ou, warm_u, sizeof(double) * N * m, hipMemcpyHostToDevice, h->stream));
+        } else if (warm_u) {
+            return fail(NMPC_E_UNSUPPORTED, "dense-B problems take cold or (x, u, lambda) starts");
+        }
+        nmpc_info tmp;
+        // the model engine reads the start into its own buffers before writing the outputs
+        const int rc = nmpc_model_solve_batch(h->dense, 1, dx0, dxr, warm_x ? ox : nullptr,
+                                              warm_x ? ou : nullptr, warm_x ? ol : nullptr, ox,
+                                              ou, ol, info ? info : &tmp, h->stream);
+        if (rc != NMPC_OK && rc != NMPC_E_NOCONV && rc != NMPC_E_NONFINITE) return rc;
+        HIP_TRY(hipMemcpyAsync(out_x, ox, sizeof(double) * N * n, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(out_lam, ol, sizeof(double) * N * n, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(out_u, ou, sizeof(double) * N * m, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return rc;
+    }
     // dense x0 | xref staged in d_out, then padded into the input buffers
     HIP_TRY(hipMemcpyAsync(h->d_out, x0, sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->d_out + n, xref, sizeof(double) * h->xref_dense(),
@@ -1042,6 +1125,9 @@ int nmpc_solve_batch(nmpc_handle *h, int32_t count, const double *x0, const doub
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
     if (start_kind(warm_x, warm_u, warm_lam) < 0)
         return fail(NMPC_E_ARG, "warm start needs (x, u, lambda), u alone, or (u, lambda)");
+    if (h->dense)
+        return nmpc_model_solve_batch(h->dense, count, x0, xref, warm_x, warm_u, warm_lam, out_x,
+                                      out_u, out_lam, info, stream);
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
@@ -1062,6 +1148,9 @@ int nmpc_residual_batch(nmpc_handle *h, int32_t count, const double *x0, const d
     if (!h || !x0 || !xref || !x || !u || !lam || !r_scaled || !r_paper)
         return fail(NMPC_E_ARG, "NULL argument");
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
+    if (h->dense)
+        return nmpc_model_residual_batch(h->dense, count, x0, xref, x, u, lam, r_scaled, r_paper,
+                                         stream);
     hipStream_t us = (hipStream_t)stream;
     HIP_TRY(hipEventRecord(h->ev, us));
     HIP_TRY(hipStreamWaitEvent(h->stream, h->ev, 0));
@@ -1143,6 +1232,7 @@ int nmpc_timing_enable(nmpc_handle *h, int32_t enable)
 {
     g_err.clear();
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    if (h->dense) return nmpc_model_timing_enable(h->dense, enable);
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->timing = enable != 0;
     if (h->timing) {
@@ -1157,6 +1247,7 @@ int nmpc_timing_read(const nmpc_handle *h, double *kernel_ms, int64_t *launches,
 {
     g_err.clear();
     if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    if (h->dense) return nmpc_model_timing_read(h->dense, kernel_ms, launches, units);
     if (kernel_ms) *kernel_ms = h->kernel_ms;
     if (launches) *launches = h->launches;
     if (units) *units = (int64_t)h->units;
@@ -1168,6 +1259,7 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
 {
     g_err.clear();
     if (!h || !x0 || !xref) return fail(NMPC_E_ARG, "NULL argument");
+    if (h->dense) return fail(NMPC_E_UNSUPPORTED, "dense-B problems have no tile to tune");
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
     if (iters < 1 || iters > 1000) return fail(NMPC_E_ARG, "iters must be 1..1000");
     if (h->streaming) return fail(NMPC_E_UNSUPPORTED, "the streaming path has no tile choices");
@@ -1253,6 +1345,7 @@ int nmpc_plant_step_batch(nmpc_handle *h, int32_t count, const double *x, const 
 {
     g_err.clear();
     if (!h || !x || !u || !out) return fail(NMPC_E_ARG, "NULL argument");
+    if (h->dense) return fail(NMPC_E_UNSUPPORTED, "the plant step takes the Kronecker input form");
     if (count < 1 || count > h->max_batch) return fail(NMPC_E_ARG, "count outside 1..max_batch");
     if (ldu < h->m) return fail(NMPC_E_ARG, "ldu smaller than the number of inputs");
     if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(NMPC_E_ARG, "dt must be finite and >= 0");
@@ -1275,6 +1368,12 @@ int nmpc_kernel_config(const nmpc_handle *h, int32_t *rows_per_lane, int32_t *wa
                        int32_t *workgroups)
 {
     if (!h) return NMPC_E_ARG;
+    if (h->dense) {   // model engine: one workgroup per instance
+        if (rows_per_lane) *rows_per_lane = 0;
+        if (waves) *waves = 0;
+        if (workgroups) *workgroups = h->max_batch;
+        return NMPC_OK;
+    }
     if (h->streaming) {   // one 256-thread workgroup per grid row of every stage
         if (rows_per_lane) *rows_per_lane = 0;
         if (waves) *waves = 4;
