@@ -430,12 +430,181 @@ def bench_c3(args):
     solver.close()
 
 
+def bench_model(args):
+    """The model engine's workloads: the paper's copper plate (13 x 13 Neumann
+    grid, 16 actuator nodes as inputs, box [T_a, T_a + 400] with tau = 100,
+    gamma = 0.5, N = 20, T = 100 s, SGS upper layer, two sweeps and two Schur
+    steps, stop at |K|_inf < 1) or the second-order damped membrane (24 x 24,
+    N = 30, 4 x 4 Gaussian actuators, Jacobi upper layer, r_scaled <= 1e-6).
+    One step = one batch of instances with their own seeded references
+    (plate) or initial states and references (wave), one workgroup per
+    instance. For the plate the paper's own scenario is also timed: one
+    instance, closed loop of 200 steps of 5 s from the ambient temperature,
+    reference a slope for 500 s and a V shape after, each step warm-started
+    from the previous solution shifted by one stage (nominal loop: the next
+    initial state is the solution's first state)."""
+    import torch
+    import paper_2004_02484_amd as nm
+    from nmpc_inputs import (make_plate_instance, make_plate_problem, make_wave_instance,
+                             make_wave_problem)
+    dev = torch.device("cuda:0")
+    plate = args.workload == "plate"
+    P = make_plate_problem() if plate else make_wave_problem()
+    inst = make_plate_instance if plate else make_wave_instance
+    B = args.batch
+    upper = UPPER[args.upper if args.upper != "jacobi" or not plate else "sgs"]
+    opts = dict(tol=1.0, residual=nm.NMPC_RES_PAPER) if plate else dict(tol=1e-6)
+    solver = nm.ModelSolver(P, max_batch=B, max_iter=5000, upper=upper, **opts)
+    nb = args.warmup + args.steps
+    host = []
+    for s in range(nb):
+        xs, rs = zip(*(inst(P, EVAL_SEED0 + s * B + b) for b in range(B)))
+        host.append((np.stack(xs), np.stack(rs)))
+    dev_in = [(torch.tensor(x, device=dev), torch.tensor(r, device=dev)) for x, r in host]
+
+    def run(batches):
+        ts, its, worst = [], [], 0
+        torch.cuda.synchronize()
+        for x0, xr in batches:
+            t = time.perf_counter()
+            rc, X, U, L, infos = solver.solve_batch(x0, xr)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+            its += [i["iters"] for i in infos]
+            worst = max(worst, rc)
+        return ts, its, worst
+
+    run(dev_in[:args.warmup])
+    solver.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    times, iters, worst = run(dev_in[args.warmup:])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = solver.timing_read()
+    solver.timing_enable(False)
+    # algorithmic bytes of one stage visit: read s_i, write its new value, the
+    # neighbours' x_{i-1}, lambda_{i+1} and the reference once per stage
+    nx = 2 * P.nodes if P.model == "wave" else P.nodes
+    bpu = 8.0 * (2 * (2 * nx + P.m) + 2 * nx + P.nodes)
+    roof = roofline_model(tm, bpu)
+    uname = [k for k, v in UPPER.items() if v == upper][0]
+    cfg = {"global_batch": B, "grid": f"{P.nsx}x{P.nsy}", "horizon": P.N, "upper": uname,
+           "iters_min": int(min(iters)), "iters_max": int(max(iters)),
+           "iters_mean": round(float(np.mean(iters)), 1), "status_worst": worst,
+           "step_ms_median": round(1e3 * float(np.median(times)), 2)}
+    if plate:
+        cfg["workload"] = ("copper plate of the paper's experiment: 13x13 nodes, zero Neumann "
+                           "boundary, 16 actuator nodes as inputs boxed to [T_a, T_a+400] (tau "
+                           "100), gamma 0.5, Q = I, R = 0.1 I, N = 20, T = 100 s, SGS upper "
+                           "layer, 2 Jacobi sweeps + 2 Schur steps, stop at |K|_inf < 1; batch "
+                           "of seeded slope / V references, cold start")
+        cfg["paper_scenario"] = plate_closed_loop(nm, P, dev)
+    else:
+        cfg["workload"] = ("second-order-in-time damped nonlinear membrane 24x24 interior nodes "
+                           "(W_tt + 2 W_t = (1 + 0.5 W) Lap W + B u, state (W, W_t)), 4x4 "
+                           "Gaussian actuators, N = 30, Jacobi upper layer with the v6 "
+                           "elimination of the lower layer, r_scaled <= 1e-6, cold start")
+    cpu = None
+    if args.cpu_budget > 0:
+        import oracle.models as om
+        ops = om.Ops(P)
+        x0s, xrs = host[args.warmup]
+        name = uname
+        t = time.perf_counter()
+        if plate:
+            done, its = 0, []
+            while done < B and (time.perf_counter() - t < args.cpu_budget or done == 0):
+                o = om.solve(ops, om.state_x0(ops, x0s[done]), xrs[done], upper=name,
+                             tol=opts["tol"], residual_kind="paper", max_iter=5000)
+                its.append(o["iters"])
+                done += 1
+            dt = time.perf_counter() - t
+            value = done / dt
+            sample = (f"the first {done} instances of the first timed batch solved by the numpy "
+                      f"oracle ({name}, {min(its)}..{max(its)} iterations), {dt:.1f} s")
+        else:
+            S = om.cold_start(ops, om.state_x0(ops, x0s[0]))
+            k = 0
+            while time.perf_counter() - t < args.cpu_budget or k == 0:
+                S = om.iterate(ops, om.state_x0(ops, x0s[0]), xrs[0], S, name)
+                k += 1
+            per_it = (time.perf_counter() - t) / k
+            it = float(np.mean(iters))
+            value = 1.0 / (per_it * it)
+            sample = (f"{k} cold-start {name} iterations of the first timed instance by the numpy "
+                      f"oracle ({per_it:.2f} s each), scaled by the GPU's mean {it:.0f} "
+                      f"iterations per solve")
+        cpu = {"value": value, "unit": "solves/s", "cores": 1, "kind": "oracle", "sample": sample}
+    line(f"NMPC solves/s, {'copper plate 13x13 N=20 (|K|_inf < 1)' if plate else 'damped membrane 24x24 N=30 (r_scaled <= 1e-6)'}",
+         B * args.steps / elapsed, args, elapsed, "f64", cfg, roof, cpu)
+    solver.close()
+
+
+def roofline_model(tm, bpu: float):
+    """HBM roofline of the model engine's persistent kernel: algorithmic bytes
+    per stage visit times the visits of a launch, over the launch time."""
+    avg_launch_s = tm["kernel_ms"] * 1e-3 / max(tm["launches"], 1)
+    units_per_launch = tm["units"] / max(tm["launches"], 1)
+    achieved = bpu * units_per_launch / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_model (persistent, one workgroup per instance)",
+            "avg_launch_us": round(avg_launch_s * 1e6, 1),
+            "units_per_launch": round(units_per_launch, 1), "bytes_per_unit": round(bpu, 1)}
+
+
+def plate_closed_loop(nm, P, dev, steps: int = 200):
+    """The paper's closed loop (Sec. 5): 1000 s at 5 s sampling from the
+    ambient temperature; the reference is a slope for the first 500 s and a V
+    shape after it, fed in over 50 s. Each step starts from the previous
+    solution shifted by one stage (the last stage repeated) and solves to
+    |K|_inf < 1 with SGS; the plant is the model (the next initial state is
+    the solution's first stage)."""
+    import torch
+    from nmpc_inputs import plate_reference
+    rng = np.random.default_rng(2020)
+    ref1 = plate_reference(P, "slope", rng)
+    ref2 = plate_reference(P, "v", rng)
+    s = nm.ModelSolver(P, max_batch=1, tol=1.0, residual=nm.NMPC_RES_PAPER, max_iter=5000,
+                       upper=UPPER["sgs"])
+    s.timing_enable(True)
+    x = torch.full((1, P.nodes), P.t_amb, dtype=torch.float64, device=dev)
+    warm = None
+    its, ts = [], []
+    for k in range(steps):
+        t_now = 5.0 * k
+        w = min(max((t_now - 500.0) / 50.0, 0.0), 1.0)
+        xr = torch.tensor(((1 - w) * ref1 + w * ref2)[None], device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc, X, U, L, infos = s.solve_batch(x, xr, warm=warm)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+        its.append(infos[0]["iters"])
+        x = X[:, 0].clone()
+        warm = (torch.cat([X[:, 1:], X[:, -1:]], 1).contiguous(),
+                torch.cat([U[:, 1:], U[:, -1:]], 1).contiguous(),
+                torch.cat([L[:, 1:], L[:, -1:]], 1).contiguous())
+    tm = s.timing_read()
+    s.close()
+    kernel_ms = tm["kernel_ms"]
+    return {"steps": steps, "iters_mean": round(float(np.mean(its)), 2), "iters_max": int(max(its)),
+            "ms_per_iteration_kernel": round(kernel_ms / max(sum(its), 1), 4),
+            "ms_per_step_median_wall": round(1e3 * float(np.median(ts)), 3),
+            "paper_ms_per_iteration": {"value": 0.416, "hardware": "Intel Core i5-8265U laptop, "
+                                       "one core, C implementation", "note": "context only"},
+            "note": "single instance, one workgroup: latency-bound; iterations count SGS "
+                    "iterations (a backward and a forward sweep each)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "plate", "wave"], default="c1",
                     help="c1: 64x64 N=40 batch 256 (headline); c2: 256x256 N=100 single "
-                         "instance; c3: 512 ragged instances")
+                         "instance; c3: 512 ragged instances; plate: the paper's copper plate "
+                         "(batch and closed loop); wave: second-order damped membrane")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
@@ -483,6 +652,8 @@ def main():
         return bench_c2(args)
     if args.workload == "c3":
         return bench_c3(args)
+    if args.workload in ("plate", "wave"):
+        return bench_model(args)
     P = make_problem("c1")
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
