@@ -262,8 +262,6 @@ def solve(P: Problem, x0, xref, start=None, tol=1e-6, max_iter=2000, n_sw=2, n_s
     hist = np.zeros(max_iter + 1) if trace else None
     if UPPER[upper] == 0 and omega != 1.0:
         raise ValueError("over-relaxation applies to the Gauss-Seidel sweeps")
-    if UPPER[upper] != 0 and P.tau > 0.0:
-        raise ValueError("the input box (tau > 0) is provided with the Jacobi upper layer")
     if UPPER[upper] == 0:
         status = lib.ref_solve(C.ptr, _d(_c(x0)), _d(xr), st, _d(X), _d(U), _d(LAM), tol,
                                max_iter, n_sw, n_schur, ctypes.byref(it), ctypes.byref(rs),

@@ -493,13 +493,50 @@ void ref_gs_sweep(const ref_problem *P, const double *x0, const double *xref, in
 }
 
 /*
+ * A Gauss-Seidel sweep cut by the fraction-to-the-boundary rule (eq.
+ * eq_alphamax) when an input box is set: the sweep's result S_sweep replaces
+ * S only as far as S + alpha (S_sweep - S), alpha the largest step that keeps
+ * every input's distance to the box above 0.005 of its value at S (the
+ * paper states the rule for the Jacobi step; a sweep is read as one such
+ * step). Sc: scratch of N (2n + m) doubles.
+ */
+static void gs_sweep_cut(const ref_problem *P, const double *x0, const double *xref,
+                         int xref_stride, double *X, double *U, double *LAM, const double *UT,
+                         int dir, int n_sw, int n_schur, double omega, double *Sc)
+{
+    int n = ref_n(P), m = P->m, N = P->N;
+    size_t nx = (size_t)N * n, nu = (size_t)N * m;
+    if (P->tau <= 0.0) {
+        ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UT, dir, n_sw, n_schur, omega);
+        return;
+    }
+    double *X0 = Sc, *L0 = Sc + nx, *U0 = Sc + 2 * nx;
+    memcpy(X0, X, sizeof(double) * nx);
+    memcpy(L0, LAM, sizeof(double) * nx);
+    memcpy(U0, U, sizeof(double) * nu);
+    ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UT, dir, n_sw, n_schur, omega);
+    double *DU = (double *)malloc(sizeof(double) * nu);
+    for (size_t t = 0; t < nu; ++t) DU[t] = U0[t] - U[t];
+    const double a = ref_alpha_max(P, U0, DU);
+    free(DU);
+    if (a < 1.0) {
+        for (size_t t = 0; t < nx; ++t) {
+            X[t] = X0[t] + a * (X[t] - X0[t]);
+            LAM[t] = L0[t] + a * (LAM[t] - L0[t]);
+        }
+        for (size_t t = 0; t < nu; ++t) U[t] = U0[t] + a * (U[t] - U0[t]);
+    }
+}
+
+/*
  * Upper layer by Gauss-Seidel sweeps: upper = 1 FGS (eq. fgs), 2 BGS,
  * 3 SGS (eq. sgs, read as a backward sweep followed by a forward sweep, both
  * with the regularization reference u~ = u^k of the iteration; in the linear
  * case this is eq. sgs exactly). Every iteration first evaluates K(S^k) and
  * its norms for the stopping test, exactly as ref_solve does; the returned
  * trajectory is the last evaluated iterate S^k. omega: the over-relaxation of
- * every sweep (SOR forward, backward; SSOR for SGS).
+ * every sweep (SOR forward, backward; SSOR for SGS). With an input box each
+ * sweep is cut by the fraction-to-the-boundary rule (gs_sweep_cut).
  */
 int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int xref_stride,
                  double *X, double *U, double *LAM, int upper, double tol, int max_iter,
@@ -511,6 +548,7 @@ int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int
     double *KL = (double *)malloc(sizeof(double) * (size_t)N * n);
     double *KU = (double *)malloc(sizeof(double) * (size_t)N * m);
     double *UK = (double *)malloc(sizeof(double) * (size_t)N * m);
+    double *Sc = (double *)malloc(sizeof(double) * (size_t)N * (2 * n + m));
     double rs = 0.0, rp = 0.0;
     for (;;) {
         ref_kkt(P, x0, xref, xref_stride, X, U, LAM, U, KX, KU, KL);
@@ -520,17 +558,17 @@ int ref_solve_gs(const ref_problem *P, const double *x0, const double *xref, int
         if (rs <= tol) { status = 0; break; }
         if (k >= max_iter) { status = 1; break; }
         if (upper == 1) {
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, +1, n_sw, n_schur, omega);
+            gs_sweep_cut(P, x0, xref, xref_stride, X, U, LAM, NULL, +1, n_sw, n_schur, omega, Sc);
         } else if (upper == 2) {
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega);
+            gs_sweep_cut(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega, Sc);
         } else {
             memcpy(UK, U, sizeof(double) * (size_t)N * m);
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega);
-            ref_gs_sweep(P, x0, xref, xref_stride, X, U, LAM, UK, +1, n_sw, n_schur, omega);
+            gs_sweep_cut(P, x0, xref, xref_stride, X, U, LAM, NULL, -1, n_sw, n_schur, omega, Sc);
+            gs_sweep_cut(P, x0, xref, xref_stride, X, U, LAM, UK, +1, n_sw, n_schur, omega, Sc);
         }
         ++k;
     }
-    free(KX); free(KL); free(KU); free(UK);
+    free(KX); free(KL); free(KU); free(UK); free(Sc);
     if (iters) *iters = k;
     if (r_scaled) *r_scaled = rs;
     if (r_paper) *r_paper = rp;

@@ -658,3 +658,60 @@ def test_box_solution_is_the_relaxed_optimum():
     Xn, Un, Ln = dense.unpack(P, S)
     assert np.abs(dense.pack_K(*dense.kkt(P, x0, xref, Xn, Un, Ln))).max() <= 1e-10
     np.testing.assert_allclose(o["U"], Un, rtol=0, atol=1e-6 * umax)
+
+
+def _newton_box_point(P, x0, xref):
+    """Dense Newton with the fraction-to-the-boundary rule from the cold start:
+    the point where K of the relaxed problem vanishes."""
+    Xc, Uc, Lc = oracle.cold_start(P, x0)
+    S = dense.pack(Xc, Uc, Lc)
+    for _ in range(200):
+        Xk, Uk, Lk = dense.unpack(P, S)
+        K = dense.pack_K(*dense.kkt(P, x0, xref, Xk, Uk, Lk))
+        if np.abs(K).max() <= 1e-12:
+            break
+        d = np.linalg.solve(dense.jacobian(P, Xk, Uk, Lk, gamma=0.0), K)
+        _, dU, _ = dense.unpack(P, d)
+        S = S - dense.alpha_max(P, Uk, dU) * d
+    return dense.unpack(P, S)
+
+
+@pytest.mark.parametrize("upper", ["fgs", "bgs", "sgs"])
+def test_box_gauss_seidel_reaches_the_relaxed_optimum(upper):
+    """The Gauss-Seidel layers with the barrier and the step rule cut per
+    sweep converge, strictly inside the box, to the dense Newton point of the
+    relaxed problem (the same point as the Jacobi layer)."""
+    P0 = make_problem("c0")
+    x0, xref = make_instance(P0, 3)
+    free = oracle.solve(P0, x0, xref, tol=1e-10, max_iter=20000)
+    umax = np.abs(free["U"]).max()
+    P = P0.with_(tau=1e-3 * P0.r * umax, u_lo=-0.5 * umax, u_hi=0.5 * umax)
+    o = oracle.solve(P, x0, xref, tol=1e-9, max_iter=50000, upper=upper)
+    assert o["status"] == "converged"
+    assert np.all(o["U"] > P.u_lo) and np.all(o["U"] < P.u_hi)
+    Xn, Un, Ln = _newton_box_point(P, x0, xref)
+    np.testing.assert_allclose(o["U"], Un, rtol=0, atol=1e-6 * umax)
+
+
+def test_box_sweep_is_cut_by_the_step_rule():
+    """From a start next to the box's bounds with a weak barrier one forward
+    sweep would leave the box; the iteration takes S + alpha (S_sweep - S)
+    with alpha from the rule on the sweep's input step, every input keeping at
+    least 0.005 of its distance to the bounds."""
+    P0 = make_problem("c0")
+    x0, xref = make_instance(P0, 3)
+    free = oracle.solve(P0, x0, xref, tol=1e-10, max_iter=20000)
+    umax = np.abs(free["U"]).max()
+    P = P0.with_(tau=1e-5 * P0.r * umax, u_lo=-0.5 * umax, u_hi=0.5 * umax)
+    U0 = np.clip(free["U"], 0.98 * P.u_lo, 0.98 * P.u_hi)
+    S = (free["X"].copy(), U0, free["LAM"].copy())
+    sw = oracle.gs_sweep(P, x0, xref, *S, +1)
+    a = oracle.alpha_max(P, S[1], S[1] - sw[1])
+    assert a < 0.5
+    o = oracle.solve(P, x0, xref, start=tuple(v.copy() for v in S), tol=0.0, max_iter=1,
+                     upper="fgs")
+    for got, s0, s1 in zip((o["X"], o["U"], o["LAM"]), S, sw):
+        np.testing.assert_allclose(got, s0 + a * (s1 - s0), rtol=1e-13, atol=1e-15)
+    g_old = np.minimum(S[1] - P.u_lo, P.u_hi - S[1])
+    g_new = np.minimum(o["U"] - P.u_lo, P.u_hi - o["U"])
+    assert np.all(g_new >= 0.005 * g_old - 1e-15)
