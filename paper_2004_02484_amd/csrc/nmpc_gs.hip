@@ -43,7 +43,6 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
     v.res_at = res ? -1 : -2;
     v.res_only = res_only;
     v.omega = a.omega;
-    v.box_at = -1;   // the input box runs with the Jacobi upper layer only
     v.du_at = redo && a.du ? b : -1;
     // forward: x_{i-1} updated (dst), lambda_{i+1} not yet (src); backward:
     // the reverse. The residual of S^j takes both from src.
@@ -66,6 +65,8 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
         v.i = i;
         v.last = i == N - 1;
         v.xro = (long long)b * a.xref_inst_stride + (long long)i * a.xref_stage_stride;
+        // input box: every stage records the limit of its step for the cut
+        v.box_at = a.P.tau > 0.0 && !res_only ? (long long)b * N + i : -1;
         if (v.pf) {
             // the stages ahead are not written in this sweep before they are
             // visited (x_{i+d}, lambda_{i+d} of buffer src)
@@ -76,6 +77,41 @@ __device__ __forceinline__ void gs_sweep(const IterArgs &a, Ctx &c, int b, int d
         }
         stage_body<T, CX, RY, LX, LY>(a, a.P, v, c, acc);
     }
+}
+
+// Input box: the fraction-to-the-boundary rule (eq. eq_alphamax) cuts each
+// sweep, S <- S + alpha (S_sweep - S), alpha the minimum of the stages' limits
+// written during the sweep. out = base + alpha (other - base) over the
+// instance's whole trajectory (out is base or other).
+__device__ double gs_alpha(const IterArgs &a, Ctx &c, int b)
+{
+    __syncthreads();   // every stage's limit and every stage's update are written
+    double *red = lds_ptr<double>(c, c.off.red);
+    double l = 1.0;
+    for (int i = c.tid; i < a.P.N; i += c.W * kWave) l = fmin(l, a.apart[(size_t)b * a.P.N + i]);
+    red[c.tid] = l;
+    __syncthreads();
+    double al = 1.0;
+    for (int t = 0; t < c.W * kWave && t < a.P.N; ++t) al = fmin(al, red[t]);
+    __syncthreads();
+    return al;
+}
+
+__device__ void gs_blend(const IterArgs &a, Ctx &c, int b, int base, int other, int out,
+                         double alpha)
+{
+    const size_t nx = (size_t)a.P.N * a.P.n, nu = (size_t)a.P.N * a.P.m;
+    const size_t xo = (size_t)b * nx, uo = (size_t)b * nu;
+    for (size_t t = c.tid; t < nx; t += (size_t)c.W * kWave) {
+        const double xb = a.X[base][xo + t], lb = a.LAM[base][xo + t];
+        a.X[out][xo + t] = xb + alpha * (a.X[other][xo + t] - xb);
+        a.LAM[out][xo + t] = lb + alpha * (a.LAM[other][xo + t] - lb);
+    }
+    for (size_t t = c.tid; t < nu; t += (size_t)c.W * kWave) {
+        const double ub = a.U[base][uo + t];
+        a.U[out][uo + t] = ub + alpha * (a.U[other][uo + t] - ub);
+    }
+    __syncthreads();
 }
 
 // upper: kUpperFgs, kUpperBgs or kUpperSgs. The FP32 kernel runs an instance's
@@ -103,10 +139,15 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
     int j = s.j, fin = -1;
     bool check_only = false;
     double rs = 0.0, rp = 0.0;
+    const bool box = a.P.tau > 0.0;
     if (PREC == kModeFp64 && s.mode == kModeFp64Redo) {
         unsigned long long none[2] = {0, 0};
         gs_sweep<T, CX, RY, LX, LY>(a, c, b, dir1, j & 1, (j & 1) ^ 1, -1, false, false, none,
                                     true);
+        if (box) {
+            const double al = gs_alpha(a, c, b);
+            if (al < 1.0) gs_blend(a, c, b, j & 1, (j & 1) ^ 1, (j & 1) ^ 1, al);
+        }
         ++s.e;
         ++j;
         check_only = true;
@@ -134,8 +175,21 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_gs(const IterArgs a, const in
             check_only = false;
             continue;
         }
+        if (box) {
+            const double al = gs_alpha(a, c, b);
+            if (al < 1.0) gs_blend(a, c, b, p, q, q, al);
+        }
         if (upper == kUpperSgs) {
-            gs_sweep<T, CX, RY, LX, LY>(a, c, b, 1, q, q, p, false, false, acc);
+            if (box) {
+                // with the cut, the forward sweep writes buffer p (S^j is no
+                // longer needed; u~ = u^j of each stage is read before that
+                // stage is overwritten) and the cut result goes to q
+                gs_sweep<T, CX, RY, LX, LY>(a, c, b, 1, q, p, p, false, false, acc);
+                const double al = gs_alpha(a, c, b);
+                gs_blend(a, c, b, q, p, q, al);
+            } else {
+                gs_sweep<T, CX, RY, LX, LY>(a, c, b, 1, q, q, p, false, false, acc);
+            }
             ++s.e;
         }
         ++j;

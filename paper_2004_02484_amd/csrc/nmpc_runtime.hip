@@ -905,9 +905,9 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     if (prob->b_kind == NMPC_B_DENSE) return create_dense(h, out);
     rc = choose_path(prob, opt, &h->streaming);
     if (rc) { delete h; return rc; }
-    if (prob->tau > 0.0 && (h->streaming || opt->upper != NMPC_UPPER_JACOBI)) {
+    if (prob->tau > 0.0 && h->streaming) {
         delete h;
-        return fail(NMPC_E_UNSUPPORTED, "the input box runs with the Jacobi upper layer on the fused path");
+        return fail(NMPC_E_UNSUPPORTED, "the input box runs on the fused path");
     }
     if (!h->streaming) {
         rc = select_all(prob, opt, h->kern, h->gs);
@@ -1022,8 +1022,6 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (rc) return rc;
     if (streaming != h->streaming)
         return fail(NMPC_E_UNSUPPORTED, "set_options cannot switch between fused and streaming paths");
-    if (h->prob.tau > 0.0 && opt->upper != NMPC_UPPER_JACOBI)
-        return fail(NMPC_E_UNSUPPORTED, "the input box runs with the Jacobi upper layer");
     nmpc_handle::Kern kn[2] = {}, gn[2] = {};
     if (!streaming) {
         rc = select_all(&h->prob, opt, kn, gn);

@@ -144,11 +144,68 @@ def test_box_2d_batch_fp32(nm):
         assert np.all(Ub > P.u_lo) and np.all(Ub < P.u_hi)
 
 
-def test_box_needs_jacobi_fused_and_no_ragged(nm):
+@pytest.mark.parametrize("upper", ["fgs", "bgs", "sgs"])
+def test_box_gauss_seidel_iterates_match_oracle(nm, upper):
+    """The Gauss-Seidel layers with the input box (the paper's pairing, SGS):
+    from a start where the fraction-to-the-boundary rule cuts the sweeps, the
+    GPU iterates follow the oracle's (each sweep cut, S + alpha (S_sweep -
+    S)); converged, the inputs equal the oracle's solution."""
+    code = {"fgs": nm.NMPC_UPPER_FGS, "bgs": nm.NMPC_UPPER_BGS, "sgs": nm.NMPC_UPPER_SGS}[upper]
+    P, x0, xref, free = boxed_c0(tau_rel=1e-5)
+    start = (free["X"].copy(), np.clip(free["U"], 0.98 * P.u_lo, 0.98 * P.u_hi),
+             free["LAM"].copy())
+    sw = oracle.gs_sweep(P, x0, xref, *start, 1 if upper == "fgs" else -1)
+    assert oracle.alpha_max(P, start[1], start[1] - sw[1]) < 0.5    # the rule cuts
+    for prec in ("fp64", "fp32"):
+        precision = nm.NMPC_FP64 if prec == "fp64" else nm.NMPC_FP32_SWEEP
+        for k in ((1, 2, 5) if prec == "fp64" else (3,)):
+            s = nm.Solver(P, tol=0.0, max_iter=k, upper=code, precision=precision)
+            rc, X, U, L, info = s.solve(x0, xref, warm=start)
+            s.close()
+            o = oracle.solve(P, x0, xref, start=tuple(a.copy() for a in start), tol=0.0,
+                             max_iter=k, upper=upper)
+            assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+            bar = 1e-10 if prec == "fp64" else 1e-3
+            assert rel(U, o["U"]) <= bar, (prec, k, rel(U, o["U"]))
+            if prec == "fp64":
+                assert rel(X, o["X"]) <= bar and rel(L, o["LAM"]) <= bar
+            assert np.all(U > P.u_lo) and np.all(U < P.u_hi)
+    s = nm.Solver(P, tol=1e-8, max_iter=20000, upper=code)
+    rc, X, U, L, info = s.solve(x0, xref)
+    o = oracle.solve(P, x0, xref, tol=1e-8, max_iter=20000, upper=upper)
+    assert rc == nm.NMPC_OK and o["status"] == "converged"
+    assert abs(info["iters"] - o["iters"]) <= 1
+    ok = o if info["iters"] == o["iters"] else oracle.solve(P, x0, xref, tol=0.0,
+                                                            max_iter=info["iters"], upper=upper)
+    assert rel(U, ok["U"]) <= 1e-9
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=50000)
+    assert rel(U, ex["U"]) <= 1e-6
+
+
+def test_box_sgs_fp32_batch_2d(nm):
+    """2D batch, SGS, FP32 sweeps with the final FP64 correction and the box:
+    every instance converges inside the box to the oracle's exact solution."""
+    import torch
+    P0 = make_problem("grid", ns=16, N=8, lattice=2)
+    x0, xr = make_batch(P0, [1, 2, 3])
+    free = [oracle.solve(P0, x0[b], xr[b], tol=1e-10, max_iter=20000) for b in range(3)]
+    umax = max(np.abs(f["U"]).max() for f in free)
+    P = P0.with_(tau=1e-3 * P0.r * umax, u_lo=-0.5 * umax, u_hi=0.5 * umax)
+    s = nm.Solver(P, max_batch=3, tol=1e-7, max_iter=20000, precision=nm.NMPC_FP32_SWEEP,
+                  upper=nm.NMPC_UPPER_SGS)
+    rc, X, U, L, infos = s.solve_batch(torch.tensor(x0, device="cuda"),
+                                       torch.tensor(xr, device="cuda"))
+    assert rc == nm.NMPC_OK
+    for b in range(3):
+        ex = oracle.solve(P, x0[b], xr[b], tol=1e-11, max_iter=50000, upper="sgs")
+        assert ex["status"] == "converged"
+        Ub = U[b].cpu().numpy()
+        assert rel(Ub, ex["U"]) <= 1e-4
+        assert np.all(Ub > P.u_lo) and np.all(Ub < P.u_hi)
+
+
+def test_box_needs_fused_and_no_ragged(nm):
     P, x0, xref, _ = boxed_c0()
-    with pytest.raises(nm.NmpcError) as e:
-        nm.Solver(P, upper=nm.NMPC_UPPER_SGS)
-    assert e.value.code == nm.NMPC_E_UNSUPPORTED
     with pytest.raises(nm.NmpcError) as e:
         nm.RaggedSolver([P], max_instances=1)
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
