@@ -149,6 +149,7 @@ struct StreamArgs {
                                     // 2: that step is the FP64 correction of an FP32-sweep solve
     unsigned long long *du;         // [B][2] as IterArgs::du
     int res_paper;                  // the test is on r_paper instead of r_scaled
+    double *apart;                  // input box: [B][N] step limit of each stage
     int *iters;
     double *rfin;
     int *ctr;                       // [2] finished, [3] in the FP32 phase
@@ -178,6 +179,7 @@ constexpr int kLowerCols = kWave - 2 * kLowerHalo;
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
     const void *lower, *lower_fin, *v3f;   // fused Schur step, final block; v3 from partials
+    const void *box_lim, *box_apply;       // input box: stage limits, then the cut step
 };
 StreamKernels stream_kernels(int prec);
 
@@ -256,6 +258,7 @@ const void *ragged_iterate_kernel(int prec, int waves, int tcase);
 const void *ragged_pad_kernel();
 const void *ragged_init_kernel();
 const void *ragged_output_kernel();
+const void *ragged_box_apply_kernel();   // (IterArgs, RgArgs): input-box step rule of one case
 // tile case of a class for a launch of `waves` waves, or -1
 int ragged_tile(int nsx, int nsy, int waves, int *cx, int *ry);
 

@@ -71,6 +71,10 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
     v.res_at = (long long)d.slot * a.rslot + us + i;
     v.res_only = d.eval_only;
     if (d.redo && a.du) v.du_at = b;
+    if (cl.P.tau > 0.0 && !a.residual_only && !d.eval_only) {   // input box: record the limit
+        v.box_at = us + i;
+        if (i == 0 && c.tid == 0) a.aupd[b] = k + 1;   // this launch updates b
+    }
     v.i = i;
     v.last = i == N - 1;
     unsigned long long acc[2] = {0, 0};
@@ -120,7 +124,17 @@ __global__ void k_rg_init(const IterArgs a, const RgArgs r, int mode, const doub
         X[t] = x;
         L[t] = l;
     }
-    for (int t = threadIdx.x; t < N * m; t += blockDim.x) U[t] = wu ? wu[r.uoff[b] + t] : 0.0;
+    // with an input box the start is strictly feasible (Sec. 4.2): given inputs
+    // are clipped to the box shrunk by 0.5 % of its width at each end
+    const double ulo = cl.P.ulo, uhi = cl.P.uhi, marg = 0.005 * (uhi - ulo);
+    for (int t = threadIdx.x; t < N * m; t += blockDim.x) {
+        double u = wu ? wu[r.uoff[b] + t] : 0.0;
+        if (wu && cl.P.tau > 0.0) {
+            if (u < ulo + marg) u = ulo + marg;
+            if (u > uhi - marg) u = uhi - marg;
+        }
+        U[t] = u;
+    }
     if (threadIdx.x == 0) {
         InstState s;
         s.status = kActive; s.mode = mode; s.e = 0; s.j = 0; s.pending = 0; s.f32 = 0;
@@ -207,7 +221,49 @@ int ragged_tile(int nsx, int nsy, int waves, int *cx, int *ry)
     return 3 * ci + r_ - 1;
 }
 
+// Input box after an iteration launch of one tile case (the units of its
+// work list): the fraction-to-the-boundary rule (eq. eq_alphamax) with alpha
+// global over an instance's stages, as for the batch kernel. Instances that
+// did not update in this launch, have no box, or have alpha = 1 return at once.
+__global__ void __launch_bounds__(256) k_rg_box_apply(const IterArgs a, const RgArgs r)
+{
+    __shared__ double red[256];
+    const int k = *(volatile const int *)(a.ctr) + a.kofs;
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * a.per_xcd + (bid >> 3);
+    if (unit >= a.units) return;
+    const int2 bi = r.umap[unit];
+    if (bi.x < 0) return;
+    const int b = bi.x, i = bi.y;
+    const RgClass &cl = r.cls[r.icls[b]];
+    if (!(cl.P.tau > 0.0) || a.aupd[b] != k + 1) return;
+    const int N = cl.P.N, n = cl.P.n, M = cl.P.m;
+    const long long us = r.ustart[b];
+    double l = 1.0;
+    for (int t = threadIdx.x; t < N; t += blockDim.x) l = fmin(l, a.apart[us + t]);
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double alpha = red[0];
+    if (!(alpha < 1.0)) return;
+    const int src = a.st[((k + 1) & 1) * a.B + b].j & 1, dst = src ^ 1;
+    const size_t so = (size_t)r.soff[b] + (size_t)i * n, uo = (size_t)r.uoff[b] + (size_t)i * M;
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+        const double xs = a.X[src][so + p], ls = a.LAM[src][so + p];
+        a.X[dst][so + p] = xs + alpha * (a.X[dst][so + p] - xs);
+        a.LAM[dst][so + p] = ls + alpha * (a.LAM[dst][so + p] - ls);
+    }
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double us_ = a.U[src][uo + j];
+        a.U[dst][uo + j] = us_ + alpha * (a.U[dst][uo + j] - us_);
+    }
+}
+
 const void *ragged_pad_kernel() { return (const void *)&k_rg_pad; }
+const void *ragged_box_apply_kernel() { return (const void *)&k_rg_box_apply; }
 const void *ragged_init_kernel() { return (const void *)&k_rg_init; }
 const void *ragged_output_kernel() { return (const void *)&k_rg_output; }
 

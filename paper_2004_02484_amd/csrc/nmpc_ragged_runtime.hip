@@ -80,6 +80,9 @@ struct nmpc_ragged {
     int *d_iters = nullptr;
     double *d_rfin = nullptr;
     unsigned long long *d_du = nullptr;   // [B][2] FP64 correction step (max |du|, max |u|)
+    double *d_apart = nullptr; size_t cap_apart = 0;   // input box: step limit per stage unit
+    int *d_aupd = nullptr;        // input box: [B] 1 + launch index of the last update
+    bool box = false;             // some class has an input box
     int *d_ctr = nullptr;
     int *h_poll = nullptr;
     int gen = 0;                  // bumped when a buffer moves (graphs hold pointers)
@@ -124,7 +127,8 @@ void rg_release(nmpc_ragged *r)
     for (void *p : {(void *)r->d_cls[0], (void *)r->d_cls[1], (void *)r->d_cls[2], (void *)r->d_g,
                     (void *)r->d_icls, (void *)r->d_off, (void *)r->d_umap, (void *)r->d_S[0],
                     (void *)r->d_S[1], (void *)r->d_in, (void *)r->d_rst, (void *)r->d_st,
-                    (void *)r->d_iters, (void *)r->d_rfin, (void *)r->d_ctr, (void *)r->d_du})
+                    (void *)r->d_iters, (void *)r->d_rfin, (void *)r->d_ctr, (void *)r->d_du,
+                    (void *)r->d_apart, (void *)r->d_aupd})
         if (p) (void)hipFree(p);
     if (r->h_poll) (void)hipHostFree(r->h_poll);
     for (hipEvent_t e : {r->ev, r->t0, r->t1})
@@ -247,8 +251,10 @@ int ensure_buffers(nmpc_ragged *r)
     int rc = grow(r->d_in, r->cap_in, 2 * r->in_len);
     if (!rc) rc = grow(r->d_rst, r->cap_rst, 6 * r->tot_units);
     if (!rc) rc = grow(r->d_umap, r->cap_umap, r->h_umap.size());
+    const size_t ap0 = r->cap_apart;
+    if (!rc && r->box) rc = grow(r->d_apart, r->cap_apart, r->tot_units);
     if (rc) return rc;
-    if (r->cap_in != in0 || r->cap_rst != rs0 || r->cap_umap != um0) ++r->gen;
+    if (r->cap_in != in0 || r->cap_rst != rs0 || r->cap_umap != um0 || r->cap_apart != ap0) ++r->gen;
     return NMPC_OK;
 }
 
@@ -262,6 +268,7 @@ IterArgs rg_iter_args(const nmpc_ragged *r)
     a.pst = r->d_rst + 3 * r->tot_units;
     a.rslot = (long long)r->tot_units;
     a.st = r->d_st; a.iters = r->d_iters; a.rfin = r->d_rfin; a.du = r->d_du;
+    a.apart = r->d_apart; a.aupd = r->d_aupd;
     a.ctr = r->d_ctr; a.kofs = 0;
     a.B = r->max_inst;
     a.units = 0;       // per launch: 8 * the segment's per_xcd
@@ -314,6 +321,9 @@ int launch_rg(nmpc_ragged *r, int prec, int waves, IterArgs a, hipStream_t s)
         if (lds > 48 * 1024)
             RG_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         RG_TRY(hipLaunchKernel(fn, dim3(8 * sg.per_xcd), dim3(nmpc::kWave * waves), args, lds, s));
+        if (r->box && !a.residual_only)   // input box: the step rule of this case's launch
+            RG_TRY(hipLaunchKernel(nmpc::ragged_box_apply_kernel(), dim3(8 * sg.per_xcd), dim3(256),
+                                   args, 0, s));
     }
     return NMPC_OK;
 }
@@ -388,6 +398,8 @@ int prepare(nmpc_ragged *r, int count, const int32_t *cls, const double *x0, con
         void *args2[] = {(void *)&g, (void *)&xref, (void *)&dst};
         RG_TRY(hipLaunchKernel(nmpc::ragged_pad_kernel(), dim3(count), dim3(256), args2, 0, r->stream));
     }
+    if (r->box)   // input box: no update recorded for this solve yet (not captured)
+        RG_TRY(hipMemsetAsync(r->d_aupd, 0, sizeof(int) * r->max_inst, r->stream));
     IterArgs a = rg_iter_args(r);
     int mode = r->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
     void *args[] = {(void *)&a, (void *)&g, (void *)&mode, (void *)&wx, (void *)&wu, (void *)&wl};
@@ -519,12 +531,20 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
     if (rc) return rc;
     for (int c = 0; c < nclass; ++c)
         if ((rc = check_class(&classes[c]))) return rc;
-    for (int c = 0; c < nclass; ++c)
-        if (classes[c].tau != 0.0) return rg_fail(NMPC_E_UNSUPPORTED, "ragged batches take no input box");
+    bool box = false;
+    for (int c = 0; c < nclass; ++c) {
+        const nmpc_problem &p = classes[c];
+        if (!(std::isfinite(p.tau) && p.tau >= 0.0)) return rg_fail(NMPC_E_ARG, "tau must be finite and >= 0");
+        if (p.tau > 0.0 && !(std::isfinite(p.u_lo) && std::isfinite(p.u_hi) && p.u_lo < 0.0 &&
+                             p.u_hi > 0.0))
+            return rg_fail(NMPC_E_ARG, "an input box needs finite u_lo < 0 < u_hi (cold start inside)");
+        box = box || p.tau > 0.0;
+    }
     nmpc_ragged *r = new (std::nothrow) nmpc_ragged();
     if (!r) return rg_fail(NMPC_E_OOM, "host allocation failed");
     r->opt = *opt;
     r->max_inst = max_instances;
+    r->box = box;
     r->cls.assign(classes, classes + nclass);
     r->gx.resize(nclass);
     r->gy.resize(nclass);
@@ -567,6 +587,7 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
     A((void **)&r->d_iters, sizeof(int) * max_instances);
     A((void **)&r->d_rfin, sizeof(double) * 2 * max_instances);
     A((void **)&r->d_du, sizeof(unsigned long long) * 2 * max_instances);
+    if (box) A((void **)&r->d_aupd, sizeof(int) * max_instances);
     A((void **)&r->d_ctr, sizeof(int) * 4);
     if (e == hipSuccess) e = hipHostMalloc((void **)&r->h_poll, 2 * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking);
@@ -585,7 +606,7 @@ int nmpc_ragged_create(const nmpc_problem *classes, int32_t nclass, const nmpc_o
         k.P.nsx = p.nsx; k.P.nsy = p.nsy; k.P.n = p.nsy * 16 * cx; k.P.N = p.horizon;
         k.P.m = 16; k.P.lx = 4; k.P.ly = 4;
         k.P.h = p.h; k.P.k0 = p.k0; k.P.k1 = p.k1; k.P.q = p.q; k.P.r = p.r; k.P.gamma = p.gamma;
-        k.P.tau = 0.0; k.P.ulo = k.P.uhi = 0.0;
+        k.P.tau = p.tau; k.P.ulo = p.u_lo; k.P.uhi = p.u_hi;
         const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
         k.P.idx2 = 1.0 / (dx * dx);
         k.P.idy2 = 1.0 / (dy * dy);

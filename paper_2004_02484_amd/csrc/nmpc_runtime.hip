@@ -534,6 +534,8 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->n; a.P.N = h->N; a.P.m = h->m;
     a.P.lx = p.lx; a.P.ly = p.ly;
     a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
+    a.P.tau = p.tau; a.P.ulo = p.u_lo; a.P.uhi = p.u_hi;
+    a.apart = h->d_apart;
     const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);
     a.P.idx2 = 1.0 / (dx * dx);
     a.P.idy2 = p.dim == 2 ? 1.0 / (dy * dy) : 0.0;
@@ -603,6 +605,10 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
             if (!fin && (rc = go(k.v3f, stages, 256, args))) return rc;
         }
         void *args[] = {(void *)&a};
+        if (h->prob.tau > 0.0) {   // input box: cut the step by the rule
+            if ((rc = go(k.box_lim, stages, nmpc::kWave, args))) return rc;
+            if ((rc = go(k.box_apply, stages, 256, args))) return rc;
+        }
         return go(k.advance, inst, 256, args);
     }
     const int passes = 1 + std::max(0, h->opt.n_sweep - 2);
@@ -643,6 +649,10 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
         }
     }
     void *args[] = {(void *)&a};
+    if (h->prob.tau > 0.0) {   // input box: cut the step by the rule
+        if ((rc = go(k.box_lim, stages, nmpc::kWave, args))) return rc;
+        if ((rc = go(k.box_apply, stages, 256, args))) return rc;
+    }
     return go(k.advance, inst, 256, args);
 }
 
@@ -905,10 +915,6 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     if (prob->b_kind == NMPC_B_DENSE) return create_dense(h, out);
     rc = choose_path(prob, opt, &h->streaming);
     if (rc) { delete h; return rc; }
-    if (prob->tau > 0.0 && h->streaming) {
-        delete h;
-        return fail(NMPC_E_UNSUPPORTED, "the input box runs on the fused path");
-    }
     if (!h->streaming) {
         rc = select_all(prob, opt, h->kern, h->gs);
         if (rc) { delete h; return rc; }

@@ -449,7 +449,10 @@ __global__ void __launch_bounds__(256) k_st_stage(const StreamArgs a)
         double bt = 0.0;
 #pragma unroll 8
         for (int u = 0; u < units; ++u) bt += pp[(size_t)u * kMaxM];
-        const double ku = P.h * (P.r * a.U[cur][(size_t)bi * m + j] + bt);
+        const double u = a.U[cur][(size_t)bi * m + j];
+        double bg = 0.0;   // gradient of the input box's barrier (eq. nlp_relaxed)
+        if (P.tau > 0.0) bg = -P.tau / (u - P.ulo) + P.tau / (P.uhi - u);
+        const double ku = P.h * (P.r * u + bg + bt);
         a.kun[(size_t)bi * m + j] = ku;
         a.v3[(size_t)bi * m + j] = 0.0;
         mu = sabits(ku);
@@ -726,8 +729,22 @@ __global__ void __launch_bounds__(256) k_st_jft(const StreamArgs a, int pass, in
     }
 }
 
-// v3 = (K^u + h B^T y4) / (h r + gamma) per stage (T arithmetic as in the
-// fused kernel). One workgroup (256 threads) per stage.
+// A_uu of input j of stage bi: h r + gamma, plus h times the Hessian of the
+// input box's barrier at the stage's current input.
+__device__ __forceinline__ double stream_auu(const StreamArgs &a, long long bi, int j)
+{
+    double au = a.P.h * a.P.r + a.P.gamma;
+    if (a.P.tau > 0.0) {
+        const int b = (int)(bi / a.P.N);
+        const double u = a.U[a.st[b].j & 1][(size_t)bi * a.P.m + j];
+        const double lo = u - a.P.ulo, hi = a.P.uhi - u;
+        au += a.P.h * (a.P.tau / (lo * lo) + a.P.tau / (hi * hi));
+    }
+    return au;
+}
+
+// v3 = (K^u + h B^T y4) / A_uu per stage (T arithmetic as in the fused
+// kernel). One workgroup (256 threads) per stage.
 template <typename T>
 __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 {
@@ -736,11 +753,12 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
     if (bi >= a.count * a.P.N) return;
     const int b = bi / a.P.N;
     if (!a.work[b]) return;
-    const T auu = T(a.P.h * a.P.r + a.P.gamma), h = T(a.P.h);
+    const T h = T(a.P.h);
     const double btd = bt_from_rows(a, bi, sh);
     if (threadIdx.x < a.P.m) {
         const int j = threadIdx.x;
         const T bt = T(btd);
+        const T auu = T(stream_auu(a, bi, j));
         a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * bt) / auu);
     }
 }
@@ -981,8 +999,62 @@ __global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
     double s = 0.0;
 #pragma unroll 8
     for (int u = 0; u < units; ++u) s += pp[(size_t)u * kMaxM];
-    const T auu = T(a.P.h * a.P.r + a.P.gamma), h = T(a.P.h);
+    const T h = T(a.P.h);
+    const T auu = T(stream_auu(a, bi, j));
     a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * T(s)) / auu);
+}
+
+// Input box, after the final block (the step S^{j+1} = S^j - ds written):
+// each stage's fraction-to-the-boundary limit from its input step v3 (one
+// wave per stage), then alpha = the instance's minimum scales the step where
+// it is below 1 (eq. eq_alphamax; one workgroup per stage).
+__global__ void k_st_box_lim(const StreamArgs a)
+{
+    const int bi = blockIdx.x, lane = threadIdx.x;
+    if (bi >= a.count * a.P.N) return;
+    const int b = bi / a.P.N;
+    if (!a.work[b]) return;
+    const int cur = a.st[b].j & 1;
+    double l = 1.0;
+    for (int j = lane; j < a.P.m; j += kWave) {
+        const double u = a.U[cur][(size_t)bi * a.P.m + j], d = a.v3[(size_t)bi * a.P.m + j];
+        double lj = 1.0;
+        if (d > 0.0) lj = 0.995 * (u - a.P.ulo) / d;
+        else if (d < 0.0) lj = 0.995 * (a.P.uhi - u) / (-d);
+        l = fmin(l, fmax(lj, 0.0));
+    }
+    for (int o = 32; o >= 1; o >>= 1) l = fmin(l, __shfl_xor(l, o, kWave));
+    if (lane == 0) a.apart[bi] = l;
+}
+
+__global__ void __launch_bounds__(256) k_st_box_apply(const StreamArgs a)
+{
+    __shared__ double red[256];
+    const int bi = blockIdx.x;
+    if (bi >= a.count * a.P.N) return;
+    const int b = bi / a.P.N;
+    if (!a.work[b]) return;
+    double l = 1.0;
+    for (int t = threadIdx.x; t < a.P.N; t += blockDim.x) l = fmin(l, a.apart[(size_t)b * a.P.N + t]);
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const double alpha = red[0];
+    if (!(alpha < 1.0)) return;
+    const int cur = a.st[b].j & 1, nxt = cur ^ 1;
+    const size_t n = (size_t)a.P.nsx * a.P.nsy, so = (size_t)bi * n, uo = (size_t)bi * a.P.m;
+    for (size_t p = threadIdx.x; p < n; p += blockDim.x) {
+        const double xs = a.X[cur][so + p], ls = a.LAM[cur][so + p];
+        a.X[nxt][so + p] = xs + alpha * (a.X[nxt][so + p] - xs);
+        a.LAM[nxt][so + p] = ls + alpha * (a.LAM[nxt][so + p] - ls);
+    }
+    for (int j = threadIdx.x; j < a.P.m; j += blockDim.x) {
+        const double us = a.U[cur][uo + j];
+        a.U[nxt][uo + j] = us + alpha * (a.U[nxt][uo + j] - us);
+    }
 }
 
 // j <- j + 1 for the instances that stepped (after every pass has used j).
@@ -997,6 +1069,8 @@ StreamKernels stream_kernels(int prec)
 {
     StreamKernels k{};
     k.advance = (const void *)&k_st_advance;
+    k.box_lim = (const void *)&k_st_box_lim;
+    k.box_apply = (const void *)&k_st_box_apply;
     if (prec == kModeFp32) {
         k.bsep = (const void *)&k_st_bsep<kModeFp32>;
         k.stage = (const void *)&k_st_stage<kModeFp32>;

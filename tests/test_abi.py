@@ -163,3 +163,12 @@ def test_input_box_arguments_checked():
         with pytest.raises(nm.NmpcError) as e:
             nm.Solver(bad)
         assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_ragged_box_arguments_checked():
+    """Ragged classes with an input box need u_lo < 0 < u_hi (the cold start
+    inside); checked before any device work."""
+    bad = _grid(32, 4, 4).with_(tau=0.1, u_lo=0.1, u_hi=1.0)
+    with pytest.raises(nm.NmpcError) as e:
+        nm.nmpc_ragged_create([bad], nm.nmpc_default_options(), 4)
+    assert e.value.code == nm.NMPC_E_ARG

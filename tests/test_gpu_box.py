@@ -204,12 +204,46 @@ def test_box_sgs_fp32_batch_2d(nm):
         assert np.all(Ub > P.u_lo) and np.all(Ub < P.u_hi)
 
 
-def test_box_needs_fused_and_no_ragged(nm):
+def test_box_arguments_are_checked(nm):
     P, x0, xref, _ = boxed_c0()
-    with pytest.raises(nm.NmpcError) as e:
-        nm.RaggedSolver([P], max_instances=1)
-    assert e.value.code == nm.NMPC_E_UNSUPPORTED
     bad = P.with_(u_lo=0.1)                          # cold start u = 0 outside
     with pytest.raises(nm.NmpcError) as e:
         nm.Solver(bad)
     assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_box_streaming_path_matches_oracle(nm):
+    """The streaming (multi-pass) path with the input box: barrier rows in
+    K^u and A_uu, stage limits from the final input step, the step cut by the
+    instance's alpha. Equal-k iterates equal the oracle's from a start where
+    the rule cuts (1D and a 2D grid); converged FP32 sweeps meet the exact
+    solution inside the box."""
+    P, x0, xref, free = boxed_c0(tau_rel=1e-5)
+    start = (free["X"].copy(), np.clip(free["U"], 0.98 * P.u_lo, 0.98 * P.u_hi),
+             free["LAM"].copy())
+    assert step_alpha(P, x0, xref, *start) < 0.1
+    for k in (1, 3):
+        s = nm.Solver(P, tol=0.0, max_iter=k, path=nm.NMPC_PATH_STREAM)
+        rc, X, U, L, info = s.solve(x0, xref, warm=start)
+        s.close()
+        o = oracle.solve(P, x0, xref, start=tuple(a.copy() for a in start), tol=0.0, max_iter=k)
+        assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+        assert rel(U, o["U"]) <= 1e-10 and rel(X, o["X"]) <= 1e-10 and rel(L, o["LAM"]) <= 1e-10
+    P0 = make_problem("grid", ns=40, N=4, lattice=4)
+    x0b, xrb = make_instance(P0, 2)
+    fr = oracle.solve(P0, x0b, xrb, tol=1e-8, max_iter=20000)
+    umax = np.abs(fr["U"]).max()
+    Pb = P0.with_(tau=1e-3 * P0.r * umax, u_lo=-0.5 * umax, u_hi=0.5 * umax)
+    for k in (2, 5):
+        s = nm.Solver(Pb, tol=0.0, max_iter=k, path=nm.NMPC_PATH_STREAM)
+        rc, X, U, L, info = s.solve(x0b, xrb)
+        s.close()
+        o = oracle.solve(Pb, x0b, xrb, tol=0.0, max_iter=k)
+        assert rel(U, o["U"]) <= 1e-10 and rel(X, o["X"]) <= 1e-10 and rel(L, o["LAM"]) <= 1e-10
+    s = nm.Solver(Pb, tol=1e-7, max_iter=20000, path=nm.NMPC_PATH_STREAM,
+                  precision=nm.NMPC_FP32_SWEEP)
+    rc, X, U, L, info = s.solve(x0b, xrb)
+    ex = oracle.solve(Pb, x0b, xrb, tol=1e-11, max_iter=50000)
+    assert rc == nm.NMPC_OK and rel(U, ex["U"]) <= 1e-4
+    assert np.all(U > Pb.u_lo) and np.all(U < Pb.u_hi)
+    assert rel(U, fr["U"]) > 0.05     # the box changed the answer

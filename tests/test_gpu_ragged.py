@@ -189,3 +189,43 @@ def test_ragged_full_size_batch(nm):
         X, U, L = (t.cpu().numpy() for t in res[b])
         r_s, _ = oracle.residual(classes[c], inst[b][0], inst[b][1], X, U, L)
         assert r_s <= 1e-6, (b, keys[c], r_s)
+
+
+def test_ragged_input_box_matches_oracle(nm):
+    """Ragged batch whose classes carry input boxes (some classes none): at
+    equal k every instance equals the oracle's Jacobi iterate with the barrier
+    and the fraction-to-the-boundary rule (alpha global over the instance's
+    stages); converged in FP32 sweeps, the inputs meet the oracle's exact
+    solution inside each box."""
+    order = [0, 1, 2, 5, 0, 3]
+    classes, inst = small_batch(order)
+    boxed = []
+    for c, P in enumerate(classes):
+        if c in (3,):             # no box for this class
+            boxed.append(P)
+            continue
+        x0, xr = make_instance(P, 7)   # a box at 0.6 of one instance's input range
+        free = oracle.solve(P, x0, xr, tol=1e-8, max_iter=20000)
+        umax = np.abs(free["U"]).max()
+        boxed.append(P.with_(tau=1e-4 * P.r * umax, u_lo=-0.6 * umax, u_hi=0.6 * umax))
+    for k in (2, 6):
+        rs = nm.RaggedSolver(boxed, max_instances=8, tol=0.0, max_iter=k)
+        rc, res, infos, _ = rs.solve(order, [dev(x) for _, x, _ in inst],
+                                     [dev(r) for _, _, r in inst])
+        rs.close()
+        for (c, x0, xr), (X, U, L), info in zip(inst, res, infos):
+            o = oracle.solve(boxed[c], x0, xr, tol=0.0, max_iter=k)
+            assert info["iters"] == k
+            assert rel(U.cpu().numpy(), o["U"]) <= REL, (c, k, rel(U.cpu().numpy(), o["U"]))
+            assert rel(X.cpu().numpy(), o["X"]) <= REL and rel(L.cpu().numpy(), o["LAM"]) <= REL
+            if boxed[c].tau > 0:
+                Uh = U.cpu().numpy()
+                assert np.all(Uh > boxed[c].u_lo) and np.all(Uh < boxed[c].u_hi)
+    rs = nm.RaggedSolver(boxed, max_instances=8, tol=1e-7, max_iter=20000,
+                         precision=nm.NMPC_FP32_SWEEP)
+    rc, res, infos, _ = rs.solve(order, [dev(x) for _, x, _ in inst], [dev(r) for _, _, r in inst])
+    assert rc == nm.NMPC_OK
+    for (c, x0, xr), (X, U, L), info in zip(inst, res, infos):
+        ex = oracle.solve(boxed[c], x0, xr, tol=1e-11, max_iter=50000)
+        assert ex["status"] == "converged"
+        assert rel(U.cpu().numpy(), ex["U"]) <= 1e-4
