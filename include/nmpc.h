@@ -88,13 +88,16 @@ typedef struct nmpc_problem {
     double gamma;         /* regularization weight >= 0 */
     double tau;           /* input box u_lo <= u <= u_hi by the log barrier
                              -tau sum_j (ln(u_j - u_lo) + ln(u_hi - u_j)) of
-                             the relaxed problem (eq. nlp_relaxed), each Jacobi
-                             step cut by the fraction-to-the-boundary rule
-                             (eq. eq_alphamax, alpha global over the stages);
-                             tau = 0: no box. tau > 0 needs u_lo < 0 < u_hi
-                             (the cold start u = 0 inside), the Jacobi upper
-                             layer and the fused path (NMPC_E_UNSUPPORTED for
-                             the others and for ragged batches) */
+                             the relaxed problem (eq. nlp_relaxed), each step
+                             of the upper layer (a Jacobi iteration, or each
+                             Gauss-Seidel sweep) cut by the fraction-to-the-
+                             boundary rule (eq. eq_alphamax, alpha global over
+                             the instance's stages: S <- S + alpha (S_step -
+                             S)); every path and upper layer, ragged batches
+                             too. tau = 0: no box. tau > 0 needs u_lo < 0 <
+                             u_hi (the cold start u = 0 inside); given start
+                             inputs are clipped to the box shrunk by 0.5 % of
+                             its width at each end */
     double u_lo, u_hi;
     int32_t b_kind;       /* NMPC_B_KRON: B from the factors gx, gy (above);
                              NMPC_B_DENSE: B is the dense matrix below, m =
