@@ -767,7 +767,7 @@ def main():
         ms = e0.elapsed_time(e1) / reps
         fb, f32 = net_flops(net, B)
         tf = (fb + f32) / (ms * 1e-3) / 1e12
-        cfg["network"] = {"inference_ms": round(ms, 3), "params": int(sum(v.numel() for v in net.params.values())),
+        cfg["network"] = {"inference_ms": round(ms, 3), "params": net.num_params(),
                           "gflop": {"bf16_layers": round(fb / 1e9, 2), "fp32_map": round(f32 / 1e9, 2)},
                           "mfma": {"bound": "mfma", "achieved": round(tf, 2),
                                    "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",

@@ -455,6 +455,78 @@ int nmpc_unpack_inputs(const float *rows, int32_t ldr, int32_t count, int32_t N,
                        float scale, double *u, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * The warm-start network as one object (the layer sequence above, run by the
+ * kernels above): a patch encoder for an ns x ns grid with an L x L actuator
+ * lattice and N stages. For actuator p of instance b it reads a win x win
+ * window of `planes` feature planes of (x0, xref) (nmpc_net_features) and
+ * predicts that actuator's inputs over the horizon:
+ *   H1 = relu(X W1 + b1), H2 = relu(H1 W2 + b2), H3 = relu(H2 W3 + b3)
+ *   (bf16 operands, fp32 accumulation, bf16 copies of H between layers),
+ *   Y = H3 W4 + b4 + X Ws[p] (the per-actuator map on fp32 operands),
+ *   u[b][i][p] = 4 Y[b L^2 + p][i].
+ * hidden = 0 leaves the per-actuator map alone. Parameters, gradients, Adam
+ * moments and activation buffers for up to max_count instances live on the
+ * device in the object. All x0 / xref / u pointers are DEVICE memory; work
+ * is queued on `stream` (hipStream_t); nmpc_net_get / _set / _load / _save and
+ * a loss pointer block. The network reaches the solver only through the
+ * warm-start inputs of nmpc_solve_batch, so the solver does not know it.
+ * ------------------------------------------------------------------------ */
+typedef struct nmpc_net_config {
+    int32_t N, ns, lattice, win, hidden, planes;   /* planes: 2 or 5 (nmpc_net_features) */
+} nmpc_net_config;
+
+typedef struct nmpc_net nmpc_net;
+
+/* Create with seeded initial weights (He-uniform hidden layers, zero biases,
+ * zero map). NMPC_E_ARG for an inconsistent configuration. */
+int nmpc_net_create(const nmpc_net_config *cfg, uint64_t seed, int32_t max_count, nmpc_net **out);
+
+/* u [count][N][L^2] predicted for x0, xref [count][ns^2] (count <= max_count). */
+int nmpc_net_forward(nmpc_net *net, int32_t count, const double *x0, const double *xref, double *u,
+                     void *stream);
+
+/* Forward pass and the gradients of the mean squared error of Y against
+ * u_target / 4 (u_target [count][N][L^2]) with respect to every parameter,
+ * kept in the object (read with nmpc_net_get, name "g" + parameter). loss
+ * (may be NULL; blocks when given) receives that error. */
+int nmpc_net_backward(nmpc_net *net, int32_t count, const double *x0, const double *xref,
+                      const double *u_target, float *loss, void *stream);
+
+/* Adam step on every parameter whose bit (W1 b1 W2 b2 W3 b3 W4 b4 Ws = bits 0..8)
+ * is clear in frozen_mask, from the gradients of the last backward pass;
+ * decoupled weight decay on the weight matrices. */
+int nmpc_net_adam_step(nmpc_net *net, float lr, float beta1, float beta2, float eps,
+                       float weight_decay, uint32_t frozen_mask, void *stream);
+
+/* nmpc_net_backward then nmpc_net_adam_step (beta1 0.9, beta2 0.999, eps 1e-8). */
+int nmpc_net_train_step(nmpc_net *net, int32_t count, const double *x0, const double *xref,
+                        const double *u_target, float lr, float weight_decay, uint32_t frozen_mask,
+                        float *loss, void *stream);
+
+/* Copy count elements of a parameter ("W1" .. "Ws", fp32), its gradient ("g"
+ * + name) or an activation buffer of the last pass ("X", "Xf", "H1", "H1b",
+ * ..., "Y", "T", "dY", "dYb", "dH1".."dH3", "dH1b".."dH3b", "Wb1".."Wb4") to
+ * host memory. "X", "Wb*" and the activation names ending in b hold bf16 bit
+ * patterns (2 bytes each), the rest fp32. NMPC_E_ARG for an unknown name or
+ * count beyond the buffer. */
+int nmpc_net_get(const nmpc_net *net, const char *name, void *host, int64_t count);
+
+/* Replace a parameter (count = its size; src host or device memory). */
+int nmpc_net_set(nmpc_net *net, const char *name, const float *src, int64_t count,
+                 int32_t src_on_device, void *stream);
+
+/* Total number of parameters. */
+int64_t nmpc_net_num_params(const nmpc_net *net);
+
+/* Weight file: "NMPCNET1", the configuration and the Adam step count as
+ * int32, then W1 b1 W2 b2 W3 b3 W4 b4 Ws as fp32 (host byte order). Load
+ * requires the same configuration (NMPC_E_ARG otherwise). */
+int nmpc_net_save(const nmpc_net *net, const char *path);
+int nmpc_net_load(nmpc_net *net, const char *path);
+
+void nmpc_net_destroy(nmpc_net *net);
+
+/* ---------------------------------------------------------------------------
  * Model engine: the double-layer method for further members of the paper's
  * PDE class (Sec. 2, eq. pde) on grids of up to 4096 nodes, one workgroup per
  * instance running the whole solve (FP64; every upper layer of

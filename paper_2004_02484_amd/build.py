@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnmpc.so")
 SOURCES = ["nmpc_kernels.hip", "nmpc_gs.hip", "nmpc_ragged.hip", "nmpc_loop.hip", "nmpc_stream.hip",
            "nmpc_runtime.hip", "nmpc_ragged_runtime.hip", "nmpc_net.hip", "nmpc_net_runtime.hip",
-           "nmpc_model.hip", "nmpc_model_runtime.hip"]
+           "nmpc_model.hip", "nmpc_model_runtime.hip", "nmpc_net_model.hip"]
 
 # Packed FP32 ops are disabled: code is written for scalar FP32/FP64 VALU.
 HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -61,9 +61,8 @@ def train(samples=81920, val=1024, epochs=40, batch=256, lr=3e-4, wd=1e-5, hidde
     log(f"labels: {samples} solves in {time.time() - t0:.1f} s")
     ntr = samples - val
     net = PatchNet(N=P.N, ns=P.nsx, lattice=P.lx, hidden=hidden, seed=seed)
-    net.params["W4"].zero_()
-    net.params["b4"].zero_()
-    net.load_state(net.state())
+    net.set_param("W4", np.zeros(net.shape("W4"), np.float32))
+    net.set_param("b4", np.zeros(net.shape("b4"), np.float32))
     # 1. the per-actuator linear map: exact minimizer of the squared error
     t1 = time.time()
     res = net.fit_linear(x0[:ntr], xr[:ntr], u[:ntr], batch=batch, ridge_rel=ridge)
@@ -85,9 +84,7 @@ def train(samples=81920, val=1024, epochs=40, batch=256, lr=3e-4, wd=1e-5, hidde
             step = ep * steps_per_epoch + k
             lr_t = lr * 0.5 * (1.0 + np.cos(np.pi * step / total)) + 1e-7
             sl = slice(k * batch, (k + 1) * batch)
-            loss, grads = net.loss_and_grads(xs[sl], rs[sl], us[sl])
-            net.adam_step(grads, lr=lr_t, wd=wd, frozen=("Ws",))
-            run += loss
+            run += net.train_step(xs[sl], rs[sl], us[sl], lr=lr_t, wd=wd, frozen=("Ws",))
         if ep % 5 == 4 or ep == epochs - 1:
             e = rel_errors(net, x0[ntr:], xr[ntr:], u[ntr:])
             med = float(np.median(e))

@@ -14,7 +14,8 @@ its adjoint carry products of the state with itself and with the reference).
 The window rows therefore hold five feature planes of the scaled fields
 xt = x0/0.1 - 1 and rt = xref/0.3: xt, rt, xt^2 - 1/3, xt rt, rt^2 - 1/3.
 
-Layers (this module only allocates torch device tensors and calls the C ABI):
+Layers (run by the library's network object, nmpc_net_*; this module only
+holds its handle, allocates torch device tensors and calls the C ABI):
 
     X  = features(x0, xref)                     rows: instance x actuator
     H1 = relu(X W1 + b1)                        window conv (32x32, stride 16)
@@ -140,129 +141,165 @@ def bf16_to_float(y):
     return a.view(np.float32)
 
 
+class nmpc_net_config(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("ns", ctypes.c_int32), ("lattice", ctypes.c_int32),
+                ("win", ctypes.c_int32), ("hidden", ctypes.c_int32), ("planes", ctypes.c_int32)]
+
+
+def _net_lib():
+    lib = _lib()
+    if not getattr(lib, "_netobj_typed", False):
+        i32, i64, f32, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_uint32
+        fp = ctypes.POINTER(ctypes.c_float)
+        lib.nmpc_net_create.argtypes = [ctypes.POINTER(nmpc_net_config), ctypes.c_uint64, i32,
+                                        ctypes.POINTER(_vp)]
+        lib.nmpc_net_forward.argtypes = [_vp, i32, _vp, _vp, _vp, _vp]
+        lib.nmpc_net_backward.argtypes = [_vp, i32, _vp, _vp, _vp, fp, _vp]
+        lib.nmpc_net_adam_step.argtypes = [_vp, f32, f32, f32, f32, f32, u32, _vp]
+        lib.nmpc_net_train_step.argtypes = [_vp, i32, _vp, _vp, _vp, f32, f32, u32, fp, _vp]
+        lib.nmpc_net_get.argtypes = [_vp, ctypes.c_char_p, _vp, i64]
+        lib.nmpc_net_set.argtypes = [_vp, ctypes.c_char_p, _vp, i64, i32, _vp]
+        lib.nmpc_net_num_params.argtypes = [_vp]
+        lib.nmpc_net_num_params.restype = i64
+        lib.nmpc_net_save.argtypes = [_vp, ctypes.c_char_p]
+        lib.nmpc_net_load.argtypes = [_vp, ctypes.c_char_p]
+        lib.nmpc_net_destroy.argtypes = [_vp]
+        lib.nmpc_net_destroy.restype = None
+        for f in ("nmpc_net_create", "nmpc_net_forward", "nmpc_net_backward", "nmpc_net_adam_step",
+                  "nmpc_net_train_step", "nmpc_net_get", "nmpc_net_set", "nmpc_net_save",
+                  "nmpc_net_load"):
+            getattr(lib, f).restype = ctypes.c_int
+        lib._netobj_typed = True
+    return lib
+
+
+PARAMS = ("W1", "b1", "W2", "b2", "W3", "b3", "W4", "b4", "Ws")
+
+
 class PatchNet:
-    """Patch encoder for an ns x ns grid with an L x L actuator lattice and N stages."""
+    """Patch encoder for an ns x ns grid with an L x L actuator lattice and N
+    stages: a handle of the library's network object (nmpc_net_*), which holds
+    the parameters, gradients, optimizer state and activations on the device
+    and runs every layer in the library's kernels."""
 
     PLANES = 5
     KSPLIT = 8      # K parts of the per-actuator map (few output tiles, long K)
 
     def __init__(self, N: int = 40, ns: int = 64, lattice: int = 4, win: int = 32,
-                 hidden: int = 512, seed: int = 0, device: str = "cuda"):
-        import torch
+                 hidden: int = 512, seed: int = 0, device: str = "cuda", max_count: int = 256):
         self.N, self.ns, self.L, self.win, self.H = N, ns, lattice, win, hidden
         self.m = lattice * lattice
         self.K0 = self.PLANES * win * win + self.m
         self.K0p = (self.K0 + 31) // 32 * 32
         self.device = device
         self.meta = {}
-        rng = np.random.default_rng(seed)
+        self.seed = seed
+        self.max_count = max_count
+        self.cfg = nmpc_net_config(N, ns, lattice, win, hidden, self.PLANES)
+        self.hd = self._create(max_count)
+        self.last_count = 0
 
-        def he(fan_in, shape, gain=2.0):
-            return rng.uniform(-1, 1, shape) * np.sqrt(3.0 * gain / fan_in)
+    def _create(self, max_count):
+        hd = _vp()
+        _ck(_net_lib().nmpc_net_create(ctypes.byref(self.cfg), self.seed, max_count,
+                                       ctypes.byref(hd)), "nmpc_net_create")
+        return hd
 
-        init = {
-            "W1": he(self.K0, (self.K0p, hidden)), "b1": np.zeros(hidden),
-            "W2": he(hidden, (hidden, hidden)), "b2": np.zeros(hidden),
-            "W3": he(hidden, (hidden, hidden)), "b3": np.zeros(hidden),
-            "W4": he(hidden, (hidden, N), gain=0.1), "b4": np.zeros(N),
-            "Ws": np.zeros((self.m, self.K0p, N)),
-        }
-        init["W1"][self.K0:] = 0.0
-        self.params: Dict[str, "torch.Tensor"] = {}
-        for k, v in init.items():
-            self.params[k] = torch.tensor(v, dtype=torch.float32, device=device)
-        self._bf = {k: to_bf16(v) for k, v in self.params.items() if k.startswith("W") and k != "Ws"}
-        self._opt = None
-        self.step = 0
+    def _ensure(self, count):
+        """Room for `count` instances (the object is rebuilt with the same parameters)."""
+        if count <= self.max_count:
+            return
+        st = self.state()
+        old = self.hd
+        self.max_count = count
+        self.hd = self._create(count)
+        _net_lib().nmpc_net_destroy(old)
+        self.load_state(st)
 
-    # ------------------------------------------------------------ buffers
+    def shape(self, name):
+        K0, H, N, m = self.K0p, self.H, self.N, self.m
+        return {"W1": (K0, H), "b1": (H,), "W2": (H, H), "b2": (H,), "W3": (H, H), "b3": (H,),
+                "W4": (H, N), "b4": (N if H > 0 else 0,), "Ws": (m, K0, N)}[name]
 
-    def _alloc(self, rows):
-        import torch
-        key = rows
-        if getattr(self, "_buf_rows", None) == key:
-            return self._buf
-        f = lambda *s: torch.empty(s, dtype=torch.float32, device=self.device)
-        h = lambda *s: torch.empty(s, dtype=torch.int16, device=self.device)
-        H, N = self.H, self.N
-        self._buf = {
-            "X": h(rows, self.K0p), "Xf": f(rows, self.K0p),
-            "H1": f(rows, H), "H1b": h(rows, H), "H2": f(rows, H), "H2b": h(rows, H),
-            "H3": f(rows, H), "H3b": h(rows, H), "Y": f(rows, N),
-            "dY": f(rows, N), "dYb": h(rows, N), "T": f(rows, N), "sse": f(rows),
-            "dH": f(rows, H), "dHb": h(rows, H), "work": f(self.KSPLIT * rows * N),
-        }
-        self._buf_rows = key
-        return self._buf
+    def num_params(self) -> int:
+        return int(_net_lib().nmpc_net_num_params(self.hd))
 
-    # ------------------------------------------------------------ forward
-
-    def forward_rows(self, x0, xref):
-        """Network output rows Y [count * m][N] (fp32) for device (x0, xref)."""
-        count = x0.shape[0]
-        rows = count * self.m
-        b = self._alloc(rows)
-        P, W = self.params, self._bf
-        H, N, K0, m = self.H, self.N, self.K0p, self.m
-        _ck(_lib().nmpc_net_features(_p(x0), _p(xref), count, self.ns, self.L, self.win,
-                                     self.PLANES, _p(b["Xf"]), _p(b["X"]), K0, _stream()),
-            "nmpc_net_features")
-        gemm(b["X"], W["W1"], rows, H, K0, C=b["H1"], bias=P["b1"], relu=True, Cb=b["H1b"])
-        gemm(b["H1b"], W["W2"], rows, H, H, C=b["H2"], bias=P["b2"], relu=True, Cb=b["H2b"])
-        gemm(b["H2b"], W["W3"], rows, H, H, C=b["H3"], bias=P["b3"], relu=True, Cb=b["H3b"])
-        gemm(b["H3b"], W["W4"], rows, N, H, C=b["Y"], bias=P["b4"])
-        # per-actuator map: group p takes rows p, p + m, ... (row stride m K0)
-        gemm_f32(b["Xf"], P["Ws"], count, N, K0, b["Y"], lda=m * K0, ldb=N, ldc=m * N,
-                 sa=K0, sb=K0 * N, sc=N, groups=m, beta=1.0, ksplit=self.KSPLIT, work=b["work"])
-        return b["Y"]
+    # ------------------------------------------------------------ passes
 
     def predict(self, x0, xref, out=None):
         """Predicted input trajectories u [count][N][m] (float64, device)."""
         import torch
         count = x0.shape[0]
-        Y = self.forward_rows(x0, xref)
+        self._ensure(count)
         u = out if out is not None else torch.empty((count, self.N, self.m), dtype=torch.float64,
-                                                     device=self.device)
-        _ck(_lib().nmpc_unpack_inputs(_p(Y), self.N, count, self.N, self.m, U_SCALE, _p(u),
-                                      _stream()), "nmpc_unpack_inputs")
+                                                     device=x0.device)
+        _ck(_net_lib().nmpc_net_forward(self.hd, count, _p(x0), _p(xref), _p(u), _stream()),
+            "nmpc_net_forward")
+        self.last_count = count
         return u
 
-    # ------------------------------------------------------------ backward
-
-    def loss_and_grads(self, x0, xref, u_target):
-        """Mean squared error of Y against u_target / U_SCALE and the parameter
-        gradients (fp32 tensors keyed like params)."""
-        import torch
+    def backward(self, x0, xref, u_target) -> float:
+        """Forward and backward pass; the gradients stay in the object
+        (``grad(name)``). Returns the mean squared error of the scaled inputs."""
         count = x0.shape[0]
-        rows = count * self.m
-        Y = self.forward_rows(x0, xref)
-        b = self._buf
-        H, N, K0, m = self.H, self.N, self.K0p, self.m
-        _ck(_lib().nmpc_pack_inputs(_p(u_target), count, N, m, 1.0 / U_SCALE, _p(b["T"]), N,
-                                    _stream()), "nmpc_pack_inputs")
-        scale = 2.0 / (rows * N)
-        _ck(_lib().nmpc_mse_grad(_p(Y), N, _p(b["T"]), N, rows, N, scale, _p(b["dY"]), _p(b["dYb"]),
-                                 N, _p(b["sse"]), _stream()), "nmpc_mse_grad")
-        g = {k: torch.empty_like(v) for k, v in self.params.items()}
-        W = self._bf
-        lib = _lib()
-        # output layer and the per-actuator map (fp32 dY)
-        gemm(b["H3b"], b["dYb"], H, N, rows, ta=1, lda=H, ldb=N, C=g["W4"])
-        gemm_f32(b["Xf"], b["dY"], K0, N, count, g["Ws"], ta=1, lda=m * K0, ldb=m * N, ldc=N,
-                 sa=K0, sb=N, sc=K0 * N, groups=m)
-        _ck(lib.nmpc_colsum(_p(b["dY"]), rows, N, N, _p(g["b4"]), _stream()), "nmpc_colsum")
-        # hidden layers: dH_l = (dH_{l+1} W_{l+1}^T) * relu'(H_l)
-        gemm(b["dYb"], W["W4"], rows, H, N, tb=1, ldb=N, C=b["dH"])
-        for l, (hin, hout) in ((3, ("H2b", "H3")), (2, ("H1b", "H2")), (1, ("X", "H1"))):
-            _ck(lib.nmpc_relu_grad(_p(b["dH"]), _p(b[hout]), _p(b["dHb"]), rows * H, _stream()),
-                "nmpc_relu_grad")
-            kin = K0 if hin == "X" else H
-            gemm(b[hin], b["dHb"], kin, H, rows, ta=1, lda=kin, ldb=H, C=g[f"W{l}"])
-            _ck(lib.nmpc_colsum(_p(b["dH"]), rows, H, H, _p(g[f"b{l}"]), _stream()), "nmpc_colsum")
-            if l > 1:
-                gemm(b["dHb"], W[f"W{l}"], rows, H, H, tb=1, ldb=H, C=b["dH"])
-        loss = float(b["sse"].sum().item()) / (rows * N)
-        return loss, g
+        self._ensure(count)
+        loss = ctypes.c_float()
+        _ck(_net_lib().nmpc_net_backward(self.hd, count, _p(x0), _p(xref), _p(u_target),
+                                         ctypes.byref(loss), _stream()), "nmpc_net_backward")
+        self.last_count = count
+        return float(loss.value)
+
+    def train_step(self, x0, xref, u_target, lr=1e-3, wd=0.0, frozen=()) -> float:
+        count = x0.shape[0]
+        self._ensure(count)
+        mask = sum(1 << PARAMS.index(k) for k in frozen)
+        loss = ctypes.c_float()
+        _ck(_net_lib().nmpc_net_train_step(self.hd, count, _p(x0), _p(xref), _p(u_target), lr, wd,
+                                           mask, ctypes.byref(loss), _stream()),
+            "nmpc_net_train_step")
+        self.last_count = count
+        return float(loss.value)
+
+    # ------------------------------------------------------------ access
+
+    def get(self, name, rows=None):
+        """Host copy of a parameter, a gradient ("g" + name) or an activation
+        of the last pass (rows of its instances; bf16 buffers as float32)."""
+        if name in PARAMS or (name[0] == "g" and name[1:] in PARAMS):
+            shape = self.shape(name if name in PARAMS else name[1:])
+            a = np.empty(shape, dtype=np.float32)
+        else:
+            rows = self.last_count * self.m if rows is None else rows
+            width = {"X": self.K0p, "Xf": self.K0p, "Y": self.N, "T": self.N, "dY": self.N,
+                     "dYb": self.N}.get(name, self.H)
+            if name.startswith("Wb"):
+                shape = self.shape("W" + name[2:])
+            else:
+                shape = (rows, width)
+            bf = name == "X" or name.startswith("Wb") or name.endswith("b")
+            a = np.empty(shape, dtype=np.uint16 if bf else np.float32)
+        if a.size:
+            _ck(_net_lib().nmpc_net_get(self.hd, name.encode(), a.ctypes.data, a.size),
+                "nmpc_net_get")
+        if a.dtype == np.uint16:
+            a = (a.astype(np.uint32) << 16).view(np.float32)
+        return a
+
+    def set_param(self, name, value):
+        """Replace a parameter from a host array or a float32 device tensor."""
+        import torch
+        n = int(np.prod(self.shape(name)))
+        if isinstance(value, torch.Tensor) and value.is_cuda:
+            v = value.to(torch.float32).contiguous()
+            _ck(_net_lib().nmpc_net_set(self.hd, name.encode(), _p(v), n, 1, _stream()),
+                "nmpc_net_set")
+        else:
+            v = np.ascontiguousarray(value, dtype=np.float32)
+            _ck(_net_lib().nmpc_net_set(self.hd, name.encode(), v.ctypes.data, n, 0, _stream()),
+                "nmpc_net_set")
+
+    def grad(self, name):
+        return self.get("g" + name)
 
     # ------------------------------------------------------------ fitting
 
@@ -279,77 +316,80 @@ class PatchNet:
         f64 = dict(dtype=torch.float64, device=self.device)
         G = torch.zeros((m, K0, K0), **f64)
         R = torch.zeros((m, K0, N), **f64)
+        Xf = torch.empty((batch * m, K0), dtype=torch.float32, device=self.device)
+        T = torch.empty((batch * m, N), dtype=torch.float32, device=self.device)
         for k in range(0, count, batch):
             c = min(batch, count - k)
-            b = self._alloc(c * m)
             _ck(_lib().nmpc_net_features(_p(x0[k:k + c]), _p(xref[k:k + c]), c, self.ns, self.L,
-                                         self.win, self.PLANES, _p(b["Xf"]), None, K0, _stream()),
+                                         self.win, self.PLANES, _p(Xf), None, K0, _stream()),
                 "nmpc_net_features")
-            _ck(_lib().nmpc_pack_inputs(_p(u[k:k + c]), c, N, m, 1.0 / U_SCALE, _p(b["T"]), N,
+            _ck(_lib().nmpc_pack_inputs(_p(u[k:k + c]), c, N, m, 1.0 / U_SCALE, _p(T), N,
                                         _stream()), "nmpc_pack_inputs")
             # group p: rows p, p + m, ... of the batch
-            gemm_f32_acc64(b["Xf"], b["Xf"], K0, K0, c, G, ta=1, lda=m * K0, ldb=m * K0, ldc=K0,
+            gemm_f32_acc64(Xf, Xf, K0, K0, c, G, ta=1, lda=m * K0, ldb=m * K0, ldc=K0,
                            sa=K0, sb=K0, sc=K0 * K0, groups=m, beta=1.0)
-            gemm_f32_acc64(b["Xf"], b["T"], K0, N, c, R, ta=1, lda=m * K0, ldb=m * N, ldc=N,
+            gemm_f32_acc64(Xf, T, K0, N, c, R, ta=1, lda=m * K0, ldb=m * N, ldc=N,
                            sa=K0, sb=N, sc=K0 * N, groups=m, beta=1.0)
         X = torch.empty_like(G)
         ls_prepare(G, X, K0, m, ridge_rel)
-        T = torch.empty_like(G)
+        Tm = torch.empty_like(G)
         Xn = torch.empty_like(G)
         sq = dict(lda=K0, ldb=K0, ldc=K0, sa=K0 * K0, sb=K0 * K0, sc=K0 * K0, groups=m)
         for _ in range(iters):
-            gemm_f64(G, X, K0, K0, K0, T, **sq)                            # T = G X
-            gemm_f64(X, T, K0, K0, K0, Xn, alpha=-1.0, beta=2.0, Cin=X, **sq)   # 2X - X G X
+            gemm_f64(G, X, K0, K0, K0, Tm, **sq)                            # T = G X
+            gemm_f64(X, Tm, K0, K0, K0, Xn, alpha=-1.0, beta=2.0, Cin=X, **sq)   # 2X - X G X
             X, Xn = Xn, X
-        gemm_f64(G, X, K0, K0, K0, T, **sq)
+        gemm_f64(G, X, K0, K0, K0, Tm, **sq)
         W = torch.empty((m, K0, N), **f64)
         gemm_f64(X, R, K0, N, K0, W, lda=K0, ldb=N, ldc=N, sa=K0 * K0, sb=K0 * N, sc=K0 * N,
                  groups=m)
-        self.params["Ws"].copy_(W)
+        self.set_param("Ws", W)
         eye = torch.eye(K0, **f64)
-        return [float(torch.linalg.matrix_norm(eye - T[p])) for p in range(m)]
-
-    def adam_step(self, grads, lr=1e-3, wd=0.0, b1=0.9, b2=0.999, eps=1e-8, frozen=()):
-        import torch
-        if self._opt is None:
-            self._opt = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in self.params.items()}
-        self.step += 1
-        for k, w in self.params.items():
-            if k in frozen:
-                continue
-            m, v = self._opt[k]
-            _ck(_lib().nmpc_adam(_p(w), _p(grads[k]), _p(m), _p(v), _p(self._bf.get(k)), w.numel(),
-                                 lr, b1, b2, eps, wd if k.startswith("W") else 0.0, self.step,
-                                 _stream()), "nmpc_adam")
+        return [float(torch.linalg.matrix_norm(eye - Tm[p])) for p in range(m)]
 
     # ------------------------------------------------------------ state
 
     def state(self) -> Dict[str, np.ndarray]:
-        return {k: v.detach().cpu().numpy() for k, v in self.params.items()}
+        return {k: self.get(k) for k in PARAMS}
 
     def load_state(self, st: Dict[str, np.ndarray]):
-        import torch
-        for k in self.params:
-            self.params[k] = torch.tensor(np.asarray(st[k], dtype=np.float32), device=self.device)
-        self._bf = {k: to_bf16(v) for k, v in self.params.items() if k.startswith("W") and k != "Ws"}
-        self._opt = None
+        for k in PARAMS:
+            if int(np.prod(self.shape(k))):
+                self.set_param(k, np.asarray(st[k], dtype=np.float32))
 
     def save(self, path: str, meta: Optional[dict] = None):
         """Weights (fp32) + JSON header with the architecture and training facts."""
         header = {"format": "nmpc-patchnet-v2", "N": self.N, "ns": self.ns, "lattice": self.L,
-                  "win": self.win, "hidden": self.H, "step": self.step, "meta": meta or {}}
+                  "win": self.win, "hidden": self.H, "meta": meta or {}}
         np.savez_compressed(path, header=np.frombuffer(json.dumps(header).encode(), np.uint8),
                             **self.state())
 
+    def save_bin(self, path: str):
+        """The library's own weight file (nmpc_net_save)."""
+        _ck(_net_lib().nmpc_net_save(self.hd, path.encode()), "nmpc_net_save")
+
+    def load_bin(self, path: str):
+        _ck(_net_lib().nmpc_net_load(self.hd, path.encode()), "nmpc_net_load")
+
     @classmethod
-    def load(cls, path: str, device: str = "cuda") -> "PatchNet":
+    def load(cls, path: str, device: str = "cuda", max_count: int = 256) -> "PatchNet":
         z = np.load(path, allow_pickle=False)
         header = json.loads(bytes(z["header"]).decode())
         if header.get("format") != "nmpc-patchnet-v2":
             raise ValueError(f"{path}: not a patch-net checkpoint")
         net = cls(N=header["N"], ns=header["ns"], lattice=header["lattice"], win=header["win"],
-                  hidden=header["hidden"], device=device)
-        net.load_state({k: z[k] for k in net.params})
-        net.step = header["step"]
+                  hidden=header["hidden"], device=device, max_count=max_count)
+        net.load_state({k: z[k] for k in PARAMS})
         net.meta = header["meta"]
         return net
+
+    def close(self):
+        if getattr(self, "hd", None):
+            _net_lib().nmpc_net_destroy(self.hd)
+            self.hd = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -172,3 +172,35 @@ def test_ragged_box_arguments_checked():
     with pytest.raises(nm.NmpcError) as e:
         nm.nmpc_ragged_create([bad], nm.nmpc_default_options(), 4)
     assert e.value.code == nm.NMPC_E_ARG
+
+
+def test_network_object_arguments_checked():
+    """nmpc_net_create rejects an inconsistent configuration (lattice not
+    dividing the grid, a window narrower than an actuator cell or of the wrong
+    parity, a feature plane count other than 2 or 5, a negative hidden width,
+    no instances) before any device call, and leaves *out NULL; every other
+    entry point rejects a NULL network."""
+    from paper_2004_02484_amd import warmstart as ws
+    lib = ws._net_lib()
+    good = dict(N=40, ns=64, lattice=4, win=32, hidden=64, planes=5)
+    bad = [dict(ns=63), dict(win=8), dict(win=31), dict(planes=3), dict(hidden=-1), dict(N=0),
+           dict(lattice=0)]
+    for b in bad:
+        cfg = ws.nmpc_net_config(**{**good, **b})
+        out = ctypes.c_void_p(1234)
+        assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 4, ctypes.byref(out)) == nm.NMPC_E_ARG, b
+        assert out.value is None
+    cfg = ws.nmpc_net_config(**good)
+    out = ctypes.c_void_p()
+    assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 0, ctypes.byref(out)) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_create(None, 0, 4, ctypes.byref(out)) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 4, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_forward(None, 1, None, None, None, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_backward(None, 1, None, None, None, None, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_get(None, b"W1", None, 0) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_set(None, b"W1", None, 0, 0, None) == nm.NMPC_E_ARG
+    assert lib.nmpc_net_save(None, b"/nonexistent") == nm.NMPC_E_ARG
+    assert lib.nmpc_net_load(None, b"/nonexistent") == nm.NMPC_E_ARG
+    assert lib.nmpc_net_num_params(None) == 0
+    lib.nmpc_net_destroy(None)

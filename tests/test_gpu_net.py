@@ -120,7 +120,7 @@ def test_linear_fit_matches_ridge_solution(ws):
     du = torch.tensor(u, device="cuda")
     res = net.fit_linear(dx0, dxr, du, batch=256, ridge_rel=1e-6, iters=45)
     assert max(res) < 1e-3
-    Ws = net.params["Ws"].cpu().numpy().astype(np.float64)
+    Ws = net.get("Ws").astype(np.float64)
     X = net_ref.features(x0, xr, 16, 2, 12, 5, net.K0p).astype(np.float32).astype(np.float64)
     T = (u / ws.U_SCALE).transpose(0, 2, 1).reshape(-1, 5)
     for p in range(4):
@@ -160,20 +160,25 @@ def test_features_match_reference(ws):
     np.testing.assert_array_equal(ws.bf16_to_float(Xb2), want2)
 
 
-def test_forward_and_gradients_match_reference(ws):
+def _net_case(ws, hidden=64, seed=3, seeds=(7, 8, 9)):
     import torch
     P = make_problem("c1")
-    x0, xr = make_batch(P, [7, 8, 9])
-    net = ws.PatchNet(hidden=64, seed=3)
+    x0, xr = make_batch(P, list(seeds))
+    net = ws.PatchNet(hidden=hidden, seed=seed, max_count=8)
     rng = np.random.default_rng(5)
-    net.params["Ws"] = torch.tensor(rng.normal(size=(16, net.K0p, 40)).astype(np.float32) * 0.02,
-                                    device="cuda")
-    net.load_state(net.state())
-    u_t = rng.normal(size=(3, 40, 16))
-    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
-    loss, g = net.loss_and_grads(dx0, dxr, torch.tensor(u_t, device="cuda"))
-    Y = net._buf["Y"].cpu().numpy().astype(np.float64)
-    torch.cuda.synchronize()
+    net.set_param("Ws", rng.normal(size=net.shape("Ws")).astype(np.float32) * 0.02)
+    u_t = rng.normal(size=(len(seeds), 40, 16))
+    dev = [torch.tensor(a, device="cuda") for a in (x0, xr, u_t)]
+    return net, x0, xr, u_t, dev
+
+
+def test_forward_and_gradients_match_reference(ws):
+    """Whole-network output, loss and gradients against the FP64 reference
+    network on the GPU's parameters (bf16 rounding of the layer operands is
+    the only model difference, so the bar is a few 1e-3 relative)."""
+    net, x0, xr, u_t, (dx0, dxr, du) = _net_case(ws)
+    loss = net.backward(dx0, dxr, du)
+    Y = net.get("Y").astype(np.float64)
     p = {k: v.astype(np.float64) for k, v in net.state().items()}
     for k in list(p):
         if k.startswith("W") and k != "Ws":
@@ -183,18 +188,160 @@ def test_forward_and_gradients_match_reference(ws):
     Yr, cache = net_ref.forward(p, net_ref.bf16_round(X), X)
     T = (u_t / ws.U_SCALE).transpose(0, 2, 1).reshape(-1, 40)
     gr = net_ref.backward(p, cache, Yr, T)
-    # bf16 activations between layers: a few 1e-3 relative
     assert np.linalg.norm(Y - Yr) <= 2e-2 * np.linalg.norm(Yr)
     assert abs(loss - net_ref.mse(Yr, T)) <= 2e-2 * net_ref.mse(Yr, T)
-    for k, v in gr.items():
-        got = g[k].cpu().numpy().astype(np.float64)
-        assert np.linalg.norm(got - v) <= 5e-2 * np.linalg.norm(v) + 1e-12, k
+    # the bf16 copies of activations and gradients (2^-9 relative each) and the
+    # ReLU masks they flip near zero leave a few percent norm-wise two layers
+    # down; each layer alone is held to the fp32 accumulation bound element by
+    # element in test_network_layers_elementwise
+    rel = {k: np.linalg.norm(net.grad(k).astype(np.float64) - v) / (np.linalg.norm(v) + 1e-30)
+           for k, v in gr.items()}
+    print({k: f"{r:.1e}" for k, r in rel.items()})
+    assert all(r <= 1e-1 for r in rel.values()), rel
+    assert all(rel[k] <= 2e-2 for k in ("W4", "b4", "Ws")), rel
     # the fp32 map alone (hidden path switched off): about fp32 accuracy
     p0 = dict(p); p0["W4"] = np.zeros_like(p["W4"]); p0["b4"] = np.zeros_like(p["b4"])
-    net.params["W4"].zero_(); net.params["b4"].zero_(); net.load_state(net.state())
-    Y0 = net.forward_rows(dx0, dxr).cpu().numpy().astype(np.float64)
+    net.set_param("W4", np.zeros(net.shape("W4"), np.float32))
+    net.set_param("b4", np.zeros(net.shape("b4"), np.float32))
+    u0 = net.predict(dx0, dxr).cpu().numpy()
     Yr0, _ = net_ref.forward(p0, net_ref.bf16_round(X), X)
-    assert np.abs(Y0 - Yr0).max() <= 1e-5 * np.abs(Yr0).max()
+    want = ws.U_SCALE * Yr0.reshape(3, 16, 40).transpose(0, 2, 1)
+    assert np.abs(u0 - want).max() <= 1e-5 * np.abs(want).max()
+
+
+U24 = 2.0 ** -24      # unit roundoff of fp32
+
+
+def _dot_bound(A, W, K, extra=0.0):
+    """Elementwise bound of an fp32-accumulated product A W (+ a term of size
+    extra): any summation order of K products, each exact (bf16 operands) or
+    rounded once (fp32 operands), stays within (K + 2) u sum_k |a_k| |w_k|."""
+    return (K + 2) * U24 * (np.abs(A) @ np.abs(W) + np.abs(extra)) + 1e-30
+
+
+def test_network_layers_elementwise(ws):
+    """Each layer of the GPU pass against its own definition evaluated in
+    float64 on the GPU's inputs to that layer: every element within the fp32
+    accumulation bound, the bf16 copies equal to the nearest-even rounding of
+    the fp32 values, the elementwise steps (dY, the ReLU mask, the bias sums
+    in their fixed order) bit-exact."""
+    net, x0, xr, u_t, (dx0, dxr, du) = _net_case(ws)
+    loss = net.backward(dx0, dxr, du)
+    rows, m, N, H, K0 = 3 * 16, 16, 40, 64, net.K0p
+    f = lambda name: net.get(name, rows=rows).astype(np.float64)
+    Xf, X = f("Xf"), f("X")
+    # features: fp32 rounding of the fp64 values, bf16 copy of that
+    want = net_ref.features(x0, xr, 64, 4, 32, 5, K0)
+    np.testing.assert_allclose(Xf, want.astype(np.float32).astype(np.float64), rtol=2**-23, atol=0)
+    np.testing.assert_array_equal(X, net_ref.bf16_round(Xf))
+    W = {k: net.get(k).astype(np.float64) for k in ws.PARAMS}
+    Wb = {}
+    for l in (1, 2, 3, 4):
+        Wb[l] = net.get(f"Wb{l}").astype(np.float64)
+        np.testing.assert_array_equal(Wb[l], net_ref.bf16_round(W[f"W{l}"]))
+    # hidden layers: H_l = relu(A_l Wb_l + b_l), A_1 = X, A_l = bf16 copy of H_{l-1}
+    A = X
+    Hs, Ab = [], [X]
+    for l in (1, 2, 3):
+        Z = A @ Wb[l] + W[f"b{l}"]
+        Hl, Hlb = f(f"H{l}"), f(f"H{l}b")
+        kin = K0 if l == 1 else H
+        assert np.all(np.abs(Hl - np.maximum(Z, 0)) <= _dot_bound(A, Wb[l], kin, W[f"b{l}"])), l
+        np.testing.assert_array_equal(Hlb, net_ref.bf16_round(Hl))
+        Hs.append(Hl)
+        A = Hlb
+        Ab.append(Hlb)
+    # output: Y = H3b Wb4 + b4 + Xf Ws[p]
+    Y = f("Y")
+    Yw = A @ Wb[4] + W["b4"] + net_ref.skip(W["Ws"], Xf)
+    # two accumulations (the bf16 layer, then the map added onto it)
+    bound = (H + K0 + 4) * U24 * (np.abs(A) @ np.abs(Wb[4]) + np.abs(W["b4"]) +
+                                  net_ref.skip(np.abs(W["Ws"]), np.abs(Xf)))
+    assert np.all(np.abs(Y - Yw) <= bound)
+    # targets, the error gradient and the loss
+    T = f("T")
+    np.testing.assert_array_equal(T, (u_t * 0.25).astype(np.float32).transpose(0, 2, 1)
+                                  .reshape(rows, N).astype(np.float64))
+    scale = np.float32(2.0) / (np.float32(rows) * np.float32(N))
+    dY32 = scale * (net.get("Y", rows=rows) - net.get("T", rows=rows))
+    dY = f("dY")
+    np.testing.assert_array_equal(dY, dY32.astype(np.float64))
+    dYb = f("dYb")
+    np.testing.assert_array_equal(dYb, net_ref.bf16_round(dY))
+    assert abs(loss - np.mean((Y - T) ** 2)) <= 1e-5 * np.mean((Y - T) ** 2)
+    # gradients of the output layer and of the map
+    colsum = lambda D: np.cumsum(D.astype(np.float32), axis=0, dtype=np.float32)[-1].astype(np.float64)
+    g = {k: net.grad(k).astype(np.float64) for k in ws.PARAMS}
+    assert np.all(np.abs(g["W4"] - A.T @ dYb) <= _dot_bound(A.T, dYb, rows))
+    np.testing.assert_array_equal(g["b4"], colsum(dY))
+    for p in range(m):
+        gw = Xf[p::m].T @ dY[p::m]
+        assert np.all(np.abs(g["Ws"][p] - gw) <= _dot_bound(Xf[p::m].T, dY[p::m], 3)), p
+    # back through the hidden layers: dH_l = (dH_{l+1}b Wb_{l+1}^T) masked by H_l > 0
+    up, upb = dY, dYb
+    for l in (3, 2, 1):
+        pre = upb @ Wb[l + 1].T
+        mask = Hs[l - 1] > 0
+        dH, dHb = f(f"dH{l}"), f(f"dH{l}b")
+        kin = N if l == 3 else H
+        assert np.all(np.abs(dH - pre * mask) <= _dot_bound(upb, np.abs(Wb[l + 1].T), kin) * mask), l
+        assert np.all(dH[~mask] == 0.0), l
+        np.testing.assert_array_equal(dHb, net_ref.bf16_round(dH))
+        assert np.all(np.abs(g[f"W{l}"] - Ab[l - 1].T @ dHb) <= _dot_bound(Ab[l - 1].T, dHb, rows)), l
+        np.testing.assert_array_equal(g[f"b{l}"], colsum(dH))
+        up, upb = dH, dHb
+
+
+def test_adam_step_elementwise(ws):
+    """The first Adam step from zero moments moves each unfrozen weight by
+    lr g / (|g| + eps) (bias-corrected moments) after the decoupled decay;
+    frozen parameters keep every bit."""
+    net, x0, xr, u_t, (dx0, dxr, du) = _net_case(ws, hidden=32)
+    net.backward(dx0, dxr, du)
+    before = net.state()
+    g = {k: net.grad(k).astype(np.float64) for k in ws.PARAMS}
+    lr, wd = 1e-3, 1e-2
+    rc = ws._net_lib().nmpc_net_adam_step(net.hd, lr, 0.9, 0.999, 1e-8, wd,
+                                          1 << ws.PARAMS.index("W2"), ws._stream())
+    assert rc == 0
+    after = net.state()
+    np.testing.assert_array_equal(after["W2"], before["W2"])
+    for k in ws.PARAMS:
+        if k == "W2" or not before[k].size:
+            continue
+        w0 = before[k].astype(np.float64)
+        decay = wd if k.startswith("W") and k != "Ws" else 0.0
+        want = w0 * (1 - lr * decay) - lr * g[k] / (np.abs(g[k]) + 1e-8)
+        # fp32 evaluation of the same few operations
+        tol = 16 * 2.0 ** -24 * (np.abs(w0) + lr) + lr * (np.abs(g[k]) < 1e-12)
+        assert np.all(np.abs(after[k] - want) <= tol), k
+    # the bf16 copies follow the updated weights
+    np.testing.assert_array_equal(net.get("Wb1").astype(np.float64),
+                                  net_ref.bf16_round(after["W1"].astype(np.float64)))
+
+
+def test_weight_file_round_trip(ws, tmp_path):
+    """nmpc_net_save / nmpc_net_load: a network of another seed takes every bit
+    of the parameters and predicts the same inputs; a file of another
+    configuration is refused."""
+    net, x0, xr, u_t, (dx0, dxr, du) = _net_case(ws, hidden=32)
+    path = str(tmp_path / "w.bin")
+    net.save_bin(path)
+    other = ws.PatchNet(hidden=32, seed=11, max_count=8)
+    assert not np.array_equal(other.get("W1"), net.get("W1"))
+    other.load_bin(path)
+    for k in ws.PARAMS:
+        np.testing.assert_array_equal(other.get(k), net.get(k))
+    np.testing.assert_array_equal(other.predict(dx0, dxr).cpu().numpy(),
+                                  net.predict(dx0, dxr).cpu().numpy())
+    wrong = ws.PatchNet(hidden=16, seed=0, max_count=8)
+    with pytest.raises(RuntimeError):
+        wrong.load_bin(path)
+    # the npz checkpoint holds the same values
+    net.save(str(tmp_path / "w.npz"))
+    back = ws.PatchNet.load(str(tmp_path / "w.npz"), max_count=8)
+    for k in ws.PARAMS:
+        np.testing.assert_array_equal(back.get(k), net.get(k))
 
 
 def test_training_steps_reduce_the_loss(ws):
@@ -203,12 +350,11 @@ def test_training_steps_reduce_the_loss(ws):
     x0, xr = make_batch(P, range(8))
     rng = np.random.default_rng(1)
     u_t = torch.tensor(rng.normal(size=(8, 40, 16)) * 2.0, device="cuda")
-    net = ws.PatchNet(hidden=64, seed=0)
+    net = ws.PatchNet(hidden=64, seed=0, max_count=8)
     dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
-    first, _ = net.loss_and_grads(dx0, dxr, u_t)
+    first = net.backward(dx0, dxr, u_t)
     for _ in range(60):
-        loss, g = net.loss_and_grads(dx0, dxr, u_t)
-        net.adam_step(g, lr=2e-3)
+        loss = net.train_step(dx0, dxr, u_t, lr=2e-3)
     assert loss < 0.2 * first
 
 
