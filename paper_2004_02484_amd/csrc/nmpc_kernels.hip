@@ -49,8 +49,10 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             d = decide<PREC>(a, c, b, i, k, N, (long long)b * N);
         }
         if (d.work) {
-            load_tables<CX, RY, LX, LY>(c, a.gx, a.gy, a.P.nsx, a.P.nsy);
             StageLoc v = jacobi_loc(d.j & 1);
+            v.tgx = a.gx;   // tables loaded after the stage's loads are issued
+            v.tgy = a.gy;
+            v.defer_norms = true;
             v.so = (long long)b * N * n;
             v.uo = (long long)b * N * M;
             v.xo = (long long)b * n;
@@ -337,12 +339,11 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
                         const double d = -1.0 - h * kk * P.c0 + h * kp * Lx[t][q];
                         ml = umax64(ml, abits(cc[t][q] - d * lam[t][q] - nb[t][q]));
                     }
-            bt_reduce<double, CX, RY, LX, LY>(lam, c, M);
+            const double bt = bt_reduce<double, CX, RY, LX, LY>(lam, c, M);
             if (c.tid < M) {   // K^u_i = h (r u_i + grad Phi(u_i) + B^T lam_i)
                 const double u = a.U[0][unit * M + c.tid];
                 double bg = 0.0;
                 if (P.tau > 0.0) bg = -P.tau / (u - P.ulo) + P.tau / (P.uhi - u);
-                const double bt = lds_ptr<double>(c, c.off.red)[c.tid];
                 mu = abits(h * (P.r * u + bg + bt));
             }
             ml = wave_max64(ml, c.lane);

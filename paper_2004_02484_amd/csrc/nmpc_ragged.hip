@@ -62,8 +62,10 @@ __global__ void __launch_bounds__(kWave * WB, 1) k_iterate_rg(const IterArgs a, 
         d = decide<PREC>(a, c, b, i, k, N, us);
     }
     if (!d.work) return;
-    load_tables<CX, RY, kRgLx, kRgLy>(c, cl.gx, cl.gy, cl.P.nsx, cl.P.nsy);
     StageLoc v = jacobi_loc(d.j & 1);
+    v.tgx = cl.gx;   // tables loaded after the stage's loads are issued
+    v.tgy = cl.gy;
+    v.defer_norms = true;
     v.so = r.soff[b];
     v.uo = r.uoff[b];
     v.xo = r.xoff[b];

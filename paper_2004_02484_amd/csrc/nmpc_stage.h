@@ -350,13 +350,15 @@ __device__ __forceinline__ void b_apply(const VS *vs, const Ctx &c, V (&o)[RY][C
     }
 }
 
-// (B^T y)_j for j < M, left in red[j] (double) by thread j, which is the only
-// thread that reads it before the next barrier (with one tile row, where the
-// stencils take no barrier, all threads are synchronized on return). Per lane: column partials t_b = sum_t gy[b][iy_t] y_t, then the
-// products with gx are formed inside the first halving step of the
-// cross-lane reduction, then the waves' partials are summed.
+// (B^T y)_j for j < M, returned to lane j of every wave (each wave sums the
+// waves' partials itself, in wave order, so all waves hold the same values).
+// The partials stay in LDS until the next barrier; with one tile row, where
+// the stencils take no barrier, all threads are synchronized on return. Per
+// lane: column partials t_b = sum_t gy[b][iy_t] y_t, then the products with
+// gx are formed inside the first halving step of the cross-lane reduction,
+// then the waves' partials are summed.
 template <typename V, int CX, int RY, int LX, int LY>
-__device__ __forceinline__ void bt_reduce(const V (&y)[RY][CX], Ctx &c, int M)
+__device__ __forceinline__ V bt_reduce(const V (&y)[RY][CX], Ctx &c, int M)
 {
     constexpr int MP = Pow2<LX * LY>::v;
     constexpr int MM = LX * LY;
@@ -397,12 +399,32 @@ __device__ __forceinline__ void bt_reduce(const V (&y)[RY][CX], Ctx &c, int M)
     constexpr int SH = 6 - Pow2<MP>::lg;
     if ((c.lane & ((1 << SH) - 1)) == 0) red[c.w * kMaxM + (c.lane >> SH)] = double(e);
     __syncthreads();
-    if (c.tid < M) {
-        V s = V(0);
-        for (int ww = 0; ww < c.W; ++ww) s += V(red[ww * kMaxM + c.tid]);
-        red[c.tid] = double(s);   // only thread tid touches column tid
-    }
+    V s = V(0);
+    if (c.lane < M)
+        for (int ww = 0; ww < c.W; ++ww) s += V(red[ww * kMaxM + c.lane]);
     if (c.Gv == 1) __syncthreads();
+    return s;
+}
+
+// The M values v (lane j of the wave holds element j) to every lane, as
+// wave-uniform values (v_readlane into scalar registers).
+template <typename T, int M>
+__device__ __forceinline__ void wave_bcast(double v, T (&o)[M])
+{
+    if constexpr (sizeof(T) == 4) {
+        const int b = __float_as_int(float(v));
+#pragma unroll
+        for (int j = 0; j < M; ++j) o[j] = __int_as_float(__builtin_amdgcn_readlane(b, j));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const unsigned l = (unsigned)__builtin_amdgcn_readlane(lo, j);
+            const unsigned hh = (unsigned)__builtin_amdgcn_readlane(hi, j);
+            o[j] = T(__longlong_as_double((long long)(((unsigned long long)hh << 32) | l)));
+        }
+    }
 }
 
 // ----------------------------------------------------------- lower layer
@@ -507,30 +529,40 @@ template <int PREC>
 __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, int Nb,
                            long long rbase)
 {
+    // up to 64 stages: the stage norms of all three residual slots are
+    // requested together with the state, so the decision waits for memory once
+    const bool one_row = Nb <= kWave;
+    unsigned long long r3[3] = {0, 0, 0}, p3[3] = {0, 0, 0};
+    if (one_row && c.lane < Nb) {
+#pragma unroll
+        for (int sl = 0; sl < 3; ++sl) {
+            r3[sl] = a.rst[(size_t)sl * a.rslot + rbase + c.lane];
+            p3[sl] = a.pst[(size_t)sl * a.rslot + rbase + c.lane];
+        }
+    }
     const InstState s = a.st[(k & 1) * a.B + b];
     InstState ns = s;
     Decision d{false, 0, 0, false, false};
     int fin = -1;
     double rs = 0.0, rp = 0.0;
     if (s.status == kActive && s.e > 0) {
-        // max over the stages' residuals of the previous evaluation (wave 0),
-        // broadcast through LDS; NaN bit patterns order above every finite value
-        unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
-        if (c.w == 0) {
-            const size_t base = (size_t)((s.e - 1) % 3) * a.rslot + rbase;
-            unsigned long long ms = 0, mp = 0;
+        // max over the stages' residuals of the previous evaluation, taken by
+        // every wave itself (no LDS and no barrier); NaN bit patterns order
+        // above every finite value
+        const int sl = (s.e - 1) % 3;
+        unsigned long long ms = 0, mp = 0;
+        if (one_row) {
+            ms = sl == 0 ? r3[0] : sl == 1 ? r3[1] : r3[2];
+            mp = sl == 0 ? p3[0] : sl == 1 ? p3[1] : p3[2];
+        } else {
+            const size_t base = (size_t)sl * a.rslot + rbase;
             for (int t = c.lane; t < Nb; t += kWave) {
                 ms = umax64(ms, a.rst[base + t]);
                 mp = umax64(mp, a.pst[base + t]);
             }
-            ms = wave_max64(ms, c.lane);
-            mp = wave_max64(mp, c.lane);
-            if (c.lane == 0) { nrm[0] = ms; nrm[1] = mp; }
         }
-        __syncthreads();
-        rs = bits2d(nrm[0]);
-        rp = bits2d(nrm[1]);
-        __syncthreads();
+        rs = bits2d(wave_max64(ms, c.lane));
+        rp = bits2d(wave_max64(mp, c.lane));
     }
     const double rt = a.res_paper ? rp : rs;   // the norm the test is on
     if (s.status == kActive) {
@@ -613,6 +645,10 @@ struct StageLoc {
     long long box_at;              // >= 0: index into a.apart for this stage's step limit
     long long du_at;               // >= 0: instance whose FP64 correction step this is
                                    // (max |du|, max |u_new| into a.du)
+    const double *tgx, *tgy;       // non-null: load the input tables after issuing the
+                                   // stage's loads (their first reader follows a barrier)
+    bool defer_norms;              // one stage per workgroup: combine the waves' norm
+                                   // partials after the lower layer's first barrier
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
     int pnb, pni;                  // stage pni of buffer pnb is prefetched once this stage
                                    // has read its own (pnb < 0: none)
@@ -664,6 +700,31 @@ __device__ __forceinline__ float recip<float>(double d) { return __builtin_amdgc
 template <>
 __device__ __forceinline__ double recip<double>(double d) { return 1.0 / d; }
 
+// The separable input factors gx [LX][nsx], gy [LY][nsy] into LDS (double and
+// float copies), laid out for the tile: gx by padded column, gy by tile row.
+template <int CX, int RY, int LX, int LY>
+__device__ __forceinline__ void load_tables(Ctx &c, const double *gxs, const double *gys, int nsx,
+                                            int nsy, bool sync = true)
+{
+    double *gx = lds_ptr<double>(c, c.off.gx);
+    double *gy = lds_ptr<double>(c, c.off.gy);
+    float *gxf = lds_ptr<float>(c, c.off.gxf);
+    float *gyf = lds_ptr<float>(c, c.off.gyf);
+    for (int t = c.tid; t < LX * 16 * CX; t += c.W * kWave) {
+        const int aq = t >> 4, aa = aq / CX, ix = (t & 15) * CX + aq % CX;
+        const double v = ix < nsx ? gxs[aa * nsx + ix] : 0.0;
+        gx[t] = v;
+        gxf[t] = float(v);
+    }
+    for (int t = c.tid; t < LY * c.GT * RY; t += c.W * kWave) {
+        const int bb = t / (c.GT * RY), iy = t % (c.GT * RY);
+        const double v = iy < nsy ? gys[bb * nsy + iy] : 0.0;
+        gy[t] = v;
+        gyf[t] = float(v);
+    }
+    if (sync) __syncthreads();
+}
+
 // acc (thread 0 only): running bit-pattern max of (r_scaled, r_paper) over
 // the stages processed with res_at == -1.
 template <typename T, int CX, int RY, int LX, int LY>
@@ -674,9 +735,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     constexpr int M = LX * LY;
     const int n = P.n;
     double *uvec = lds_ptr<double>(c, c.off.uvec);
-    double *v3 = lds_ptr<double>(c, c.off.v3);
     double *kun = lds_ptr<double>(c, c.off.kun);
-    double *red = lds_ptr<double>(c, c.off.red);
     unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
 
     const StageLoc &sv = v;
@@ -707,6 +766,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     StageCoef<T, CX, RY> K;
     T b1[RY][CX], b2[RY][CX];
     unsigned long long mx = 0, ml = 0;
+    double btl;   // (B^T lambda_i)_j in lane j < M
     {
         double xc[RY][CX], lc[RY][CX], Lx[RY][CX];
 #pragma unroll
@@ -724,7 +784,10 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 }
             }
         if (c.tid < M) uvec[c.tid] = a.U[v.src][v.uo + (size_t)v.i * M + c.tid];
+        if (v.tgx) load_tables<CX, RY, LX, LY>(c, v.tgx, v.tgy, P.nsx, P.nsy, false);
+        __builtin_amdgcn_sched_barrier(0);
         nbsum<double, CX, RY>(xc, Lx, c);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -735,7 +798,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             for (int t = 0; t < RY; ++t)
 #pragma unroll
                 for (int q = 0; q < CX; ++q) g[t][q] = P.k0 * (1.0 + P.k1 * xc[t][q]) * lc[t][q];
+            __builtin_amdgcn_sched_barrier(0);
             nbsum<double, CX, RY>(g, Lg, c);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -759,7 +824,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         if (c.Gv == 1) __syncthreads();   // publish uvec (no stencil barrier ran)
         {
             double Bu[RY][CX];
+            __builtin_amdgcn_sched_barrier(0);
             b_apply<double, CX, RY, LX, LY>(uvec, c, Bu);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -775,6 +842,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                     b1[t][q] = T(kx);
                 }
         }
+        __builtin_amdgcn_sched_barrier(0);
         // stage coefficients of the lower layer (after the FP64 rows, so
         // their registers are not live during the residual)
 #pragma unroll
@@ -787,7 +855,8 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 K.cpk[t][q] = T(h * kk);
                 K.g2[t][q] = T(kp * lc[t][q]);
             }
-        bt_reduce<double, CX, RY, LX, LY>(lc, c, M);
+        __builtin_amdgcn_sched_barrier(0);
+        btl = bt_reduce<double, CX, RY, LX, LY>(lc, c, M);
     }
     unsigned long long mu = 0;
     if (c.tid < M) {
@@ -795,24 +864,17 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         // reference is another buffer's input (second sweep of SGS) keeps it
         double bg = 0.0;   // gradient of the input-box barrier
         if (P.tau > 0.0) bg = -P.tau / (uvec[c.tid] - P.ulo) + P.tau / (P.uhi - uvec[c.tid]);
-        const double ku = h * (P.r * uvec[c.tid] + bg + red[c.tid]);
+        const double ku = h * (P.r * uvec[c.tid] + bg + btl);
         const double reg = v.utb >= 0
             ? P.gamma * (uvec[c.tid] - a.U[v.utb][v.uo + (size_t)v.i * M + c.tid]) : 0.0;
         kun[c.tid] = ku + reg;
-        v3[c.tid] = 0.0;
         mu = abits(ku);
     }
-    if (want_res) {
-        mx = wave_max64(mx, c.lane);
-        ml = wave_max64(ml, c.lane);
-        mu = wave_max64(mu, c.lane);
-        if (c.lane == 0) {
-            nrm[c.w * 4 + 0] = mx;
-            nrm[c.w * 4 + 1] = ml;
-            nrm[c.w * 4 + 2] = mu;
-        }
-        __syncthreads();
-        if (c.tid == 0) {
+    // the waves' norm partials go to LDS; thread 0 combines them after a
+    // barrier: at once, or (defer_norms) after the lower layer's first one
+    bool norms_owed = false;
+    auto combine_norms = [&]() {
+        if (norms_owed && c.tid == 0) {
             unsigned long long ax = 0, al = 0, au = 0;
             for (int ww = 0; ww < c.W; ++ww) {
                 ax = umax64(ax, nrm[ww * 4 + 0]);
@@ -837,8 +899,24 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 acc[1] = umax64(acc[1], abits(rp));
             }
         }
+        norms_owed = false;
+    };
+    if (want_res) {
+        mx = wave_max64(mx, c.lane);
+        ml = wave_max64(ml, c.lane);
+        mu = wave_max64(mu, c.lane);
+        if (c.lane == 0) {
+            nrm[c.w * 4 + 0] = mx;
+            nrm[c.w * 4 + 1] = ml;
+            nrm[c.w * 4 + 2] = mu;
+        }
+        norms_owed = true;
+        if (!v.defer_norms) {
+            __syncthreads();
+            combine_norms();
+        }
     } else {
-        __syncthreads();   // publish kun / v3 (the norm path's barrier)
+        __syncthreads();   // the norm path's barrier
     }
     // every wave has read its x_i, lambda_i (before the first stencil barrier):
     // the prefetch region may take the next stage's
@@ -846,12 +924,24 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         const size_t sn = (size_t)v.so + (size_t)v.pni * n;
         prefetch_xl(c, a.X[v.pnb] + sn, a.LAM[v.pnb] + sn, n);
     }
-    if (a.residual_only || v.res_only) return;
+    if (a.residual_only || v.res_only) {
+        if (norms_owed) {
+            __syncthreads();
+            combine_norms();
+        }
+        return;
+    }
 
     // ---- lower layer (T)
     const T hT = T(h), qT = T(P.q), c0T = T(P.c0);
     const double auu = h * P.r + P.gamma;
     T y5[RY][CX], y4[RY][CX];
+    // v3 (the input step): element j in lane j < M of every wave (v3me) and as
+    // wave-uniform values (v3s) for the applications of B
+    double v3me = 0.0;
+    T v3s[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) v3s[j] = T(0);
     for (int s = 0; s < a.n_schur; ++s) {
         T cc[RY][CX];
         if (s == 0) {
@@ -861,7 +951,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 for (int q = 0; q < CX; ++q) cc[t][q] = -b1[t][q];
         } else {
             T Bv[RY][CX];
-            b_apply<T, CX, RY, LX, LY>(v3, c, Bv);
+            b_apply<T, CX, RY, LX, LY>(v3s, c, Bv);
 #pragma unroll
             for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -877,23 +967,28 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 for (int q = 0; q < CX; ++q) cc[t][q] = -b2[t][q] - Ay[t][q];
         }
         jac_ft<T, CX, RY>(cc, y4, K, a.n_sw, c);
-        bt_reduce<T, CX, RY, LX, LY>(y4, c, M);
-        if (c.tid < M) {
-            const T bt = T(red[c.tid]);
+        const T bt = bt_reduce<T, CX, RY, LX, LY>(y4, c, M);
+        if (s == 0) combine_norms();   // bt_reduce's barrier follows the partials
+        // every wave forms v3 itself (same operands, same order): no barrier
+        if (c.lane < M) {
             double au = auu;   // plus the barrier's Hessian with an input box
             if (P.tau > 0.0) {
-                const double lo = uvec[c.tid] - P.ulo, hi = P.uhi - uvec[c.tid];
+                const double lo = uvec[c.lane] - P.ulo, hi = P.uhi - uvec[c.lane];
                 au += h * (P.tau / (lo * lo) + P.tau / (hi * hi));
             }
-            v3[c.tid] = double((T(kun[c.tid]) + hT * bt) / T(au));
+            v3me = double((T(kun[c.lane]) + hT * bt) / T(au));
         }
+        wave_bcast<T, M>(v3me, v3s);
+    }
+    if (norms_owed) {   // no Schur step ran
         __syncthreads();
+        combine_norms();
     }
     {
         T cc[RY][CX];
         {
             T Bv[RY][CX];
-            b_apply<T, CX, RY, LX, LY>(v3, c, Bv);
+            b_apply<T, CX, RY, LX, LY>(v3s, c, Bv);
 #pragma unroll
             for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -925,10 +1020,10 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                 Lw[p] = Lc[p] - om * double(y4[t][q]);
             }
     if (c.tid < M) {
-        const double un = uvec[c.tid] - om * v3[c.tid];
+        const double un = uvec[c.tid] - om * v3me;
         a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = un;
         if (v.du_at >= 0) {   // size of the FP64 correction step (reported per result)
-            atomicMax(a.du + 2 * v.du_at, abits(om * v3[c.tid]));
+            atomicMax(a.du + 2 * v.du_at, abits(om * v3me));
             atomicMax(a.du + 2 * v.du_at + 1, abits(un));
         }
     }
@@ -938,7 +1033,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         // instance's stages and scales the steps when it is below 1
         double *lim = lds_ptr<double>(c, c.off.red);
         if (c.tid < M) {
-            const double u = uvec[c.tid], d = v3[c.tid];
+            const double u = uvec[c.tid], d = v3me;
             double l = 1.0;
             if (d > 0.0) l = 0.995 * (u - P.ulo) / d;
             else if (d < 0.0) l = 0.995 * (P.uhi - u) / (-d);
@@ -951,31 +1046,6 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             a.apart[v.box_at] = l;
         }
     }
-}
-
-// The separable input factors gx [LX][nsx], gy [LY][nsy] into LDS (double and
-// float copies), laid out for the tile: gx by padded column, gy by tile row.
-template <int CX, int RY, int LX, int LY>
-__device__ __forceinline__ void load_tables(Ctx &c, const double *gxs, const double *gys, int nsx,
-                                            int nsy)
-{
-    double *gx = lds_ptr<double>(c, c.off.gx);
-    double *gy = lds_ptr<double>(c, c.off.gy);
-    float *gxf = lds_ptr<float>(c, c.off.gxf);
-    float *gyf = lds_ptr<float>(c, c.off.gyf);
-    for (int t = c.tid; t < LX * 16 * CX; t += c.W * kWave) {
-        const int aq = t >> 4, aa = aq / CX, ix = (t & 15) * CX + aq % CX;
-        const double v = ix < nsx ? gxs[aa * nsx + ix] : 0.0;
-        gx[t] = v;
-        gxf[t] = float(v);
-    }
-    for (int t = c.tid; t < LY * c.GT * RY; t += c.W * kWave) {
-        const int bb = t / (c.GT * RY), iy = t % (c.GT * RY);
-        const double v = iy < nsy ? gys[bb * nsy + iy] : 0.0;
-        gy[t] = v;
-        gyf[t] = float(v);
-    }
-    __syncthreads();
 }
 
 // Workgroup geometry for a CX x RY tile on a grid of nsy rows.
