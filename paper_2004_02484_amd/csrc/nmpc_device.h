@@ -73,6 +73,8 @@ struct IterArgs {
     int residual_only, res_slot;
     int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
+    int xp_lds;                     // Jacobi kernel: x_{i-1} is copied into LDS (after the
+                                    // layout's total) while the stage's first stencils run
     double omega;                   // Gauss-Seidel kernel: over-relaxation of each stage's step
     int fp32_finish;                // FP32 phase: a passed test finishes (no FP64 correction)
     double *apart;                  // input box: [B][N] step limit of each stage's update
@@ -207,6 +209,8 @@ struct LdsOff {
 // (64 lanes x 16 bytes); doubles per array region, after the layout's total.
 __host__ __device__ inline size_t gs_pf_doubles(int n) { return (size_t)((n * 8 + 1023) / 1024) * 128; }
 __host__ __device__ inline size_t gs_pf_bytes(int n) { return 2 * gs_pf_doubles(n) * 8; }
+// Jacobi kernel: one such array (x_{i-1}).
+__host__ __device__ inline size_t xp_stage_bytes(int n) { return gs_pf_doubles(n) * 8; }
 
 __host__ __device__ inline size_t lds_align16(size_t p) { return (p + 15) & ~(size_t)15; }
 

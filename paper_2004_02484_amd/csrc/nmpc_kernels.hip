@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             v.tgx = a.gx;   // tables loaded after the stage's loads are issued
             v.tgy = a.gy;
             v.defer_norms = true;
+            v.xp_lds = a.xp_lds != 0;
             v.so = (long long)b * N * n;
             v.uo = (long long)b * N * M;
             v.xo = (long long)b * n;

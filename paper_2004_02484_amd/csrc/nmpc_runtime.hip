@@ -125,14 +125,19 @@ int select_kernel(const nmpc_problem *p, int prec, int ry, nmpc_handle::Kern *k,
                                         p->lx, p->ly, cfg.rows).total;
     if (lds > nmpc::kLdsBytes)
         return fail(NMPC_E_UNSUPPORTED, "tile needs more LDS than a CU has");
-    // the Gauss-Seidel kernel prefetches the next stage into LDS where it fits
+    // the Gauss-Seidel kernel prefetches the next stage into LDS where it fits;
+    // the Jacobi kernel copies x_{i-1} into LDS where that still leaves room
+    // for the workgroups per CU its registers allow (two of up to four waves,
+    // one of eight)
     const int np = p->nsy * 16 * cfg.cx;
-    const int pf = gs && lds + nmpc::gs_pf_bytes(np) <= nmpc::kLdsBytes ? 1 : 0;
+    const size_t extra = gs ? nmpc::gs_pf_bytes(np) : nmpc::xp_stage_bytes(np);
+    const size_t cap = gs || waves > 4 ? nmpc::kLdsBytes : nmpc::kLdsBytes / 2;
+    const int pf = lds + extra <= cap ? 1 : 0;
     if (k) {
         k->fn = fn;
         k->cfg = cfg;
         k->waves = waves;
-        k->lds = pf ? lds + nmpc::gs_pf_bytes(np) : lds;
+        k->lds = pf ? lds + extra : lds;
         k->pf = pf;
     }
     return NMPC_OK;
@@ -326,7 +331,9 @@ IterArgs iter_args(const nmpc_handle *h, int count)
 int launch_iterate(nmpc_handle *h, int prec, const IterArgs &a, hipStream_t s)
 {
     const nmpc_handle::Kern &k = h->kern[prec];
-    void *args[] = {(void *)&a};
+    IterArgs ak = a;
+    ak.xp_lds = k.pf;
+    void *args[] = {(void *)&ak};
     HIP_TRY(hipLaunchKernel(k.fn, dim3(8 * a.per_xcd), dim3(nmpc::kWave * k.waves), args, k.lds, s));
     if (h->prob.tau > 0.0 && !a.residual_only)   // input box: step rule of this launch
         HIP_TRY(hipLaunchKernel(nmpc::box_apply_kernel(), dim3(8 * a.per_xcd), dim3(256), args, 0,

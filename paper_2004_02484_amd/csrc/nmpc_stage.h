@@ -647,6 +647,7 @@ struct StageLoc {
                                    // (max |du|, max |u_new| into a.du)
     const double *tgx, *tgy;       // non-null: load the input tables after issuing the
                                    // stage's loads (their first reader follows a barrier)
+    bool xp_lds;                   // copy x_{i-1} into LDS at the start (a.xp_lds)
     bool defer_norms;              // one stage per workgroup: combine the waves' norm
                                    // partials after the lower layer's first barrier
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
@@ -674,6 +675,23 @@ __device__ __forceinline__ void prefetch_xl(const Ctx &c, const double *x, const
         const double *src = (isl ? l : x) + e;
         double *dst = base + (isl ? npf : 0) + cc * 128;
         __builtin_amdgcn_global_load_lds((GPtr)src, (LPtr)dst, 16, 0, 0);
+    }
+}
+
+// Start the copy of one array of n doubles (padded layout) into LDS at
+// c.off.total, 16 bytes per lane (1 KB per wave instruction) spread over the
+// waves, without registers; read after s_waitcnt and a barrier. Lanes past the
+// end re-read the last 16 bytes into slots nobody reads (n is even).
+__device__ __forceinline__ void stage_copy(const Ctx &c, const double *x, int n)
+{
+    typedef const __attribute__((address_space(1))) void *GPtr;
+    typedef __attribute__((address_space(3))) void *LPtr;
+    const int chunks = (n * 8 + 1023) / 1024;
+    double *base = lds_ptr<double>(c, c.off.total);
+    for (int ch = c.w; ch < chunks; ch += c.W) {
+        int e = ch * 128 + c.lane * 2;
+        e = e < n - 2 ? e : n - 2;
+        __builtin_amdgcn_global_load_lds((GPtr)(x + e), (LPtr)(base + ch * 128), 16, 0, 0);
     }
 }
 
@@ -785,6 +803,7 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             }
         if (c.tid < M) uvec[c.tid] = a.U[v.src][v.uo + (size_t)v.i * M + c.tid];
         if (v.tgx) load_tables<CX, RY, LX, LY>(c, v.tgx, v.tgy, P.nsx, P.nsy, false);
+        if (v.xp_lds) stage_copy(c, Xp, n);   // x_{i-1}, requested with x_i
         __builtin_amdgcn_sched_barrier(0);
         nbsum<double, CX, RY>(xc, Lx, c);
         __builtin_amdgcn_sched_barrier(0);
@@ -798,6 +817,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             for (int t = 0; t < RY; ++t)
 #pragma unroll
                 for (int q = 0; q < CX; ++q) g[t][q] = P.k0 * (1.0 + P.k1 * xc[t][q]) * lc[t][q];
+            // the x_{i-1} copy has landed (this wave's part), and the
+            // stencil's barrier publishes every wave's part
+            if (v.xp_lds) __builtin_amdgcn_s_waitcnt(0);
             __builtin_amdgcn_sched_barrier(0);
             nbsum<double, CX, RY>(g, Lg, c);
             __builtin_amdgcn_sched_barrier(0);
@@ -835,7 +857,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                     if (valid(t, q)) {
                         const double kk = P.k0 * (1.0 + P.k1 * xc[t][q]);
                         const double fx = h * (kk * Lx[t][q] + Bu[t][q]);
-                        kx = Xp[pidx(t, q)] - xc[t][q] + fx;
+                        const double xp = v.xp_lds ? lds_ptr<double>(c, c.off.total)[pidx(t, q)]
+                                                   : Xp[pidx(t, q)];
+                        kx = xp - xc[t][q] + fx;
                         kxr = xdiff ? Xq[pidx(t, q)] - xc[t][q] + fx : kx;
                     }
                     mx = umax64(mx, abits(kxr));
