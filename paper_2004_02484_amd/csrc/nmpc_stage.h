@@ -647,7 +647,8 @@ struct StageLoc {
                                    // (max |du|, max |u_new| into a.du)
     const double *tgx, *tgy;       // non-null: load the input tables after issuing the
                                    // stage's loads (their first reader follows a barrier)
-    bool xp_lds;                   // copy x_{i-1} into LDS at the start (a.xp_lds)
+    bool xp_lds;                   // copy x_{i-1} into LDS at the start, then x_i for the
+                                   // update during the lower layer (a.xp_lds)
     bool defer_norms;              // one stage per workgroup: combine the waves' norm
                                    // partials after the lower layer's first barrier
     bool pf;                       // x_i, lambda_i are in the LDS prefetch region
@@ -881,6 +882,9 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             }
         __builtin_amdgcn_sched_barrier(0);
         btl = bt_reduce<double, CX, RY, LX, LY>(lc, c, M);
+        // every wave has read x_{i-1} from LDS (before bt_reduce's barrier):
+        // the region now takes x_i for the update, copied during the lower layer
+        if (v.xp_lds && !(a.residual_only || v.res_only)) stage_copy(c, Xc, n);
     }
     unsigned long long mu = 0;
     if (c.tid < M) {
@@ -1034,13 +1038,19 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     double *Xn = a.X[v.dst] + si;
     double *Lw = a.LAM[v.dst] + si;
     const double om = v.omega;
+    const double *Xs = Xc;
+    if (v.xp_lds) {   // x_i from the LDS copy
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        Xs = lds_ptr<double>(c, c.off.total);
+    }
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll
         for (int q = 0; q < CX; ++q)
             if (valid(t, q)) {
                 const int p = pidx(t, q);
-                Xn[p] = Xc[p] - om * double(y5[t][q]);
+                Xn[p] = Xs[p] - om * double(y5[t][q]);
                 Lw[p] = Lc[p] - om * double(y4[t][q]);
             }
     if (c.tid < M) {
