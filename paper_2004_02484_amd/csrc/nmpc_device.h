@@ -87,6 +87,9 @@ struct IterArgs {
 struct InitArgs {
     int count, B, N, nsx, nsy, sx, m, mode;
     int trajectory_only;            // 1: write S^0 only, keep the iteration state
+    int nst;                        // stages written per instance (0: all N)
+    int pad_only;                   // 1: of x and lambda write only the zero padding (the
+                                    // start's rollout writes the grid points)
     int project;                    // 1: move given inputs strictly inside [ulo, uhi]
     double ulo, uhi;                // input box (with project)
     const double *x0, *wx, *wu, *wl;

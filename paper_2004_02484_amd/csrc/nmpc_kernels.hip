@@ -275,13 +275,13 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
         const double *Xi = a.X[0] + unit * n;
         double *Li = a.LAM[0] + unit * n;
         const double *Xr = a.xref + (size_t)b * a.xref_inst_stride + (size_t)i * a.xref_stage_stride;
-        double x[RY][CX], Lx[RY][CX], lam[RY][CX];
+        double x[RY][CX], Lx[RY][CX], lam[RY][CX];   // the costate sweeps start from zero
 #pragma unroll
         for (int t = 0; t < RY; ++t)
 #pragma unroll
             for (int q = 0; q < CX; ++q) {
                 x[t][q] = valid(t, q) ? Xi[pidx(t, q)] : 0.0;
-                lam[t][q] = valid(t, q) ? Li[pidx(t, q)] : 0.0;
+                lam[t][q] = 0.0;
             }
         nbsum<double, CX, RY>(x, Lx, c);
         double cc[RY][CX], invd[RY][CX], cpk[RY][CX];
@@ -397,7 +397,8 @@ __global__ void k_choose_flags(const IterArgs a, int *start_used, int used_if_ke
     start_used[b] = (bits2d(mw) <= bits2d(mc)) ? used_if_kept : 0;
 }
 
-// Copy buffer 1's start over buffer 0 for the instances that fell back.
+// Write the cold start (x_i = x0 with its zero padding, u_i = 0, lambda_i =
+// 0) into buffer 0 for the instances that fell back.
 __global__ void k_choose_copy(const IterArgs a, const int *start_used)
 {
     const size_t np = a.P.n, N = a.P.N, m = a.P.m;
@@ -407,13 +408,11 @@ __global__ void k_choose_copy(const IterArgs a, const int *start_used)
         const size_t b = t / per, r = t % per;
         if (start_used[b] != 0) continue;
         if (r < N * np) {
-            a.X[0][b * N * np + r] = a.X[1][b * N * np + r];
+            a.X[0][b * N * np + r] = a.x0[b * np + r % np];
         } else if (r < 2 * N * np) {
-            const size_t q = r - N * np;
-            a.LAM[0][b * N * np + q] = a.LAM[1][b * N * np + q];
+            a.LAM[0][b * N * np + (r - N * np)] = 0.0;
         } else {
-            const size_t q = r - 2 * N * np;
-            a.U[0][b * N * m + q] = a.U[1][b * N * m + q];
+            a.U[0][b * N * m + (r - 2 * N * np)] = 0.0;
         }
     }
 }
@@ -431,33 +430,37 @@ __global__ void k_advance(int *ctr, int len)
 __global__ void k_init(const InitArgs a)
 {
     const size_t np = (size_t)a.nsy * a.sx;             // padded points per stage
-    const size_t nN = (size_t)a.count * a.N * np;
-    const size_t mN = (size_t)a.count * a.N * a.m;
+    const size_t nst = a.nst > 0 ? a.nst : a.N;        // stages written per instance
+    const size_t nN = (size_t)a.count * nst * np;
+    const size_t mN = (size_t)a.count * nst * a.m;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nN; t += stride) {
-        const size_t unit = t / np, p = t % np;
+        const size_t us = t / np, p = t % np;
+        const size_t b = us / nst, unit = b * a.N + us % nst;
         const int row = (int)(p / a.sx), col = (int)(p % a.sx);
-        const size_t b = unit / a.N;
+        if (a.pad_only && col < a.nsx) continue;
         double x = 0.0, l = 0.0;
         if (col < a.nsx) {
             const size_t dense = unit * (size_t)a.nsx * a.nsy + (size_t)row * a.nsx + col;
             x = a.wx ? a.wx[dense] : a.x0[b * np + p];
             l = a.wl ? a.wl[dense] : 0.0;
         }
-        a.X[t] = x;
-        a.LAM[t] = l;
+        a.X[unit * np + p] = x;
+        a.LAM[unit * np + p] = l;
     }
     // with an input box the method starts from a strictly feasible S^0
     // (Sec. 4.2): given inputs are clipped to the box shrunk by 0.5 % of its
     // width at each end (NaN stays NaN, so the residual test still rejects it)
     const double marg = 0.005 * (a.uhi - a.ulo);
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < mN; t += stride) {
-        double u = a.wu ? a.wu[t] : 0.0;
+        const size_t b = t / (nst * a.m), r = t % (nst * a.m);
+        const size_t e = b * a.N * a.m + r;
+        double u = a.wu ? a.wu[e] : 0.0;
         if (a.project && a.wu) {
             if (u < a.ulo + marg) u = a.ulo + marg;
             if (u > a.uhi - marg) u = a.uhi - marg;
         }
-        a.U[t] = u;
+        a.U[e] = u;
     }
     if (a.trajectory_only) return;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.count;

@@ -448,6 +448,8 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
     if (h->d_aupd)   // input box: no update recorded for this solve yet (not captured)
         HIP_TRY(hipMemsetAsync(h->d_aupd, 0, sizeof(int) * h->max_batch, h->stream));
     const bool check = kind != kStartCold && h->opt.fallback && !h->streaming;
+    // a start built from inputs gets its states and costates from the rollout
+    if (kind == kStartInputs && !h->streaming) ia.pad_only = 1;
     {
         void *args[] = {(void *)&ia};
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
@@ -480,10 +482,15 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         ic.wx = ic.wu = ic.wl = nullptr;
         ic.X = h->X(1); ic.U = h->U(1); ic.LAM = h->L(1);
         ic.trajectory_only = 1;
+        ic.pad_only = 0;
+        // with one reference for all stages only stage 0 is evaluated, which
+        // reads stages 0 and 1 (the instances that fall back get the cold start
+        // written into buffer 0 by the choice)
+        ic.nst = !h->opt.xref_per_stage && h->N > 2 ? 2 : 0;
         void *args[] = {(void *)&ic};
         HIP_TRY(hipLaunchKernel(nmpc::init_kernel(),
-                                dim3(launch_grid((size_t)count * h->N * h->np)), dim3(256), args,
-                                0, h->side));
+                                dim3(launch_grid((size_t)count * (ic.nst ? ic.nst : h->N) * h->np)),
+                                dim3(256), args, 0, h->side));
         // with one reference for all stages the cold start's stage residuals
         // are all equal (x_i = x0, u = 0, lambda = 0): stage 0 stands for all
         const int rc = launch_residual(h, count, 1, 1, h->side, !h->opt.xref_per_stage);
