@@ -145,6 +145,8 @@ struct StreamArgs {
     double *rowt;                   // [B][N][nsy][kMaxLx] row partials of B^T y4 (multi-pass)
     unsigned long long *rst, *pst;  // [B][N] stage norms (bit patterns)
     double *part;                   // [B][N][units per stage][kMaxM] partial B^T lambda / y4
+    double *part2;                  // the same, B^T y4 of the first Schur step when the
+                                    // residual pass takes that step
     unsigned long long *unorm;      // [B][N][units per stage][2] partial max |K^x|, |K^lambda|
     int nstrip, nrb;                // lower pass: column strips and row blocks per stage
     long long lunits;               // lower pass: count * N * nrb * nstrip wave units
@@ -173,17 +175,21 @@ __host__ __device__ inline size_t stream_lds_bytes(int nsx, int elem = 8, int ar
     return (size_t)arrays * (kStreamRows + 2) * nsx * elem;
 }
 
-// The fused lower-layer pass (two point-Jacobi sweeps per solve): one wave per
-// strip of kLowerCols owned grid columns (64 lanes = the strip and 3 halo
-// columns each side) and kLowerRows grid rows, marching down the rows
-// (kLowerRows + 6 a multiple of the pass's prefetch distance, 6).
+// The marching-strip passes (two point-Jacobi sweeps per solve): one wave per
+// strip of kLowerCols owned grid columns (64 lanes = the strip and kLowerHaloX
+// halo columns each side: the residual pass fused with the first Schur step
+// needs four) and kLowerRows grid rows, marching down the rows from kLowerHalo
+// rows above the block (kLowerRows + 6 a multiple of the lower pass's
+// prefetch distance, 6).
 constexpr int kLowerRows = 30;
 constexpr int kLowerHalo = 3;
-constexpr int kLowerCols = kWave - 2 * kLowerHalo;
+constexpr int kLowerHaloX = 4;
+constexpr int kLowerCols = kWave - 2 * kLowerHaloX;
 
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
     const void *lower, *lower_fin, *v3f;   // fused Schur step, final block; v3 from partials
+    const void *res1;                      // residual pass with the first Schur step
     const void *box_lim, *box_apply;       // input box: stage limits, then the cut step
 };
 StreamKernels stream_kernels(int prec);

@@ -538,7 +538,7 @@ size_t stream_doubles(const nmpc_handle *h)
     const size_t lunits = (size_t)((h->prob.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols) *
                           ((h->prob.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows);
     return 10 * B * N * n + B * N * h->prob.ly * h->prob.nsx + 2 * B * N * m +
-           B * N * h->prob.nsy * nmpc::kMaxLx + B * N * lunits * (nmpc::kMaxM + 2);
+           B * N * h->prob.nsy * nmpc::kMaxLx + B * N * lunits * (2 * nmpc::kMaxM + 2);
 }
 
 nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
@@ -570,6 +570,7 @@ nmpc::StreamArgs stream_args(const nmpc_handle *h, int count)
     a.nstrip = (p.nsx + nmpc::kLowerCols - 1) / nmpc::kLowerCols;
     a.nrb = (p.nsy + nmpc::kLowerRows - 1) / nmpc::kLowerRows;
     a.part = q; q += B * N * a.nrb * a.nstrip * nmpc::kMaxM;
+    a.part2 = q; q += B * N * a.nrb * a.nstrip * nmpc::kMaxM;
     a.unorm = reinterpret_cast<unsigned long long *>(q);
     a.lunits = (long long)count * h->N * a.nrb * a.nstrip;
     a.lper_xcd = (int)(((a.lunits + 3) / 4 + 7) / 8);
@@ -605,18 +606,25 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
     };
     int rc;
     if (h->opt.n_sweep == 2) {
-        // fused lower layer: one pass per Schur step and one for the final block
+        // fused lower layer: one pass per Schur step and one for the final
+        // block; the first Schur step (v3 = 0) rides in the residual pass
+        const bool first_in_res = h->opt.n_schur >= 1;
         {
             void *args[] = {(void *)&a};
-            if ((rc = go(k.res, lower, 256, args))) return rc;
+            if ((rc = go(first_in_res ? k.res1 : k.res, lower, 256, args))) return rc;
             if ((rc = go(k.stage, stages, 256, args))) return rc;
             if ((rc = go(k.decide, dim3(a.count), nmpc::kWave, args))) return rc;
         }
-        for (int sch = 0; sch <= h->opt.n_schur; ++sch) {
+        for (int sch = first_in_res ? 1 : 0; sch <= h->opt.n_schur; ++sch) {
             const bool fin = sch == h->opt.n_schur;
             void *args[] = {(void *)&a};
+            int which = 1;
+            void *args_first[] = {(void *)&a, (void *)&which};
+            if (sch == 1 && first_in_res && (rc = go(k.v3f, stages, 256, args_first))) return rc;
             if ((rc = go(fin ? k.lower_fin : k.lower, lower, 256, args))) return rc;
-            if (!fin && (rc = go(k.v3f, stages, 256, args))) return rc;
+            int w0 = 0;
+            void *args_v3[] = {(void *)&a, (void *)&w0};
+            if (!fin && (rc = go(k.v3f, stages, 256, args_v3))) return rc;
         }
         void *args[] = {(void *)&a};
         if (h->prob.tau > 0.0) {   // input box: cut the step by the rule

@@ -250,7 +250,7 @@ __device__ __forceinline__ double st_recip<double>(double d) { return 1.0 / d; }
 
 // KKT rows of S^j (FP64), the lower layer's right-hand sides and
 // coefficients (stored in T) and the unit partials of the stage norms and of
-// B^T lambda. Units as in the lower-layer pass: one wave per strip of 58
+// B^T lambda. Units as in the lower-layer pass: one wave per strip of 56
 // owned columns and kLowerRows rows, each lane marching down its column from
 // one row above the block to one below; x and g = k(x) lambda of the row
 // above, the row and the row below stay in registers, horizontal neighbours
@@ -272,10 +272,10 @@ __global__ void __launch_bounds__(256, 3) k_st_res(const StreamArgs a)
     if (!evaluating<PREC>(a, b)) return;
     const DevProblem &P = a.P;
     const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy;
-    const int ix = sp * kLowerCols - kLowerHalo + lane;
+    const int ix = sp * kLowerCols - kLowerHaloX + lane;
     const bool col_in = ix >= 0 && ix < nsx;
     const int ixc = col_in ? ix : 0;
-    const bool own = lane >= kLowerHalo && lane < kWave - kLowerHalo && col_in;
+    const bool own = lane >= kLowerHaloX && lane < kWave - kLowerHaloX && col_in;
     const int r0 = rb * kLowerRows;
     const int cur = a.st[b].j & 1;
     const bool last = i == P.N - 1;
@@ -769,7 +769,7 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 //   c' = sgn b2 - A_xx y5,   z1 = cpk c' / d,  y4 = (c' - N(z1)) / d      (F_x^T solve)
 // then the partial sums of B^T y4 (Schur step) or the update
 // S^{k+1} = S^k - (y5, v3, y4) (final block). One wave per unit of
-// kLowerRows rows and a strip of 64 columns whose 58 inner lanes own their
+// kLowerRows rows and a strip of 64 columns whose 56 inner lanes own their
 // column: horizontal neighbours come from the adjacent lanes (DPP wave
 // shifts), vertical ones from the rows the lane has already visited, so the
 // pass needs no LDS and no barrier. Each lane walks its column from three
@@ -794,9 +794,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
     if (!a.work[b]) return;
     const DevProblem &P = a.P;
     const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy, m = P.m;
-    const int ix = sp * kLowerCols - kLowerHalo + lane;
+    const int ix = sp * kLowerCols - kLowerHaloX + lane;
     const bool col_in = ix >= 0 && ix < nsx;
-    const bool own = lane >= kLowerHalo && lane < kWave - kLowerHalo && col_in;
+    const bool own = lane >= kLowerHaloX && lane < kWave - kLowerHaloX && col_in;
     const int r0 = rb * kLowerRows;
     const T sgn = fin ? T(1) : T(-1);
     const T h = T(P.h), ax = T(P.idx2), ay = T(P.idy2), qw = T(P.q), c0 = T(P.c0);
@@ -983,10 +983,239 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
     }
 }
 
-// v3 = (K^u + h B^T y4) / (h r + gamma) per stage from the fused pass's unit
-// partials (in unit order). One workgroup (256 threads) per stage; thread j < m.
+// The residual pass fused with the first Schur step (two sweeps per solve,
+// at least one Schur step). In the first step v3 = 0, so its right-hand side
+// c = -b1 needs no reduction over the stage, and the step can trail the KKT
+// rows in the same march: each lane walks its column from four rows above the
+// block to four below; the KKT rows and coefficients (FP64, rounded to T as
+// the stored ones) trail the loaded row by one, and the Schur step trails
+// them as the lower pass trails its loaded row (y5 by 1, c' and z1 by 2, y4
+// by 3). Four halo columns: each of the four stencils on the way to y4
+// spoils one more column at the strip ends. Writes the lower layer's
+// right-hand sides and coefficients for the later passes (block rows, owned
+// columns), the unit partials of the norms and of B^T lambda (part) and of
+// B^T y4 (part2). The arithmetic is that of k_st_res followed by k_st_lower
+// with v3 = 0, so the iterates do not change.
 template <typename T>
-__global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
+__global__ void __launch_bounds__(256, 2) k_st_res1(const StreamArgs a)
+{
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    const long long gu = (long long)(blockIdx.x & 7) * a.lper_xcd + (blockIdx.x >> 3);
+    const long long unit = gu * (blockDim.x / kWave) + wv;
+    if (unit >= a.lunits) return;
+    const int sp = (int)(unit % a.nstrip);
+    const long long t1 = unit / a.nstrip;
+    const int rb = (int)(t1 % a.nrb);
+    const long long bi = t1 / a.nrb;
+    const int b = (int)(bi / a.P.N), i = (int)(bi % a.P.N);
+    constexpr int PREC = std::is_same<T, float>::value ? kModeFp32 : kModeFp64;
+    if (!evaluating<PREC>(a, b)) return;
+    const DevProblem &P = a.P;
+    const int nsx = P.nsx, nsy = P.nsy, n = nsx * nsy;
+    const int ix = sp * kLowerCols - kLowerHaloX + lane;
+    const bool col_in = ix >= 0 && ix < nsx;
+    const int ixc = col_in ? ix : 0;
+    const bool own = lane >= kLowerHaloX && lane < kWave - kLowerHaloX && col_in;
+    const int r0 = rb * kLowerRows;
+    const int cur = a.st[b].j & 1;
+    const bool last = i == P.N - 1;
+    const double *x = a.X[cur] + bi * n, *lam = a.LAM[cur] + bi * n;
+    const double *xp = i == 0 ? a.x0 + (size_t)b * n : x - n;
+    const double *ln = last ? lam : lam + n;   // not read at the last stage (value 0)
+    const double *xr = a.xref + (size_t)b * a.xref_inst_stride + (size_t)i * a.xref_stage_stride;
+    T *b1 = reinterpret_cast<T *>(a.b1) + bi * n, *b2 = reinterpret_cast<T *>(a.b2) + bi * n;
+    T *invd = reinterpret_cast<T *>(a.invd) + bi * n, *cpk = reinterpret_cast<T *>(a.cpk) + bi * n;
+    T *g2 = reinterpret_cast<T *>(a.g2) + bi * n;
+    const double h = P.h, kp = P.k0 * P.k1, ax = P.idx2, ay = P.idy2;
+    const T hT = T(P.h), axT = T(P.idx2), ayT = T(P.idy2), qT = T(P.q), c0T = T(P.c0);
+    auto K = [&](double w) { return P.k0 * (1.0 + P.k1 * w); };
+    // the column factor of B u for this lane (lane j holds u_j)
+    double scb[kMaxLy];
+    {
+        const double ul = lane < P.m ? a.U[cur][bi * P.m + lane] : 0.0;
+        const long long ub = __double_as_longlong(ul);
+        const int ulo = (int)ub, uhi = (int)(ub >> 32);
+        double gxv[kMaxLx];
+#pragma unroll
+        for (int aa = 0; aa < kMaxLx; ++aa) {
+            const double gv = a.gx[(aa < P.lx ? aa : 0) * nsx + ixc];
+            gxv[aa] = aa < P.lx && col_in ? gv : 0.0;
+        }
+#pragma unroll
+        for (int bb = 0; bb < kMaxLy; ++bb) {
+            double sum = 0.0;
+#pragma unroll
+            for (int aa = 0; aa < kMaxLx; ++aa) {
+                const int j = bb < P.ly && aa < P.lx ? bb * P.lx + aa : 0;
+                const long long w = ((long long)__builtin_amdgcn_readlane(uhi, j) << 32) |
+                                    (long long)(unsigned)__builtin_amdgcn_readlane(ulo, j);
+                sum += gxv[aa] * __longlong_as_double(w);
+            }
+            scb[bb] = bb < P.ly ? sum : 0.0;
+        }
+    }
+    constexpr int HY = kLowerHalo + 1;             // rows above / below the block
+    constexpr int NR = kLowerRows + 2 * HY;        // rows r0 - HY .. r0 + kLowerRows + HY - 1
+    constexpr int SLICE = 2 * kMaxLy * (kWave + 1);   // doubles per wave (>= NR kMaxLy)
+    static_assert(NR * kMaxLy <= SLICE, "gy rows fit the wave's slice");
+    __shared__ double slice[4][SLICE];
+    double *gyl = slice[wv];   // [NR][kMaxLy], then [2][kMaxLy][65] for the partials
+#pragma unroll
+    for (int it = 0; it < (NR * kMaxLy + kWave - 1) / kWave; ++it) {
+        const int e = lane + it * kWave;
+        const int rr = e / kMaxLy, bb = e - rr * kMaxLy, row = r0 - HY + rr;
+        const bool ok = e < NR * kMaxLy && bb < P.ly && row >= 0 && row < nsy;
+        const double v = a.gy[ok ? bb * nsy + row : 0];
+        if (e < NR * kMaxLy) gyl[e] = ok ? v : 0.0;
+    }
+    constexpr int PFR = 2;
+    static_assert(NR % PFR == 0, "whole groups of rows");
+    double qx[PFR], ql[PFR], qp[PFR], qn[PFR], qr[PFR];
+    auto load_row = [&](int k, double &vx, double &vl, double &vp, double &vn, double &vr) {
+        const int pc = (k >= 0 && k < nsy ? k : 0) * nsx + ixc;
+        vx = x[pc]; vl = lam[pc]; vp = xp[pc]; vn = ln[pc]; vr = xr[pc];
+    };
+#pragma unroll
+    for (int t = 0; t < PFR; ++t) load_row(r0 - HY + t, qx[t], ql[t], qp[t], qn[t], qr[t]);
+    // KKT windows (FP64)
+    double x_2 = 0, x_1 = 0, x_0 = 0, g_2 = 0, g_1 = 0, g_0 = 0;
+    double l_1 = 0, l_0 = 0, p_1 = 0, p_0 = 0, n_1 = 0, n_0 = 0, r_1 = 0, r_0 = 0;
+    unsigned long long mx = 0, ml = 0;
+    double cl[kMaxLy];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb) cl[bb] = 0.0;
+    // Schur-step windows (T), indexed by rows behind the newest KKT row
+    T c_1 = 0, c_0 = 0;
+    T y1_2 = 0, y1_1 = 0, y1_0 = 0;
+    T y5_3 = 0, y5_2 = 0, y5_1 = 0;
+    T w_3 = 0, w_2 = 0, w_1 = 0;
+    T cp_3 = 0, cp_2 = 0;
+    T z_4 = 0, z_3 = 0, z_2 = 0;
+    T d_3 = 0, d_2 = 0, d_1 = 0, d_0 = 0;
+    T k_2 = 0, k_1 = 0, k_0 = 0;
+    T gg_2 = 0, gg_1 = 0, gg_0 = 0;
+    T e_2 = 0, e_1 = 0, e_0 = 0;   // b2
+    T colsum[kMaxLy];
+#pragma unroll
+    for (int bb = 0; bb < kMaxLy; ++bb) colsum[bb] = T(0);
+#pragma unroll 1
+    for (int g0 = 0; g0 < NR; g0 += PFR)
+#pragma unroll
+    for (int st = 0; st < PFR; ++st) {
+        const int kk = g0 + st, k = r0 - HY + kk;
+        x_2 = x_1; x_1 = x_0; g_2 = g_1; g_1 = g_0;
+        l_1 = l_0; p_1 = p_0; n_1 = n_0; r_1 = r_0;
+        const bool in = col_in && k >= 0 && k < nsy;
+        const double vx = qx[st], vl = ql[st], vp = qp[st], vn = qn[st], vr = qr[st];
+        load_row(k + PFR, qx[st], ql[st], qp[st], qn[st], qr[st]);
+        x_0 = in ? vx : 0.0;
+        l_0 = in ? vl : 0.0;
+        p_0 = vp; n_0 = last ? 0.0 : vn; r_0 = vr;
+        g_0 = K(x_0) * l_0;
+        if (kk < 2) continue;
+        // ---- KKT rows and coefficients of row r = k - 1
+        const int r = k - 1;
+        const bool rin = col_in && r >= 0 && r < nsy;
+        const double Lx = ax * (wshr(x_1) + wshl(x_1)) + ay * (x_2 + x_0) - P.c0 * x_1;
+        const double Lg = ax * (wshr(g_1) + wshl(g_1)) + ay * (g_2 + g_0) - P.c0 * g_1;
+        double bu = 0.0;
+#pragma unroll
+        for (int bb = 0; bb < kMaxLy; ++bb) bu += gyl[(kk - 1) * kMaxLy + bb] * scb[bb];
+        const double kl = n_1 - l_1 + h * (P.q * (x_1 - r_1) + Lg + kp * Lx * l_1);
+        const double kx = p_1 - x_1 + h * (K(x_1) * Lx + bu);
+        const double dd = -1.0 - h * K(x_1) * P.c0 + h * kp * Lx;
+        const T tb1 = T(kx), tb2 = T(kl), tinvd = st_recip<T>(dd), tcpk = T(h * K(x_1));
+        const T tg2 = T(kp * l_1);
+        const bool blk = own && r >= r0 && r < r0 + kLowerRows && r < nsy;
+        {
+            const unsigned long long ax_ = sabits(kx), al_ = sabits(kl);
+            mx = blk && ax_ > mx ? ax_ : mx;
+            ml = blk && al_ > ml ? al_ : ml;
+            const double lv = blk ? l_1 : 0.0;
+#pragma unroll
+            for (int bb = 0; bb < kMaxLy; ++bb) cl[bb] += gyl[(kk - 1) * kMaxLy + bb] * lv;
+            if (blk) {
+                const int pp = r * nsx + ix;
+                b1[pp] = tb1;
+                b2[pp] = tb2;
+                invd[pp] = tinvd;
+                cpk[pp] = tcpk;
+                g2[pp] = tg2;
+            }
+        }
+        // ---- first Schur step (v3 = 0): row r enters as the lower pass's loaded row
+        const int kl2 = kk - 2;   // that pass's row counter (row r0 - kLowerHalo + kl2)
+        c_1 = c_0; y1_2 = y1_1; y1_1 = y1_0;
+        d_3 = d_2; d_2 = d_1; d_1 = d_0; k_2 = k_1; k_1 = k_0; gg_2 = gg_1; gg_1 = gg_0;
+        e_2 = e_1; e_1 = e_0;
+        d_0 = rin ? tinvd : T(0);
+        k_0 = rin ? tcpk : T(0);
+        gg_0 = rin ? tg2 : T(0);
+        e_0 = rin ? tb2 : T(0);
+        c_0 = rin ? T(-1) * (tb1 - hT * T(0)) : T(0);
+        y1_0 = c_0 * d_0;
+        if (kl2 >= 2) {   // y5 and w at row r - 1
+            y5_3 = y5_2; y5_2 = y5_1; w_3 = w_2; w_2 = w_1;
+            const T nb = axT * (wshr(y1_1) + wshl(y1_1)) + ayT * (y1_2 + y1_0);
+            y5_1 = (c_1 - k_1 * nb) * d_1;
+            w_1 = gg_1 * y5_1;
+        }
+        if (kl2 >= 4) {   // c' and z1 at row r - 2
+            cp_3 = cp_2; z_4 = z_3; z_3 = z_2;
+            const T n1 = axT * (wshr(y5_2) + wshl(y5_2)) + ayT * (y5_3 + y5_1);
+            const T n2 = axT * (wshr(w_2) + wshl(w_2)) + ayT * (w_3 + w_1);
+            const T Ay = hT * ((qT - T(2) * c0T * gg_2) * y5_2 + gg_2 * n1 + n2);
+            cp_2 = T(-1) * e_2 - Ay;
+            z_2 = k_2 * cp_2 * d_2;
+        }
+        if (kl2 >= 6) {   // y4 at row r - 3 (a block row)
+            const T nb = axT * (wshr(z_3) + wshl(z_3)) + ayT * (z_4 + z_2);
+            const T y4 = (cp_3 - nb) * d_3;
+            const int ry = r - 3;
+            const T y4o = own && ry < nsy ? y4 : T(0);
+            const int gr = ry - (r0 - HY);   // gy table row
+#pragma unroll
+            for (int bb = 0; bb < kMaxLy; ++bb) colsum[bb] += T(gyl[gr * kMaxLy + bb]) * y4o;
+        }
+    }
+    // unit partials: norms, B^T lambda (part) and B^T y4 (part2) over the owned lanes
+    const long long upart = (bi * a.nrb + rb) * a.nstrip + sp;
+    mx = wave_umax(mx);
+    ml = wave_umax(ml);
+    if (lane == 0) {
+        a.unorm[2 * upart] = mx;
+        a.unorm[2 * upart + 1] = ml;
+    }
+    double (*cs)[kWave + 1] = reinterpret_cast<double (*)[kWave + 1]>(gyl);
+    double (*gs)[kWave + 1] = cs + kMaxLy;
+#pragma unroll
+    for (int q = 0; q < kMaxLy; ++q) {
+        cs[q][lane] = own ? cl[q] : 0.0;
+        const double gv = a.gx[(q < P.lx ? q : 0) * nsx + ixc];
+        gs[q][lane] = q < P.lx && col_in ? gv : 0.0;
+    }
+    if (lane < P.m) {
+        const int bb = lane / P.lx, aa = lane - bb * P.lx;
+        double v = 0.0;
+        for (int l = 0; l < kWave; ++l) v += cs[bb][l] * gs[aa][l];
+        a.part[upart * kMaxM + lane] = v;
+    }
+    // B^T y4 in T, as the lower pass forms it
+#pragma unroll
+    for (int q = 0; q < kMaxLy; ++q) cs[q][lane] = own ? double(colsum[q]) : 0.0;
+    if (lane < P.m) {
+        const int bb = lane / P.lx, aa = lane - bb * P.lx;
+        T v = 0;
+        for (int l = 0; l < kWave; ++l) v += T(cs[bb][l]) * T(gs[aa][l]);
+        a.part2[upart * kMaxM + lane] = double(v);
+    }
+}
+
+// v3 = (K^u + h B^T y4) / (h r + gamma) per stage from the fused pass's unit
+// partials (in unit order; which = 1: those of the residual pass's first
+// Schur step). One workgroup (256 threads) per stage; thread j < m.
+template <typename T>
+__global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a, int which)
 {
     const int bi = blockIdx.x;
     if (bi >= a.count * a.P.N) return;
@@ -995,7 +1224,7 @@ __global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a)
     const int j = threadIdx.x;
     if (j >= a.P.m) return;
     const int units = a.nrb * a.nstrip;
-    const double *pp = a.part + (size_t)bi * units * kMaxM + j;
+    const double *pp = (which ? a.part2 : a.part) + (size_t)bi * units * kMaxM + j;
     double s = 0.0;
 #pragma unroll 8
     for (int u = 0; u < units; ++u) s += pp[(size_t)u * kMaxM];
@@ -1083,6 +1312,7 @@ StreamKernels stream_kernels(int prec)
         k.lower = (const void *)&k_st_lower<float, false>;
         k.lower_fin = (const void *)&k_st_lower<float, true>;
         k.v3f = (const void *)&k_st_v3f<float>;
+        k.res1 = (const void *)&k_st_res1<float>;
     } else {
         k.bsep = (const void *)&k_st_bsep<kModeFp64>;
         k.stage = (const void *)&k_st_stage<kModeFp64>;
@@ -1095,6 +1325,7 @@ StreamKernels stream_kernels(int prec)
         k.lower = (const void *)&k_st_lower<double, false>;
         k.lower_fin = (const void *)&k_st_lower<double, true>;
         k.v3f = (const void *)&k_st_v3f<double>;
+        k.res1 = (const void *)&k_st_res1<double>;
     }
     return k;
 }
