@@ -873,18 +873,29 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
     static_assert((kLowerRows + 2 * kLowerHalo) % PF == 0, "whole groups of rows");
     T qd[PF], qk[PF], qg[PF], qe[PF], qb[PF];
     double qx[PF], ql[PF];   // final block: x and lambda of the row (for the update)
+    // the final block reads x and lambda for the update anyway, so it forms the
+    // coefficients from them (the residual pass's FP64 expressions, rounded to
+    // T: the same values) instead of reading the stored ones
     auto load_row = [&](int k, int t) {
         const int kc = k >= 0 && k < nsy ? k : 0;   // in-range address, value masked later
         const int pc = kc * nsx + ixc;
-        qd[t] = invd[pc]; qk[t] = cpk[pc]; qg[t] = g2[pc]; qe[t] = b2[pc]; qb[t] = b1[pc];
+        qe[t] = b2[pc]; qb[t] = b1[pc];
         if constexpr (FIN) {
             qx[t] = xo[pc];
             ql[t] = lo[pc];
+        } else {
+            qd[t] = invd[pc]; qk[t] = cpk[pc]; qg[t] = g2[pc];
         }
     };
 #pragma unroll
     for (int t = 0; t < PF; ++t) load_row(r0 - kLowerHalo + t, t);
     double xw_1 = 0, xw_0 = 0, lw_3 = 0, lw_2 = 0, lw_1 = 0, lw_0 = 0;
+    double xa = 0.0;   // final block: x of the row above the row being loaded (0 off the grid)
+    if constexpr (FIN) {
+        const int ka = r0 - kLowerHalo - 1;
+        if (col_in && ka >= 0 && ka < nsy) xa = xo[ka * nsx + ix];
+    }
+    const double hd = P.h, kpd = P.k0 * P.k1;
 #pragma unroll 1
     for (int g0 = 0; g0 < kLowerRows + 2 * kLowerHalo; g0 += PF)
 #pragma unroll
@@ -896,11 +907,24 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
         d_3 = d_2; d_2 = d_1; d_1 = d_0; k_2 = k_1; k_1 = k_0; g_2 = g_1; g_1 = g_0; e_2 = e_1; e_1 = e_0;
         // row k from ring slot st; row k + PF refills it
         const bool rin = k >= 0 && k < nsy, in = col_in && rin;
-        const T vd = qd[st], vk = qk[st], vg = qg[st], ve = qe[st], vb = qb[st];
+        T vd, vk, vg;
+        const T ve = qe[st], vb = qb[st];
         if constexpr (FIN) {
             xw_1 = xw_0; lw_3 = lw_2; lw_2 = lw_1; lw_1 = lw_0;
             xw_0 = qx[st];
             lw_0 = ql[st];
+            // coefficients of row k: L x from the rows above and below (the
+            // ring's next slot holds row k + 1), as in the residual pass
+            const double xk = in ? xw_0 : 0.0;
+            const double xb = col_in && k + 1 >= 0 && k + 1 < nsy ? qx[(st + 1) % PF] : 0.0;
+            const double Lx = P.idx2 * (wshr(xk) + wshl(xk)) + P.idy2 * (xa + xb) - P.c0 * xk;
+            const double kk0 = P.k0 * (1.0 + P.k1 * xk);
+            vd = st_recip<T>(-1.0 - hd * kk0 * P.c0 + hd * kpd * Lx);
+            vk = T(hd * kk0);
+            vg = T(kpd * (in ? lw_0 : 0.0));
+            xa = xk;
+        } else {
+            vd = qd[st]; vk = qk[st]; vg = qg[st];
         }
         load_row(k + PF, st);
         T bu = 0;
