@@ -188,7 +188,7 @@ constexpr int kLowerCols = kWave - 2 * kLowerHaloX;
 
 struct StreamKernels {
     const void *bsep, *res, *stage, *decide, *jf, *axx, *jft, *v3, *advance;
-    const void *lower, *lower_fin, *v3f;   // fused Schur step, final block; v3 from partials
+    const void *lower, *lower_fin;         // fused Schur step, final block (v3 from partials)
     const void *res1;                      // residual pass with the first Schur step
     const void *box_lim, *box_apply;       // input box: stage limits, then the cut step
 };

@@ -615,16 +615,13 @@ int launch_stream_iteration(nmpc_handle *h, int prec, const nmpc::StreamArgs &a,
             if ((rc = go(k.stage, stages, 256, args))) return rc;
             if ((rc = go(k.decide, dim3(a.count), nmpc::kWave, args))) return rc;
         }
+        // each lower pass forms v3 from the previous step's partials: those of
+        // the residual pass's step are in part2, and the steps alternate
         for (int sch = first_in_res ? 1 : 0; sch <= h->opt.n_schur; ++sch) {
             const bool fin = sch == h->opt.n_schur;
-            void *args[] = {(void *)&a};
-            int which = 1;
-            void *args_first[] = {(void *)&a, (void *)&which};
-            if (sch == 1 && first_in_res && (rc = go(k.v3f, stages, 256, args_first))) return rc;
+            int which = sch == 0 ? -1 : (sch & 1);
+            void *args[] = {(void *)&a, (void *)&which};
             if ((rc = go(fin ? k.lower_fin : k.lower, lower, 256, args))) return rc;
-            int w0 = 0;
-            void *args_v3[] = {(void *)&a, (void *)&w0};
-            if (!fin && (rc = go(k.v3f, stages, 256, args_v3))) return rc;
         }
         void *args[] = {(void *)&a};
         if (h->prob.tau > 0.0) {   // input box: cut the step by the rule

@@ -15,9 +15,12 @@
 // With two point-Jacobi sweeps per solve (the default) the residual pass and
 // each Schur step / final block are single marching-strip passes (one wave
 // per strip of columns and block of rows, stencils in registers and lane
-// shifts, no LDS stencils or barriers). Other sweep counts use row-block
-// passes with LDS-staged stencils: a solve is one pass for its first two
-// sweeps and one per further sweep.
+// shifts, no LDS stencils or barriers): the residual pass also takes the
+// first Schur step (v3 = 0 needs no stage reduction), each later pass forms
+// its v3 from the previous step's unit partials, and the final block forms
+// the stage coefficients from the x and lambda it reads for the update. Other
+// sweep counts use row-block passes with LDS-staged stencils: a solve is one
+// pass for its first two sweeps and one per further sweep.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -778,8 +781,14 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 // 3). Outside the grid d^-1 = 0 makes every value zero, which is the
 // Dirichlet condition of the stencils. The halo lanes' values are wrong near
 // the strip ends, and only the inner lanes are used.
+// which < 0: v3 is read from a.v3 (zero after the stage kernel); which = 0 / 1:
+// each wave forms v3 = (K^u + h B^T y4) / A_uu of its stage from the previous
+// Schur step's unit partials in part / part2 (summed in unit order, T
+// arithmetic as in the fused stage kernel), and a Schur step writes its own
+// partials to the other buffer.
 template <typename T, bool FIN>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_lower(const StreamArgs a)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_lower(const StreamArgs a,
+                                                                                      int which)
 {
     constexpr bool fin = FIN;
     const int lane = threadIdx.x & (kWave - 1);
@@ -818,8 +827,20 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
     }
     // v3 (m <= 64 values): lane j loads v3[j], the others read it with readlane
     T scol[kMaxLy];
+    double v3l = 0.0;
+    if (which < 0) {
+        v3l = lane < m ? a.v3[bi * m + lane] : 0.0;
+    } else if (lane < m) {
+        const int units = a.nrb * a.nstrip;
+        const double *pp = (which ? a.part2 : a.part) + (size_t)bi * units * kMaxM + lane;
+        double sum = 0.0;
+#pragma unroll 8
+        for (int u = 0; u < units; ++u) sum += pp[(size_t)u * kMaxM];
+        const T hT = T(a.P.h);
+        const T auu = T(stream_auu(a, bi, lane));
+        v3l = double((T(a.kun[(size_t)bi * m + lane]) + hT * T(sum)) / auu);
+    }
     {
-        const double v3l = lane < m ? a.v3[bi * m + lane] : 0.0;
         const long long vb = __double_as_longlong(v3l);
         const int vlo = (int)vb, vhi = (int)(vb >> 32);
 #pragma unroll
@@ -973,14 +994,16 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
     }
     const long long upart = (bi * a.nrb + rb) * a.nstrip + sp;
     if constexpr (FIN) {
-        if (rb == 0 && sp == 0) {
+        if (rb == 0 && sp == 0) {   // m <= 64: lane j holds v3_j
             const double *uc = a.U[cur] + bi * m;
             double *un = a.U[nxt] + bi * m;
             const int b = (int)(bi / a.P.N);
-            for (int j = lane; j < m; j += kWave) {
-                un[j] = uc[j] - a.v3[bi * m + j];
+            if (lane < m) {
+                const int j = lane;
+                un[j] = uc[j] - v3l;
+                a.v3[bi * m + j] = v3l;   // the step's input part (input-box rule)
                 if (a.work[b] == 2 && a.du) {   // size of the FP64 correction step
-                    atomicMax(a.du + 2 * b, sabits(a.v3[bi * m + j]));
+                    atomicMax(a.du + 2 * b, sabits(v3l));
                     atomicMax(a.du + 2 * b + 1, sabits(un[j]));
                 }
             }
@@ -1003,7 +1026,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_
         const int bb = lane / P.lx, aa = lane - bb * P.lx;
         T v = 0;
         for (int l = 0; l < kWave; ++l) v += cs[bb][l] * gs[aa][l];
-        a.part[upart * kMaxM + lane] = double(v);
+        (which == 0 ? a.part2 : a.part)[upart * kMaxM + lane] = double(v);
     }
 }
 
@@ -1235,27 +1258,6 @@ __global__ void __launch_bounds__(256, 2) k_st_res1(const StreamArgs a)
     }
 }
 
-// v3 = (K^u + h B^T y4) / (h r + gamma) per stage from the fused pass's unit
-// partials (in unit order; which = 1: those of the residual pass's first
-// Schur step). One workgroup (256 threads) per stage; thread j < m.
-template <typename T>
-__global__ void __launch_bounds__(256) k_st_v3f(const StreamArgs a, int which)
-{
-    const int bi = blockIdx.x;
-    if (bi >= a.count * a.P.N) return;
-    const int b = bi / a.P.N;
-    if (!a.work[b]) return;
-    const int j = threadIdx.x;
-    if (j >= a.P.m) return;
-    const int units = a.nrb * a.nstrip;
-    const double *pp = (which ? a.part2 : a.part) + (size_t)bi * units * kMaxM + j;
-    double s = 0.0;
-#pragma unroll 8
-    for (int u = 0; u < units; ++u) s += pp[(size_t)u * kMaxM];
-    const T h = T(a.P.h);
-    const T auu = T(stream_auu(a, bi, j));
-    a.v3[(size_t)bi * a.P.m + j] = double((T(a.kun[(size_t)bi * a.P.m + j]) + h * T(s)) / auu);
-}
 
 // Input box, after the final block (the step S^{j+1} = S^j - ds written):
 // each stage's fraction-to-the-boundary limit from its input step v3 (one
@@ -1335,7 +1337,6 @@ StreamKernels stream_kernels(int prec)
         k.v3 = (const void *)&k_st_v3<float>;
         k.lower = (const void *)&k_st_lower<float, false>;
         k.lower_fin = (const void *)&k_st_lower<float, true>;
-        k.v3f = (const void *)&k_st_v3f<float>;
         k.res1 = (const void *)&k_st_res1<float>;
     } else {
         k.bsep = (const void *)&k_st_bsep<kModeFp64>;
@@ -1348,7 +1349,6 @@ StreamKernels stream_kernels(int prec)
         k.v3 = (const void *)&k_st_v3<double>;
         k.lower = (const void *)&k_st_lower<double, false>;
         k.lower_fin = (const void *)&k_st_lower<double, true>;
-        k.v3f = (const void *)&k_st_v3f<double>;
         k.res1 = (const void *)&k_st_res1<double>;
     }
     return k;
