@@ -19,6 +19,9 @@ struct GemmArgs {
     int relu;
     unsigned short *Cb;        // bf16 output (may be null)
     int ldcb;
+    int ksplit, kc;            // K split in ksplit parts of kc (blockIdx.z = part); > 1:
+    float *work;               // raw partial products [ksplit][M][N], the epilogue in
+                               // k_gemm_reduce
 };
 
 struct GemmMxArgs {
@@ -57,6 +60,12 @@ const void *gemm_kernel(int ta, int tb);
 const void *gemm_mx_kernel(int ta, int in64, int acc64);
 const void *ls_prepare_kernel();
 const void *splitk_reduce_kernel();
+const void *gemm_reduce_kernel();   // (GemmArgs): split-K sum and the bf16 GEMM's epilogue
+// The bf16 GEMM with K split in `ksplit` parts (work: ksplit * M * N floats),
+// for the network object; ksplit = 1 is nmpc_gemm_bf16.
+int gemm_bf16_split(int ta, int tb, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B,
+                    int ldb, float beta, float *C, int ldc, const float *bias, int relu, uint16_t *Cb,
+                    int ldcb, int ksplit, float *work, void *stream);
 const void *features_kernel();
 const void *relu_grad_kernel();
 const void *colsum_kernel();

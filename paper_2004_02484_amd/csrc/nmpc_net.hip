@@ -47,6 +47,9 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    // split K: this workgroup's part [kb, ke) (kc a multiple of kBK)
+    const int kb = g.ksplit > 1 ? blockIdx.z * g.kc : 0;
+    const int ke = g.ksplit > 1 ? min(g.K, kb + g.kc) : g.K;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -58,11 +61,11 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
     // as one 16-byte load
     const bool vecA = !TA && (g.lda & 7) == 0 && (((uintptr_t)g.A) & 15) == 0;
     const bool vecB = !TB && (g.ldb & 7) == 0 && (((uintptr_t)g.B) & 15) == 0;
-    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+    for (int k0 = kb; k0 < ke; k0 += kBK) {
         // stage a 64 x 32 tile of A and of B^T (8 elements per thread each)
         {
             const int r0 = (tid * 8) / kBK, kk0 = (tid * 8) % kBK;   // !TA: 8 consecutive k
-            if (vecA && m0 + r0 < g.M && k0 + kk0 + 8 <= g.K) {
+            if (vecA && m0 + r0 < g.M && k0 + kk0 + 8 <= ke) {
                 const uint4 q = *(const uint4 *)&g.A[(size_t)(m0 + r0) * g.lda + k0 + kk0];
                 *(uint4 *)&As[r0][kk0] = q;
             } else {
@@ -74,14 +77,14 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                     else    { r = idx / kBK; kk = idx % kBK; }   // consecutive threads walk k
                     const int gm = m0 + r, gk = k0 + kk;
                     unsigned short v = 0;
-                    if (gm < g.M && gk < g.K) v = TA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
+                    if (gm < g.M && gk < ke) v = TA ? g.A[(size_t)gk * g.lda + gm] : g.A[(size_t)gm * g.lda + gk];
                     As[r][kk] = v;
                 }
             }
         }
         {
             const int kk0 = (tid * 8) / kBN, c0 = (tid * 8) % kBN;   // !TB: 8 consecutive n
-            if (vecB && k0 + kk0 < g.K && n0 + c0 + 8 <= g.N) {
+            if (vecB && k0 + kk0 < ke && n0 + c0 + 8 <= g.N) {
                 const uint4 q = *(const uint4 *)&g.B[(size_t)(k0 + kk0) * g.ldb + n0 + c0];
                 const unsigned short *qs = (const unsigned short *)&q;
 #pragma unroll
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                     else    { kk = idx / kBN; c = idx % kBN; }   // consecutive threads walk n
                     const int gn = n0 + c, gk = k0 + kk;
                     unsigned short v = 0;
-                    if (gn < g.N && gk < g.K) v = TB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
+                    if (gn < g.N && gk < ke) v = TB ? g.B[(size_t)gn * g.ldb + gk] : g.B[(size_t)gk * g.ldb + gn];
                     Bs[c][kk] = v;
                 }
             }
@@ -135,12 +138,33 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                 const int gn = n0 + wn + j * 16 + (lane & 15);
                 if (gm >= g.M || gn >= g.N) continue;
                 float v = acc[i][j][r];
+                if (g.ksplit > 1) {   // raw partial; k_gemm_reduce applies the epilogue
+                    g.work[((size_t)blockIdx.z * g.M + gm) * g.N + gn] = v;
+                    continue;
+                }
                 if (g.C && g.beta != 0.f) v += g.beta * g.C[(size_t)gm * g.ldc + gn];
                 if (g.bias) v += g.bias[gn];
                 if (g.relu) v = v > 0.f ? v : 0.f;
                 if (g.C) g.C[(size_t)gm * g.ldc + gn] = v;
                 if (g.Cb) g.Cb[(size_t)gm * g.ldcb + gn] = f2bf(v);
             }
+}
+
+// Split-K epilogue of k_gemm: the parts summed in a fixed order, then beta C,
+// the bias, the ReLU and the fp32 / bf16 outputs. One thread per (m, n).
+__global__ void k_gemm_reduce(const GemmArgs g)
+{
+    const size_t mn = (size_t)g.M * g.N;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= mn) return;
+    const int gm = (int)(t / g.N), gn = (int)(t % g.N);
+    float v = 0.f;
+    for (int p = 0; p < g.ksplit; ++p) v += g.work[(size_t)p * mn + t];
+    if (g.C && g.beta != 0.f) v += g.beta * g.C[(size_t)gm * g.ldc + gn];
+    if (g.bias) v += g.bias[gn];
+    if (g.relu) v = v > 0.f ? v : 0.f;
+    if (g.C) g.C[(size_t)gm * g.ldc + gn] = v;
+    if (g.Cb) g.Cb[(size_t)gm * g.ldcb + gn] = f2bf(v);
 }
 
 // Grouped GEMM on the matrix cores with fp32 or fp64 products: the
@@ -452,6 +476,7 @@ const void *gemm_mx_kernel(int ta, int in64, int acc64)
 }
 const void *ls_prepare_kernel() { return (const void *)&k_ls_prepare; }
 const void *splitk_reduce_kernel() { return (const void *)&k_splitk_reduce<float>; }
+const void *gemm_reduce_kernel() { return (const void *)&k_gemm_reduce; }
 const void *relu_grad_kernel() { return (const void *)&k_relu_grad; }
 const void *colsum_kernel() { return (const void *)&k_colsum; }
 const void *mse_kernel() { return (const void *)&k_mse; }

@@ -15,6 +15,7 @@
 // with hidden = 0 the network is the per-actuator map alone.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +24,7 @@
 #include <vector>
 
 #include "nmpc.h"
+#include "nmpc_net.h"
 
 namespace {
 
@@ -113,8 +115,13 @@ int forward_rows(nmpc_net *n, int count, const double *x0, const double *xref, h
     NET_RC(nmpc_net_features(x0, xref, count, n->cfg.ns, n->cfg.lattice, n->cfg.win, n->cfg.planes,
                              n->Xf, n->X, K0, s));
     if (H > 0) {
-        NET_RC(nmpc_gemm_bf16(0, 0, rows, H, K0, n->X, K0, n->wb[P_W1], H, 0.f, n->H1, H, n->w[P_B1], 1,
-                              n->H1b, H, s));
+        // the first layer has few output tiles and a long K: split K so that
+        // about 512 workgroups run (the partials fit the workspace: at most
+        // 512 tiles of 64 x 64)
+        const int tiles = ((H + 63) / 64) * ((rows + 63) / 64);
+        const int ks = std::max(1, std::min(8, 512 / tiles));
+        NET_RC(nmpc::gemm_bf16_split(0, 0, rows, H, K0, n->X, K0, n->wb[P_W1], H, 0.f, n->H1, H,
+                                     n->w[P_B1], 1, n->H1b, H, ks, n->work, s));
         NET_RC(nmpc_gemm_bf16(0, 0, rows, H, H, n->H1b, H, n->wb[P_W2], H, 0.f, n->H2, H, n->w[P_B2], 1,
                               n->H2b, H, s));
         NET_RC(nmpc_gemm_bf16(0, 0, rows, H, H, n->H2b, H, n->wb[P_W3], H, 0.f, n->H3, H, n->w[P_B3], 1,
@@ -173,7 +180,9 @@ int nmpc_net_create(const nmpc_net_config *cfg, uint64_t seed, int32_t max_count
     A((void **)&n->Y, sizeof(float) * R * N); A((void **)&n->T, sizeof(float) * R * N);
     A((void **)&n->dY, sizeof(float) * R * N); A((void **)&n->dYb, sizeof(uint16_t) * R * N);
     A((void **)&n->sse, sizeof(float) * R);
-    A((void **)&n->work, sizeof(float) * kKsplit * R * N);
+    // split-K partials: the per-actuator map (kKsplit parts of N columns) and
+    // the first hidden layer (up to 8 parts of H columns)
+    A((void **)&n->work, sizeof(float) * std::max<size_t>((size_t)kKsplit * R * N, (size_t)8 * R * H));
     for (int l = 0; l < 3; ++l) {
         A((void **)&n->dH[l], sizeof(float) * R * H);
         A((void **)&n->dHb[l], sizeof(uint16_t) * R * H);

@@ -80,6 +80,35 @@ int scratch_for_current_device(float **out)
 
 }  // namespace
 
+namespace nmpc {
+
+int gemm_bf16_split(int ta, int tb, int M, int N, int K, const uint16_t *A, int lda, const uint16_t *B,
+                    int ldb, float beta, float *C, int ldc, const float *bias, int relu, uint16_t *Cb,
+                    int ldcb, int ksplit, float *work, void *stream)
+{
+    if (M < 1 || N < 1 || K < 1 || !A || !B || (!C && !Cb))
+        return net_fail(NMPC_E_ARG, "gemm: bad sizes or NULL operand");
+    if (lda < (ta ? M : K) || ldb < (tb ? K : N) || (C && ldc < N) || (Cb && ldcb < N))
+        return net_fail(NMPC_E_ARG, "gemm: leading dimension too small");
+    if (beta != 0.f && !C) return net_fail(NMPC_E_ARG, "gemm: beta needs C");
+    if (ksplit < 1 || (ksplit > 1 && !work)) return net_fail(NMPC_E_ARG, "gemm: split K needs a workspace");
+    // parts of a whole number of 32-wide K steps; no empty part
+    const int steps = (K + 31) / 32;
+    ksplit = std::min(ksplit, steps);
+    const int kc = (steps + ksplit - 1) / ksplit * 32;
+    ksplit = (K + kc - 1) / kc;
+    GemmArgs g{M, N, K, A, lda, B, ldb, beta, C, ldc, bias, relu ? 1 : 0, Cb, ldcb, ksplit, kc, work};
+    void *args[] = {(void *)&g};
+    NET_TRY(hipLaunchKernel(gemm_kernel(ta != 0, tb != 0), dim3((N + 63) / 64, (M + 63) / 64, ksplit),
+                            dim3(256), args, 0, (hipStream_t)stream));
+    if (ksplit > 1)
+        NET_TRY(hipLaunchKernel(gemm_reduce_kernel(), dim3((unsigned)(((size_t)M * N + 255) / 256)),
+                                dim3(256), args, 0, (hipStream_t)stream));
+    return NMPC_OK;
+}
+
+}  // namespace nmpc
+
 extern "C" {
 
 int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32_t K,
@@ -87,17 +116,8 @@ int nmpc_gemm_bf16(int32_t trans_a, int32_t trans_b, int32_t M, int32_t N, int32
                    float *C, int32_t ldc, const float *bias, int32_t relu, uint16_t *Cb,
                    int32_t ldcb, void *stream)
 {
-    if (M < 1 || N < 1 || K < 1 || !A || !B || (!C && !Cb))
-        return net_fail(NMPC_E_ARG, "gemm: bad sizes or NULL operand");
-    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N) || (C && ldc < N) || (Cb && ldcb < N))
-        return net_fail(NMPC_E_ARG, "gemm: leading dimension too small");
-    if (beta != 0.f && !C) return net_fail(NMPC_E_ARG, "gemm: beta needs C");
-    nmpc::GemmArgs g{M, N, K, A, lda, B, ldb, beta, C, ldc, bias, relu ? 1 : 0, Cb, ldcb};
-    void *args[] = {(void *)&g};
-    NET_TRY(hipLaunchKernel(nmpc::gemm_kernel(trans_a != 0, trans_b != 0),
-                            dim3((N + 63) / 64, (M + 63) / 64), dim3(256), args, 0,
-                            (hipStream_t)stream));
-    return NMPC_OK;
+    return nmpc::gemm_bf16_split(trans_a, trans_b, M, N, K, A, lda, B, ldb, beta, C, ldc, bias, relu,
+                                 Cb, ldcb, 1, nullptr, stream);
 }
 
 int nmpc_gemm_f32(int32_t trans_a, int32_t M, int32_t N, int32_t K, const float *A, int32_t lda,
