@@ -3,7 +3,7 @@
 // actuator's input trajectory.
 //
 // The hidden layers are GEMMs on bf16 operands with fp32 accumulation on the
-// matrix cores (v_mfma_f32_16x16x16_bf16), so forward, data gradient and
+// matrix cores (v_mfma_f32_16x16x32_bf16), so forward, data gradient and
 // weight gradient are the three operand layouts of one kernel:
 //   forward  C = X W          (A [M][K], B [K][N])
 //   dgrad    C = dY W^T       (B stored [N][K])
@@ -19,7 +19,7 @@
 
 namespace nmpc {
 
-using bf16x4 = __attribute__((ext_vector_type(4))) short;
+using bf16x8 = __attribute__((ext_vector_type(8))) __bf16;
 using f32x4 = __attribute__((ext_vector_type(4))) float;
 
 __device__ __forceinline__ unsigned short f2bf(float f)
@@ -104,26 +104,22 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
             }
         }
         __syncthreads();
+        {
+            // gfx950's 16 x 16 x 32 bf16 MFMA, one per block and K step:
+            // lane l holds row / column l % 16 and k = 8 (l / 16) .. + 7
+            const int kq = 8 * (lane >> 4);
+            bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int ks = 0; ks < kBK; ks += 16) {
-            // fragments: lane l holds rows/cols l % 16, k = 4 (l / 16) .. +3
-            const int kq = ks + 4 * (lane >> 4);
-            bf16x4 af[2], bfr[2];
+            for (int i = 0; i < 2; ++i)
+                __builtin_memcpy(&af[i], &As[wm + i * 16 + (lane & 15)][kq], 16);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const unsigned short *p = &As[wm + i * 16 + (lane & 15)][kq];
-                af[i] = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const unsigned short *p = &Bs[wn + j * 16 + (lane & 15)][kq];
-                bfr[j] = bf16x4{(short)p[0], (short)p[1], (short)p[2], (short)p[3]};
-            }
+            for (int j = 0; j < 2; ++j)
+                __builtin_memcpy(&bfr[j], &Bs[wn + j * 16 + (lane & 15)][kq], 16);
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
