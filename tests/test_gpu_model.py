@@ -240,3 +240,48 @@ def test_model_rejects_what_it_does_not_cover(nm):
     with pytest.raises(nm.NmpcError) as e:
         nm.ModelSolver(make_wave_problem(ns=80, N=4))
     assert e.value.code == nm.NMPC_E_UNSUPPORTED
+
+
+LARGE = {
+    # node counts past 1024 and 2048 take the engine's 4- and 8-node-per-thread
+    # kernels; 64 x 64 is its largest grid
+    "heat64x64": (lambda: dense_heat(nsx=64, nsy=64, N=2, m=4), "jacobi"),
+    "heat40x40": (lambda: dense_heat(nsx=40, nsy=40, N=2, m=4), "sgs"),
+    "plate45": (lambda: make_plate_problem(ns=45, N=2), "sgs"),
+    "wave40": (lambda: make_wave_problem(ns=40, N=2), "jacobi"),
+}
+
+
+@pytest.mark.parametrize("case", list(LARGE))
+def test_model_largest_grids_match_oracle(nm, case):
+    """The engine's multi-node-per-thread kernels (1,600 .. 4,096 nodes, the
+    largest grid it takes) against the oracle at equal k."""
+    make, upper = LARGE[case]
+    P = make()
+    ops = om.Ops(P)
+    x0, xref = instance(P, 3)
+    for k in (1, 2):
+        rc, X, U, L, info = gpu_solve(nm, P, x0, xref, tol=0.0, max_iter=k, upper=UPPERS[upper])
+        o = om.solve(ops, om.state_x0(ops, x0), xref, upper=upper, tol=0.0, max_iter=k)
+        assert rc == nm.NMPC_E_NOCONV and info["iters"] == k
+        compare(ops, o, X, U, L, REL)
+        assert abs(info["r_scaled"] - o["r_scaled"]) <= 1e-9 * o["r_scaled"]
+
+
+def test_model_grid_beyond_the_engine_is_refused(nm):
+    with pytest.raises(nm.NmpcError) as e:
+        nm.ModelSolver(dense_heat(nsx=65, nsy=64, N=2, m=4))
+    assert e.value.code == nm.NMPC_E_UNSUPPORTED
+
+
+def test_model_batch_count_outside_the_handle_is_refused(nm):
+    import torch
+    P = small_plate()
+    s = nm.ModelSolver(P, max_batch=2)
+    for count in (0, 3):
+        x0 = torch.zeros((count, s.nx), dtype=torch.float64, device="cuda")
+        xr = torch.zeros((count, P.nodes), dtype=torch.float64, device="cuda")
+        with pytest.raises(nm.NmpcError) as e:
+            s.solve_batch(x0, xr)
+        assert e.value.code == nm.NMPC_E_ARG
+    s.close()

@@ -282,3 +282,21 @@ def test_widest_fused_grid(nm, upper):
                      upper="jacobi" if upper == 0 else "sgs")
     assert rc == nm.NMPC_E_NOCONV and info["iters"] == 2
     assert rel(X, o["X"]) <= REL and rel(U, o["U"]) <= REL and rel(L, o["LAM"]) <= REL
+
+
+def test_batch_count_outside_the_handle_is_refused(nm):
+    """An empty batch and a batch beyond the handle's capacity are argument
+    errors, reported before any device work (the outputs stay untouched)."""
+    import torch
+    P = make_problem("c0")
+    s = nm.Solver(P, max_batch=2)
+    n = P.nsx * P.nsy
+    for count in (0, 3):
+        x0 = torch.zeros((count, n), dtype=torch.float64, device="cuda")
+        out = tuple(torch.full(sh, 7.0, dtype=torch.float64, device="cuda")
+                    for sh in ((count, P.N, n), (count, P.N, P.m), (count, P.N, n)))
+        with pytest.raises(nm.NmpcError) as e:
+            s.solve_batch(x0, x0.clone(), out=out)
+        assert e.value.code == nm.NMPC_E_ARG
+        assert all(bool((o == 7.0).all()) for o in out)
+    s.close()
