@@ -128,12 +128,11 @@ int forward_rows(nmpc_net *n, int count, const double *x0, const double *xref, h
                               n->H3b, H, s));
         NET_RC(nmpc_gemm_bf16(0, 0, rows, N, H, n->H3b, H, n->wb[P_W4], N, 0.f, n->Y, N, n->w[P_B4], 0,
                               nullptr, 0, s));
-    } else {
-        NET_HIP(hipMemsetAsync(n->Y, 0, sizeof(float) * (size_t)rows * N, s));
     }
-    // per-actuator map: group p takes rows p, p + m, ... (row stride m K0)
-    return nmpc_gemm_f32(0, count, N, K0, n->Xf, m * K0, K0, n->w[P_WS], N, (int64_t)K0 * N, 1.f, n->Y,
-                         m * N, N, m, kKsplit, n->work, s);
+    // per-actuator map: group p takes rows p, p + m, ... (row stride m K0),
+    // added to the hidden path's output, or written alone (beta 0) without it
+    return nmpc_gemm_f32(0, count, N, K0, n->Xf, m * K0, K0, n->w[P_WS], N, (int64_t)K0 * N,
+                         H > 0 ? 1.f : 0.f, n->Y, m * N, N, m, kKsplit, n->work, s);
 }
 
 }  // namespace

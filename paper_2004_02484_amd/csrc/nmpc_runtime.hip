@@ -299,7 +299,6 @@ IterArgs iter_args(const nmpc_handle *h, int count)
     a.P.nsx = p.nsx; a.P.nsy = p.nsy; a.P.n = h->np; a.P.N = h->N; a.P.m = h->m;
     a.P.lx = p.lx; a.P.ly = p.ly;
     a.P.h = p.h; a.P.k0 = p.k0; a.P.k1 = p.k1; a.P.q = p.q; a.P.r = p.r; a.P.gamma = p.gamma;
-    a.P.tau = 0.0; a.P.ulo = a.P.uhi = 0.0;   // the streaming path takes no input box
     a.P.tau = p.tau; a.P.ulo = p.u_lo; a.P.uhi = p.u_hi;
     a.apart = h->d_apart; a.aupd = h->d_aupd;
     const double dx = 1.0 / (p.nsx + 1), dy = 1.0 / (p.nsy + 1);

@@ -372,13 +372,16 @@ class PatchNet:
         _ck(_net_lib().nmpc_net_load(self.hd, path.encode()), "nmpc_net_load")
 
     @classmethod
-    def load(cls, path: str, device: str = "cuda", max_count: int = 256) -> "PatchNet":
+    def load(cls, path: str, device: str = "cuda", max_count: int = 256,
+             mlp: bool = True) -> "PatchNet":
+        """mlp=False builds the network without its hidden path (hidden = 0):
+        the prediction is the per-actuator linear map alone."""
         z = np.load(path, allow_pickle=False)
         header = json.loads(bytes(z["header"]).decode())
         if header.get("format") != "nmpc-patchnet-v2":
             raise ValueError(f"{path}: not a patch-net checkpoint")
         net = cls(N=header["N"], ns=header["ns"], lattice=header["lattice"], win=header["win"],
-                  hidden=header["hidden"], device=device, max_count=max_count)
+                  hidden=header["hidden"] if mlp else 0, device=device, max_count=max_count)
         net.load_state({k: z[k] for k in PARAMS})
         net.meta = header["meta"]
         return net

@@ -393,9 +393,36 @@ def test_trained_network_cuts_iterations_without_moving_the_solution(ws):
     assert err <= 1e-4
 
 
+def test_map_only_network_is_the_full_network_without_its_hidden_output(ws):
+    """PatchNet.load(mlp=False) builds the committed network with hidden = 0:
+    its prediction is the per-actuator map alone, bit for bit the full
+    network's prediction once the hidden path's output layer (W4, b4) is
+    zero; the committed hidden path moves the prediction by far less than the
+    map's own error."""
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(ws.__file__), "weights", "c1_patchnet.npz")
+    full = ws.PatchNet.load(path, max_count=8)
+    lin = ws.PatchNet.load(path, max_count=8, mlp=False)
+    assert lin.H == 0 and full.H > 0
+    P = make_problem("c1")
+    x0, xr = make_batch(P, list(range(2_100_000, 2_100_008)))
+    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
+    u_full = full.predict(dx0, dxr).clone()
+    u_lin = lin.predict(dx0, dxr).clone()
+    full.set_param("W4", np.zeros(full.shape("W4"), np.float32))
+    full.set_param("b4", np.zeros(full.shape("b4"), np.float32))
+    u_zero = full.predict(dx0, dxr)
+    assert torch.equal(u_lin, u_zero)
+    rel = ((u_full - u_lin).abs().amax(dim=(1, 2)) / u_lin.abs().amax(dim=(1, 2))).max().item()
+    print(f"hidden path's share of the prediction: {rel:.2e} (relative, max over instances)")
+    assert 0.0 < rel <= 1e-4
+
+
 def test_full_batch_in_the_benchmark_configuration(ws):
     """The benchmark's launch configuration at its full size: 256 unseen
-    64 x 64, N = 40 instances, learned start with the fallback check, 14
+    64 x 64, N = 40 instances, learned start (the committed network's
+    per-actuator map, as the benchmark runs it) with the fallback check, 14
     rollout sweeps, FP32 sweeps with the final FP64 correction, tol 1e-6.
     Every instance reports convergence; on sampled instances the oracle's
     residual of the returned trajectory meets the tolerance and the inputs
@@ -405,7 +432,7 @@ def test_full_batch_in_the_benchmark_configuration(ws):
     import paper_2004_02484_amd as nm
     import oracle
     path = os.path.join(os.path.dirname(ws.__file__), "weights", "c1_patchnet.npz")
-    net = ws.PatchNet.load(path)
+    net = ws.PatchNet.load(path, mlp=False)
     P = make_problem("c1")
     B = 256
     x0, xr = make_batch(P, list(range(3_000_000, 3_000_000 + B)))
