@@ -478,7 +478,9 @@ typedef struct nmpc_net_config {
 typedef struct nmpc_net nmpc_net;
 
 /* Create with seeded initial weights (He-uniform hidden layers, zero biases,
- * zero map). NMPC_E_ARG for an inconsistent configuration. */
+ * zero map). NMPC_E_ARG for an inconsistent configuration; NMPC_E_UNSUPPORTED
+ * for N > 48 or lattice > 8 (the forward pass's map kernel, which gathers the
+ * features inside the product, holds 48 output columns per instance tile). */
 int nmpc_net_create(const nmpc_net_config *cfg, uint64_t seed, int32_t max_count, nmpc_net **out);
 
 /* u [count][N][L^2] predicted for x0, xref [count][ns^2] (count <= max_count). */
@@ -507,8 +509,11 @@ int nmpc_net_train_step(nmpc_net *net, int32_t count, const double *x0, const do
  * + name) or an activation buffer of the last pass ("X", "Xf", "H1", "H1b",
  * ..., "Y", "T", "dY", "dYb", "dH1".."dH3", "dH1b".."dH3b", "Wb1".."Wb4") to
  * host memory. "X", "Wb*" and the activation names ending in b hold bf16 bit
- * patterns (2 bytes each), the rest fp32. NMPC_E_ARG for an unknown name or
- * count beyond the buffer. */
+ * patterns (2 bytes each), the rest fp32. The forward pass writes "Y" and,
+ * with hidden > 0, "X" and the hidden activations; "Xf" (the fp32 feature
+ * rows) is written by the backward pass only, since the forward pass's map
+ * gathers its features in place. NMPC_E_ARG for an unknown name or count
+ * beyond the buffer. */
 int nmpc_net_get(const nmpc_net *net, const char *name, void *host, int64_t count);
 
 /* Replace a parameter (count = its size; src host or device memory). */

@@ -46,6 +46,17 @@ struct FeatArgs {
     unsigned short *Xb;        // [count * L * L][ld] bf16 (may be null)
 };
 
+// The per-actuator map of the forward pass fused with the feature gather
+// (k_map_fwd): partial sums over K parts of Y[b][p] = X(b, p) Ws[p].
+struct MapArgs {
+    const double *x0, *xref;   // [count][ns * ns]
+    int count, ns, L, win, planes;
+    const float *Ws;           // [L * L][K0][N]
+    int K0, N;
+    int chunks, cpp, ksplit;   // 32-pixel window chunks, chunks per part, parts
+    float *work;               // [L * L][ksplit][count][N]
+};
+
 struct AdamArgs {
     float *w;
     const float *g;
@@ -67,6 +78,12 @@ int gemm_bf16_split(int ta, int tb, int M, int N, int K, const uint16_t *A, int 
                     int ldb, float beta, float *C, int ldc, const float *bias, int relu, uint16_t *Cb,
                     int ldcb, int ksplit, float *work, void *stream);
 const void *features_kernel();
+const void *map_fwd_kernel();
+// Y rows b L^2 + p (row stride L^2 N) = beta Y + X(b, p) Ws[p] for count
+// instances, the features gathered inside the product (work: 8 L^2 count N
+// floats); fused form of nmpc_net_features followed by the grouped fp32 map.
+int map_forward(const double *x0, const double *xref, int count, int ns, int L, int win, int planes,
+                const float *Ws, int K0, int N, float beta, float *Y, float *work, void *stream);
 const void *relu_grad_kernel();
 const void *colsum_kernel();
 const void *mse_kernel();

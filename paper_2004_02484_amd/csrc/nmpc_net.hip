@@ -334,40 +334,146 @@ __global__ void __launch_bounds__(1024) k_ls_prepare(double *G, int n, int ld, l
 // xt, rt, xt^2 - 1/3, xt rt, rt^2 - 1/3 (the first two, or all five); zero
 // outside the grid. Then a one-hot actuator index and zeros up to the row
 // length ld. Row b * L^2 + p; fp32 (Xf) and/or bf16 (Xb) copies.
+// One workgroup per row: each thread takes window pixels, reads x0 and xref
+// once per pixel and writes the pixel's value in every plane (consecutive
+// pixels of a plane are consecutive columns, so the stores coalesce).
 __global__ void k_features(const FeatArgs a)
 {
-    const int rows = a.count * a.L * a.L;
+    const int row = blockIdx.x;
+    const int LL = a.L * a.L, b = row / LL, p = row % LL;
     const int ww = a.win * a.win, feat = a.planes * ww;
-    const int ld = a.ld;
-    const size_t tot = (size_t)rows * ld, stride = (size_t)gridDim.x * blockDim.x;
     const int s = a.ns / a.L, off = (a.win - s) / 2;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-        const int row = (int)(t / ld), col = (int)(t % ld);
-        const int b = row / (a.L * a.L), p = row % (a.L * a.L);
-        float v = 0.f;
-        if (col < feat) {
-            const int ch = col / ww, r = col % ww;
-            const int wy = r / a.win, wx = r % a.win;
-            const int iy = (p / a.L) * s - off + wy, ix = (p % a.L) * s - off + wx;
-            if (iy >= 0 && iy < a.ns && ix >= 0 && ix < a.ns) {
-                const size_t gi = (size_t)b * a.ns * a.ns + (size_t)iy * a.ns + ix;
-                const double xt = a.x0[gi] / 0.1 - 1.0, rt = a.xref[gi] / 0.3;
+    const int iy0 = (p / a.L) * s - off, ix0 = (p % a.L) * s - off;
+    const size_t base = (size_t)row * a.ld;
+    const double *x0 = a.x0 + (size_t)b * a.ns * a.ns, *xr = a.xref + (size_t)b * a.ns * a.ns;
+    auto put = [&](int col, float v) {
+        if (a.Xf) a.Xf[base + col] = v;
+        if (a.Xb) a.Xb[base + col] = f2bf(v);
+    };
+    for (int r = threadIdx.x; r < ww; r += blockDim.x) {
+        const int iy = iy0 + r / a.win, ix = ix0 + r % a.win;
+        double xt = 0.0, rt = 0.0;
+        const bool in = iy >= 0 && iy < a.ns && ix >= 0 && ix < a.ns;
+        if (in) {
+            const int gi = iy * a.ns + ix;
+            xt = x0[gi] / 0.1 - 1.0;
+            rt = xr[gi] / 0.3;
+        }
+        put(r, in ? (float)xt : 0.f);
+        put(ww + r, in ? (float)rt : 0.f);
+        if (a.planes == 5) {
+            put(2 * ww + r, in ? (float)(__dmul_rn(xt, xt) - 1.0 / 3.0) : 0.f);
+            put(3 * ww + r, in ? (float)__dmul_rn(xt, rt) : 0.f);
+            put(4 * ww + r, in ? (float)(__dmul_rn(rt, rt) - 1.0 / 3.0) : 0.f);
+        }
+    }
+    for (int col = feat + threadIdx.x; col < a.ld; col += blockDim.x)
+        put(col, col - feat == p ? 1.f : 0.f);
+}
+
+// Forward pass of the per-actuator map with the features gathered in place
+// (no feature rows in HBM). Workgroup (instance tile of 64, K part, actuator
+// p): for each 32-pixel chunk of the window a thread loads x0 and xref of one
+// pixel for 8 instances (a wave's lanes read consecutive pixels) and a
+// contiguous slice of the chunk's Ws rows for every plane; then per plane the
+// feature values (the same arithmetic as k_features) and the Ws rows go
+// through LDS into v_mfma_f32_16x16x4_f32 (each wave 16 instances x 48
+// columns, N <= 48). The one-hot column's contribution, the row
+// Ws[p][planes win^2 + p], is added by part 0. Partial sums [p][part][b][n]
+// are summed in a fixed order by k_splitk_reduce.
+constexpr int kMapBM = 64, kMapBN = 48, kMapKC = 32;
+
+__global__ void __launch_bounds__(256) k_map_fwd(const MapArgs a)
+{
+    __shared__ float As[kMapBM][kMapKC + 4];   // [instance][pixel]
+    __shared__ float Bs[kMapBN][kMapKC + 4];   // [column][pixel]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.x * kMapBM, part = blockIdx.y, p = blockIdx.z;
+    const int ww = a.win * a.win, feat = a.planes * ww;
+    const int s = a.ns / a.L, off = (a.win - s) / 2;
+    const int iy0 = (p / a.L) * s - off, ix0 = (p % a.L) * s - off;
+    const float *W = a.Ws + (size_t)p * a.K0 * a.N;
+    const int kk = tid & (kMapKC - 1), q0 = tid >> 5;   // A: pixel kk of instances q0 + 8 q
+    const size_t img = (size_t)a.ns * a.ns;
+    f32x4 acc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int c0 = part * a.cpp, c1 = min(a.chunks, c0 + a.cpp);
+    for (int c = c0; c < c1; ++c) {
+        const int r = c * kMapKC + kk;
+        const int iy = iy0 + r / a.win, ix = ix0 + r % a.win;
+        const bool pix = r < ww && iy >= 0 && iy < a.ns && ix >= 0 && ix < a.ns;
+        const int gi = pix ? iy * a.ns + ix : 0;
+        double xt[8], rt[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int gm = m0 + q0 + 8 * q;
+            xt[q] = 0.0; rt[q] = 0.0;
+            if (pix && gm < a.count) {
+                xt[q] = a.x0[(size_t)gm * img + gi] / 0.1 - 1.0;
+                rt[q] = a.xref[(size_t)gm * img + gi] / 0.3;
+            }
+        }
+        // the chunk's Ws rows of a plane are one contiguous block of kr * N floats
+        const int kr = min(kMapKC, ww - c * kMapKC), nb = kr * a.N;
+        float bv[5][6];
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int idx = tid + 256 * e;
+                bv[ch][e] = (ch < a.planes && idx < nb)
+                                ? W[(size_t)(ch * ww + c * kMapKC) * a.N + idx] : 0.f;
+            }
+#pragma unroll
+        for (int ch = 0; ch < 5; ++ch) {
+            if (ch >= a.planes) break;
+            __syncthreads();   // the previous plane's fragments are read
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
                 double f;
                 switch (ch) {
-                case 0: f = xt; break;
-                case 1: f = rt; break;
-                case 2: f = __dmul_rn(xt, xt) - 1.0 / 3.0; break;
-                case 3: f = __dmul_rn(xt, rt); break;
-                default: f = __dmul_rn(rt, rt) - 1.0 / 3.0; break;
+                case 0: f = xt[q]; break;
+                case 1: f = rt[q]; break;
+                case 2: f = __dmul_rn(xt[q], xt[q]) - 1.0 / 3.0; break;
+                case 3: f = __dmul_rn(xt[q], rt[q]); break;
+                default: f = __dmul_rn(rt[q], rt[q]) - 1.0 / 3.0; break;
                 }
-                v = (float)f;
+                const bool in = pix && m0 + q0 + 8 * q < a.count;
+                As[q0 + 8 * q][kk] = in ? (float)f : 0.f;
             }
-        } else if (col < feat + a.L * a.L) {
-            v = (col - feat) == p ? 1.f : 0.f;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) {
+                const int idx = tid + 256 * e;
+                if (idx < kMapKC * kMapBN) {
+                    const int k = idx / a.N, n = idx % a.N;
+                    if (k < kMapKC) Bs[n][k] = idx < nb ? bv[ch][e] : 0.f;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kMapKC; ks += 4) {
+                const int kq = ks + (lane >> 4);
+                const float af = As[w * 16 + (lane & 15)][kq];
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int n = j * 16 + (lane & 15);
+                    const float bf = n < a.N ? Bs[n][kq] : 0.f;
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[j], 0, 0, 0);
+                }
+            }
         }
-        if (a.Xf) a.Xf[t] = v;
-        if (a.Xb) a.Xb[t] = f2bf(v);
     }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = m0 + w * 16 + 4 * (lane >> 4) + r, n = j * 16 + (lane & 15);
+            if (m >= a.count || n >= a.N) continue;
+            float v = acc[j][r];
+            if (part == 0) v += W[(size_t)(feat + p) * a.N + n];
+            a.work[(((size_t)p * a.ksplit + part) * a.count + m) * a.N + n] = v;
+        }
 }
 
 // dH = dH * (H > 0), also as bf16.
@@ -461,6 +567,7 @@ const void *gemm_kernel(int ta, int tb)
     return (const void *)&k_gemm<true, true>;
 }
 const void *features_kernel() { return (const void *)&k_features; }
+const void *map_fwd_kernel() { return (const void *)&k_map_fwd; }
 const void *gemm_mx_kernel(int ta, int in64, int acc64)
 {
     if (!acc64) return ta ? (const void *)&k_gemm_mx<true, float, float>

@@ -109,11 +109,15 @@ int refresh_bf16(nmpc_net *n, hipStream_t s)
 }
 
 // Y [rows][N] for `count` instances (device x0, xref [count][ns^2]).
-int forward_rows(nmpc_net *n, int count, const double *x0, const double *xref, hipStream_t s)
+int forward_rows(nmpc_net *n, int count, const double *x0, const double *xref, hipStream_t s,
+                 bool keep_xf)
 {
     const int rows = count * n->m, H = n->H, N = n->N, K0 = n->K0p, m = n->m;
-    NET_RC(nmpc_net_features(x0, xref, count, n->cfg.ns, n->cfg.lattice, n->cfg.win, n->cfg.planes,
-                             n->Xf, n->X, K0, s));
+    // feature rows in HBM: bf16 for the hidden path, fp32 for the map's
+    // gradient (the map itself gathers its features in place)
+    if (H > 0 || keep_xf)
+        NET_RC(nmpc_net_features(x0, xref, count, n->cfg.ns, n->cfg.lattice, n->cfg.win, n->cfg.planes,
+                                 keep_xf ? n->Xf : nullptr, H > 0 ? n->X : nullptr, K0, s));
     if (H > 0) {
         // the first layer has few output tiles and a long K: split K so that
         // about 512 workgroups run (the partials fit the workspace: at most
@@ -129,10 +133,10 @@ int forward_rows(nmpc_net *n, int count, const double *x0, const double *xref, h
         NET_RC(nmpc_gemm_bf16(0, 0, rows, N, H, n->H3b, H, n->wb[P_W4], N, 0.f, n->Y, N, n->w[P_B4], 0,
                               nullptr, 0, s));
     }
-    // per-actuator map: group p takes rows p, p + m, ... (row stride m K0),
-    // added to the hidden path's output, or written alone (beta 0) without it
-    return nmpc_gemm_f32(0, count, N, K0, n->Xf, m * K0, K0, n->w[P_WS], N, (int64_t)K0 * N,
-                         H > 0 ? 1.f : 0.f, n->Y, m * N, N, m, kKsplit, n->work, s);
+    // per-actuator map (rows p, p + m, ... of Y), added to the hidden path's
+    // output, or written alone (beta 0) without it
+    return nmpc::map_forward(x0, xref, count, n->cfg.ns, n->cfg.lattice, n->cfg.win, n->cfg.planes,
+                             n->w[P_WS], K0, N, H > 0 ? 1.f : 0.f, n->Y, n->work, s);
 }
 
 }  // namespace
@@ -147,6 +151,8 @@ int nmpc_net_create(const nmpc_net_config *cfg, uint64_t seed, int32_t max_count
         cfg->win < cfg->ns / cfg->lattice || (cfg->win - cfg->ns / cfg->lattice) % 2 ||
         (cfg->planes != 2 && cfg->planes != 5) || cfg->hidden < 0 || max_count < 1)
         return nfail(NMPC_E_ARG, "net_create: bad configuration");
+    if (cfg->N > 48 || cfg->lattice > 8)
+        return nfail(NMPC_E_UNSUPPORTED, "net_create: the map kernel takes N <= 48 and lattice <= 8");
     nmpc_net *n = new (std::nothrow) nmpc_net();
     if (!n) return nfail(NMPC_E_OOM, "host allocation failed");
     n->cfg = *cfg;
@@ -179,7 +185,7 @@ int nmpc_net_create(const nmpc_net_config *cfg, uint64_t seed, int32_t max_count
     A((void **)&n->Y, sizeof(float) * R * N); A((void **)&n->T, sizeof(float) * R * N);
     A((void **)&n->dY, sizeof(float) * R * N); A((void **)&n->dYb, sizeof(uint16_t) * R * N);
     A((void **)&n->sse, sizeof(float) * R);
-    // split-K partials: the per-actuator map (kKsplit parts of N columns) and
+    // split-K partials: the per-actuator map (up to kKsplit parts of N columns) and
     // the first hidden layer (up to 8 parts of H columns)
     A((void **)&n->work, sizeof(float) * std::max<size_t>((size_t)kKsplit * R * N, (size_t)8 * R * H));
     for (int l = 0; l < 3; ++l) {
@@ -276,7 +282,7 @@ int nmpc_net_forward(nmpc_net *n, int32_t count, const double *x0, const double 
     if (!n || !x0 || !xref || !u) return nfail(NMPC_E_ARG, "net_forward: NULL argument");
     if (count < 1 || count * n->m > n->max_rows) return nfail(NMPC_E_ARG, "net_forward: count");
     hipStream_t s = (hipStream_t)stream;
-    NET_RC(forward_rows(n, count, x0, xref, s));
+    NET_RC(forward_rows(n, count, x0, xref, s, false));
     return nmpc_unpack_inputs(n->Y, n->N, count, n->N, n->m, kUScale, u, s);
 }
 
@@ -287,7 +293,7 @@ int nmpc_net_backward(nmpc_net *n, int32_t count, const double *x0, const double
     if (count < 1 || count * n->m > n->max_rows) return nfail(NMPC_E_ARG, "net_backward: count");
     hipStream_t s = (hipStream_t)stream;
     const int rows = count * n->m, H = n->H, N = n->N, K0 = n->K0p, m = n->m;
-    NET_RC(forward_rows(n, count, x0, xref, s));
+    NET_RC(forward_rows(n, count, x0, xref, s, true));
     NET_RC(nmpc_pack_inputs(u_target, count, N, m, 1.0f / kUScale, n->T, N, s));
     NET_RC(nmpc_mse_grad(n->Y, N, n->T, N, rows, N, 2.0f / ((float)rows * N), n->dY, n->dYb, N,
                          n->sse, s));

@@ -107,6 +107,30 @@ int gemm_bf16_split(int ta, int tb, int M, int N, int K, const uint16_t *A, int 
     return NMPC_OK;
 }
 
+int map_forward(const double *x0, const double *xref, int count, int ns, int L, int win, int planes,
+                const float *Ws, int K0, int N, float beta, float *Y, float *work, void *stream)
+{
+    if (!x0 || !xref || !Ws || !Y || !work || count < 1 || ns < 1 || L < 1 || L > 8 || ns % L ||
+        win < ns / L || (win - ns / L) % 2 || (planes != 2 && planes != 5) || N < 1 || N > 48 ||
+        K0 < planes * win * win + L * L)
+        return net_fail(NMPC_E_ARG, "map_forward: bad arguments");
+    const int chunks = (win * win + 31) / 32;
+    int ksplit = std::min(8, chunks);
+    const int cpp = (chunks + ksplit - 1) / ksplit;
+    ksplit = (chunks + cpp - 1) / cpp;   // no empty part
+    MapArgs a{x0, xref, count, ns, L, win, planes, Ws, K0, N, chunks, cpp, ksplit, work};
+    void *args[] = {(void *)&a};
+    NET_TRY(hipLaunchKernel(map_fwd_kernel(), dim3((count + 63) / 64, ksplit, L * L), dim3(256), args,
+                            0, (hipStream_t)stream));
+    // the parts summed in a fixed order, beta Y added (row stride L^2 N, group stride N)
+    GemmMxArgs g{count, N, K0, nullptr, 0, nullptr, 0, 1.0, (double)beta, nullptr, Y, L * L * N,
+                 0, 0, (long long)N, ksplit, 0, work};
+    void *rargs[] = {(void *)&g};
+    NET_TRY(hipLaunchKernel(splitk_reduce_kernel(), dim3((unsigned)(((size_t)count * N + 255) / 256), L * L),
+                            dim3(256), rargs, 0, (hipStream_t)stream));
+    return NMPC_OK;
+}
+
 }  // namespace nmpc
 
 extern "C" {
@@ -195,8 +219,7 @@ int nmpc_net_features(const double *x0, const double *xref, int32_t count, int32
         return net_fail(NMPC_E_ARG, "features: ld too small");
     nmpc::FeatArgs a{x0, xref, count, ns, lattice, win, planes, ld, Xf, Xb};
     void *args[] = {(void *)&a};
-    NET_TRY(hipLaunchKernel(nmpc::features_kernel(),
-                            dim3(grid_for((size_t)count * lattice * lattice * ld)), dim3(256),
+    NET_TRY(hipLaunchKernel(nmpc::features_kernel(), dim3(count * lattice * lattice), dim3(256),
                             args, 0, (hipStream_t)stream));
     return NMPC_OK;
 }

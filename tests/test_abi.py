@@ -195,6 +195,11 @@ def test_network_object_arguments_checked():
     assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 0, ctypes.byref(out)) == nm.NMPC_E_ARG
     assert lib.nmpc_net_create(None, 0, 4, ctypes.byref(out)) == nm.NMPC_E_ARG
     assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 4, None) == nm.NMPC_E_ARG
+    for b in (dict(N=49), dict(ns=72, lattice=9, win=8)):   # beyond the map kernel
+        cfg = ws.nmpc_net_config(**{**good, **b})
+        out = ctypes.c_void_p(1234)
+        assert lib.nmpc_net_create(ctypes.byref(cfg), 0, 4, ctypes.byref(out)) == nm.NMPC_E_UNSUPPORTED, b
+        assert out.value is None
     assert lib.nmpc_net_forward(None, 1, None, None, None, None) == nm.NMPC_E_ARG
     assert lib.nmpc_net_backward(None, 1, None, None, None, None, None) == nm.NMPC_E_ARG
     assert lib.nmpc_net_adam_step(None, 1e-3, 0.9, 0.999, 1e-8, 0.0, 0, None) == nm.NMPC_E_ARG

@@ -219,6 +219,40 @@ def _dot_bound(A, W, K, extra=0.0):
     return (K + 2) * U24 * (np.abs(A) @ np.abs(W) + np.abs(extra)) + 1e-30
 
 
+@pytest.mark.parametrize("ns,L,win,planes,count,N", [
+    (64, 4, 32, 5, 3, 40),     # the committed network's shape, a partial instance tile
+    (64, 4, 32, 5, 70, 40),    # two instance tiles
+    (48, 4, 24, 2, 5, 17),     # window of 576 pixels: a partial last chunk
+    (32, 2, 20, 5, 2, 48),     # 48 output columns, the kernel's limit
+    (16, 8, 6, 5, 1, 3),       # 8 x 8 lattice, windows past the grid edge
+])
+def test_map_forward_elementwise(ws, ns, L, win, planes, count, N):
+    """The forward pass of a network without hidden path is the per-actuator
+    map with its features gathered inside the product (no feature rows in
+    HBM): every output against the fp64 product of the fp32 feature rows of
+    the definition (rounded once from fp64) with Ws, within the fp32
+    accumulation bound of K0 + 8 terms (the split-K parts and the one-hot
+    row); the returned inputs are 4 Y, transposed to [count][N][L^2]."""
+    import torch
+    rng = np.random.default_rng(ns + L + win + count)
+    cls = type("Net", (ws.PatchNet,), {"PLANES": planes})   # the object takes 2 or 5 planes
+    net = cls(N=N, ns=ns, lattice=L, win=win, hidden=0, max_count=count)
+    Ws = rng.normal(size=net.shape("Ws")).astype(np.float32) * 0.05
+    net.set_param("Ws", Ws)
+    x0 = 0.1 + 0.05 * rng.standard_normal((count, ns * ns))
+    xr = 0.3 * rng.random((count, ns * ns))
+    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
+    u = net.predict(dx0, dxr).cpu().numpy()
+    rows, m = count * L * L, L * L
+    Y = net.get("Y", rows=rows).astype(np.float64)
+    X32 = net_ref.features(x0, xr, ns, L, win, planes, net.K0p).astype(np.float32).astype(np.float64)
+    want = net_ref.skip(Ws.astype(np.float64), X32)
+    bound = (net.K0p + 8) * U24 * net_ref.skip(np.abs(Ws).astype(np.float64), np.abs(X32)) + 1e-30
+    assert np.all(np.abs(Y - want) <= bound)
+    np.testing.assert_array_equal(u, 4.0 * Y.astype(np.float32).astype(np.float64)
+                                  .reshape(count, m, N).transpose(0, 2, 1))
+
+
 def test_network_layers_elementwise(ws):
     """Each layer of the GPU pass against its own definition evaluated in
     float64 on the GPU's inputs to that layer: every element within the fp32
