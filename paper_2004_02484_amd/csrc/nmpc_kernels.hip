@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kWave * WB, OCC) k_iterate(const IterArgs a)
             v.i = i;
             v.last = i == N - 1;
             unsigned long long acc[2] = {0, 0};
-            stage_body<T, CX, RY, LX, LY>(a, a.P, v, c, acc);
+            stage_body<T, CX, RY, LX, LY, CX == 4>(a, a.P, v, c, acc);
         }
     }
 }

@@ -683,6 +683,33 @@ __device__ __forceinline__ void prefetch_xl(const Ctx &c, const double *x, const
 // c.off.total, 16 bytes per lane (1 KB per wave instruction) spread over the
 // waves, without registers; read after s_waitcnt and a barrier. Lanes past the
 // end re-read the last 16 bytes into slots nobody reads (n is even).
+// A lane's tile of a padded stage slice (row stride 16 CX): rows past the
+// grid are not read; columns past the grid read the row's padding, which is
+// masked to zero here, so the even-width tiles load 16 bytes at a time.
+template <int CX, int RY>
+__device__ __forceinline__ void load_tile(const double *base, double (&o)[RY][CX], int ix0, int iy0,
+                                          int nsx, int nsy)
+{
+    constexpr int sx = 16 * CX;
+#pragma unroll
+    for (int t = 0; t < RY; ++t) {
+        const bool row = iy0 + t < nsy;
+        const double *r = base + (size_t)(iy0 + t) * sx + ix0;
+        if constexpr (CX % 2 == 0) {
+#pragma unroll
+            for (int q = 0; q < CX; q += 2) {
+                double2 v = make_double2(0.0, 0.0);
+                if (row) v = *reinterpret_cast<const double2 *>(r + q);
+                o[t][q] = ix0 + q < nsx ? v.x : 0.0;
+                o[t][q + 1] = ix0 + q + 1 < nsx ? v.y : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < CX; ++q) o[t][q] = row && ix0 + q < nsx ? r[q] : 0.0;
+        }
+    }
+}
+
 __device__ __forceinline__ void stage_copy(const Ctx &c, const double *x, int n)
 {
     typedef const __attribute__((address_space(1))) void *GPtr;
@@ -745,8 +772,12 @@ __device__ __forceinline__ void load_tables(Ctx &c, const double *gxs, const dou
 }
 
 // acc (thread 0 only): running bit-pattern max of (r_scaled, r_paper) over
-// the stages processed with res_at == -1.
-template <typename T, int CX, int RY, int LX, int LY>
+// the stages processed with res_at == -1. WIDE: the residual's global reads
+// of x_i, lambda_i, lambda_{i+1} and xref_i go through load_tile (16-byte
+// loads; the batch kernel's 4-column tiles, where this saves memory
+// instructions without spills; the other kernels and tiles keep element
+// loads, which need fewer registers there).
+template <typename T, int CX, int RY, int LX, int LY, bool WIDE = false>
 __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &P,
                                            const StageLoc &v, Ctx &c,
                                            unsigned long long (&acc)[2])
@@ -788,20 +819,25 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
     double btl;   // (B^T lambda_i)_j in lane j < M
     {
         double xc[RY][CX], lc[RY][CX], Lx[RY][CX];
+        if constexpr (WIDE) {   // the batch kernel: no prefetched slices
+            load_tile<CX, RY>(Xc, xc, ix0, iy0, P.nsx, P.nsy);
+            load_tile<CX, RY>(Lc, lc, ix0, iy0, P.nsx, P.nsy);
+        } else {
 #pragma unroll
-        for (int t = 0; t < RY; ++t)
+            for (int t = 0; t < RY; ++t)
 #pragma unroll
-            for (int q = 0; q < CX; ++q) {
-                const bool v = valid(t, q);
-                if (sv.pf) {
-                    const double *px = lds_ptr<double>(c, c.off.total);
-                    xc[t][q] = v ? px[pidx(t, q)] : 0.0;
-                    lc[t][q] = v ? px[gs_pf_doubles(n) + pidx(t, q)] : 0.0;
-                } else {
-                    xc[t][q] = v ? Xc[pidx(t, q)] : 0.0;
-                    lc[t][q] = v ? Lc[pidx(t, q)] : 0.0;
+                for (int q = 0; q < CX; ++q) {
+                    const bool v = valid(t, q);
+                    if (sv.pf) {
+                        const double *px = lds_ptr<double>(c, c.off.total);
+                        xc[t][q] = v ? px[pidx(t, q)] : 0.0;
+                        lc[t][q] = v ? px[gs_pf_doubles(n) + pidx(t, q)] : 0.0;
+                    } else {
+                        xc[t][q] = v ? Xc[pidx(t, q)] : 0.0;
+                        lc[t][q] = v ? Lc[pidx(t, q)] : 0.0;
+                    }
                 }
-            }
+        }
         if (c.tid < M) uvec[c.tid] = a.U[v.src][v.uo + (size_t)v.i * M + c.tid];
         if (v.tgx) load_tables<CX, RY, LX, LY>(c, v.tgx, v.tgy, P.nsx, P.nsy, false);
         if (v.xp_lds) stage_copy(c, Xp, n);   // x_{i-1}, requested with x_i
@@ -824,6 +860,18 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
             __builtin_amdgcn_sched_barrier(0);
             nbsum<double, CX, RY>(g, Lg, c);
             __builtin_amdgcn_sched_barrier(0);
+            double lnt[RY][CX], xrt[RY][CX];
+            if constexpr (WIDE) {
+                load_tile<CX, RY>(Xr, xrt, ix0, iy0, P.nsx, P.nsy);
+                if (last) {
+#pragma unroll
+                    for (int t = 0; t < RY; ++t)
+#pragma unroll
+                        for (int q = 0; q < CX; ++q) lnt[t][q] = 0.0;
+                } else {
+                    load_tile<CX, RY>(Ln, lnt, ix0, iy0, P.nsx, P.nsy);
+                }
+            }
 #pragma unroll
             for (int t = 0; t < RY; ++t)
 #pragma unroll
@@ -832,8 +880,8 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
                     // valid neighbour is dropped (norms, right-hand sides)
                     double kl = 0.0, klr = 0.0;
                     if (valid(t, q)) {
-                        const double ln = last ? 0.0 : Ln[pidx(t, q)];
-                        const double xr = Xr[pidx(t, q)];
+                        const double ln = WIDE ? lnt[t][q] : (last ? 0.0 : Ln[pidx(t, q)]);
+                        const double xr = WIDE ? xrt[t][q] : Xr[pidx(t, q)];
                         const double gg = P.k0 * (1.0 + P.k1 * xc[t][q]) * lc[t][q];
                         const double rest = h * (P.q * (xc[t][q] - xr) + (Lg[t][q] - P.c0 * gg) +
                                                  kp * Lx[t][q] * lc[t][q]);
