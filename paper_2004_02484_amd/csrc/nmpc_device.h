@@ -75,6 +75,8 @@ struct IterArgs {
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region
     int xp_lds;                     // Jacobi kernel: x_{i-1} is copied into LDS (after the
                                     // layout's total) while the stage's first stencils run
+    int eval_fp64;                  // FP32 kernel: also takes the FP64 phase's owed
+                                    // evaluation-only units (residual in FP64, no step)
     double omega;                   // Gauss-Seidel kernel: over-relaxation of each stage's step
     int fp32_finish;                // FP32 phase: a passed test finishes (no FP64 correction)
     double *apart;                  // input box: [B][N] step limit of each stage's update

@@ -342,9 +342,13 @@ int launch_iterate(nmpc_handle *h, int prec, const IterArgs &a, hipStream_t s)
 
 // Captured sequence of check_every launches of the precision-`prec` kernel.
 // After FP32 sweeps the FP64 phase is the final correction, which takes three
-// launches per instance (the FP64 re-evaluation of the accepted iterate, the
-// correction step, the final test): its graph is four launches long, and the
-// host relaunches it if an instance needs more.
+// launches per instance (the FP64 re-evaluation of the accepted iterate with
+// the correction step, the evaluation of its result, the final test): its
+// graph is four launches long, and the host relaunches it if an instance needs
+// more. Its second launch, where the evaluations fall, runs the FP32 kernel
+// (two workgroups per CU against one) with eval_fp64 set: it evaluates the
+// owed results and leaves every other unit of the FP64 phase to the next
+// launch.
 int ensure_graph(nmpc_handle *h, int prec, int count)
 {
     const int len = (prec == nmpc::kModeFp64 && main_prec(h->opt) == nmpc::kModeFp32)
@@ -357,9 +361,11 @@ int ensure_graph(nmpc_handle *h, int prec, int count)
     IterArgs a = iter_args(h, count);
     HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     int rc = NMPC_OK;
+    const bool phase64 = prec == nmpc::kModeFp64 && main_prec(h->opt) == nmpc::kModeFp32;
     for (int t = 0; t < len && rc == NMPC_OK; ++t) {
         a.kofs = t;
-        rc = launch_iterate(h, prec, a, h->stream);
+        a.eval_fp64 = phase64 && t == 1 ? 1 : 0;
+        rc = launch_iterate(h, a.eval_fp64 ? nmpc::kModeFp32 : prec, a, h->stream);
     }
     if (rc == NMPC_OK) {
         int *ctr = h->d_ctr;

@@ -521,7 +521,9 @@ struct Decision {
 //                                     FP64 step S^{j+1}; owe the evaluation of S^{j+1}
 //   FP64 mode, test passed, owed   -> evaluate S^{j+1} without an update (its
 //                                     own test decides; a failed test makes
-//                                     the next step re-evaluate S^{j+1})
+//                                     the next step re-evaluate S^{j+1}); the
+//                                     FP32 kernel takes this too in a launch
+//                                     with a.eval_fp64
 //   FP64 mode, test passed         -> finished, S^j returned
 // Nb: the instance's stages; rbase: offset of its stage residuals within a
 // residual slot (slot stride a.rslot).
@@ -584,7 +586,9 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
                     if (a.fp32_finish) fin = kStatusOk;
                     else ns.mode = kModeFp64Redo;
                 } else if (s.pending) {
-                    if (PREC == kModeFp64) {
+                    // an evaluation only: the FP32 kernel may take it when
+                    // the launch asks (its residual is the same FP64 code)
+                    if (PREC == kModeFp64 || a.eval_fp64) {
                         ns.pending = 0;
                         d.work = true;
                         d.j = s.j + 1;
@@ -605,7 +609,7 @@ __device__ Decision decide(const IterArgs &a, Ctx &c, int b, int stage, int k, i
             ns.e = s.e + 1;
             ns.j = d.j;
             ns.eonly = d.eval_only ? 1 : 0;
-            if (PREC == kModeFp32) ns.f32 = s.f32 + 1;
+            if (PREC == kModeFp32 && s.mode == kModeFp32) ns.f32 = s.f32 + 1;
         }
         if (fin >= 0) ns.status = fin;
     }
@@ -1092,15 +1096,34 @@ __device__ __forceinline__ void stage_body(const IterArgs &a, const DevProblem &
         __syncthreads();
         Xs = lds_ptr<double>(c, c.off.total);
     }
+    if constexpr (WIDE) {
+        // 16-byte stores of whole tile rows: the row padding receives zeros
 #pragma unroll
-    for (int t = 0; t < RY; ++t)
+        for (int t = 0; t < RY; ++t) {
+            if (iy0 + t >= P.nsy) continue;
 #pragma unroll
-        for (int q = 0; q < CX; ++q)
-            if (valid(t, q)) {
+            for (int q = 0; q < CX; q += 2) {
                 const int p = pidx(t, q);
-                Xn[p] = Xs[p] - om * double(y5[t][q]);
-                Lw[p] = Lc[p] - om * double(y4[t][q]);
+                const bool v0 = ix0 + q < P.nsx, v1 = ix0 + q + 1 < P.nsx;
+                const double x0v = v0 ? Xs[p] - om * double(y5[t][q]) : 0.0;
+                const double x1v = v1 ? Xs[p + 1] - om * double(y5[t][q + 1]) : 0.0;
+                const double l0v = v0 ? Lc[p] - om * double(y4[t][q]) : 0.0;
+                const double l1v = v1 ? Lc[p + 1] - om * double(y4[t][q + 1]) : 0.0;
+                *reinterpret_cast<double2 *>(Xn + p) = make_double2(x0v, x1v);
+                *reinterpret_cast<double2 *>(Lw + p) = make_double2(l0v, l1v);
             }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q)
+                if (valid(t, q)) {
+                    const int p = pidx(t, q);
+                    Xn[p] = Xs[p] - om * double(y5[t][q]);
+                    Lw[p] = Lc[p] - om * double(y4[t][q]);
+                }
+    }
     if (c.tid < M) {
         const double un = uvec[c.tid] - om * v3me;
         a.U[v.dst][v.uo + (size_t)v.i * M + c.tid] = un;
