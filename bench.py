@@ -628,9 +628,11 @@ def main():
                     help="FP32 sweeps: 0 (default) ends with the final FP64 correction step; "
                          "1 returns the iterate whose FP64-evaluated test passed in the FP32 "
                          "phase (same test, same tolerance, no FP64 step)")
-    ap.add_argument("--warm-sweeps", type=int, default=14,
+    ap.add_argument("--warm-sweeps", type=int, default=10,
                     help="sweeps per stage (point-Jacobi, Chebyshev weights) when the library "
-                         "builds the learned start's states and costates")
+                         "builds the learned start's states")
+    ap.add_argument("--warm-sweeps-lambda", type=int, default=14,
+                    help="the same for the learned start's costates")
     ap.add_argument("--start", choices=["learned", "cold"], default="learned",
                     help="start timed for the value (the other one is reported beside it)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -669,15 +671,16 @@ def main():
     P = make_problem("c1")
     B = args.batch
     prec = nm.NMPC_FP32_SWEEP if args.precision == "fp32" else nm.NMPC_FP64
-    # warm_sweeps: Chebyshev-weighted point-Jacobi sweeps per stage when the
-    # library builds states and costates from the predicted inputs (12 already
-    # give the iteration counts of many more on this grid and step, 10 leave an
-    # error the upper iteration takes longer to remove; 14 keep a margin)
+    # warm_sweeps / warm_sweeps_lambda: Chebyshev-weighted point-Jacobi sweeps
+    # per stage when the library builds the states / the costates from the
+    # predicted inputs. On this grid and step the states keep the iteration
+    # counts down to 8 sweeps (6 cost three times the iterations), the
+    # costates down to 12 (10 cost half again as many): 10 and 14 keep a margin
     inner = dict(n_sweep=args.n_sweep, n_schur=args.n_schur)
     fin = args.fp32_finish if prec == nm.NMPC_FP32_SWEEP else 0
     solver = nm.Solver(P, max_batch=B, precision=prec, tol=1e-6, max_iter=5000,
                        check_every=16, fallback=1, upper=UPPER[args.upper],
-                       warm_sweeps=args.warm_sweeps,
+                       warm_sweeps=args.warm_sweeps, warm_sweeps_lambda=args.warm_sweeps_lambda,
                        fp32_finish=fin, **inner)
     kind = "jacobi" if args.upper == "jacobi" else "gs"
     net = None
@@ -797,7 +800,8 @@ def main():
         # on the same batches (the FP32-sweep variant is the timed value)
         s64 = nm.Solver(P, max_batch=B, precision=nm.NMPC_FP64, tol=1e-6, max_iter=5000,
                         check_every=16, fallback=1, upper=UPPER[args.upper],
-                        warm_sweeps=args.warm_sweeps, **inner)
+                        warm_sweeps=args.warm_sweeps, warm_sweeps_lambda=args.warm_sweeps_lambda,
+                        **inner)
         timed_steps(s64, dev_in[:1], out, net, ubuf)
         timed_steps(s64, dev_in[:1], out)
         t64, it64, _, w64 = timed_steps(s64, dev_in[args.warmup:], out, net, ubuf)

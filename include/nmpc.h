@@ -134,9 +134,9 @@ typedef struct nmpc_options {
                              chosen by the tile autotuner); unsupported values
                              give NMPC_E_UNSUPPORTED */
     int32_t warm_sweeps;  /* sweeps per stage (point-Jacobi with Chebyshev
-                             weights) for the states and for the costates
-                             when a start is built from an input trajectory
-                             (0 = 24) */
+                             weights) for the states, and for the costates
+                             unless warm_sweeps_lambda is set, when a start is
+                             built from an input trajectory (0 = 24) */
     int32_t fallback;     /* 1: for a warm start, compare its residual with the
                              cold start's per instance and keep the smaller
                              (non-finite counts as larger) */
@@ -173,6 +173,11 @@ typedef struct nmpc_options {
     int32_t residual;     /* NMPC_RES_SCALED (default): stop when r_scaled <= tol;
                              NMPC_RES_PAPER: stop when r_paper = |K|_inf <= tol,
                              the paper's rule (Table tab_NMPC_para) */
+    int32_t warm_sweeps_lambda; /* sweeps per stage for the costates of a start
+                             built from an input trajectory (0 = warm_sweeps);
+                             0..1000. The costate error enters r_scaled divided
+                             by h, the state error not, so the costates may
+                             need more sweeps than the states */
 } nmpc_options;
 
 /* Per-instance result information. */

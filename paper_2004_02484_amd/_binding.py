@@ -59,7 +59,7 @@ class nmpc_options(ctypes.Structure):
                 ("warm_sweeps", ctypes.c_int32), ("fallback", ctypes.c_int32),
                 ("upper", ctypes.c_int32), ("path", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("fp32_finish", ctypes.c_int32),
-                ("residual", ctypes.c_int32)]
+                ("residual", ctypes.c_int32), ("warm_sweeps_lambda", ctypes.c_int32)]
 
 
 class nmpc_model_problem(ctypes.Structure):

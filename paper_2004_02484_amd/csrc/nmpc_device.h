@@ -70,6 +70,7 @@ struct IterArgs {
     long long rslot;                // residual slot stride of rst / pst
     double tol;
     int max_iter, n_sw, n_schur;
+    int n_sw_lam;                   // rollout: costate sweeps per stage (n_sw: state sweeps)
     int residual_only, res_slot;
     int res_first_stage;            // residual_only: unit b evaluates stage 0 of instance b only
     int gs_pf;                      // Gauss-Seidel kernel: LDS holds a stage prefetch region

@@ -149,7 +149,8 @@ __device__ __forceinline__ double cheb_next(int s, double w, double mu2)
 // which the weights bring to about 0.23 per sweep. The bound is taken per
 // stage from the sweep's starting point, with 2 % margin; a spectrum slightly
 // wider than the bound still converges, only more slowly. The costate sweeps
-// start from the lambda already in buffer 0 (a supplied guess, or 0). One
+// start from the lambda already in buffer 0 (a supplied guess, or 0). a.n_sw
+// sweeps per stage for the states, a.n_sw_lam for the costates. One
 // workgroup per instance.
 // The start's KKT residual comes out of the same pass: after each stage's
 // sweeps the kernel evaluates that stage's rows (K^x from the built state,
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
     auto valid = [&](int t, int q) { return ix0 + q < P.nsx && iy0 + t < P.nsy; };
     auto pidx = [&](int t, int q) { return (iy0 + t) * sx + ix0 + q; };
     const double h = P.h, kp = P.k0 * P.k1;
-    const int nsw = a.n_sw;
+    const int nsw = a.n_sw, nswl = a.n_sw_lam > 0 ? a.n_sw_lam : a.n_sw;
     unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
 
     // ---- states, forward in the horizon
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
             for (int q = 0; q < CX; ++q) mu = fmax(mu, P.c0 * cpk[t][q] * fabs(invd[t][q]));
         mu = fmin(1.02 * block_max_nonneg(mu, c, nrm), 0.995);
         double lo[RY][CX], w = 1.0;
-        for (int s = 0; s < nsw; ++s) {
+        for (int s = 0; s < nswl; ++s) {
             double z[RY][CX], nb[RY][CX];
 #pragma unroll
             for (int t = 0; t < RY; ++t)

@@ -205,6 +205,8 @@ int check_options(const nmpc_options *o)
         return fail(NMPC_E_ARG, "xref_per_stage must be 0 or 1");
     if (o->tile_rows < 0 || o->tile_rows > 16) return fail(NMPC_E_ARG, "tile_rows must be 0..16");
     if (o->warm_sweeps < 0 || o->warm_sweeps > 1000) return fail(NMPC_E_ARG, "warm_sweeps must be 0..1000");
+    if (o->warm_sweeps_lambda < 0 || o->warm_sweeps_lambda > 1000)
+        return fail(NMPC_E_ARG, "warm_sweeps_lambda must be 0..1000");
     if (o->fallback != 0 && o->fallback != 1) return fail(NMPC_E_ARG, "fallback must be 0 or 1");
     if (o->upper < NMPC_UPPER_JACOBI || o->upper > NMPC_UPPER_SGS)
         return fail(NMPC_E_ARG, "unknown upper layer");
@@ -473,6 +475,7 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         IterArgs a = iter_args(h, count);
         a.units = count;
         a.n_sw = h->opt.warm_sweeps > 0 ? h->opt.warm_sweeps : 24;
+        a.n_sw_lam = h->opt.warm_sweeps_lambda > 0 ? h->opt.warm_sweeps_lambda : a.n_sw;
         void *args[] = {(void *)&a};
         HIP_TRY(hipLaunchKernel(h->roll.fn, dim3(count), dim3(nmpc::kWave * h->roll.waves), args,
                                 h->roll.lds, h->stream));
@@ -875,6 +878,7 @@ void nmpc_default_options(nmpc_options *opt)
     opt->omega = 1.0;
     opt->fp32_finish = 0;
     opt->residual = NMPC_RES_SCALED;
+    opt->warm_sweeps_lambda = 0;
 }
 
 }  // extern "C"

@@ -78,7 +78,9 @@ def test_unsupported_shapes_reported():
                                          ("max_iter", -1), ("tol", -1.0), ("tile_rows", -1),
                                          ("tile_rows", 17), ("upper", 4), ("upper", -1),
                                          ("path", 3), ("omega", 0.0), ("omega", 2.0),
-                                         ("omega", 1.2), ("fp32_finish", 2)])
+                                         ("omega", 1.2), ("fp32_finish", 2),
+                                         ("warm_sweeps", -1), ("warm_sweeps", 1001),
+                                         ("warm_sweeps_lambda", -1), ("warm_sweeps_lambda", 1001)])
 def test_invalid_options_rejected(field, value):
     o = nm.nmpc_default_options(**{field: value})
     with pytest.raises(nm.NmpcError) as e:

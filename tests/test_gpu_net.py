@@ -456,8 +456,9 @@ def test_map_only_network_is_the_full_network_without_its_hidden_output(ws):
 def test_full_batch_in_the_benchmark_configuration(ws):
     """The benchmark's launch configuration at its full size: 256 unseen
     64 x 64, N = 40 instances, learned start (the committed network's
-    per-actuator map, as the benchmark runs it) with the fallback check, 14
-    rollout sweeps, FP32 sweeps with the final FP64 correction, tol 1e-6.
+    per-actuator map, as the benchmark runs it) with the fallback check, 10
+    state and 14 costate rollout sweeps, FP32 sweeps with the final FP64
+    correction, tol 1e-6.
     Every instance reports convergence; on sampled instances the oracle's
     residual of the returned trajectory meets the tolerance and the inputs
     meet the FP32-sweep bar against the oracle's exact solution."""
@@ -472,7 +473,7 @@ def test_full_batch_in_the_benchmark_configuration(ws):
     x0, xr = make_batch(P, list(range(3_000_000, 3_000_000 + B)))
     dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xr, device="cuda")
     s = nm.Solver(P, max_batch=B, precision=nm.NMPC_FP32_SWEEP, tol=1e-6, max_iter=5000,
-                  check_every=16, fallback=1, warm_sweeps=14)
+                  check_every=16, fallback=1, warm_sweeps=10, warm_sweeps_lambda=14)
     up = net.predict(dx0, dxr)
     rc, X, U, L, infos = s.solve_batch(dx0, dxr, warm=(None, up, None))
     assert rc == nm.NMPC_OK

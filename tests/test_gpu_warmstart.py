@@ -139,21 +139,22 @@ def test_fallback_decision_follows_the_start_residuals(nm, c1_case, name, per_st
     assert seen == {0, 2}
 
 
-@pytest.mark.parametrize("sweeps,bar", [(14, 1e-6), (24, 1e-11)])
-def test_rollout_matches_the_exact_input_start(nm, c1_case, sweeps, bar):
+@pytest.mark.parametrize("sweeps,sweeps_lam,bar", [(14, 0, 1e-6), (24, 0, 1e-11), (10, 14, 3e-4)])
+def test_rollout_matches_the_exact_input_start(nm, c1_case, sweeps, sweeps_lam, bar):
     """The start built on the GPU from u (Chebyshev-weighted point-Jacobi
-    sweeps per stage) against the oracle's start solved to rounding. With the
-    sweep matrices' spectral radius mu ~ 0.44 the weights reduce a stage's
-    error by about 2 r^s, r = mu / (1 + sqrt(1 - mu^2)) ~ 0.23: ~3e-9 after
-    14 sweeps, rounding after 24; the bars allow for the 40 stages passing
-    their errors on."""
+    sweeps per stage; sweeps_lam > 0: that many for the costates) against the
+    oracle's start solved to rounding. With the sweep matrices' spectral
+    radius mu ~ 0.44 the weights reduce a stage's error by about 2 r^s, r =
+    mu / (1 + sqrt(1 - mu^2)) ~ 0.23: ~3e-9 after 14 sweeps, ~8e-7 after 10,
+    rounding after 24; the bars allow for the 40 stages passing their errors
+    on (the costates inherit the states' error)."""
     P, x0, xref, ex = c1_case
     U = ex["U"] * (1.0 + 1e-2 * np.random.default_rng(8).standard_normal(ex["U"].shape))
-    s = nm.Solver(P, tol=0.0, max_iter=0, warm_sweeps=sweeps)
+    s = nm.Solver(P, tol=0.0, max_iter=0, warm_sweeps=sweeps, warm_sweeps_lambda=sweeps_lam)
     rc, X, Uo, L, info = s.solve(x0, xref, warm=(None, U, None))
     assert info["start_used"] == 2
     Xe, _, Le = input_start(P, x0, xref, U)
     ex_ = np.abs(X - Xe).max() / np.abs(Xe).max()
     el_ = np.abs(L - Le).max() / np.abs(Le).max()
-    print(f"{sweeps} sweeps: state rel. error {ex_:.2e}, costate rel. error {el_:.2e}")
+    print(f"{sweeps}/{sweeps_lam} sweeps: state rel. error {ex_:.2e}, costate rel. error {el_:.2e}")
     assert ex_ <= bar and el_ <= bar
