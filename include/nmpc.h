@@ -126,7 +126,13 @@ typedef struct nmpc_options {
                              sweep of an iteration) and FP64 iterations continue
                              until the test passes at an FP64-stepped iterate
                              (final FP64 correction) */
-    int32_t check_every;  /* iterations between host convergence polls (>= 1) */
+    int32_t check_every;  /* iterations between host convergence polls (>= 1).
+                             An FP32-sweep Jacobi solve whose handle's previous
+                             solve converged in J iterations, J + 4 <=
+                             check_every, starts with one graph of J + 1 FP32
+                             launches and the three of the final FP64
+                             correction, so a solve like the previous one
+                             needs a single poll */
     int32_t xref_per_stage; /* 0: xref is [n] per instance; 1: [N][n] */
     int32_t tile_rows;    /* grid rows per lane of the stage kernel's register
                              tile for the main precision; 0 = default. Other

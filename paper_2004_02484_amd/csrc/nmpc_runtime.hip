@@ -89,9 +89,12 @@ struct nmpc_handle {
     double kernel_ms = 0.0;
     long long launches = 0;
     long long units = 0;
-    hipGraph_t graph[2] = {nullptr, nullptr};
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int graph_count[2] = {-1, -1}, graph_len[2] = {0, 0};
+    // [0], [1]: graphs of the FP32 and FP64 kernels; [2]: the first graph of
+    // an FP32-sweep solve sized from the previous solve (ensure_first_graph)
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+    int graph_count[3] = {-1, -1, -1}, graph_len[3] = {0, 0, 0};
+    int last_iters = -1;                   // largest iteration count of the last solve (-1: none)
     size_t xref_len = 0;                   // padded xref elements per instance (device)
 
     double *X(int b) const { return d_S[b]; }
@@ -272,7 +275,7 @@ int raise_lds(const nmpc_handle::Kern &k)
 void release(nmpc_handle *h)
 {
     if (!h) return;
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < 3; ++q) {
         if (h->gexec[q]) (void)hipGraphExecDestroy(h->gexec[q]);
         if (h->graph[q]) (void)hipGraphDestroy(h->graph[q]);
     }
@@ -383,6 +386,45 @@ int ensure_graph(nmpc_handle *h, int prec, int count)
     h->graph[prec] = g;
     HIP_TRY(hipGraphInstantiate(&h->gexec[prec], g, nullptr, nullptr, 0));
     h->graph_count[prec] = count; h->graph_len[prec] = len;
+    return NMPC_OK;
+}
+
+// First graph of an FP32-sweep solve whose previous solve converged in J
+// iterations: nf = J + 1 FP32 launches (the last one takes the test that
+// passes), then the FP64 phase's three launches (the correction step, the
+// evaluation of its result on the FP32 kernel, the final test). A solve that
+// converges as the previous one did ends with this one graph and one poll;
+// one that needs more continues with the ordinary graphs (the state machine
+// lets each instance wait for the kernel of its phase).
+int ensure_first_graph(nmpc_handle *h, int count, int nf)
+{
+    const int len = nf + 3;
+    if (h->gexec[2] && h->graph_count[2] == count && h->graph_len[2] == len) return NMPC_OK;
+    if (h->gexec[2]) { (void)hipGraphExecDestroy(h->gexec[2]); h->gexec[2] = nullptr; }
+    if (h->graph[2]) { (void)hipGraphDestroy(h->graph[2]); h->graph[2] = nullptr; }
+    IterArgs a = iter_args(h, count);
+    HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = NMPC_OK;
+    for (int t = 0; t < len && rc == NMPC_OK; ++t) {
+        a.kofs = t;
+        a.eval_fp64 = t == nf + 1 ? 1 : 0;
+        const int prec = t < nf || t == nf + 1 ? nmpc::kModeFp32 : nmpc::kModeFp64;
+        rc = launch_iterate(h, prec, a, h->stream);
+    }
+    if (rc == NMPC_OK) {
+        int *ctr = h->d_ctr;
+        void *args[] = {(void *)&ctr, (void *)&len};
+        const hipError_t e = hipLaunchKernel(nmpc::advance_kernel(), dim3(1), dim3(64), args, 0,
+                                             h->stream);
+        if (e != hipSuccess) rc = fail(NMPC_E_DEVICE, std::string("advance: ") + hipGetErrorString(e));
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != NMPC_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(NMPC_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    h->graph[2] = g;
+    HIP_TRY(hipGraphInstantiate(&h->gexec[2], g, nullptr, nullptr, 0));
+    h->graph_count[2] = count; h->graph_len[2] = len;
     return NMPC_OK;
 }
 
@@ -769,13 +811,20 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
     int prec = h->opt.precision == NMPC_FP32_SWEEP ? nmpc::kModeFp32 : nmpc::kModeFp64;
     const long long cap = 2 * ((long long)h->opt.max_iter + 8 + h->opt.check_every);
     long long launched = 0;
+    // the first graph sized from the previous solve when its FP32 launches
+    // and the FP64 phase fit in one graph of check_every launches
+    bool first = prec == nmpc::kModeFp32 && !h->streaming && !h->opt.fp32_finish &&
+                 h->last_iters >= 0 && h->last_iters + 4 <= h->opt.check_every;
     for (;;) {
-        int rc = h->streaming ? ensure_stream_graph(h, prec, count) : ensure_graph(h, prec, count);
+        const int q = first ? 2 : prec;
+        int rc = first ? ensure_first_graph(h, count, h->last_iters + 1)
+                       : h->streaming ? ensure_stream_graph(h, prec, count) : ensure_graph(h, prec, count);
         if (rc != NMPC_OK) return rc;
+        first = false;
         if (h->timing) HIP_TRY(hipEventRecord(h->t0, h->stream));
-        HIP_TRY(hipGraphLaunch(h->gexec[prec], h->stream));
+        HIP_TRY(hipGraphLaunch(h->gexec[q], h->stream));
         if (h->timing) HIP_TRY(hipEventRecord(h->t1, h->stream));
-        launched += h->graph_len[prec];
+        launched += h->graph_len[q];
         HIP_TRY(hipMemcpyAsync(h->h_poll, h->d_ctr + 2, 2 * sizeof(int), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -783,7 +832,7 @@ int run(nmpc_handle *h, int count, const double *wx, const double *wu, const dou
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, h->t0, h->t1));
             h->kernel_ms += ms;
-            h->launches += h->graph_len[prec];
+            h->launches += h->graph_len[q];
         }
         if (h->h_poll[0] >= count) break;
         if (prec == nmpc::kModeFp32 && h->h_poll[1] <= 0) prec = nmpc::kModeFp64;
@@ -836,9 +885,10 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
     HIP_TRY(hipMemcpyAsync(st2.data(), h->d_st + h->max_batch, sizeof(InstState) * count,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    int worst = NMPC_OK;
+    int worst = NMPC_OK, most = 0;
     for (int b = 0; b < count; ++b) {
         const InstState &s = st[b].status != nmpc::kActive ? st[b] : st2[b];
+        most = std::max(most, iters[b]);
         if (h->timing) h->units += (long long)s.e * h->N;
         const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
         if (info) {
@@ -853,6 +903,7 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
         }
         if (status != NMPC_OK && worst == NMPC_OK) worst = status;
     }
+    h->last_iters = worst == NMPC_OK ? most : -1;
     return worst;
 }
 
@@ -1072,7 +1123,8 @@ int nmpc_set_options(nmpc_handle *h, const nmpc_options *opt)
     if (opt->xref_per_stage != h->opt.xref_per_stage)
         h->xref_len = (size_t)h->np * (opt->xref_per_stage ? h->N : 1);
     h->opt = *opt;
-    h->graph_count[0] = h->graph_count[1] = -1;   // recapture: options are kernel arguments
+    h->graph_count[0] = h->graph_count[1] = h->graph_count[2] = -1;   // recapture: options are kernel arguments
+    h->last_iters = -1;
     return NMPC_OK;
 }
 
@@ -1344,7 +1396,7 @@ int nmpc_autotune(nmpc_handle *h, int32_t count, const double *x0, const double 
     if (best_ry < 0) { slot = keep; return fail(NMPC_E_UNSUPPORTED, "no tile to tune"); }
     slot = best;
     h->opt.tile_rows = best_ry;
-    h->graph_count[0] = h->graph_count[1] = -1;
+    h->graph_count[0] = h->graph_count[1] = h->graph_count[2] = -1;
     if (tile_rows) *tile_rows = best_ry;
     return NMPC_OK;
 }

@@ -173,6 +173,45 @@ def test_batch_matches_single_solves(nm):
     assert [i["iters"] for i in infos2] == [i["iters"] for i in infos]
 
 
+def test_first_graph_sized_from_the_previous_solve_keeps_the_results(nm):
+    """FP32-sweep Jacobi solves of one handle: the first graph of a solve is
+    sized from the previous solve's iteration count (its FP32 launches, then
+    the final FP64 correction's three). Whether the estimate is exact (the
+    same warm solve again) or too short (a cold solve after a warm one), every
+    result equals, bit for bit, that of a fresh handle, which runs the
+    ordinary graphs."""
+    import torch
+    P = make_problem("c1")
+    x0, xref = make_batch(P, [20, 21, 22])
+    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xref, device="cuda")
+    opts = dict(max_batch=4, precision=nm.NMPC_FP32_SWEEP, check_every=16)
+
+    def fresh(warm=None):
+        s = nm.Solver(P, **opts)
+        out = s.solve_batch(dx0, dxr, warm=warm)
+        s.close()
+        return out
+
+    rc, Xc, Uc, Lc, ic = fresh()
+    assert rc == nm.NMPC_OK
+    rng = np.random.default_rng(4)   # a warm start: the solution with noisy inputs
+    Up = (Uc * (1.0 + 1e-4 * torch.tensor(rng.standard_normal(Uc.shape), device="cuda"))).contiguous()
+    warm = (Xc.clone(), Up, Lc.clone())
+    rw, Xw, Uw, Lw, iw = fresh(warm)
+    assert rw == nm.NMPC_OK
+    assert max(i["iters"] for i in iw) + 4 <= 16 < max(i["iters"] for i in ic)
+    s = nm.Solver(P, **opts)
+    for want, w in (((Xw, Uw, Lw, iw), warm),       # sets the estimate
+                    ((Xw, Uw, Lw, iw), warm),       # estimate exact
+                    ((Xc, Uc, Lc, ic), None)):      # estimate too short
+        rc, X, U, L, info = s.solve_batch(dx0, dxr, warm=w)
+        assert rc == nm.NMPC_OK
+        assert torch.equal(X, want[0]) and torch.equal(U, want[1]) and torch.equal(L, want[2])
+        for a, b in zip(info, want[3]):
+            assert (a["iters"], a["fp32_iters"], a["r_scaled"], a["err_vs_fp64"]) == \
+                   (b["iters"], b["fp32_iters"], b["r_scaled"], b["err_vs_fp64"])
+
+
 def test_residual_batch_matches_oracle(nm):
     import torch
     P = make_problem("c1")
