@@ -391,8 +391,10 @@ int ensure_graph(nmpc_handle *h, int prec, int count)
 
 // First graph of an FP32-sweep solve whose previous solve converged in J
 // iterations: nf = J + 1 FP32 launches (the last one takes the test that
-// passes), then the FP64 phase's three launches (the correction step, the
-// evaluation of its result on the FP32 kernel, the final test). A solve that
+// passes), then the FP64 phase's three launches (the correction step on the
+// FP64 kernel, then the evaluation of its result and the final test on the
+// FP32 kernel with eval_fp64: a decision needs no FP64 arithmetic, and an
+// instance whose final test fails waits for the next FP64 launch). A solve that
 // converges as the previous one did ends with this one graph and one poll;
 // one that needs more continues with the ordinary graphs (the state machine
 // lets each instance wait for the kernel of its phase).
@@ -407,8 +409,8 @@ int ensure_first_graph(nmpc_handle *h, int count, int nf)
     int rc = NMPC_OK;
     for (int t = 0; t < len && rc == NMPC_OK; ++t) {
         a.kofs = t;
-        a.eval_fp64 = t == nf + 1 ? 1 : 0;
-        const int prec = t < nf || t == nf + 1 ? nmpc::kModeFp32 : nmpc::kModeFp64;
+        a.eval_fp64 = t > nf ? 1 : 0;
+        const int prec = t == nf ? nmpc::kModeFp64 : nmpc::kModeFp32;
         rc = launch_iterate(h, prec, a, h->stream);
     }
     if (rc == NMPC_OK) {
