@@ -213,10 +213,10 @@ def timed_steps(solver, batches, out, net=None, ubuf=None, errs=None):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
         worst = max(worst, rc)
-        iters += [i["iters"] for i in infos]
-        used += [i["start_used"] for i in infos]
+        iters += infos["iters"].tolist()
+        used += infos["start_used"].tolist()
         if errs is not None:
-            errs += [i["err_vs_fp64"] for i in infos]
+            errs += infos["err_vs_fp64"].tolist()
     return times, iters, used, worst
 
 
@@ -247,7 +247,7 @@ def closed_loop(solver, net, P, x0, xr, steps: int, ubuf):
                 rc, Xo, Uo, Lo, inf = solver.solve_batch(xs, xr, warm=warm)
             torch.cuda.synchronize()
             out[kind]["t"] += time.perf_counter() - t
-            out[kind]["it"] += [i["iters"] for i in inf]
+            out[kind]["it"] += inf["iters"].tolist()
         X, U, L = Xo.clone(), Uo.clone(), Lo.clone()   # the shifted solve's trajectory
     n = B * (steps - 1)
     return {k: {"solves_per_s": round(n / v["t"], 1), "iters_mean": round(float(np.mean(v["it"])), 1),
@@ -378,7 +378,7 @@ def bench_c3(args):
             rc, _, infos, _ = solver.solve(cls, x0, xr)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-            its.append([i["iters"] for i in infos])
+            its.append(infos["iters"].tolist())
             worst = max(worst, rc)
         return ts, its, worst
 
@@ -477,7 +477,7 @@ def bench_model(args):
             rc, X, U, L, infos = solver.solve_batch(x0, xr)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-            its += [i["iters"] for i in infos]
+            its += infos["iters"].tolist()
             worst = max(worst, rc)
         return ts, its, worst
 
@@ -588,7 +588,7 @@ def plate_closed_loop(nm, P, dev, steps: int = 200):
         rc, X, U, L, infos = s.solve_batch(x, xr, warm=warm)
         torch.cuda.synchronize()
         ts.append(time.perf_counter() - t)
-        its.append(infos[0]["iters"])
+        its.append(int(infos[0]["iters"]))
         x = X[:, 0].clone()
         warm = (torch.cat([X[:, 1:], X[:, -1:]], 1).contiguous(),
                 torch.cat([U[:, 1:], U[:, -1:]], 1).contiguous(),
@@ -831,7 +831,8 @@ def main():
                               max_iter=20000)
             smp[str(b)] = {"control_rel_err_vs_oracle_exact":
                            float(np.abs(Uh[b] - ex["U"]).max() / np.abs(ex["U"]).max()),
-                           "err_vs_fp64": infos[b]["err_vs_fp64"], "iters": infos[b]["iters"]}
+                           "err_vs_fp64": float(infos[b]["err_vs_fp64"]),
+                           "iters": int(infos[b]["iters"])}
         cfg["sampled_vs_oracle"] = {"instances_of_first_timed_batch": smp,
                                     "bar": 1e-4 if prec == nm.NMPC_FP32_SWEEP else 1e-6}
 

@@ -86,6 +86,19 @@ class nmpc_info(ctypes.Structure):
                 "start_used": self.start_used, "err_vs_fp64": self.err_vs_fp64}
 
 
+# nmpc_info as a numpy record: batched calls return one structured array (the
+# library writes into it directly; infos[b]["iters"], infos["iters"]), which
+# costs nothing per instance, unlike a list of dicts.
+INFO_DTYPE = np.dtype([(name, np.float64 if ct is ctypes.c_double else np.int32)
+                       for name, ct in nmpc_info._fields_], align=True)
+assert INFO_DTYPE.itemsize == ctypes.sizeof(nmpc_info)
+
+
+def _info_array(count: int):
+    a = np.zeros(count, dtype=INFO_DTYPE)
+    return a, a.ctypes.data_as(ctypes.POINTER(nmpc_info))
+
+
 class NmpcError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -292,7 +305,8 @@ def _stream():
 def nmpc_solve_batch(hd, x0, xref, warm=None, out=None, *, n: int, m: int, N: int,
                      xref_stages: bool = False):
     """Device-tensor solve of count = x0.shape[0] instances on torch's current
-    stream. Returns (status, X, U, LAM, [info dicts])."""
+    stream. Returns (status, X, U, LAM, infos): infos is a numpy structured
+    array of nmpc_info records (INFO_DTYPE)."""
     import torch
     B = x0.shape[0]
     xs = (B, N, n) if xref_stages else (B, n)
@@ -309,12 +323,12 @@ def nmpc_solve_batch(hd, x0, xref, warm=None, out=None, *, n: int, m: int, N: in
         pw = [None if warm[0] is None else _dev(warm[0], (B, N, n), "warm x"),
               None if warm[1] is None else _dev(warm[1], (B, N, m), "warm u"),
               None if warm[2] is None else _dev(warm[2], (B, N, n), "warm lam")]
-    infos = (nmpc_info * B)()
+    infos, pinfo = _info_array(B)
     rc = _load().nmpc_solve_batch(hd, B, px0, pxr, pw[0], pw[1], pw[2], po[0], po[1], po[2],
-                                  infos, _stream())
+                                  pinfo, _stream())
     if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
         raise NmpcError(rc, "nmpc_solve_batch")
-    return rc, out[0], out[1], out[2], [i.as_dict() for i in infos]
+    return rc, out[0], out[1], out[2], infos
 
 
 def nmpc_residual_batch(hd, x0, xref, X, U, LAM, *, n: int, m: int, N: int,
@@ -426,12 +440,12 @@ def nmpc_ragged_solve(hd, cls, x0, xref, warm, out, sizes):
     if warm is not None:
         pw = [_dev(warm[0], (nS,), "warm x"), _dev(warm[1], (nU,), "warm u"),
               _dev(warm[2], (nS,), "warm lam")]
-    infos = (nmpc_info * len(c))()
+    infos, pinfo = _info_array(len(c))
     rc = _load().nmpc_ragged_solve(hd, len(c), cp, px0, pxr, pw[0], pw[1], pw[2], po[0], po[1],
-                                   po[2], infos, _stream())
+                                   po[2], pinfo, _stream())
     if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
         raise NmpcError(rc, "nmpc_ragged_solve")
-    return rc, [i.as_dict() for i in infos]
+    return rc, infos
 
 
 def nmpc_ragged_autotune(hd, cls, x0, xref, nx: int, iters: int = 8) -> int:
@@ -655,7 +669,8 @@ def nmpc_model_create(problem, options: nmpc_options, max_batch: int = 1):
 class ModelSolver:
     """Model engine handle (plate, wave, dense-B heat); device tensors in and
     out on torch's current stream. x0 [B][nx], xref [B][nodes]; returns
-    (status, X [B][N][nx], U [B][N][m], LAM [B][N][nx], [info dicts])."""
+    (status, X [B][N][nx], U [B][N][m], LAM [B][N][nx], infos: a numpy structured array of
+    nmpc_info records)."""
 
     def __init__(self, problem, *, max_batch: int = 1, **options):
         _load()
@@ -689,12 +704,12 @@ class ModelSolver:
         if warm is not None:
             pw = [_dev(warm[0], (B, N, nx), "warm x"), _dev(warm[1], (B, N, m), "warm u"),
                   _dev(warm[2], (B, N, nx), "warm lam")]
-        infos = (nmpc_info * B)()
+        infos, pinfo = _info_array(B)
         rc = _load().nmpc_model_solve_batch(self.hd, B, px0, pxr, pw[0], pw[1], pw[2], po[0],
-                                            po[1], po[2], infos, _stream())
+                                            po[1], po[2], pinfo, _stream())
         if rc not in (NMPC_OK, NMPC_E_NOCONV, NMPC_E_NONFINITE):
             raise NmpcError(rc, "nmpc_model_solve_batch")
-        return rc, out[0], out[1], out[2], [i.as_dict() for i in infos]
+        return rc, out[0], out[1], out[2], infos
 
     def residual_batch(self, x0, xref, X, U, LAM):
         B, N, nx, m = x0.shape[0], self.N, self.nx, self.m
