@@ -265,6 +265,26 @@ const void *pad_kernel();
 const void *advance_kernel();
 const void *output_kernel();
 
+// One instance's results gathered on the device, so that the host reads a
+// batch's results with one copy: both state slots, the final norms, the
+// FP64 correction step, the iteration count and the start used.
+struct InfoPack {
+    InstState s[2];
+    double rf[2];
+    unsigned long long du[2];
+    int iters, used;
+};
+struct PackArgs {
+    const InstState *st;            // [2][B]
+    const int *iters;
+    const double *rfin;             // [B][2]
+    const unsigned long long *du;   // [B][2]
+    const int *start;               // [B] or null
+    int count, B;
+    InfoPack *out;                  // [count]
+};
+const void *info_pack_kernel();     // (PackArgs)
+
 const void *shift_kernel();   // (const double *s, double *out, long long count, int N, long long w)
 const void *plant_kernel();   // (PlantArgs)
 

@@ -1,4 +1,5 @@
-// nmpc_loop.hip -- closed-loop helpers: the shifted start and the plant step.
+// nmpc_loop.hip -- closed-loop helpers: the shifted start and the plant step;
+// and the gathering of a batch's per-instance results for one host copy.
 //
 // Shifted start (Remark rmk_gamma reuses the previous step's optimum): the
 // previous solution moved one stage ahead, s_i <- s_{i+1}, with the last
@@ -48,6 +49,24 @@ __global__ void k_plant(const PlantArgs a)
     }
 }
 
+// out[b] = instance b's results (one thread per instance).
+__global__ void k_info_pack(const PackArgs a)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.count) return;
+    InfoPack p;
+    p.s[0] = a.st[b];
+    p.s[1] = a.st[a.B + b];
+    p.rf[0] = a.rfin[2 * b];
+    p.rf[1] = a.rfin[2 * b + 1];
+    p.du[0] = a.du[2 * b];
+    p.du[1] = a.du[2 * b + 1];
+    p.iters = a.iters[b];
+    p.used = a.start ? a.start[b] : -1;
+    a.out[b] = p;
+}
+
+const void *info_pack_kernel() { return (const void *)&k_info_pack; }
 const void *shift_kernel() { return (const void *)&k_shift; }
 const void *plant_kernel() { return (const void *)&k_plant; }
 

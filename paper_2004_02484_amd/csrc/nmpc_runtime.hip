@@ -83,6 +83,8 @@ struct nmpc_handle {
     unsigned long long *d_du = nullptr;    // [B][2] FP64 correction step (max |du|, max |u|)
     int *d_ctr = nullptr;                  // [4]
     int *h_poll = nullptr;                 // pinned
+    nmpc::InfoPack *d_info = nullptr;      // [B] results gathered for one copy
+    nmpc::InfoPack *h_info = nullptr;      // [B] pinned
     nmpc_model *dense = nullptr;           // dense-B problems: the model engine's handle
     bool timing = false;
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -283,9 +285,10 @@ void release(nmpc_handle *h)
                     (void *)h->d_x0, (void *)h->d_xref, (void *)h->d_out, (void *)h->d_rst,
                     (void *)h->d_st, (void *)h->d_iters, (void *)h->d_rfin, (void *)h->d_ctr,
                     (void *)h->d_start, (void *)h->d_stream, (void *)h->d_work,
-                    (void *)h->d_apart, (void *)h->d_aupd, (void *)h->d_du})
+                    (void *)h->d_apart, (void *)h->d_aupd, (void *)h->d_du, (void *)h->d_info})
         if (p) (void)hipFree(p);
     if (h->h_poll) (void)hipHostFree(h->h_poll);
+    if (h->h_info) (void)hipHostFree(h->h_info);
     if (h->ev) (void)hipEventDestroy(h->ev);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
@@ -868,40 +871,34 @@ namespace {
 
 int collect_info(nmpc_handle *h, int count, nmpc_info *info)
 {
-    std::vector<int> iters(count);
-    std::vector<double> rf(2 * (size_t)count);
-    std::vector<InstState> st(count);
     // the final state lives in the parity slot of the last kernel + 1; the
-    // status is sticky once set, so read both slots and take the final one.
-    std::vector<InstState> st2(count);
-    std::vector<int> used(count, h->last_start_kind);
-    if (h->last_fallback)
-        HIP_TRY(hipMemcpyAsync(used.data(), h->d_start, sizeof(int) * count, hipMemcpyDeviceToHost,
-                               h->stream));
-    HIP_TRY(hipMemcpyAsync(iters.data(), h->d_iters, sizeof(int) * count, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(rf.data(), h->d_rfin, sizeof(double) * 2 * count, hipMemcpyDeviceToHost, h->stream));
-    std::vector<unsigned long long> du(2 * (size_t)count);
-    HIP_TRY(hipMemcpyAsync(du.data(), h->d_du, sizeof(unsigned long long) * 2 * count,
-                           hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(st.data(), h->d_st, sizeof(InstState) * count, hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipMemcpyAsync(st2.data(), h->d_st + h->max_batch, sizeof(InstState) * count,
+    // status is sticky once set, so both slots come back and the final one
+    // is taken. Everything of the batch is gathered on the device first and
+    // read with one copy into pinned memory.
+    nmpc::PackArgs pa{h->d_st, h->d_iters, h->d_rfin, h->d_du,
+                      h->last_fallback ? h->d_start : nullptr, count, h->max_batch, h->d_info};
+    void *pargs[] = {(void *)&pa};
+    HIP_TRY(hipLaunchKernel(nmpc::info_pack_kernel(), dim3((count + 255) / 256), dim3(256), pargs, 0,
+                            h->stream));
+    HIP_TRY(hipMemcpyAsync(h->h_info, h->d_info, sizeof(nmpc::InfoPack) * count,
                            hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     int worst = NMPC_OK, most = 0;
     for (int b = 0; b < count; ++b) {
-        const InstState &s = st[b].status != nmpc::kActive ? st[b] : st2[b];
-        most = std::max(most, iters[b]);
+        const nmpc::InfoPack &pk = h->h_info[b];
+        const InstState &s = pk.s[0].status != nmpc::kActive ? pk.s[0] : pk.s[1];
+        most = std::max(most, pk.iters);
         if (h->timing) h->units += (long long)s.e * h->N;
         const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
         if (info) {
-            info[b].r_scaled = rf[2 * b];
-            info[b].r_paper = rf[2 * b + 1];
-            info[b].iters = iters[b];
+            info[b].r_scaled = pk.rf[0];
+            info[b].r_paper = pk.rf[1];
+            info[b].iters = pk.iters;
             info[b].status = status;
             info[b].fp32_iters = s.f32;
-            info[b].start_used = used[b];
+            info[b].start_used = h->last_fallback ? pk.used : h->last_start_kind;
             info[b].err_vs_fp64 = nmpc::fp32_step_error(main_prec(h->opt) == nmpc::kModeFp32,
-                                                  h->opt.fp32_finish != 0, s, &du[2 * b]);
+                                                  h->opt.fp32_finish != 0, s, pk.du);
         }
         if (status != NMPC_OK && worst == NMPC_OK) worst = status;
     }
@@ -1042,6 +1039,7 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
     ALLOC(h->d_du, sizeof(unsigned long long) * 2 * B);
     ALLOC(h->d_ctr, sizeof(int) * 4);
     ALLOC(h->d_start, sizeof(int) * B);
+    ALLOC(h->d_info, sizeof(nmpc::InfoPack) * B);
     if (prob->tau > 0.0) {
         ALLOC(h->d_apart, sizeof(double) * B * h->N);
         ALLOC(h->d_aupd, sizeof(int) * B);
@@ -1063,6 +1061,8 @@ int nmpc_create(const nmpc_problem *prob, const nmpc_options *opt, int32_t max_b
 
 #undef ALLOC
     hipError_t e = hipHostMalloc((void **)&h->h_poll, 2 * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&h->h_info, sizeof(nmpc::InfoPack) * B, hipHostMallocDefault);
     for (int prec : {nmpc::kModeFp64, nmpc::kModeFp32})
         for (const nmpc_handle::Kern *k : {&h->kern[prec], &h->gs[prec]})
             if (e == hipSuccess && k->fn && k->lds > 48 * 1024)
