@@ -104,6 +104,8 @@ struct InitArgs {
 
 struct OutArgs {
     int count, N, nsx, nsy, sx, m;
+    int vec;                        // 1: column pairs as 16-byte accesses (nsx, sx even,
+                                    // ox and ol 16-byte aligned)
     const int *iters;
     const double *X[2], *U[2], *LAM[2];
     double *ox, *ou, *ol;

@@ -492,26 +492,35 @@ __global__ void k_pad(const double *src, double *dst, long long rows, int nsx, i
     }
 }
 
-// Copy each instance's returned iterate (buffer iters[b] & 1) out, from the
-// padded stage layout to the dense [count][N][n] layout.
+// Returned iterates to the caller's dense outputs: unit (instance, stage)
+// blockIdx.y (strided), its points over blockIdx.x; each instance reads the
+// buffer that holds its returned iterate (iters[b] & 1).
 __global__ void k_output(const OutArgs a)
 {
-    const size_t n = (size_t)a.nsx * a.nsy, np = (size_t)a.nsy * a.sx;
-    const size_t w = (size_t)a.N * n, wm = (size_t)a.N * a.m;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.count * w;
-         t += stride) {
-        const size_t unit = t / n, p = t % n;
-        const int b = (int)(t / w);
-        const int buf = a.iters[b] & 1;
-        const size_t src = unit * np + (p / a.nsx) * a.sx + p % a.nsx;
-        a.ox[t] = a.X[buf][src];
-        a.ol[t] = a.LAM[buf][src];
-    }
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < (size_t)a.count * wm;
-         t += stride) {
-        const int b = (int)(t / wm);
-        a.ou[t] = a.U[a.iters[b] & 1][t];
+    const int units = a.count * a.N, n = a.nsx * a.nsy;
+    const size_t np = (size_t)a.nsy * a.sx;
+    for (int unit = blockIdx.y; unit < units; unit += gridDim.y) {
+        const int buf = a.iters[unit / a.N] & 1;
+        const double *X = a.X[buf] + unit * np, *L = a.LAM[buf] + unit * np;
+        double *ox = a.ox + (size_t)unit * n, *ol = a.ol + (size_t)unit * n;
+        if (a.vec) {   // pairs of columns of one row
+            for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n / 2; t += gridDim.x * blockDim.x) {
+                const int p = 2 * t, row = p / a.nsx;
+                const size_t src = (size_t)row * a.sx + (p - row * a.nsx);
+                *reinterpret_cast<double2 *>(ox + p) = *reinterpret_cast<const double2 *>(X + src);
+                *reinterpret_cast<double2 *>(ol + p) = *reinterpret_cast<const double2 *>(L + src);
+            }
+        } else {
+            for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x) {
+                const int row = p / a.nsx;
+                const size_t src = (size_t)row * a.sx + (p - row * a.nsx);
+                ox[p] = X[src];
+                ol[p] = L[src];
+            }
+        }
+        if (blockIdx.x == 0)
+            for (int j = threadIdx.x; j < a.m; j += blockDim.x)
+                a.ou[(size_t)unit * a.m + j] = a.U[buf][(size_t)unit * a.m + j];
     }
 }
 

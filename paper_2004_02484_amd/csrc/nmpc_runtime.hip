@@ -759,9 +759,13 @@ int launch_output(nmpc_handle *h, int count, double *ox, double *ou, double *ol)
     oa.nsx = h->prob.nsx; oa.nsy = h->prob.nsy; oa.sx = h->sx;
     for (int b = 0; b < 2; ++b) { oa.X[b] = h->X(b); oa.U[b] = h->U(b); oa.LAM[b] = h->L(b); }
     oa.ox = ox; oa.ou = ou; oa.ol = ol;
+    oa.vec = h->prob.nsx % 2 == 0 && h->sx % 2 == 0 &&
+             ((uintptr_t)ox % 16) == 0 && ((uintptr_t)ol % 16) == 0;
     void *args[] = {(void *)&oa};
-    HIP_TRY(hipLaunchKernel(nmpc::output_kernel(), dim3(launch_grid((size_t)count * h->N * h->n)),
-                            dim3(256), args, 0, h->stream));
+    const int per = oa.vec ? h->n / 2 : h->n;   // threads' items per unit
+    const unsigned gx = (unsigned)std::min(64, (per + 255) / 256);
+    const unsigned gy = (unsigned)std::min(count * h->N, 65535);
+    HIP_TRY(hipLaunchKernel(nmpc::output_kernel(), dim3(gx, gy), dim3(256), args, 0, h->stream));
     return NMPC_OK;
 }
 
