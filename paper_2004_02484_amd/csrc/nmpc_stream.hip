@@ -787,7 +787,7 @@ __global__ void __launch_bounds__(256) k_st_v3(const StreamArgs a)
 // arithmetic as in the fused stage kernel), and a Schur step writes its own
 // partials to the other buffer.
 template <typename T, bool FIN>
-__global__ void __launch_bounds__(256, sizeof(T) == 4 ? (FIN ? 3 : 4) : 2) k_st_lower(const StreamArgs a,
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 3 : 2) k_st_lower(const StreamArgs a,
                                                                                       int which)
 {
     constexpr bool fin = FIN;
