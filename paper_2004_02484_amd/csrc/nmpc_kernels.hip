@@ -435,7 +435,9 @@ __global__ void k_init(const InitArgs a)
     const size_t nN = (size_t)a.count * nst * np;
     const size_t mN = (size_t)a.count * nst * a.m;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nN; t += stride) {
+    // padding only, and the rows have none: nothing to write here
+    const size_t nNw = a.pad_only && a.sx == a.nsx ? 0 : nN;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nNw; t += stride) {
         const size_t us = t / np, p = t % np;
         const size_t b = us / nst, unit = b * a.N + us % nst;
         const int row = (int)(p / a.sx), col = (int)(p % a.sx);
