@@ -402,20 +402,16 @@ __global__ void k_choose_flags(const IterArgs a, int *start_used, int used_if_ke
 // 0) into buffer 0 for the instances that fell back.
 __global__ void k_choose_copy(const IterArgs a, const int *start_used)
 {
+    // one workgroup per (instance, stage); instances that keep their start
+    // return at once
     const size_t np = a.P.n, N = a.P.N, m = a.P.m;
-    const size_t per = N * (2 * np + m);
-    const size_t tot = (size_t)a.units * per, stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < tot; t += stride) {
-        const size_t b = t / per, r = t % per;
-        if (start_used[b] != 0) continue;
-        if (r < N * np) {
-            a.X[0][b * N * np + r] = a.x0[b * np + r % np];
-        } else if (r < 2 * N * np) {
-            a.LAM[0][b * N * np + (r - N * np)] = 0.0;
-        } else {
-            a.U[0][b * N * m + (r - 2 * N * np)] = 0.0;
-        }
+    const size_t unit = blockIdx.x, b = unit / N;
+    if (b >= (size_t)a.units || start_used[b] != 0) return;
+    for (size_t p = threadIdx.x; p < np; p += blockDim.x) {
+        a.X[0][unit * np + p] = a.x0[b * np + p];
+        a.LAM[0][unit * np + p] = 0.0;
     }
+    for (size_t j = threadIdx.x; j < m; j += blockDim.x) a.U[0][unit * m + j] = 0.0;
 }
 
 // Advances the device kernel base index after a captured sequence of `len`

@@ -573,8 +573,7 @@ int build_start(nmpc_handle *h, int count, const double *wx, const double *wu,
         }
         {
             void *args[] = {(void *)&a, (void *)&st};
-            HIP_TRY(hipLaunchKernel(nmpc::choose_copy_kernel(),
-                                    dim3(launch_grid((size_t)count * h->N * (2 * h->np + h->m))),
+            HIP_TRY(hipLaunchKernel(nmpc::choose_copy_kernel(), dim3((unsigned)(count * h->N)),
                                     dim3(256), args, 0, h->stream));
         }
         h->last_fallback = true;
