@@ -189,32 +189,52 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
     unsigned long long *nrm = lds_ptr<unsigned long long>(c, c.off.nrm);
 
     // ---- states, forward in the horizon
+    // Each stage starts with one barrier that publishes its inputs (two LDS
+    // slots by stage parity: the v3 region, unused here, is the second), the
+    // waves' parts of the sweep bound mu (from the previous state, so they
+    // are formed at the end of the previous stage) and the previous stage's
+    // state-row norms; then the sweeps' stencils and the residual's.
+    double *uvs[2] = {uvec, lds_ptr<double>(c, c.off.v3)};
     double xp[RY][CX];
 #pragma unroll
     for (int t = 0; t < RY; ++t)
 #pragma unroll
         for (int q = 0; q < CX; ++q) xp[t][q] = valid(t, q) ? a.x0[(size_t)b * n + pidx(t, q)] : 0.0;
-    for (int i = 0; i < P.N; ++i) {
-        const size_t unit = (size_t)b * P.N + i;
-        __syncthreads();   // previous stage's readers of uvec are done
-        if (c.tid < M) uvec[c.tid] = a.U[0][unit * M + c.tid];
-        __syncthreads();
-        double Bu[RY][CX], x[RY][CX];
-        b_apply<double, CX, RY, LX, LY>(uvec, c, Bu);
-#pragma unroll
-        for (int t = 0; t < RY; ++t)
-#pragma unroll
-            for (int q = 0; q < CX; ++q) x[t][q] = xp[t][q];
-        double mu = 0.0;
+    // the sweep matrix's row-sum bound for the state after `xs`, this wave's part
+    auto mu_part = [&](const double (&xs)[RY][CX]) {
+        double m = 0.0;
 #pragma unroll
         for (int t = 0; t < RY; ++t)
 #pragma unroll
             for (int q = 0; q < CX; ++q)
                 if (valid(t, q)) {
-                    const double hk = h * P.k0 * (1.0 + P.k1 * xp[t][q]) * P.c0;
-                    mu = fmax(mu, hk / (1.0 + hk));
+                    const double hk = h * P.k0 * (1.0 + P.k1 * xs[t][q]) * P.c0;
+                    m = fmax(m, hk / (1.0 + hk));
                 }
-        mu = fmin(1.02 * block_max_nonneg(mu, c, nrm), 0.995);
+        const unsigned long long mb = wave_max64(abits(m), c.lane);
+        if (c.lane == 0) nrm[c.w * 4 + 3] = mb;
+    };
+    if (c.tid < M) uvs[0][c.tid] = a.U[0][(size_t)b * P.N * M + c.tid];
+    mu_part(xp);
+    for (int i = 0; i < P.N; ++i) {
+        const size_t unit = (size_t)b * P.N + i;
+        __syncthreads();   // inputs, mu parts and the previous stage's norms are in LDS
+        unsigned long long mb = 0;
+        for (int ww = 0; ww < c.W; ++ww) mb = umax64(mb, nrm[ww * 4 + 3]);
+        const double mu = fmin(1.02 * bits2d(mb), 0.995);
+        if (i > 0 && c.tid == 0) {   // provisional: the state rows' norm, completed below
+            unsigned long long ax = 0;
+            for (int ww = 0; ww < c.W; ++ww) ax = umax64(ax, nrm[ww * 4]);
+            a.rst[unit - 1] = ax;
+        }
+        if (c.Gv == 1) __syncthreads();   // no stencil barrier comes before the slots are rewritten
+        const double *uv = uvs[i & 1];
+        double Bu[RY][CX], x[RY][CX];
+        b_apply<double, CX, RY, LX, LY>(uv, c, Bu);
+#pragma unroll
+        for (int t = 0; t < RY; ++t)
+#pragma unroll
+            for (int q = 0; q < CX; ++q) x[t][q] = xp[t][q];
         double xo[RY][CX], w = 1.0;
         for (int s = 0; s < nsw; ++s) {
             double nb[RY][CX];
@@ -249,12 +269,12 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
                     }
             mx = wave_max64(mx, c.lane);
             if (c.lane == 0) nrm[c.w * 4] = mx;
-            __syncthreads();
-            if (c.tid == 0) {   // provisional: the state rows' norm, completed below
-                unsigned long long ax = 0;
-                for (int ww = 0; ww < c.W; ++ww) ax = umax64(ax, nrm[ww * 4]);
-                a.rst[unit] = ax;
-            }
+        }
+        // the next stage's inputs (the slot its predecessor read two stages
+        // ago) and its mu parts
+        if (i + 1 < P.N) {
+            if (c.tid < M) uvs[(i + 1) & 1][c.tid] = a.U[0][(unit + 1) * M + c.tid];
+            mu_part(x);
         }
         double *Xo = a.X[0] + unit * n;
 #pragma unroll
@@ -264,6 +284,12 @@ __global__ void __launch_bounds__(kWave * WB) k_rollout(const IterArgs a)
                 if (valid(t, q)) Xo[pidx(t, q)] = x[t][q];
                 xp[t][q] = x[t][q];
             }
+    }
+    __syncthreads();
+    if (c.tid == 0) {   // the last stage's state-row norm
+        unsigned long long ax = 0;
+        for (int ww = 0; ww < c.W; ++ww) ax = umax64(ax, nrm[ww * 4]);
+        a.rst[(size_t)b * P.N + P.N - 1] = ax;
     }
     // ---- costates, backward in the horizon
     double ln[RY][CX];
