@@ -70,13 +70,33 @@ def test_c1_iterates_match_oracle(nm, k):
     check_same_iterate(P, x0, xref, k, nm)
 
 
-@pytest.mark.parametrize("shape", [(13, 37, 6), (64, 5, 3), (7, 16, 4), (40, 64, 2)])
+@pytest.mark.parametrize("shape", [(13, 37, 6), (64, 5, 3), (7, 16, 4), (40, 64, 2), (57, 23, 3)])
 def test_ragged_shapes_match_oracle(nm, shape):
-    """Grids that leave lanes, rows and waves partly empty (ragged tails)."""
+    """Grids that leave lanes, rows and waves partly empty (ragged tails);
+    57 columns: 4-column tiles whose last lanes are partly or wholly past the
+    grid (the 16-byte accesses of those tiles mask them)."""
     nsx, nsy, N = shape
     P = ragged2d(nsx, nsy, N)
     x0, xref = make_instance(P, 5)
     check_same_iterate(P, x0, xref, 5, nm)
+
+
+def test_partial_four_column_tiles_fp32_solve(nm):
+    """FP32 sweeps with the final correction on a 57 x 23 grid (4-column
+    tiles with lanes past the grid, partial rows): the returned trajectory
+    meets the tolerance by the oracle's residual and the FP32-sweep bar
+    against the oracle's exact solution."""
+    P = ragged2d(57, 23, 4)
+    x0, xref = make_instance(P, 6)
+    s = nm.Solver(P, precision=nm.NMPC_FP32_SWEEP, tol=1e-6)
+    rc, X, U, L, info = s.solve(x0, xref)
+    s.close()
+    assert rc == nm.NMPC_OK
+    rs, _ = oracle.residual(P, x0, xref, X, U, L)
+    ex = oracle.solve(P, x0, xref, tol=1e-12, max_iter=20000)
+    err = np.abs(U - ex["U"]).max() / np.abs(ex["U"]).max()
+    print(f"57 x 23: {info['iters']} iterations, oracle residual {rs:.2e}, control error {err:.2e}")
+    assert rs <= 1e-6 and err <= 1e-4
 
 
 @pytest.mark.parametrize("nsw,nsc", [(1, 0), (3, 1), (4, 3)])
