@@ -700,10 +700,12 @@ def main():
     ubuf = torch.empty((B, P.N, P.m), dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    # warmup: graphs, network buffers, both starts
-    timed_steps(solver, dev_in[:args.warmup], out, net, ubuf)
+    # warmup: graphs, network buffers, both starts; the timed kind last, so
+    # the handle enters the timed region as in steady operation (its first
+    # graph is sized from the previous solve of the same kind)
     if net is not None:
         timed_steps(solver, dev_in[:args.warmup], out)
+    timed_steps(solver, dev_in[:args.warmup], out, net, ubuf)
 
     # timed region: exactly K steps with the selected start
     solver.timing_enable(True)
@@ -802,8 +804,8 @@ def main():
                         check_every=16, fallback=1, upper=UPPER[args.upper],
                         warm_sweeps=args.warm_sweeps, warm_sweeps_lambda=args.warm_sweeps_lambda,
                         **inner)
-        timed_steps(s64, dev_in[:1], out, net, ubuf)
         timed_steps(s64, dev_in[:1], out)
+        timed_steps(s64, dev_in[:1], out, net, ubuf)
         t64, it64, _, w64 = timed_steps(s64, dev_in[args.warmup:], out, net, ubuf)
         p64, pit64, _, pw64 = timed_steps(s64, dev_in[args.warmup:], out)
         cfg["fp64_variant"] = {
