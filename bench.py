@@ -54,7 +54,7 @@ KERNELS = {
                ("nmpc_kernels.hip", "nmpc_stage.h"), "k_iterate_c1_b256_traffic.json"),
     "gs": ("k_gs (persistent Gauss-Seidel sweeps, one workgroup per instance)",
            ("nmpc_gs.hip", "nmpc_stage.h"), "k_gs_c1_b256_traffic.json"),
-    "stream": ("streaming upper iteration (row-block passes k_st_*, one captured graph)",
+    "stream": ("streaming upper iteration (marching-strip passes k_st_*, one captured graph)",
                ("nmpc_stream.hip",), "stream_c2_traffic.json"),
     "ragged": ("k_iterate_rg (ragged batch; one upper iteration = one launch per tile case)",
                ("nmpc_ragged.hip", "nmpc_stage.h"), "k_iterate_rg_c3_b512_traffic.json"),
@@ -321,7 +321,7 @@ def bench_c2(args):
     roof = roofline("stream", tm, bytes_per_unit(P.n, P.m, P.N))
     cfg = {"workload": "2D nonlinear heat 256x256, N=100, 64 Gaussian inputs (8x8 lattice), "
                        "single instance per step, cold start, Jacobi upper layer, streaming "
-                       "row-block path, tol 1e-6",
+                       "marching-strip path, tol 1e-6",
            "global_batch": 1, "grid": "256x256", "horizon": P.N, "path": cfg_path,
            "iters_min": int(min(iters)), "iters_max": int(max(iters)),
            "status_worst": worst, "step_ms_median": round(1e3 * float(np.median(times)), 2)}
