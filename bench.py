@@ -74,11 +74,26 @@ def bytes_per_unit(n: int, m: int, N: int, word: int = 8, sweeps: int = 1) -> fl
     return word * (sweeps * 2.0 * (2 * n + m) + 2.0 * n / N)
 
 
+def extra_flags(src: str):
+    """The per-source compiler flags the library build adds to this source."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "_nmpc_build", os.path.join(ROOT, "paper_2004_02484_amd", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.EXTRA.get(src, [])
+
+
 def kernel_digest(sources) -> str:
+    """Digest of a kernel's sources and of the per-source flags they are built
+    with (a counter summary is valid only for the binary it was taken on)."""
     h = hashlib.sha256()
     for src in sources:
         with open(os.path.join(CSRC, src), "rb") as f:
             h.update(f.read())
+        flags = extra_flags(src)
+        if flags:
+            h.update(" ".join(flags).encode())
     return h.hexdigest()[:16]
 
 
