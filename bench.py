@@ -66,12 +66,19 @@ EVAL_SEED0 = 1_000_000         # disjoint from any training seeds
 
 
 def bytes_per_unit(n: int, m: int, N: int, word: int = 8, sweeps: int = 1) -> float:
-    """Algorithmic HBM bytes of one (instance, stage) unit of one upper
-    iteration: each of the iteration's stage sweeps (one for Jacobi, FGS and
-    BGS, two for SGS) reads s_i and writes its new value (2n + m values each);
-    the instance's x0 and xref are read once per iteration (2n values shared
-    by N stages)."""
+    """Algorithmic HBM bytes of one (instance, stage) unit: each stage sweep
+    reads s_i and writes its new value (2n + m values each); the instance's x0
+    and xref are read once per sweep (2n values shared by N stages). The
+    library counts one unit per stage sweep (a Jacobi iteration is one sweep,
+    an SGS iteration two), so the rooflines take sweeps = 1."""
     return word * (sweeps * 2.0 * (2 * n + m) + 2.0 * n / N)
+
+
+def eval_bytes_per_unit(n: int, m: int, N: int, word: int = 8) -> float:
+    """Algorithmic HBM bytes of an evaluation-only unit (the residual check of
+    the FP64-corrected iterate): it reads s_i and its share of x0 and xref and
+    writes no new iterate."""
+    return word * ((2 * n + m) + 2.0 * n / N)
 
 
 def extra_flags(src: str):
@@ -280,19 +287,23 @@ def copy_calibration(dev):
     torch.cuda.synchronize()
 
 
-def roofline(kind: str, tm, bpu: float):
+def roofline(kind: str, tm, bpu: float, bpu_eval: float = 0.0):
     """HBM roofline of the dominant kernel from the library's HIP-event timing
-    (kernel_ms, launches, units) and the algorithmic bytes per unit."""
+    (kernel_ms, launches, units updated, evaluation-only units) and the
+    algorithmic bytes of an updated and of an evaluation-only unit."""
     avg_launch_s = tm["kernel_ms"] * 1e-3 / max(tm["launches"], 1)
     units_per_launch = tm["units"] / max(tm["launches"], 1)
-    achieved = bpu * units_per_launch / avg_launch_s / 1e9
+    eval_per_launch = tm.get("eval_units", 0) / max(tm["launches"], 1)
+    achieved = (bpu * units_per_launch + bpu_eval * eval_per_launch) / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_per_launch(kind, units_per_launch),
             "kernel": KERNELS[kind][0],
             "avg_launch_us": round(avg_launch_s * 1e6, 1),
             "units_per_launch": round(units_per_launch, 1),
-            "bytes_per_unit": round(bpu, 1)}
+            "bytes_per_unit": round(bpu, 1),
+            "eval_units_per_launch": round(eval_per_launch, 1),
+            "eval_bytes_per_unit": round(bpu_eval, 1)}
 
 
 def line(metric, value, args, elapsed, dtype, cfg, roof, cpu=None):
@@ -409,14 +420,16 @@ def bench_c3(args):
     if args.copy_calibration:
         copy_calibration(dev)
     # algorithmic bytes per unit, weighted over the instances' stage-iterations
-    wsum = bsum = 0.0
+    wsum = bsum = esum = ewsum = 0.0
     for (cls, _, _, _), it in zip(batches[args.warmup:], its):
         for c, k in zip(cls, it):
             P = classes[c]
             w = float(k + 1) * P.N
             wsum += w
             bsum += w * bytes_per_unit(P.n, P.m, P.N)
-    roof = roofline("ragged", tm, bsum / wsum)
+            ewsum += P.N
+            esum += P.N * eval_bytes_per_unit(P.n, P.m, P.N)
+    roof = roofline("ragged", tm, bsum / wsum, esum / ewsum)
     allit = np.concatenate([np.asarray(i) for i in its])
     cfg = {"workload": "512 independent 2D heat instances per step, grids {32,48,64,96}^2 and "
                        "horizons {20,40,60} drawn uniformly, 4x4 Gaussian lattice, cold start, "
@@ -738,7 +751,8 @@ def main():
 
     solves = B * args.steps
     value = solves / elapsed
-    roof = roofline(kind, tm, bytes_per_unit(P.n, P.m, P.N, sweeps=2 if args.upper == "sgs" else 1))
+    # one unit per stage sweep for every upper layer (an SGS iteration is two)
+    roof = roofline(kind, tm, bytes_per_unit(P.n, P.m, P.N), eval_bytes_per_unit(P.n, P.m, P.N))
 
     start_desc = ("learned warm start (network" + (" with hidden path" if net.H else ": linear map on "
                   "second-order features") + " + rollout + adjoint, cold fallback)") \

@@ -273,10 +273,20 @@ int nmpc_timing_enable(nmpc_handle *hd, int32_t enable);
 
 /* Read the counters since the last enable: GPU milliseconds spent in the
  * iteration kernels, number of iteration-kernel launches, and number of
- * (instance, stage) units that were evaluated and updated. NULL pointers are
- * skipped. */
+ * (instance, stage) units that were evaluated and updated (a Gauss-Seidel
+ * sweep over a stage is one unit; a streaming solve counts its updates).
+ * NULL pointers are skipped. */
 int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches,
                      int64_t *units);
+
+/* Evaluation-only (instance, stage) units since the last enable, which
+ * nmpc_timing_read leaves out: the residual check of the FP64-corrected
+ * iterate of an FP32-sweep solve (Sec. 4 with the final correction step),
+ * one visit per stage of each instance that reaches it; such a unit reads
+ * the stage and writes no new iterate. 0 for FP64 and fp32_finish solves and
+ * for the streaming path and the model engine. NULL eval_units is skipped;
+ * NMPC_E_ARG for a NULL handle. */
+int nmpc_timing_read_eval(const nmpc_handle *hd, int64_t *eval_units);
 
 /* Set the calling thread's last-error text (used by the network calls). */
 void nmpc_set_last_error(const char *msg);
@@ -346,10 +356,11 @@ int nmpc_ragged_autotune(nmpc_ragged *rg, int32_t count, const int32_t *cls, con
 /* Workgroup size (waves) a solve of a batch with these classes would use. */
 int nmpc_ragged_config(const nmpc_ragged *rg, int32_t count, const int32_t *cls, int32_t *waves);
 
-/* Kernel timing of later ragged solves, as nmpc_timing_enable/read. */
+/* Kernel timing of later ragged solves, as nmpc_timing_enable/read/read_eval. */
 int nmpc_ragged_timing_enable(nmpc_ragged *rg, int32_t enable);
 int nmpc_ragged_timing_read(const nmpc_ragged *rg, double *kernel_ms, int64_t *launches,
                             int64_t *units);
+int nmpc_ragged_timing_read_eval(const nmpc_ragged *rg, int64_t *eval_units);
 
 /* Release the ragged solver. NULL is ignored. */
 void nmpc_ragged_destroy(nmpc_ragged *rg);

@@ -151,6 +151,8 @@ def _load():
                                      ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(ctypes.c_int64)]
     lib.nmpc_timing_read.restype = ctypes.c_int
+    lib.nmpc_timing_read_eval.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.nmpc_timing_read_eval.restype = ctypes.c_int
     i32p = ctypes.POINTER(ctypes.c_int32)
     lib.nmpc_shift_batch.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp]
     lib.nmpc_shift_batch.restype = ctypes.c_int
@@ -177,6 +179,8 @@ def _load():
                                             ctypes.POINTER(ctypes.c_int64),
                                             ctypes.POINTER(ctypes.c_int64)]
     lib.nmpc_ragged_timing_read.restype = ctypes.c_int
+    lib.nmpc_ragged_timing_read_eval.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.nmpc_ragged_timing_read_eval.restype = ctypes.c_int
     lib.nmpc_ragged_destroy.argtypes = [vp]
     lib.nmpc_ragged_destroy.restype = None
     lib.nmpc_model_create.argtypes = [ctypes.POINTER(nmpc_model_problem),
@@ -362,10 +366,14 @@ def nmpc_timing_enable(hd, enable: bool = True) -> None:
 
 def nmpc_timing_read(hd):
     ms = ctypes.c_double(); la = ctypes.c_int64(); un = ctypes.c_int64()
+    ev = ctypes.c_int64()
     rc = _load().nmpc_timing_read(hd, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un))
+    if rc == NMPC_OK:
+        rc = _load().nmpc_timing_read_eval(hd, ctypes.byref(ev))
     if rc != NMPC_OK:
         raise NmpcError(rc, "nmpc_timing_read")
-    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
+    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value,
+            "eval_units": ev.value}
 
 
 def nmpc_shift_batch(hd, X, U, LAM, out=None, *, n: int, m: int, N: int, **_):
@@ -476,10 +484,14 @@ def nmpc_ragged_timing_enable(hd, enable: bool = True) -> None:
 
 def nmpc_ragged_timing_read(hd):
     ms = ctypes.c_double(); la = ctypes.c_int64(); un = ctypes.c_int64()
+    ev = ctypes.c_int64()
     rc = _load().nmpc_ragged_timing_read(hd, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un))
+    if rc == NMPC_OK:
+        rc = _load().nmpc_ragged_timing_read_eval(hd, ctypes.byref(ev))
     if rc != NMPC_OK:
         raise NmpcError(rc, "nmpc_ragged_timing_read")
-    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value}
+    return {"kernel_ms": ms.value, "launches": la.value, "units": un.value,
+            "eval_units": ev.value}
 
 
 def nmpc_ragged_destroy(hd) -> None:

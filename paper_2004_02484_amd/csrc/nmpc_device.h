@@ -253,6 +253,7 @@ __host__ __device__ inline LdsOff lds_layout(int GT, int W, int CX, int tsize, i
 // nmpc_info.err_vs_fp64 of one result from its final state and the recorded
 // FP64 correction step (host code, nmpc_runtime.hip).
 double fp32_step_error(bool fp32, bool finish, const InstState &s, const unsigned long long *du);
+int eval_only_visits(bool fp32, bool finish, bool streaming, const InstState &s);
 
 // ry = 0 selects the default tile height for (prec, cx).
 const void *iterate_kernel(int prec, int cx, int ry, int lx, int ly, TileCfg *cfg);

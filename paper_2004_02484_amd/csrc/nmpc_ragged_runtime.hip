@@ -108,7 +108,7 @@ struct nmpc_ragged {
     std::map<unsigned long long, int> tuned;   // class-set mask -> waves
     bool timing = false;
     double kernel_ms = 0.0;
-    long long launches = 0, units = 0;
+    long long launches = 0, units = 0, units_eval = 0;   // units: evaluated and updated
 
     double *X(int b) const { return d_S[b]; }
     double *L(int b) const { return d_S[b] + S_len; }
@@ -453,7 +453,12 @@ int collect(nmpc_ragged *r, nmpc_info *info)
     int worst = NMPC_OK;
     for (int b = 0; b < count; ++b) {
         const InstState &s = st[b].status != nmpc::kActive ? st[b] : st2[b];
-        if (r->timing) r->units += (long long)s.e * r->cls[r->h_icls[b]].horizon;
+        if (r->timing) {
+            const int eo = nmpc::eval_only_visits(r->opt.precision == NMPC_FP32_SWEEP, false, false, s);
+            const long long hz = r->cls[r->h_icls[b]].horizon;
+            r->units += (long long)(s.e - eo) * hz;
+            r->units_eval += (long long)eo * hz;
+        }
         const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
         if (info) {
             info[b].r_scaled = rf[2 * b];
@@ -722,7 +727,7 @@ int nmpc_ragged_timing_enable(nmpc_ragged *r, int32_t enable)
     if (!r) return NMPC_E_ARG;
     RG_TRY(hipStreamSynchronize(r->stream));
     r->timing = enable != 0;
-    if (r->timing) { r->kernel_ms = 0.0; r->launches = 0; r->units = 0; }
+    if (r->timing) { r->kernel_ms = 0.0; r->launches = 0; r->units = 0; r->units_eval = 0; }
     return NMPC_OK;
 }
 
@@ -733,6 +738,13 @@ int nmpc_ragged_timing_read(const nmpc_ragged *r, double *kernel_ms, int64_t *la
     if (kernel_ms) *kernel_ms = r->kernel_ms;
     if (launches) *launches = r->launches;
     if (units) *units = r->units;
+    return NMPC_OK;
+}
+
+int nmpc_ragged_timing_read_eval(const nmpc_ragged *r, int64_t *eval_units)
+{
+    if (!r) return NMPC_E_ARG;
+    if (eval_units) *eval_units = r->units_eval;
     return NMPC_OK;
 }
 

@@ -90,7 +90,8 @@ struct nmpc_handle {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double kernel_ms = 0.0;
     long long launches = 0;
-    long long units = 0;
+    long long units = 0;                   // evaluated and updated (instance, stage) units
+    long long units_eval = 0;              // evaluation-only units
     // [0], [1]: graphs of the FP32 and FP64 kernels; [2]: the first graph of
     // an FP32-sweep solve sized from the previous solve (ensure_first_graph)
     hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
@@ -868,6 +869,15 @@ double fp32_step_error(bool fp32, bool finish, const InstState &s, const unsigne
     return u > 0.0 ? d / u : d;
 }
 
+// Evaluation-only visits of one finished instance (R14): the check of the
+// FP64-corrected iterate in an FP32-sweep solve, one per instance that
+// reached it (final mode FP64 with no correction still owed). The streaming
+// path counts updates only and reports none.
+int eval_only_visits(bool fp32, bool finish, bool streaming, const InstState &s)
+{
+    return fp32 && !finish && !streaming && s.mode == nmpc::kModeFp64 && !s.pending ? 1 : 0;
+}
+
 }  // namespace nmpc
 
 namespace {
@@ -891,7 +901,12 @@ int collect_info(nmpc_handle *h, int count, nmpc_info *info)
         const nmpc::InfoPack &pk = h->h_info[b];
         const InstState &s = pk.s[0].status != nmpc::kActive ? pk.s[0] : pk.s[1];
         most = std::max(most, pk.iters);
-        if (h->timing) h->units += (long long)s.e * h->N;
+        if (h->timing) {
+            const int eo = nmpc::eval_only_visits(h->opt.precision == NMPC_FP32_SWEEP,
+                                                  h->opt.fp32_finish != 0, h->streaming, s);
+            h->units += (long long)(s.e - eo) * h->N;
+            h->units_eval += (long long)eo * h->N;
+        }
         const int status = s.status == nmpc::kActive ? NMPC_E_DEVICE : s.status;
         if (info) {
             info[b].r_scaled = pk.rf[0];
@@ -1328,6 +1343,7 @@ int nmpc_timing_enable(nmpc_handle *h, int32_t enable)
         h->kernel_ms = 0.0;
         h->launches = 0;
         h->units = 0;
+        h->units_eval = 0;
     }
     return NMPC_OK;
 }
@@ -1340,6 +1356,14 @@ int nmpc_timing_read(const nmpc_handle *h, double *kernel_ms, int64_t *launches,
     if (kernel_ms) *kernel_ms = h->kernel_ms;
     if (launches) *launches = h->launches;
     if (units) *units = (int64_t)h->units;
+    return NMPC_OK;
+}
+
+int nmpc_timing_read_eval(const nmpc_handle *h, int64_t *eval_units)
+{
+    g_err.clear();
+    if (!h) return fail(NMPC_E_ARG, "handle is NULL");
+    if (eval_units) *eval_units = h->dense ? 0 : (int64_t)h->units_eval;
     return NMPC_OK;
 }
 

@@ -145,6 +145,9 @@ def test_ragged_null_handle_calls():
     w = ctypes.c_int32()
     assert lib.nmpc_ragged_config(None, 1, c, ctypes.byref(w)) == nm.NMPC_E_ARG
     assert lib.nmpc_ragged_timing_enable(None, 1) == nm.NMPC_E_ARG
+    ev = ctypes.c_int64()
+    assert lib.nmpc_ragged_timing_read_eval(None, ctypes.byref(ev)) == nm.NMPC_E_ARG
+    assert lib.nmpc_timing_read_eval(None, ctypes.byref(ev)) == nm.NMPC_E_ARG
     assert lib.nmpc_ragged_solve(None, 1, c, None, None, None, None, None, None, None, None,
                                  None, None) == nm.NMPC_E_ARG
     assert lib.nmpc_autotune(None, 1, None, None, 4, None, None) == nm.NMPC_E_ARG

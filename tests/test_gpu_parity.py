@@ -193,6 +193,35 @@ def test_batch_matches_single_solves(nm):
     assert [i["iters"] for i in infos2] == [i["iters"] for i in infos]
 
 
+@pytest.mark.parametrize("upper", ["jacobi", "sgs"])
+def test_timing_counts_evaluation_only_units_apart(nm, upper):
+    """The timing counters count a unit per stage visit that evaluates and
+    updates, and apart from them the evaluation-only visits: the check of the
+    FP64-corrected iterate of an FP32-sweep solve, one visit per stage of each
+    instance. FP64 and fp32_finish solves have none."""
+    import torch
+    P = make_problem("c0")
+    x0, xref = make_batch(P, [30, 31, 32])
+    dx0, dxr = torch.tensor(x0, device="cuda"), torch.tensor(xref, device="cuda")
+    up = {"jacobi": nm.NMPC_UPPER_JACOBI, "sgs": nm.NMPC_UPPER_SGS}[upper]
+    for prec, fin, evals in ((nm.NMPC_FP32_SWEEP, 0, 3 * P.N), (nm.NMPC_FP64, 0, 0),
+                             (nm.NMPC_FP32_SWEEP, 1, 0)):
+        s = nm.Solver(P, max_batch=4, precision=prec, fp32_finish=fin, upper=up)
+        s.timing_enable(True)
+        rc, X, U, L, infos = s.solve_batch(dx0, dxr)
+        tm = s.timing_read()
+        s.close()
+        assert rc == nm.NMPC_OK
+        assert tm["eval_units"] == evals, (prec, fin, tm)
+        if upper == "jacobi":
+            # S^0 .. S^j evaluated with their (speculative) updates, plus the
+            # FP64 step from S^j in the corrected variant (iters counts it)
+            assert tm["units"] == sum((i["iters"] + 1) * P.N for i in infos), (prec, fin, tm)
+        else:
+            # two sweeps per SGS iteration after the first evaluation
+            assert tm["units"] >= sum(2 * i["iters"] * P.N for i in infos), (prec, fin, tm)
+
+
 def test_first_graph_sized_from_the_previous_solve_keeps_the_results(nm):
     """FP32-sweep Jacobi solves of one handle: the first graph of a solve is
     sized from the previous solve's iteration count (its FP32 launches, then

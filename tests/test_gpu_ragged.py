@@ -98,8 +98,16 @@ def test_ragged_fp32_converges_to_the_exact_solution(nm):
     classes, inst = small_batch(order)
     rs = nm.RaggedSolver(classes, max_instances=8, tol=1e-6, max_iter=20000,
                          precision=nm.NMPC_FP32_SWEEP)
+    rs.timing_enable(True)
     rc, res, infos, _ = rs.solve(order, [dev(x) for _, x, _ in inst], [dev(r) for _, _, r in inst])
+    tm = rs.timing_read()
     assert rc == nm.NMPC_OK
+    # every instance visits its stages once per iteration, once more for the
+    # FP64 correction of the accepted FP32 iterate, and once for the
+    # evaluation-only check of the corrected one, counted apart
+    Ns = [classes[c].N for c in order]
+    assert tm["units"] == sum((i["iters"] + 1) * n for i, n in zip(infos, Ns))
+    assert tm["eval_units"] == sum(Ns)
     for (c, x0, xr), (X, U, L), info in zip(inst, res, infos):
         ex = oracle.solve(classes[c], x0, xr, tol=1e-11, max_iter=50000)
         assert ex["status"] == "converged"
