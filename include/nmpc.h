@@ -281,8 +281,10 @@ int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches
 
 /* Evaluation-only (instance, stage) units since the last enable, which
  * nmpc_timing_read leaves out: the residual check of the FP64-corrected
- * iterate of an FP32-sweep solve (Sec. 4 with the final correction step),
- * one visit per stage of each instance that reaches it; such a unit reads
+ * iterate that ends an FP32-sweep solve (NMPC_FP32_SWEEP with its final
+ * correction step, a precision option of this library rather than part of
+ * the paper's method), one visit per stage of each instance that reaches
+ * it; such a unit reads
  * the stage and writes no new iterate. 0 for FP64 and fp32_finish solves and
  * for the streaming path and the model engine. NULL eval_units is skipped;
  * NMPC_E_ARG for a NULL handle. */
