@@ -284,10 +284,9 @@ int nmpc_timing_read(const nmpc_handle *hd, double *kernel_ms, int64_t *launches
  * iterate that ends an FP32-sweep solve (NMPC_FP32_SWEEP with its final
  * correction step, a precision option of this library rather than part of
  * the paper's method), one visit per stage of each instance that reaches
- * it; such a unit reads
- * the stage and writes no new iterate. 0 for FP64 and fp32_finish solves and
- * for the streaming path and the model engine. NULL eval_units is skipped;
- * NMPC_E_ARG for a NULL handle. */
+ * it; such a unit reads the stage and writes no new iterate. 0 for FP64 and
+ * fp32_finish solves and for the streaming path and the model engine. NULL
+ * eval_units is skipped; NMPC_E_ARG for a NULL handle. */
 int nmpc_timing_read_eval(const nmpc_handle *hd, int64_t *eval_units);
 
 /* Set the calling thread's last-error text (used by the network calls). */
